@@ -1,0 +1,95 @@
+"""Survival probabilities of reactor antineutrinos (oracle; test infrastructure).
+
+Units: u = L/E in m/MeV; dm2_ee and dm2_31 in 1e-3 eV^2; dm2_21 in 1e-5 eV^2.
+The oscillation phase Delta m^2 L / 4E (Eq. 1, natural units) is
+PHASE_K * dm2[eV^2] * u with PHASE_K = 1 / (4 hbar c) expressed in
+MeV / (eV^2 m), hbar c = 1.973269804593025e-7 eV m (exact SI-2019 constants).
+
+All functions accept complex arguments so that complex-step derivatives pass
+through them.
+"""
+import numpy as np
+
+PHASE_K = 1.266932679039099
+DM2_EE_UNIT = 1e-3
+DM2_31_UNIT = 1e-3
+DM2_21_UNIT = 1e-5
+
+
+def sin2_t13_from_sin2_2t13(s2_2t13):
+    """sin^2(theta13) from sin^2(2 theta13), branch theta13 <= pi/4."""
+    return 0.5 * (1.0 - np.sqrt(1.0 - s2_2t13))
+
+
+def prob_eq1(u, s2_2t13, dm2_ee, s2_t12, dm2_21):
+    """Short-baseline survival probability exactly as Eq. 1 prints it.
+
+    P = 1 - sin^2(2 th13) sin^2(dm2_ee L/4E) - cos^4(th13) sin^2(2 th12) sin^2(dm2_21 L/4E).
+    """
+    s2_t13 = sin2_t13_from_sin2_2t13(s2_2t13)
+    c4_t13 = (1.0 - s2_t13) ** 2
+    s2_2t12 = 4.0 * s2_t12 * (1.0 - s2_t12)
+    ph_ee = PHASE_K * (dm2_ee * DM2_EE_UNIT) * u
+    ph_21 = PHASE_K * (dm2_21 * DM2_21_UNIT) * u
+    return 1.0 - s2_2t13 * np.sin(ph_ee) ** 2 - c4_t13 * s2_2t12 * np.sin(ph_21) ** 2
+
+
+def prob_3nu(u, s2_t12, s2_t13, dm2_21, dm2_31):
+    """Exact vacuum three-flavour electron-antineutrino survival probability.
+
+    P = 1 - 4|Ue1|^2|Ue2|^2 sin^2 D21 - 4|Ue1|^2|Ue3|^2 sin^2 D31 - 4|Ue2|^2|Ue3|^2 sin^2 D32,
+    |Ue1|^2 = c12^2 c13^2, |Ue2|^2 = s12^2 c13^2, |Ue3|^2 = s13^2, dm2_32 = dm2_31 - dm2_21.
+    This is the formula Eq. 10 rewrites for medium baselines (see prob_eq10).
+    The sign of dm2_31 selects the ordering (positive: normal, negative: inverted).
+    """
+    c2_12 = 1.0 - s2_t12
+    c2_13 = 1.0 - s2_t13
+    ue1 = c2_12 * c2_13
+    ue2 = s2_t12 * c2_13
+    ue3 = s2_t13
+    m21 = dm2_21 * DM2_21_UNIT
+    m31 = dm2_31 * DM2_31_UNIT
+    m32 = m31 - m21
+    d21 = PHASE_K * m21 * u
+    d31 = PHASE_K * m31 * u
+    d32 = PHASE_K * m32 * u
+    return (1.0 - 4.0 * ue1 * ue2 * np.sin(d21) ** 2
+            - 4.0 * ue1 * ue3 * np.sin(d31) ** 2
+            - 4.0 * ue2 * ue3 * np.sin(d32) ** 2)
+
+
+def dm2_ee_from_3nu(s2_t12, dm2_21, dm2_31):
+    """Eq. 2: dm2_ee = cos^2(th12)|dm2_31| + sin^2(th12)|dm2_32|, in units of 1e-3 eV^2."""
+    m31 = dm2_31 * DM2_31_UNIT
+    m32 = m31 - dm2_21 * DM2_21_UNIT
+    return ((1.0 - s2_t12) * abs(m31) + s2_t12 * abs(m32)) / DM2_EE_UNIT
+
+
+def prob_eq10(u, s2_t12, s2_t13, dm2_21, dm2_31):
+    """Eq. 10, medium-baseline form, under the reading used throughout this project.
+
+    The printed equation is garbled by text extraction; it is read as
+      P = 1 - 1/2 sin^2(2th13) [1 - sqrt(1 - sin^2(2th12) sin^2 D21) cos(2 D_ee +- phi)]
+            - sin^2(2th12) cos^4(th13) sin^2 D21,
+      D_ab = dm2_ab L / 4E, dm2_ee from Eq. 2,
+      phi = atan2(cos(2th12) sin D21, cos D21) - D21 cos(2th12)  (quadrant-correct arctan),
+      + for normal ordering (dm2_31 > 0), - for inverted.
+    Real arguments only (identity check against prob_3nu).
+    """
+    s2_2t12 = 4.0 * s2_t12 * (1.0 - s2_t12)
+    c2t12 = 1.0 - 2.0 * s2_t12
+    s2_2t13 = 4.0 * s2_t13 * (1.0 - s2_t13)
+    c4_t13 = (1.0 - s2_t13) ** 2
+    dee = dm2_ee_from_3nu(s2_t12, dm2_21, dm2_31)
+    d21 = PHASE_K * dm2_21 * DM2_21_UNIT * u
+    dee_ph = PHASE_K * dee * DM2_EE_UNIT * u
+    phi = np.arctan2(c2t12 * np.sin(d21), np.cos(d21)) - d21 * c2t12
+    sign = 1.0 if dm2_31 > 0 else -1.0
+    amp = np.sqrt(1.0 - s2_2t12 * np.sin(d21) ** 2)
+    return (1.0 - 0.5 * s2_2t13 * (1.0 - amp * np.cos(2 * dee_ph + sign * phi))
+            - s2_2t12 * c4_t13 * np.sin(d21) ** 2)
+
+
+def prob_two_flavour(u, s2_2t, dm2_ev2):
+    """Textbook two-flavour survival probability 1 - sin^2(2th) sin^2(dm2 L/4E), dm2 in eV^2."""
+    return 1.0 - s2_2t * np.sin(PHASE_K * dm2_ev2 * u) ** 2

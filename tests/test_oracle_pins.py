@@ -1,0 +1,483 @@
+"""Pins of the oracle against what the paper and mathematics fix (CPU only).
+
+Each test checks the oracle against an independent route: a physical constant,
+a textbook limit, the quantum-mechanical amplitude, a library routine
+(scipy.stats, scipy.integrate), a closed form or brute force on hand-placed
+inputs. None of them retypes the oracle's own formula.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+from scipy import integrate, stats
+
+from oracle import oscillation as osc
+from oracle.model import Model
+from oracle import fold as F
+from oracle import spectrum as SP
+from oracle import likelihood as LK
+from oracle import fit as FIT
+from paper_2502_15253_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- oscillation
+
+def test_phase_constant_from_codata():
+    # Delta m^2 L / 4E in natural units, with dm2 in eV^2, L in m, E in MeV.
+    hbar_c_ev_m = sc.hbar * sc.c / sc.e
+    assert osc.PHASE_K == pytest.approx(1.0 / (4.0 * 1e6 * hbar_c_ev_m), rel=1e-15)
+
+
+def _pmns_first_row_sq(s2_t12, s2_t13):
+    """|U_e j|^2 from the product of rotation matrices R23 R13 R12 (delta = 0)."""
+    t12, t13, t23 = np.arcsin(np.sqrt(s2_t12)), np.arcsin(np.sqrt(s2_t13)), 0.7
+
+    def rot(i, j, t):
+        R = np.eye(3)
+        R[i, i] = R[j, j] = np.cos(t)
+        R[i, j] = np.sin(t)
+        R[j, i] = -np.sin(t)
+        return R
+
+    U = rot(1, 2, t23) @ rot(0, 2, t13) @ rot(0, 1, t12)
+    return U[0] ** 2
+
+
+def _p_amplitude(u, s2_t12, s2_t13, dm2_21, dm2_31):
+    """|sum_j |U_ej|^2 exp(-i m_j^2 L / 2E)|^2 with m_1 = 0 (vacuum, QM amplitude)."""
+    row = _pmns_first_row_sq(s2_t12, s2_t13)
+    m2 = np.array([0.0, dm2_21 * 1e-5, dm2_31 * 1e-3])
+    ph = 2.0 * osc.PHASE_K * np.outer(u, m2)          # m^2 L / 2E
+    amp = (row[None, :] * np.exp(-1j * ph)).sum(axis=1)
+    return np.abs(amp) ** 2
+
+
+@pytest.mark.parametrize("dm2_31", [2.53, -2.45])
+def test_3nu_equals_quantum_amplitude(dm2_31):
+    rng = np.random.default_rng(5)
+    u = rng.uniform(10, 30000, 5000)
+    for s12, s13, d21 in [(0.307, 0.0218, 7.53), (0.25, 0.04, 9.0), (0.4, 0.01, 5.0)]:
+        a = osc.prob_3nu(u, s12, s13, d21, dm2_31)
+        b = _p_amplitude(u, s12, s13, d21, dm2_31)
+        assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_eq10_reading_is_the_three_flavour_sum():
+    rng = np.random.default_rng(7)
+    u = rng.uniform(52e3, 53e3, 20000) / rng.uniform(1.8, 12, 20000)
+    for dm31 in (2.53, -2.45):
+        assert np.max(np.abs(osc.prob_eq10(u, 0.307, 0.0218, 7.53, dm31)
+                             - osc.prob_3nu(u, 0.307, 0.0218, 7.53, dm31))) < 1e-13
+
+
+def test_no_mixing_gives_unit_probability():
+    u = np.linspace(1, 30000, 1001)
+    assert np.all(osc.prob_eq1(u, 0.0, 2.5, 0.0, 7.53) == 1.0)
+    assert np.all(osc.prob_3nu(u, 0.0, 0.0, 7.53, 2.53) == 1.0)
+
+
+def test_theta13_zero_is_two_flavour_solar():
+    u = np.linspace(1, 30000, 1001)
+    s12 = 0.307
+    s2_2t12 = 4 * s12 * (1 - s12)
+    two = osc.prob_two_flavour(u, s2_2t12, 7.53e-5)
+    assert np.max(np.abs(osc.prob_eq1(u, 0.0, 2.5, s12, 7.53) - two)) < 1e-14
+    assert np.max(np.abs(osc.prob_3nu(u, s12, 0.0, 7.53, 2.53) - two)) < 1e-14
+
+
+def test_solar_off_is_two_flavour_atmospheric():
+    u = np.linspace(1, 30000, 1001)
+    s2 = 0.085
+    assert np.max(np.abs(osc.prob_eq1(u, s2, 2.5, 0.0, 7.53)
+                         - osc.prob_two_flavour(u, s2, 2.5e-3))) < 1e-14
+    s13 = 0.0218
+    s2_2t13 = 4 * s13 * (1 - s13)
+    assert np.max(np.abs(osc.prob_3nu(u, 0.0, s13, 7.53, 2.53)
+                         - osc.prob_two_flavour(u, s2_2t13, 2.53e-3))) < 1e-14
+    # first atmospheric maximum: Delta_ee = pi/2 -> P = 1 - sin^2(2 theta13)
+    u_max = (np.pi / 2) / (osc.PHASE_K * 2.5e-3)
+    assert osc.prob_eq1(u_max, s2, 2.5, 0.0, 7.53) == pytest.approx(1 - s2, abs=1e-15)
+
+
+def test_eq1_differs_from_3nu_only_in_the_atmospheric_bracket():
+    # Exact three-flavour P minus Eq. 1 (with dm2_ee from Eq. 2) must equal
+    # sin^2(2th13) [sin^2 D_ee - c12^2 sin^2 D31 - s12^2 sin^2 D32]: the solar terms agree
+    # (including cos^4 th13), so any mistake in Eq. 1's solar term breaks this.
+    rng = np.random.default_rng(3)
+    u = rng.uniform(10, 1100.0 / 1.8, 4000)   # Double Chooz range of L/E
+    s12, s13, d21, d31 = 0.307, 0.0218, 7.53, 2.53
+    s2_2t13 = 4 * s13 * (1 - s13)
+    dee = osc.dm2_ee_from_3nu(s12, d21, d31)
+    p1 = osc.prob_eq1(u, s2_2t13, dee, s12, d21)
+    p3 = _p_amplitude(u, s12, s13, d21, d31)
+    k = osc.PHASE_K
+    D = lambda m: k * m * u
+    bracket = (np.sin(D(dee * 1e-3)) ** 2 - (1 - s12) * np.sin(D(d31 * 1e-3)) ** 2
+               - s12 * np.sin(D(d31 * 1e-3 - d21 * 1e-5)) ** 2)
+    assert np.max(np.abs((p3 - p1) - s2_2t13 * bracket)) < 1e-14
+    # and Eq. 1 is a good short-baseline approximation (survey of the paper's use)
+    assert np.max(np.abs(p3 - p1)) < 1e-4
+
+
+def test_probability_bounds():
+    rng = np.random.default_rng(11)
+    u = rng.uniform(1, 60000, 20000)
+    for _ in range(20):
+        s12, s13 = rng.uniform(0, 1, 2)
+        p = osc.prob_3nu(u, s12, s13, rng.uniform(1, 10), rng.uniform(-3, 3))
+        assert p.min() >= -1e-15 and p.max() <= 1 + 1e-15
+        # Eq. 1 is not unitary: only the upper bound holds for arbitrary mixing
+        p = osc.prob_eq1(u, rng.uniform(0, 1), rng.uniform(1, 4), s12, rng.uniform(1, 10))
+        assert p.max() <= 1 + 1e-15
+
+
+# ---------------------------------------------------------------- fold
+
+def _one_ds_model(formula="3nu", K=3, S=2, y0=1.0, wf=1.0, baselines=(500.0, 900.0)):
+    if formula == "3nu":
+        o = dict(formula="3nu", sin2_t12=dict(param="a"), sin2_t13=dict(param="b"),
+                 dm2_21=dict(param="c"), dm2_31=dict(param="d"))
+        params = [synth.param("a", 0.307), synth.param("b", 0.0218),
+                  synth.param("c", 7.53), synth.param("d", 2.53)]
+    else:
+        o = dict(formula="eq1", sin2_2t13=dict(param="a"), dm2_ee=dict(param="b"),
+                 sin2_t12=dict(value=0.307), dm2_21=dict(value=7.53))
+        params = [synth.param("a", 0.085), synth.param("b", 2.5)]
+    edges = [y0 + wf * i for i in range(K + 1)]
+    ds = dict(name="t", fine=dict(y0=y0, width=wf, n=K), edges=edges,
+              sources=[dict(baseline_m=b, norm=[]) for b in baselines[:S]], norm=[],
+              flux=None, escale=None, backgrounds=[])
+    return dict(version=1, osc=o, params=params, cov_priors=[], datasets=[ds])
+
+
+def test_fold_mono_energetic_closed_form():
+    desc = _one_ds_model()
+    m = Model(desc)
+    n = 50
+    ev = dict(e_true=np.full(n, 3.3), e_reco=np.full(n, 2.5), source=np.ones(n, np.uint8),
+              weight=np.linspace(0.5, 1.5, n).astype(np.float32))
+    th = np.array([0.307, 0.0218, 7.53, 2.53])
+    S = F.fold_all(m, [ev], th)[0]
+    p = _p_amplitude(np.array([900.0 / 3.3]), 0.307, 0.0218, 7.53, 2.53)[0]
+    expect = np.zeros((2, 3))
+    expect[1, 1] = p * ev["weight"].astype(np.float64).sum()
+    assert np.max(np.abs(S - expect)) < 1e-12 * expect.max()
+
+
+def test_fold_brute_force_hand_placed():
+    # Three fine bins [1,2), [2,3), [3,4); two sources at 500 m and 900 m.
+    desc = _one_ds_model()
+    m = Model(desc)
+    e_reco = np.array([1.0, 1.5, 1.999, 2.0, 2.7, 3.0, 3.99, 4.0, 0.99, 2.2, 3.5, 1.2])
+    # expected fine bin by hand (None: dropped)
+    kk = [0, 0, 0, 1, 1, 2, 2, None, None, 1, 2, 0]
+    src = np.array([0, 1, 0, 1, 0, 1, 0, 1, 0, 0, 1, 1], np.uint8)
+    e_true = np.array([2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0, 7.5])
+    w = np.array([1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12], np.float32)
+    ev = dict(e_true=e_true, e_reco=e_reco, source=src, weight=w)
+    th = np.array([0.307, 0.0218, 7.53, 2.53])
+    S = F.fold_all(m, [ev], th)[0]
+    L = [500.0, 900.0]
+    expect = np.zeros((2, 3))
+    for e in range(len(w)):
+        if kk[e] is None:
+            continue
+        p = _p_amplitude(np.array([L[src[e]] / e_true[e]]), 0.307, 0.0218, 7.53, 2.53)[0]
+        expect[src[e], kk[e]] += float(w[e]) * p
+    assert np.max(np.abs(S - expect)) < 1e-13
+    assert F.dropped_events(m, [ev]) == [2]
+
+
+def test_fold_totals_and_permutation():
+    desc, evs = synth.model_and_events(1, 20000)
+    m = Model(desc)
+    ev = evs[0]
+    th = synth.start_vector(desc)
+    # mixing off: histogram total = summed weight of in-range events
+    th0 = th.copy()
+    th0[m.index["osc.sin2_2t13"]] = 0.0
+    desc0 = json.loads(json.dumps(desc))
+    desc0["osc"]["sin2_t12"] = dict(value=0.0)
+    m0 = Model(desc0)
+    S0 = F.fold_all(m0, [ev], th0)[0]
+    y = F.fine_edges(m0.datasets[0])
+    inr = (ev["e_reco"] >= y[0]) & (ev["e_reco"] < y[-1])
+    assert S0.sum() == pytest.approx(ev["weight"][inr].astype(np.float64).sum(), rel=1e-13)
+    # permutation invariance
+    perm = np.random.default_rng(1).permutation(len(ev["weight"]))
+    evp = {k: v[perm] for k, v in ev.items()}
+    S1 = F.fold_all(m, [ev], th)[0]
+    S2 = F.fold_all(m, [evp], th)[0]
+    assert np.max(np.abs(S1 - S2)) < 1e-12 * S1.max()
+
+
+def test_fine_grid_is_gcd_of_widths():
+    g = json.load(open(os.path.join(GOLDEN, "paper_structure.json")))
+    lo, hi = g["flux_grid_lo_mev"], g["flux_grid_hi_mev"]
+    # custom analysis widths, all multiples of 0.25 MeV, spanning [1, 11.25]
+    widths = [0.5, 0.25, 0.75, 1.0, 0.5, 0.5, 1.25, 0.25, 0.5, 0.75, 1.0, 1.5, 1.5]
+    edges = np.concatenate([[lo], lo + np.cumsum(widths)])
+    assert edges[-1] == pytest.approx(hi)
+    y0, width, n = F.fine_grid_from_edges(edges)
+    assert (y0, n) == (lo, g["flux_params_per_dataset"])
+    assert width == pytest.approx(0.25, abs=1e-12)
+
+
+# ---------------------------------------------------------------- energy scale / spline
+
+def _hist(rng, K, zeros=0):
+    H = rng.uniform(0.0, 10.0, K)
+    if zeros:
+        H[rng.choice(K, zeros, replace=False)] = 0.0
+    return H
+
+
+def test_spline_conserves_area_and_is_nonnegative():
+    rng = np.random.default_rng(2)
+    wf, y0 = 0.25, 1.0
+    for trial in range(30):
+        K = int(rng.integers(3, 25))
+        H = _hist(rng, K, zeros=int(rng.integers(0, K // 2)))
+        parts = SP.spline_parts(H, wf)
+        for k in range(K):
+            a, b = y0 + k * wf, y0 + (k + 1) * wf
+            val, _ = integrate.quad(lambda y: SP.density(H, wf, y0, y, parts), a, b,
+                                    epsabs=1e-13, epsrel=1e-13)
+            assert val == pytest.approx(H[k], abs=1e-11)
+        ys = np.linspace(y0, y0 + K * wf, 40 * K, endpoint=False)
+        assert min(SP.density(H, wf, y0, y, parts) for y in ys) >= -1e-12
+
+
+def test_spline_is_continuous_at_edges():
+    rng = np.random.default_rng(4)
+    wf, y0 = 0.5, 0.0
+    H = _hist(rng, 12)
+    parts = SP.spline_parts(H, wf)
+    for k in range(1, 12):
+        e = y0 + k * wf
+        lo = SP.density(H, wf, y0, e - 1e-10, parts)
+        hi = SP.density(H, wf, y0, e + 1e-10, parts)
+        assert abs(lo - hi) < 1e-7
+
+
+def test_constant_histogram_gives_flat_density_and_shift_closed_form():
+    K, wf, y0 = 20, 0.5, 1.0
+    H = np.full(K, 3.0)
+    parts = SP.spline_parts(H, wf)
+    for y in np.linspace(y0, y0 + K * wf, 97, endpoint=False):
+        assert SP.density(H, wf, y0, y, parts) == pytest.approx(6.0, abs=1e-12)
+    # pure shift f(E) = E + c0: s_i = m * length of [x_i - c0, x_{i+1} - c0] inside the range
+    desc = _one_ds_model(formula="eq1", K=K, S=1, y0=y0, wf=wf)
+    edges = np.array([2.0, 3.1, 4.05, 7.3, 10.9, 12.0])
+    desc["datasets"][0]["edges"] = list(edges)
+    ds = Model(desc).datasets[0]
+    c0 = 0.137
+    s = SP.rebin(ds, H, [c0, 0.0, 0.0])
+    lo, hi = y0, y0 + K * wf
+    expect = [6.0 * (min(max(b - c0, lo), hi) - min(max(a - c0, lo), hi))
+              for a, b in zip(edges[:-1], edges[1:])]
+    assert np.max(np.abs(s - expect)) < 1e-12
+
+
+def test_identity_map_on_fine_edges_sums_fine_bins():
+    rng = np.random.default_rng(6)
+    K, wf, y0 = 30, 0.25, 1.0
+    desc = _one_ds_model(formula="eq1", K=K, S=1, y0=y0, wf=wf)
+    idx = [2, 5, 6, 11, 20, 27]
+    desc["datasets"][0]["edges"] = [y0 + wf * i for i in idx]
+    ds = Model(desc).datasets[0]
+    H = _hist(rng, K)
+    s = SP.rebin(ds, H, [0.0, 0.0, 0.0])
+    expect = [H[a:b].sum() for a, b in zip(idx[:-1], idx[1:])]
+    assert np.max(np.abs(s - expect)) < 1e-12 * H.sum()
+
+
+def test_rebin_agrees_with_quadrature_in_data_space():
+    # Second route: s_i = integral over data energy x of rho(g(x)) g'(x) dx,
+    # with g' = 1 / f'(g(x)), by Gauss-Legendre on pieces between fine edges.
+    rng = np.random.default_rng(8)
+    K, wf, y0 = 24, 0.3, 0.9
+    desc = _one_ds_model(formula="eq1", K=K, S=1, y0=y0, wf=wf)
+    edges = np.array([1.0, 1.7, 2.2, 3.5, 4.4, 5.0, 6.3, 7.2, 7.8])
+    desc["datasets"][0]["edges"] = list(edges)
+    ds = Model(desc).datasets[0]
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    for trial in range(10):
+        H = _hist(rng, K)
+        c = [rng.uniform(-0.05, 0.05), rng.uniform(-0.02, 0.02), rng.uniform(-0.004, 0.004)]
+        s = SP.rebin(ds, H, c)
+        parts = SP.spline_parts(H, wf)
+        f = lambda E: c[0] + (1 + c[1]) * E + c[2] * E * E
+        fp = lambda E: (1 + c[1]) + 2 * c[2] * E
+        # data-space images of the fine edges split the integrals into smooth pieces
+        knots = sorted(set([f(y0 + wf * k) for k in range(K + 1)]))
+        for i in range(len(edges) - 1):
+            a, b = edges[i], edges[i + 1]
+            pts = [a] + [q for q in knots if a < q < b] + [b]
+            tot = 0.0
+            for p0, p1 in zip(pts[:-1], pts[1:]):
+                x = 0.5 * (p1 - p0) * xg + 0.5 * (p1 + p0)
+                vals = []
+                for xx in x:
+                    E = SP.energy_map_inverse(xx, c)
+                    vals.append(SP.density(H, wf, y0, E, parts) / fp(E))
+                tot += 0.5 * (p1 - p0) * np.dot(wg, vals)
+            assert s[i] == pytest.approx(tot, abs=1e-11 * H.sum())
+
+
+def test_energy_map_inverse_roundtrip():
+    rng = np.random.default_rng(9)
+    E = rng.uniform(0.5, 12, 1000)
+    for c in [(0.02, 0.01, 0.002), (-0.02, -0.01, -0.002), (0.0, 0.0, 1e-12), (0.01, 0.0, 0.0)]:
+        f = c[0] + (1 + c[1]) * E + c[2] * E * E
+        g = np.array([SP.energy_map_inverse(x, c) for x in f])
+        assert np.max(np.abs(g - E)) < 1e-13
+
+
+def test_rebin_matches_per_event_binning_statistically():
+    desc, evs = synth.model_and_events(1, 200000)
+    m = Model(desc)
+    ds = m.datasets[0]
+    ev = evs[0]
+    th = synth.start_vector(desc)
+    c = [0.05, 0.02, -0.001]
+    S = F.fold_all(m, [ev], th)[0]
+    s = SP.rebin(ds, S[0], c)
+    k, keep = F.bin_events(ds, ev["e_reco"])
+    u = ds.baselines[ev["source"].astype(int)] / ev["e_true"]
+    p = osc.prob_eq1(u, *m.osc_values(th))
+    x = c[0] + (1 + c[1]) * ev["e_reco"] + c[2] * ev["e_reco"] ** 2
+    hb, _ = np.histogram(x[keep], bins=ds.edges, weights=(ev["weight"] * p)[keep])
+    w2, _ = np.histogram(x[keep], bins=ds.edges, weights=((ev["weight"] * p) ** 2)[keep])
+    pull = (s - hb) / np.sqrt(w2 + 1e-30)
+    assert np.sqrt(np.mean(pull ** 2)) < 3.0
+
+
+# ---------------------------------------------------------------- rescale and backgrounds
+
+def test_rescale_norms_and_flux_by_hand():
+    desc = synth.tiny_model(1, n_datasets=1, n_sources=2, escale=False)
+    m = Model(desc)
+    ds = m.datasets[0]
+    th = synth.start_vector(desc)
+    S = np.arange(2 * ds.K, dtype=float).reshape(2, ds.K) + 1.0
+    H = SP.rescale(ds, S, th)
+    for k in range(ds.K):
+        a0 = th[m.index["src0.norm"]] * th[m.index["ds0.norm"]]
+        a1 = th[m.index["src1.norm"]] * th[m.index["ds0.norm"]]
+        fk = sum(th[m.index[f"ds0.flux[{j}]"]] * desc["datasets"][0]["flux"]["basis"][j][k]
+                 for j in range(3))
+        assert H[k] == pytest.approx((a0 * S[0, k] + a1 * S[1, k]) * (1 + fk), rel=1e-14)
+
+
+def test_background_linearity():
+    desc = synth.tiny_model(2, n_datasets=1)
+    m = Model(desc)
+    ds = m.datasets[0]
+    th = synth.start_vector(desc)
+    B = SP.backgrounds(ds, th)
+    ir = m.index["ds0.bkg.rate"]
+    th2 = th.copy(); th2[ir] *= 2.0
+    assert np.max(np.abs(SP.backgrounds(ds, th2) - 2 * B)) < 1e-12 * B.max()
+    i3 = m.index["ds0.bkg.shape[3]"]
+    th3 = th.copy(); th3[i3] += 0.1
+    B3 = SP.backgrounds(ds, th3)
+    assert B3[3] == pytest.approx(B[3] * (1 + th3[i3]) / (1 + th[i3]), rel=1e-13)
+    assert np.all(np.delete(B3, 3) == np.delete(B, 3))
+
+
+# ---------------------------------------------------------------- likelihood
+
+def test_deviance_matches_scipy_poisson():
+    rng = np.random.default_rng(12)
+    mu = rng.uniform(0.1, 50, 200)
+    n = rng.poisson(mu).astype(float)
+    n[:5] = 0.0
+    ref = np.sum(-stats.poisson.logpmf(n, mu) + stats.poisson.logpmf(n, n))
+    assert LK.poisson_deviance_half(n, mu) == pytest.approx(ref, rel=1e-12)
+
+
+def test_priors_match_scipy_normal_densities():
+    desc = synth.tiny_model(3, n_datasets=2)
+    m = Model(desc)
+    rng = np.random.default_rng(13)
+    th = synth.start_vector(desc) + 0.01 * rng.standard_normal(m.P)
+    ref = 0.0
+    for i, mean, sigma in m.gauss:
+        ref -= stats.norm.logpdf(th[i], mean, sigma) - stats.norm.logpdf(mean, mean, sigma)
+    for idx, mean, cov in m.blocks:
+        mv = stats.multivariate_normal(mean, cov)
+        ref -= mv.logpdf(th[idx]) - mv.logpdf(mean)
+    assert LK.prior_terms(m, th) == pytest.approx(ref, rel=1e-11)
+
+
+def _center_priors_on(desc, theta):
+    for p, v in zip(desc["params"], theta):
+        if p["prior"] is not None:
+            p["prior"][0] = float(v)
+    for c in desc["cov_priors"]:
+        c["mean"] = [float(theta[[q["name"] for q in desc["params"]].index(n)])
+                     for n in c["params"]]
+
+
+@pytest.mark.parametrize("formula", ["eq1", "3nu"])
+def test_asimov_data_gives_zero_deviance_and_gradient(formula):
+    desc = synth.tiny_model(4, formula=formula)
+    ev = synth.tiny_events(desc, 3000, 17)
+    th = synth.start_vector(desc)
+    _center_priors_on(desc, th)
+    m = Model(desc)
+    mus, ok = LK.expected(m, ev, th)
+    assert ok
+    f, g = LK.nll_grad(m, ev, mus, th)
+    assert abs(f) < 1e-9
+    assert np.max(np.abs(g)) < 1e-8
+    assert LK.saturated_statistic(f) == pytest.approx(0.0, abs=1e-9)
+
+
+def test_nonpositive_expectation_gives_infinite_nll():
+    desc = synth.tiny_model(5, n_datasets=1)
+    ev = synth.tiny_events(desc, 500, 1)
+    m = Model(desc)
+    th = synth.start_vector(desc)
+    data = [np.ones(ds.Nb) for ds in m.datasets]
+    th[m.index["ds0.norm"]] = -1.0
+    th[m.index["ds0.bkg.rate"]] = -1.0
+    f, g = LK.nll_grad(m, ev, data, th)
+    assert f == np.inf and np.all(g == 0)
+
+
+@pytest.mark.parametrize("formula", ["eq1", "3nu"])
+def test_complex_step_gradient_matches_central_differences(formula):
+    desc = synth.tiny_model(6, formula=formula)
+    ev = synth.tiny_events(desc, 2000, 23)
+    m = Model(desc)
+    th = synth.start_vector(desc)
+    data = [np.round(mu * 1.1 + 3) for mu in LK.expected(m, ev, th)[0]]
+    f, g = LK.nll_grad(m, ev, data, th)
+    h = 1e-6
+    gfd = np.zeros(m.P)
+    for j in range(m.P):
+        e = np.zeros(m.P); e[j] = h
+        gfd[j] = (LK.nll(m, ev, data, th + e) - LK.nll(m, ev, data, th - e)) / (2 * h)
+    assert np.max(np.abs(g - gfd)) <= 1e-5 * max(1.0, np.max(np.abs(g)))
+
+
+def test_asimov_fit_recovers_truth():
+    desc, evs = synth.model_and_events(1, 20000)
+    m = Model(desc)
+    th = synth.start_vector(desc)
+    data = LK.expected(m, evs, th)[0]
+    start = th.copy()
+    start[m.index["osc.sin2_2t13"]] = 0.06
+    start[m.index["osc.dm2_ee"]] = 2.4
+    start[m.index["norm"]] = 1.01
+    r = FIT.fit(m, evs, data, start)
+    assert r["nll"] < 1e-8
+    assert r["edm"] < 1e-7
+    assert abs(r["theta"][m.index["osc.sin2_2t13"]] - 0.085) < 1e-4
+    assert abs(r["theta"][m.index["osc.dm2_ee"]] - 2.5) < 1e-3
