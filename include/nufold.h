@@ -1,0 +1,166 @@
+/*
+ * nufold: forward-folding binned-likelihood engine for reactor-neutrino
+ * oscillation fits on AMD Instinct MI355X (gfx950).
+ *
+ * One model evaluation follows the paper's likelihood (Eq. 3-6, 9) and its
+ * three-step signal calculation ("Structure of the framework"):
+ *   1. every MC event is weighted by the survival probability (Eq. 1, or the
+ *      exact three-flavour form that Eq. 10 rewrites) and summed into fine
+ *      reconstructed-energy bins per dataset and source;
+ *   2. the fine spectrum is rescaled by rate normalisations and flux-shape
+ *      parameters;
+ *   3. an area-conserving quadratic spline of the fine spectrum is integrated
+ *      over the pre-images of the analysis bins under the second-order
+ *      energy-scale polynomial; data-driven background templates are added;
+ * then the binned Poisson negative log-likelihood (deviance form) plus
+ * Gaussian and correlated-Gaussian priors is reduced in FP64, and its
+ * gradient is obtained by one adjoint (reverse) pass.
+ *
+ * Conventions
+ *   - Return codes: 0 OK; >0 warnings; <0 errors (see NF_* below).
+ *     nf_last_error() returns a message owned by the context.
+ *   - A context owns all device memory it allocates and is used by one host
+ *     thread at a time.
+ *   - Host-pointer calls are synchronous. Calls taking device pointers are
+ *     enqueued on the context's stream and return without synchronising.
+ *   - Units: energies in MeV, baselines in m, dm2_ee and dm2_31 in 1e-3 eV^2,
+ *     dm2_21 in 1e-5 eV^2 ("fit units").
+ *   - Parameter vectors theta have nf_num_params() entries, in the order of
+ *     the model description's "params" list.
+ */
+#ifndef NUFOLD_H
+#define NUFOLD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define NF_OK 0
+#define NF_WDOMAIN 1   /* some expectation <= 0, energy map not monotone, or oscillation
+                          parameter outside its domain: NLL = +inf, gradient = 0        */
+#define NF_WNOCONV 2   /* fit stopped at its iteration limit before reaching the EDM goal */
+#define NF_EINVAL -1   /* invalid argument: NaN/inf, bad size or index, null pointer      */
+#define NF_ESTATE -2   /* call out of order (evaluation before events and data are set)  */
+#define NF_ENOMEM -3   /* device or host allocation failed                                 */
+#define NF_EDEVICE -4  /* no usable HIP device, or a HIP call failed                       */
+#define NF_EPARSE -5   /* model description is not valid JSON or violates the schema      */
+
+/* precision modes */
+#define NF_M64 0       /* everything FP64; event stream u = L/E as f64, weights f32         */
+#define NF_M32 1       /* per-event oscillation weight and per-lane sums in FP32 (u, w f32);
+                          per-wave and later sums, bin stages, NLL and gradient in FP64     */
+
+typedef struct nf_ctx nf_ctx;
+
+/*
+ * Create a context from a JSON model description (paper: "Structure of the
+ * framework", the configuration component). Schema:
+ *   {"params": [{"name", "start", "prior": [mean, sigma] | null, "fixed"}],
+ *    "cov_priors": [{"params": [names], "mean": [..], "cov": [[..]]}],
+ *    "osc": {"formula": "eq1" | "3nu", <slot>: {"param": name} | {"value": v}},
+ *    "datasets": [{"fine": {"y0", "width", "n"}, "edges": [Nb+1],
+ *                  "sources": [{"baseline_m", "norm": [names]}], "norm": [names],
+ *                  "flux": {"params": [M names], "basis": [M][n]},
+ *                  "escale": {"c0", "c1", "c2": name | null},
+ *                  "backgrounds": [{"rate": name | null, "scale",
+ *                                   "template": [Nb], "shape": [Nb names|null] | null}]}]}
+ * eq1 slots: sin2_2t13, dm2_ee, sin2_t12, dm2_21 (Eq. 1).
+ * 3nu slots: sin2_t12, sin2_t13, dm2_21, dm2_31 (exact vacuum form; sign of dm2_31 = ordering).
+ * model_json: NUL-terminated, caller-owned, copied. mode: NF_M64 or NF_M32.
+ * hip_stream: hipStream_t to order device work on, or NULL for a stream the
+ * context creates and owns. On error *out is NULL and the return code says why
+ * (NF_EPARSE for schema errors, NF_EDEVICE without a GPU).
+ */
+int nf_create(nf_ctx** out, const char* model_json, int mode, void* hip_stream);
+
+/* Free the context and every device buffer it owns. NULL is allowed. */
+void nf_destroy(nf_ctx* ctx);
+
+/* Message for the last non-OK return on this context (or of the last failed
+ * nf_create when ctx is NULL). Valid until the next call on the context. */
+const char* nf_last_error(const nf_ctx* ctx);
+
+int nf_num_params(const nf_ctx* ctx);
+int nf_num_datasets(const nf_ctx* ctx);
+/* Number of analysis bins of dataset d, or NF_EINVAL. */
+int nf_num_bins(const nf_ctx* ctx, int dataset);
+/* Index of a named parameter, or NF_EINVAL if unknown. */
+int nf_param_index(const nf_ctx* ctx, const char* name);
+
+/*
+ * Load the MC events of one dataset (paper: events are copied to the device
+ * once and sorted by energy for locality; "GPU accelerated computation").
+ * n events, SoA: e_true (MeV, > 0), e_reco (MeV), source index (< number of
+ * sources; NULL means all 0), weight (NULL means all 1). Events with e_reco
+ * outside the dataset's fine range [y0, y0 + n*width) are dropped and counted.
+ * on_device != 0: the four pointers are device pointers; otherwise host.
+ * The context copies the data; the caller keeps ownership. Replaces any
+ * previous events of the dataset. n == 0 is allowed (empty signal).
+ */
+int nf_set_events(nf_ctx* ctx, int dataset, int64_t n, const double* e_true,
+                  const double* e_reco, const uint8_t* source, const float* weight,
+                  int on_device);
+
+/* Number of events of a dataset dropped as out of range by nf_set_events. */
+int64_t nf_dropped_events(const nf_ctx* ctx, int dataset);
+
+/*
+ * Observed counts n_{d,i} of one dataset (Eq. 3-5, 9): nbins must equal
+ * nf_num_bins(dataset); counts >= 0 and finite (non-integer values allowed,
+ * e.g. Asimov data). Copied; on_device as above.
+ */
+int nf_set_data(nf_ctx* ctx, int dataset, int nbins, const double* counts, int on_device);
+
+/*
+ * Evaluate NLL(theta) = sum_{d,i} [mu - n + n ln(n/mu)] + priors
+ * (Eq. 3-6, 9 in deviance form: constants dropped, 2*NLL at a best fit is the
+ * saturated-model statistic of Eq. 8). theta: host, nf_num_params() values.
+ * Returns NF_OK, NF_WDOMAIN (nll = +inf), NF_EINVAL (NaN/inf in theta) or
+ * NF_ESTATE (events or data missing for some dataset).
+ */
+int nf_eval_nll(nf_ctx* ctx, const double* theta, double* nll);
+
+/* As nf_eval_nll, plus dNLL/dtheta in grad (host, nf_num_params() values),
+ * from one forward fold with forward-mode oscillation derivatives and one
+ * adjoint pass over the bin stages. */
+int nf_eval_nll_grad(nf_ctx* ctx, const double* theta, double* nll, double* grad);
+
+/*
+ * Device-pointer evaluation, enqueued on the context stream, no host sync.
+ * theta_dev: P doubles. out_dev: 1 + P doubles (NLL, then gradient; the
+ * gradient part is left untouched when want_grad == 0). status_dev: NULL or
+ * one int32 receiving the status bits (1 = domain warning). Inputs are not
+ * validated on the host (NaN parameters produce a domain warning).
+ */
+int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev,
+                   int32_t* status_dev, int want_grad);
+
+/* Expected counts mu_{d,i}(theta) for every dataset, concatenated in dataset
+ * order (host buffer of sum_d nf_num_bins(d) doubles). Needs events only. */
+int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
+
+/*
+ * Tuning knobs (autotuner hooks). key: "chunk" (events per fold work item,
+ * multiple of 256, default 2048), "fold_block" (threads per fold workgroup:
+ * 64, 128, 256, 512), "tail_threads" (256, 512 or 1024). Changing "chunk"
+ * rebuilds the work-item list. "timing" (0/1) turns per-kernel event timing
+ * on or off (see nf_timing). Returns NF_EINVAL for unknown keys/values.
+ */
+int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
+
+/*
+ * Per-kernel device time, measured with HIP events recorded on the context
+ * stream around the fold and the bin-stage kernels of every evaluation while
+ * option "timing" is 1. nf_timing synchronises the stream and returns, for the
+ * evaluations enqueued since the last reset: their count, the summed fold
+ * time and the summed bin-stage time (ms). reset != 0 starts a new window.
+ */
+int nf_timing(nf_ctx* ctx, int reset, int64_t* count, double* fold_ms, double* tail_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NUFOLD_H */

@@ -1,0 +1,899 @@
+// Host runtime and C-ABI of the engine: model parsing into a flat device plan,
+// the device-resident event store (sorted by dataset, source and fine bin,
+// padded, split into work items), and the evaluation entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/nufold.h"
+#include "json.hpp"
+#include "kernels.hpp"
+
+using namespace nufold;
+
+namespace {
+
+struct ApiError : std::runtime_error {
+  int code;
+  ApiError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string& m) { throw ApiError(code, m); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? NF_ENOMEM : NF_EDEVICE,
+                            std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct HostBkg {
+  int rate = -1;
+  double scale = 0.0;
+  std::vector<double> tmpl;
+  std::vector<int> shape;  // empty: no shape parameters
+};
+
+struct HostDataset {
+  std::string name;
+  double y0 = 0, wf = 0;
+  int K = 0, Nb = 0, S = 0, M = 0;
+  std::vector<double> edges;
+  std::vector<double> baselines;
+  std::vector<std::vector<int>> srcnorm;  // dataset norms followed by source norms
+  std::vector<int> flux_param;
+  std::vector<double> basis;  // M x K
+  int cidx[3] = {-1, -1, -1};
+  std::vector<HostBkg> bkgs;
+  // events, sorted by (source, fine bin), each segment padded to a multiple of 4
+  bool has_events = false;
+  bool has_data = false;
+  std::vector<double> u64;
+  std::vector<float> u32;
+  std::vector<float> w;
+  std::vector<int64_t> seg_count;  // padded events per segment, S*K
+  std::vector<double> Wseg;        // weight sum per segment
+  int64_t dropped = 0;
+  std::vector<double> data;
+  int seg0 = 0, bins0 = 0;
+};
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+    n = count;
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    if (v.size() != n) alloc(v.size());
+    if (!v.empty()) hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s),
+                              "hipMemcpyAsync H2D");
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Inverse of a symmetric positive-definite matrix by Cholesky (host, FP64).
+bool spd_inverse(const std::vector<double>& A, int n, std::vector<double>& inv) {
+  std::vector<double> L(A.size(), 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(s > 0.0)) return false;
+    const double d = std::sqrt(s);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = t / d;
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    // solve L y = e_c, then L^T x = y
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * col[k];
+      col[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = col[i];
+      for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * inv[(size_t)k * n + c];
+      inv[(size_t)i * n + c] = t / L[(size_t)i * n + i];
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+struct nf_ctx {
+  std::string err;
+  int mode = NF_M64;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  int P = 0;
+  std::vector<std::string> names;
+  std::map<std::string, int> index;
+  OscPlan osc{};
+  std::vector<HostDataset> ds;
+  int nbins_total = 0;
+
+  // flat plan
+  std::vector<double> dpool;
+  std::vector<int> ipool;
+  std::vector<DsPlan> dsplan;
+  std::vector<BkgPlan> bkgplan;
+  DevPlan plan{};
+
+  DevBuf<double> d_dpool;
+  DevBuf<int> d_ipool;
+  DevBuf<DsPlan> d_ds;
+  DevBuf<BkgPlan> d_bkg;
+  DevBuf<double> d_u64;
+  DevBuf<float> d_u32;
+  DevBuf<float> d_w;
+  DevBuf<WorkItem> d_items;
+  DevBuf<int> d_seg_item;
+  DevBuf<double> d_Wseg;
+  DevBuf<double> d_part;
+  DevBuf<double> d_theta;
+  DevBuf<double> d_out;
+  DevBuf<int32_t> d_status;
+  DevBuf<double> d_data;
+  DevBuf<double> d_mu;
+  DevBuf<double> d_scratch;
+  double* h_stage = nullptr;  // pinned: theta, out, mu
+  int32_t* h_status = nullptr;
+  int nitems = 0;
+
+  int64_t chunk = 2048;
+  int fold_block = 256;
+  int tail_threads = 512;
+  int timing = 0;
+  std::vector<std::array<hipEvent_t, 3>> tev;  // per-evaluation timing events
+  size_t tcount = 0;
+
+  ~nf_ctx() {
+    d_dpool.release(); d_ipool.release(); d_ds.release(); d_bkg.release();
+    d_u64.release(); d_u32.release(); d_w.release(); d_items.release(); d_seg_item.release();
+    d_Wseg.release(); d_part.release(); d_theta.release(); d_out.release(); d_status.release();
+    d_data.release(); d_mu.release(); d_scratch.release();
+    if (h_stage) (void)hipHostFree(h_stage);
+    if (h_status) (void)hipHostFree(h_status);
+    for (auto& t : tev)
+      for (auto& e : t)
+        if (e) (void)hipEventDestroy(e);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int param_ref(nf_ctx* c, const Json& v, bool allow_null, const std::string& where) {
+  if (v.is_null()) {
+    if (allow_null) return -1;
+    fail(NF_EPARSE, where + ": parameter name required");
+  }
+  auto it = c->index.find(v.string());
+  if (it == c->index.end()) fail(NF_EPARSE, where + ": unknown parameter '" + v.string() + "'");
+  return it->second;
+}
+
+std::vector<double> num_array(const Json& v, const std::string& where) {
+  std::vector<double> out;
+  for (const auto& e : v.array()) {
+    if (e.kind != Json::Number) fail(NF_EPARSE, where + ": expected numbers");
+    out.push_back(e.num);
+  }
+  return out;
+}
+
+void parse_model(nf_ctx* c, const char* text) {
+  Json root;
+  try {
+    root = parse_json(text);
+  } catch (const JsonError& e) {
+    fail(NF_EPARSE, e.what());
+  }
+  try {
+    // parameters
+    const auto& params = root.at("params").array();
+    if (params.empty()) fail(NF_EPARSE, "params: empty");
+    for (const auto& p : params) {
+      const std::string& n = p.at("name").string();
+      if (c->index.count(n)) fail(NF_EPARSE, "duplicate parameter '" + n + "'");
+      c->index[n] = (int)c->names.size();
+      c->names.push_back(n);
+    }
+    c->P = (int)c->names.size();
+    std::vector<int> gidx;
+    std::vector<double> gmean, ginv;
+    for (int i = 0; i < c->P; ++i) {
+      const Json& pr = params[i].get("prior");
+      if (pr.is_null()) continue;
+      const auto& a = pr.array();
+      if (a.size() != 2 || !(a[1].number() > 0.0)) fail(NF_EPARSE, "prior of '" + c->names[i] + "' must be [mean, sigma>0]");
+      gidx.push_back(i);
+      gmean.push_back(a[0].number());
+      ginv.push_back(1.0 / (a[1].number() * a[1].number()));
+    }
+    // oscillation
+    const Json& o = root.at("osc");
+    const std::string& f = o.at("formula").string();
+    static const char* eq1[NSLOT] = {"sin2_2t13", "dm2_ee", "sin2_t12", "dm2_21"};
+    static const char* nu3[NSLOT] = {"sin2_t12", "sin2_t13", "dm2_21", "dm2_31"};
+    const char** slots;
+    if (f == "eq1") { c->osc.formula = FORM_EQ1; slots = eq1; }
+    else if (f == "3nu") { c->osc.formula = FORM_3NU; slots = nu3; }
+    else fail(NF_EPARSE, "osc.formula must be eq1 or 3nu");
+    for (int j = 0; j < NSLOT; ++j) {
+      const Json& s = o.at(slots[j]);
+      if (s.has("param")) {
+        c->osc.slot_param[j] = param_ref(c, s.at("param"), false, std::string("osc.") + slots[j]);
+        c->osc.slot_value[j] = 0.0;
+      } else {
+        c->osc.slot_param[j] = -1;
+        c->osc.slot_value[j] = s.at("value").number();
+      }
+    }
+    // datasets
+    const auto& dsj = root.at("datasets").array();
+    if (dsj.empty()) fail(NF_EPARSE, "datasets: empty");
+    int seg0 = 0, bins0 = 0;
+    for (const auto& dj : dsj) {
+      HostDataset d;
+      d.name = dj.get("name").kind == Json::String ? dj.get("name").string() : "";
+      const Json& fine = dj.at("fine");
+      d.y0 = fine.at("y0").number();
+      d.wf = fine.at("width").number();
+      d.K = (int)fine.at("n").number();
+      if (!(d.wf > 0.0) || d.K < 1 || d.K > 8192) fail(NF_EPARSE, "fine binning invalid in dataset " + d.name);
+      d.edges = num_array(dj.at("edges"), "edges");
+      d.Nb = (int)d.edges.size() - 1;
+      if (d.Nb < 1 || d.Nb > 8192) fail(NF_EPARSE, "edges: need 2..8193 values");
+      for (int i = 0; i < d.Nb; ++i)
+        if (!(d.edges[i + 1] > d.edges[i])) fail(NF_EPARSE, "edges must increase");
+      std::vector<int> dnorm;
+      if (!dj.get("norm").is_null())
+        for (const auto& n : dj.at("norm").array()) dnorm.push_back(param_ref(c, n, false, "norm"));
+      const auto& srcs = dj.at("sources").array();
+      d.S = (int)srcs.size();
+      if (d.S < 1 || d.S > MAX_SOURCES) fail(NF_EPARSE, "sources: need 1..64");
+      for (const auto& s : srcs) {
+        const double L = s.at("baseline_m").number();
+        if (!(L > 0.0)) fail(NF_EPARSE, "baseline_m must be > 0");
+        d.baselines.push_back(L);
+        std::vector<int> lst = dnorm;
+        if (!s.get("norm").is_null())
+          for (const auto& n : s.at("norm").array()) lst.push_back(param_ref(c, n, false, "source norm"));
+        d.srcnorm.push_back(lst);
+      }
+      const Json& fl = dj.get("flux");
+      if (!fl.is_null()) {
+        for (const auto& n : fl.at("params").array()) d.flux_param.push_back(param_ref(c, n, false, "flux"));
+        d.M = (int)d.flux_param.size();
+        const auto& basis = fl.at("basis").array();
+        if ((int)basis.size() != d.M) fail(NF_EPARSE, "flux.basis must have one row per mode");
+        for (const auto& row : basis) {
+          auto r = num_array(row, "flux.basis");
+          if ((int)r.size() != d.K) fail(NF_EPARSE, "flux.basis rows must have fine.n entries");
+          d.basis.insert(d.basis.end(), r.begin(), r.end());
+        }
+      }
+      const Json& es = dj.get("escale");
+      if (!es.is_null()) {
+        d.cidx[0] = param_ref(c, es.get("c0"), true, "escale.c0");
+        d.cidx[1] = param_ref(c, es.get("c1"), true, "escale.c1");
+        d.cidx[2] = param_ref(c, es.get("c2"), true, "escale.c2");
+      }
+      if (!dj.get("backgrounds").is_null()) {
+        for (const auto& bj : dj.at("backgrounds").array()) {
+          HostBkg b;
+          b.rate = param_ref(c, bj.get("rate"), true, "background rate");
+          b.scale = bj.at("scale").number();
+          b.tmpl = num_array(bj.at("template"), "template");
+          if ((int)b.tmpl.size() != d.Nb) fail(NF_EPARSE, "template must have Nb entries");
+          const Json& sh = bj.get("shape");
+          if (!sh.is_null()) {
+            if ((int)sh.array().size() != d.Nb) fail(NF_EPARSE, "shape must have Nb entries");
+            for (const auto& n : sh.array()) b.shape.push_back(param_ref(c, n, true, "background shape"));
+          }
+          d.bkgs.push_back(b);
+        }
+      }
+      d.seg0 = seg0;
+      d.bins0 = bins0;
+      seg0 += d.S * d.K;
+      bins0 += d.Nb;
+      c->ds.push_back(std::move(d));
+    }
+    c->nbins_total = bins0;
+
+    // ---- flat pools
+    auto& dp = c->dpool;
+    auto& ip = c->ipool;
+    DevPlan& pl = c->plan;
+    pl.P = c->P;
+    pl.D = (int)c->ds.size();
+    pl.G = seg0;
+    pl.nbins_total = bins0;
+    pl.osc = c->osc;
+    pl.max_K = pl.max_Nb = pl.max_S = 0;
+    for (auto& d : c->ds) {
+      DsPlan q{};
+      q.y0 = d.y0; q.wf = d.wf; q.K = d.K; q.Nb = d.Nb; q.S = d.S; q.M = d.M;
+      q.nbkg = (int)d.bkgs.size();
+      q.seg0 = d.seg0;
+      q.data = d.bins0;
+      q.bins0 = d.bins0;
+      q.edges = (int)dp.size();
+      dp.insert(dp.end(), d.edges.begin(), d.edges.end());
+      // source norm lists: S+1 absolute offsets, then indices
+      q.srcnorm_ptr = (int)ip.size();
+      ip.resize(ip.size() + d.S + 1);
+      for (int s = 0; s < d.S; ++s) {
+        ip[q.srcnorm_ptr + s] = (int)ip.size();
+        ip.insert(ip.end(), d.srcnorm[s].begin(), d.srcnorm[s].end());
+      }
+      ip[q.srcnorm_ptr + d.S] = (int)ip.size();
+      // flux basis: CSR over fine bins, CSC over modes (exact zeros dropped)
+      q.md_param = (int)ip.size();
+      ip.insert(ip.end(), d.flux_param.begin(), d.flux_param.end());
+      std::vector<int> rmode, rptr(d.K + 1, 0), ck, cptr(d.M + 1, 0);
+      std::vector<double> rcoef, ccoef;
+      for (int k = 0; k < d.K; ++k) {
+        rptr[k] = (int)rmode.size();
+        for (int m = 0; m < d.M; ++m) {
+          const double v = d.basis[(size_t)m * d.K + k];
+          if (v != 0.0) { rmode.push_back(m); rcoef.push_back(v); }
+        }
+      }
+      rptr[d.K] = (int)rmode.size();
+      for (int m = 0; m < d.M; ++m) {
+        cptr[m] = (int)ck.size();
+        for (int k = 0; k < d.K; ++k) {
+          const double v = d.basis[(size_t)m * d.K + k];
+          if (v != 0.0) { ck.push_back(k); ccoef.push_back(v); }
+        }
+      }
+      cptr[d.M] = (int)ck.size();
+      q.fx_coef = (int)dp.size();
+      dp.insert(dp.end(), rcoef.begin(), rcoef.end());
+      q.fx_mode = (int)ip.size();
+      ip.insert(ip.end(), rmode.begin(), rmode.end());
+      // row pointers and column pointers are entry numbers relative to the
+      // dataset's entry arrays (fx_mode/fx_coef and md_k/md_coef bases)
+      q.fx_row = (int)ip.size();
+      ip.insert(ip.end(), rptr.begin(), rptr.end());
+      q.md_coef = (int)dp.size();
+      dp.insert(dp.end(), ccoef.begin(), ccoef.end());
+      q.md_k = (int)ip.size();
+      ip.insert(ip.end(), ck.begin(), ck.end());
+      q.md_col = (int)ip.size();
+      for (int m = 0; m <= d.M; ++m) ip.push_back(cptr[m]);
+      for (int j = 0; j < 3; ++j) q.cidx[j] = d.cidx[j];
+      q.bkg0 = (int)c->bkgplan.size();
+      for (auto& b : d.bkgs) {
+        BkgPlan bp{};
+        bp.scale = b.scale;
+        bp.rate = b.rate;
+        bp.tmpl = (int)dp.size();
+        dp.insert(dp.end(), b.tmpl.begin(), b.tmpl.end());
+        if (b.shape.empty()) bp.shape = -1;
+        else {
+          bp.shape = (int)ip.size();
+          ip.insert(ip.end(), b.shape.begin(), b.shape.end());
+        }
+        c->bkgplan.push_back(bp);
+      }
+      c->dsplan.push_back(q);
+      pl.max_K = std::max(pl.max_K, d.K);
+      pl.max_Nb = std::max(pl.max_Nb, d.Nb);
+      pl.max_S = std::max(pl.max_S, d.S);
+    }
+    // priors
+    pl.ngauss = (int)gidx.size();
+    pl.gidx = (int)ip.size();
+    ip.insert(ip.end(), gidx.begin(), gidx.end());
+    pl.gmean = (int)dp.size();
+    dp.insert(dp.end(), gmean.begin(), gmean.end());
+    pl.ginv = (int)dp.size();
+    dp.insert(dp.end(), ginv.begin(), ginv.end());
+    const Json& cp = root.get("cov_priors");
+    std::vector<int> bptr, bidx, binv;
+    std::vector<double> bmean;
+    if (!cp.is_null()) {
+      for (const auto& bj : cp.array()) {
+        std::vector<int> idx;
+        for (const auto& n : bj.at("params").array()) idx.push_back(param_ref(c, n, false, "cov_priors"));
+        auto mean = num_array(bj.at("mean"), "cov_priors.mean");
+        const int n = (int)idx.size();
+        if (n < 1 || (int)mean.size() != n) fail(NF_EPARSE, "cov_priors: params/mean size mismatch");
+        std::vector<double> cov;
+        const auto& rows = bj.at("cov").array();
+        if ((int)rows.size() != n) fail(NF_EPARSE, "cov_priors: cov must be n x n");
+        for (const auto& r : rows) {
+          auto v = num_array(r, "cov_priors.cov");
+          if ((int)v.size() != n) fail(NF_EPARSE, "cov_priors: cov must be n x n");
+          cov.insert(cov.end(), v.begin(), v.end());
+        }
+        std::vector<double> inv;
+        if (!spd_inverse(cov, n, inv)) fail(NF_EPARSE, "cov_priors: covariance not positive definite");
+        bptr.push_back((int)bidx.size());
+        bidx.insert(bidx.end(), idx.begin(), idx.end());
+        bmean.insert(bmean.end(), mean.begin(), mean.end());
+        binv.push_back((int)dp.size());
+        dp.insert(dp.end(), inv.begin(), inv.end());
+      }
+    }
+    pl.nblk = (int)binv.size();
+    bptr.push_back((int)bidx.size());
+    pl.blk_ptr = (int)ip.size();
+    ip.insert(ip.end(), bptr.begin(), bptr.end());
+    pl.blk_idx = (int)ip.size();
+    ip.insert(ip.end(), bidx.begin(), bidx.end());
+    pl.blk_mean = (int)dp.size();
+    dp.insert(dp.end(), bmean.begin(), bmean.end());
+    pl.blk_inv = (int)ip.size();
+    ip.insert(ip.end(), binv.begin(), binv.end());
+  } catch (const JsonError& e) {
+    fail(NF_EPARSE, e.what());
+  }
+}
+
+void upload_plan(nf_ctx* c) {
+  c->d_dpool.upload(c->dpool.empty() ? std::vector<double>{0.0} : c->dpool, c->stream);
+  c->d_ipool.upload(c->ipool.empty() ? std::vector<int>{0} : c->ipool, c->stream);
+  c->d_ds.upload(c->dsplan, c->stream);
+  std::vector<BkgPlan> b = c->bkgplan;
+  if (b.empty()) b.push_back(BkgPlan{});
+  c->d_bkg.upload(b, c->stream);
+  c->plan.ds = c->d_ds.p;
+  c->plan.bkg = c->d_bkg.p;
+  c->plan.dpool = c->d_dpool.p;
+  c->plan.ipool = c->d_ipool.p;
+  c->d_theta.alloc(c->P);
+  c->d_out.alloc(1 + c->P);
+  c->d_status.alloc(1);
+  c->d_data.alloc(std::max(1, c->nbins_total));
+  c->d_mu.alloc(std::max(1, c->nbins_total));
+  c->d_scratch.alloc((size_t)std::max(1, c->plan.max_S) * std::max(1, c->plan.max_K));
+  hip_check(hipHostMalloc((void**)&c->h_stage, sizeof(double) * (2 + 2 * c->P + c->nbins_total)),
+            "hipHostMalloc");
+  hip_check(hipHostMalloc((void**)&c->h_status, sizeof(int32_t) * 4), "hipHostMalloc");
+  hip_check(hipMemsetAsync(c->d_data.p, 0, sizeof(double) * std::max(1, c->nbins_total), c->stream),
+            "hipMemsetAsync");
+}
+
+// Fine bin of every event: the largest k with y_k <= E, y_k = y0 + k*width
+// (edges evaluated exactly as written, no fused multiply-add); -1 / K outside.
+#pragma clang fp contract(off)
+int fine_bin(double E, double y0, double wf, int K) {
+  double t = std::floor((E - y0) / wf);
+  int k;
+  if (!(t > -2.0)) k = -1;
+  else if (t > (double)K + 1.0) k = K;
+  else k = (int)t;
+  auto edge = [&](int j) {
+    const double step = wf * (double)j;
+    return y0 + step;
+  };
+  if (k > K) k = K;
+  if (k < -1) k = -1;
+  while (k >= 0 && E < edge(k)) --k;
+  while (k + 1 <= K && E >= edge(k + 1)) ++k;
+  return k;  // in [-1, K]
+}
+#pragma clang fp contract(on)
+
+void rebuild_events(nf_ctx* c) {
+  std::vector<int> seg_item(c->plan.G + 1, 0);
+  std::vector<double> Wseg(c->plan.G, 0.0);
+  std::vector<WorkItem> items;
+  int64_t total = 0;
+  for (auto& d : c->ds) total += (int64_t)d.w.size();
+  std::vector<double> u64;
+  std::vector<float> u32, w;
+  if (c->mode == NF_M64) u64.reserve(total); else u32.reserve(total);
+  w.reserve(total);
+  const int64_t chunk = c->chunk;
+  for (auto& d : c->ds) {
+    int64_t local = 0;
+    for (int s = 0; s < d.S; ++s) {
+      for (int k = 0; k < d.K; ++k) {
+        const int g = d.seg0 + s * d.K + k;
+        seg_item[g] = (int)items.size();
+        if (!d.has_events) continue;
+        const int64_t cnt = d.seg_count[s * d.K + k];
+        const int64_t base = (int64_t)w.size();
+        for (int64_t off = 0; off < cnt; off += chunk) {
+          WorkItem it;
+          it.begin = base + off;
+          it.count = (int32_t)std::min<int64_t>(chunk, cnt - off);
+          it.seg = g;
+          items.push_back(it);
+        }
+        Wseg[g] = d.Wseg[s * d.K + k];
+        if (c->mode == NF_M64) u64.insert(u64.end(), d.u64.begin() + local, d.u64.begin() + local + cnt);
+        else u32.insert(u32.end(), d.u32.begin() + local, d.u32.begin() + local + cnt);
+        w.insert(w.end(), d.w.begin() + local, d.w.begin() + local + cnt);
+        local += cnt;
+      }
+    }
+  }
+  seg_item[c->plan.G] = (int)items.size();
+  if (items.size() > (size_t)0x7fffffff) fail(NF_EINVAL, "too many work items");
+  c->nitems = (int)items.size();
+  if (c->mode == NF_M64) c->d_u64.upload(u64, c->stream); else c->d_u32.upload(u32, c->stream);
+  c->d_w.upload(w, c->stream);
+  c->d_items.upload(items, c->stream);
+  c->d_seg_item.upload(seg_item, c->stream);
+  c->d_Wseg.upload(Wseg, c->stream);
+  c->d_part.alloc((size_t)MAX_MOM * std::max(1, c->nitems));
+  c->plan.G = (int)Wseg.size();
+  c->plan.nitems = c->nitems;
+  c->plan.seg_item = c->d_seg_item.p;
+  c->plan.Wseg = c->d_Wseg.p;
+  hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+void set_events_impl(nf_ctx* c, int dsi, int64_t n, const double* e_true, const double* e_reco,
+                     const uint8_t* source, const float* weight, int on_device) {
+  if (dsi < 0 || dsi >= (int)c->ds.size()) fail(NF_EINVAL, "dataset index out of range");
+  if (n < 0) fail(NF_EINVAL, "negative event count");
+  if (n > 0 && (!e_true || !e_reco)) fail(NF_EINVAL, "null energy pointer");
+  HostDataset& d = c->ds[dsi];
+  std::vector<double> et(n), er(n);
+  std::vector<uint8_t> src(n, 0);
+  std::vector<float> wt(n, 1.0f);
+  if (n > 0) {
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    hip_check(hipMemcpy(et.data(), e_true, n * sizeof(double), kind), "copy e_true");
+    hip_check(hipMemcpy(er.data(), e_reco, n * sizeof(double), kind), "copy e_reco");
+    if (source) hip_check(hipMemcpy(src.data(), source, n, kind), "copy source");
+    if (weight) hip_check(hipMemcpy(wt.data(), weight, n * sizeof(float), kind), "copy weight");
+  }
+  const int K = d.K, S = d.S;
+  std::vector<int> key(n);
+  std::vector<int64_t> cnt((size_t)S * K, 0);
+  int64_t dropped = 0;
+  for (int64_t e = 0; e < n; ++e) {
+    if (!(std::isfinite(et[e]) && et[e] > 0.0)) fail(NF_EINVAL, "e_true must be finite and > 0");
+    if (!std::isfinite(er[e])) fail(NF_EINVAL, "e_reco must be finite");
+    if (!std::isfinite(wt[e])) fail(NF_EINVAL, "weights must be finite");
+    if (src[e] >= S) fail(NF_EINVAL, "source index out of range");
+    const int k = fine_bin(er[e], d.y0, d.wf, K);
+    if (k < 0 || k >= K) {
+      key[e] = -1;
+      ++dropped;
+      continue;
+    }
+    key[e] = src[e] * K + k;
+    ++cnt[key[e]];
+  }
+  // stable counting sort; segments padded to a multiple of 4 with zero weights
+  std::vector<int64_t> padded(cnt.size()), start(cnt.size() + 1, 0);
+  for (size_t g = 0; g < cnt.size(); ++g) {
+    padded[g] = (cnt[g] + 3) & ~int64_t(3);
+    start[g + 1] = start[g] + padded[g];
+  }
+  const int64_t npad = start.back();
+  std::vector<double> u64;
+  std::vector<float> u32;
+  if (c->mode == NF_M64) u64.assign(npad, 0.0); else u32.assign(npad, 0.0f);
+  std::vector<float> w(npad, 0.0f);
+  std::vector<double> Wseg(cnt.size(), 0.0);
+  std::vector<int64_t> fill(start.begin(), start.end() - 1);
+  for (int64_t e = 0; e < n; ++e) {
+    const int g = key[e];
+    if (g < 0) continue;
+    const double u = d.baselines[g / K] / et[e];
+    const int64_t pos = fill[g]++;
+    if (c->mode == NF_M64) u64[pos] = u; else u32[pos] = (float)u;
+    w[pos] = wt[e];
+    Wseg[g] += (double)wt[e];
+  }
+  d.u64.swap(u64);
+  d.u32.swap(u32);
+  d.w.swap(w);
+  d.seg_count.swap(padded);
+  d.Wseg.swap(Wseg);
+  d.dropped = dropped;
+  d.has_events = true;
+  rebuild_events(c);
+}
+
+void require_ready(nf_ctx* c, bool need_data) {
+  for (auto& d : c->ds) {
+    if (!d.has_events) fail(NF_ESTATE, "events not set for dataset '" + d.name + "'");
+    if (need_data && !d.has_data) fail(NF_ESTATE, "data not set for dataset '" + d.name + "'");
+  }
+}
+
+void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* status_dev, double* mu_dev,
+                  int want_nll, int want_grad) {
+  FoldArgs fa{};
+  fa.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
+  fa.w = c->d_w.p;
+  fa.items = c->d_items.p;
+  fa.nitems = c->nitems;
+  fa.theta = theta_dev;
+  fa.osc = c->osc;
+  fa.part = c->d_part.p;
+  TailArgs ta{};
+  ta.plan = c->plan;
+  ta.theta = theta_dev;
+  ta.part = c->d_part.p;
+  ta.data = c->d_data.p;
+  ta.out = out_dev;
+  ta.status = status_dev;
+  ta.mu_out = mu_dev;
+  ta.scratch = c->d_scratch.p;
+  ta.want_grad = want_grad;
+  ta.want_nll = want_nll;
+  hipEvent_t* ev = nullptr;
+  if (c->timing) {
+    if (c->tcount == c->tev.size()) {
+      std::array<hipEvent_t, 3> t{};
+      for (auto& e : t) hip_check(hipEventCreate(&e), "hipEventCreate");
+      c->tev.push_back(t);
+    }
+    ev = c->tev[c->tcount++].data();
+    hip_check(hipEventRecord(ev[0], c->stream), "hipEventRecord");
+  }
+  hip_check(launch_fold(c->mode, fa, c->fold_block, c->stream), "fold launch");
+  if (ev) hip_check(hipEventRecord(ev[1], c->stream), "hipEventRecord");
+  hip_check(launch_tail(ta, c->tail_threads, c->stream), "tail launch");
+  if (ev) hip_check(hipEventRecord(ev[2], c->stream), "hipEventRecord");
+}
+
+int eval_host(nf_ctx* c, const double* theta, double* nll, double* grad, double* mu) {
+  const bool want_nll = nll != nullptr;
+  require_ready(c, want_nll);
+  if (!theta) fail(NF_EINVAL, "theta is null");
+  for (int i = 0; i < c->P; ++i)
+    if (!std::isfinite(theta[i])) fail(NF_EINVAL, "theta[" + std::to_string(i) + "] is not finite");
+  double* h_theta = c->h_stage;
+  double* h_out = c->h_stage + c->P;
+  double* h_mu = c->h_stage + 2 * c->P + 1;
+  std::memcpy(h_theta, theta, sizeof(double) * c->P);
+  hip_check(hipMemcpyAsync(c->d_theta.p, h_theta, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream),
+            "theta H2D");
+  enqueue_eval(c, c->d_theta.p, c->d_out.p, c->d_status.p, mu ? c->d_mu.p : nullptr, want_nll ? 1 : 0,
+               grad ? 1 : 0);
+  if (want_nll)
+    hip_check(hipMemcpyAsync(h_out, c->d_out.p, sizeof(double) * (grad ? 1 + c->P : 1), hipMemcpyDeviceToHost,
+                             c->stream), "out D2H");
+  hip_check(hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream),
+            "status D2H");
+  if (mu)
+    hip_check(hipMemcpyAsync(h_mu, c->d_mu.p, sizeof(double) * c->nbins_total, hipMemcpyDeviceToHost, c->stream),
+              "mu D2H");
+  hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (want_nll) {
+    *nll = h_out[0];
+    if (grad) std::memcpy(grad, h_out + 1, sizeof(double) * c->P);
+  }
+  if (mu) std::memcpy(mu, h_mu, sizeof(double) * c->nbins_total);
+  if (*c->h_status & ST_DOMAIN) {
+    c->err = "expectation <= 0, energy map not monotone, or oscillation parameter out of domain";
+    return NF_WDOMAIN;
+  }
+  return NF_OK;
+}
+
+template <typename F>
+int guarded(nf_ctx* c, F&& f) {
+  if (!c) return NF_EINVAL;
+  try {
+    c->err.clear();
+    return f();
+  } catch (const ApiError& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return NF_ENOMEM;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return NF_EINVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nf_create(nf_ctx** out, const char* model_json, int mode, void* hip_stream) {
+  if (!out) return NF_EINVAL;
+  *out = nullptr;
+  g_create_error.clear();
+  if (!model_json) { g_create_error = "model_json is null"; return NF_EINVAL; }
+  if (mode != NF_M64 && mode != NF_M32) { g_create_error = "mode must be NF_M64 or NF_M32"; return NF_EINVAL; }
+  nf_ctx* c = nullptr;
+  try {
+    c = new nf_ctx();
+    c->mode = mode;
+    parse_model(c, model_json);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(NF_EDEVICE, "no HIP device available");
+    if (hip_stream) c->stream = static_cast<hipStream_t>(hip_stream);
+    else {
+      hip_check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+      c->own_stream = true;
+    }
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    int maxlds = 0;
+    hip_check(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
+    const size_t need = tail_lds_bytes(c->plan, 1024);
+    if (need > (size_t)maxlds)
+      fail(NF_EINVAL, "model too large for one workgroup's LDS (" + std::to_string(need) + " > " +
+                          std::to_string(maxlds) + " bytes)");
+    if (need > 65536) hip_check(tail_set_lds_limit(need), "hipFuncSetAttribute");
+    upload_plan(c);
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    *out = c;
+    return NF_OK;
+  } catch (const ApiError& e) {
+    g_create_error = e.what();
+    delete c;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    delete c;
+    return NF_ENOMEM;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    delete c;
+    return NF_EINVAL;
+  }
+}
+
+void nf_destroy(nf_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* nf_last_error(const nf_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+int nf_num_params(const nf_ctx* ctx) { return ctx ? ctx->P : NF_EINVAL; }
+int nf_num_datasets(const nf_ctx* ctx) { return ctx ? (int)ctx->ds.size() : NF_EINVAL; }
+int nf_num_bins(const nf_ctx* ctx, int d) {
+  if (!ctx || d < 0 || d >= (int)ctx->ds.size()) return NF_EINVAL;
+  return ctx->ds[d].Nb;
+}
+int nf_param_index(const nf_ctx* ctx, const char* name) {
+  if (!ctx || !name) return NF_EINVAL;
+  auto it = ctx->index.find(name);
+  return it == ctx->index.end() ? NF_EINVAL : it->second;
+}
+
+int nf_set_events(nf_ctx* ctx, int dataset, int64_t n, const double* e_true, const double* e_reco,
+                  const uint8_t* source, const float* weight, int on_device) {
+  return guarded(ctx, [&] {
+    set_events_impl(ctx, dataset, n, e_true, e_reco, source, weight, on_device);
+    return NF_OK;
+  });
+}
+
+int64_t nf_dropped_events(const nf_ctx* ctx, int dataset) {
+  if (!ctx || dataset < 0 || dataset >= (int)ctx->ds.size()) return NF_EINVAL;
+  return ctx->ds[dataset].dropped;
+}
+
+int nf_set_data(nf_ctx* ctx, int dataset, int nbins, const double* counts, int on_device) {
+  return guarded(ctx, [&] {
+    if (dataset < 0 || dataset >= (int)ctx->ds.size()) fail(NF_EINVAL, "dataset index out of range");
+    HostDataset& d = ctx->ds[dataset];
+    if (nbins != d.Nb) fail(NF_EINVAL, "nbins does not match the dataset's analysis bins");
+    if (!counts) fail(NF_EINVAL, "counts is null");
+    std::vector<double> v(nbins);
+    hip_check(hipMemcpy(v.data(), counts, sizeof(double) * nbins,
+                        on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost), "copy counts");
+    for (double x : v)
+      if (!(std::isfinite(x) && x >= 0.0)) fail(NF_EINVAL, "counts must be finite and >= 0");
+    d.data = v;
+    hip_check(hipMemcpyAsync(ctx->d_data.p + d.bins0, d.data.data(), sizeof(double) * nbins,
+                             hipMemcpyHostToDevice, ctx->stream), "data H2D");
+    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    d.has_data = true;
+    return NF_OK;
+  });
+}
+
+int nf_eval_nll(nf_ctx* ctx, const double* theta, double* nll) {
+  return guarded(ctx, [&] {
+    if (!nll) fail(NF_EINVAL, "nll is null");
+    return eval_host(ctx, theta, nll, nullptr, nullptr);
+  });
+}
+
+int nf_eval_nll_grad(nf_ctx* ctx, const double* theta, double* nll, double* grad) {
+  return guarded(ctx, [&] {
+    if (!nll || !grad) fail(NF_EINVAL, "null output");
+    return eval_host(ctx, theta, nll, grad, nullptr);
+  });
+}
+
+int nf_expected(nf_ctx* ctx, const double* theta, double* mu) {
+  return guarded(ctx, [&] {
+    if (!mu) fail(NF_EINVAL, "mu is null");
+    return eval_host(ctx, theta, nullptr, nullptr, mu);
+  });
+}
+
+int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev, int32_t* status_dev, int want_grad) {
+  return guarded(ctx, [&] {
+    require_ready(ctx, true);
+    if (!theta_dev || !out_dev) fail(NF_EINVAL, "null device pointer");
+    enqueue_eval(ctx, theta_dev, out_dev, status_dev, nullptr, 1, want_grad ? 1 : 0);
+    return NF_OK;
+  });
+}
+
+int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
+  return guarded(ctx, [&] {
+    if (!key) fail(NF_EINVAL, "key is null");
+    const std::string k = key;
+    if (k == "chunk") {
+      if (value < 256 || value % 256 != 0 || value > (1 << 24)) fail(NF_EINVAL, "chunk must be a multiple of 256");
+      ctx->chunk = value;
+      bool any = false;
+      for (auto& d : ctx->ds) any = any || d.has_events;
+      if (any) rebuild_events(ctx);
+    } else if (k == "fold_block") {
+      if (value != 64 && value != 128 && value != 256) fail(NF_EINVAL, "fold_block must be 64, 128 or 256");
+      ctx->fold_block = (int)value;
+    } else if (k == "tail_threads") {
+      if (value != 256 && value != 512 && value != 1024) fail(NF_EINVAL, "tail_threads must be 256, 512 or 1024");
+      ctx->tail_threads = (int)value;
+    } else if (k == "timing") {
+      ctx->timing = value ? 1 : 0;
+      ctx->tcount = 0;
+    } else {
+      fail(NF_EINVAL, "unknown option '" + k + "'");
+    }
+    return NF_OK;
+  });
+}
+
+int nf_timing(nf_ctx* ctx, int reset, int64_t* count, double* fold_ms, double* tail_ms) {
+  return guarded(ctx, [&] {
+    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    double f = 0.0, t = 0.0;
+    for (size_t i = 0; i < ctx->tcount; ++i) {
+      float a = 0.f, b = 0.f;
+      hip_check(hipEventElapsedTime(&a, ctx->tev[i][0], ctx->tev[i][1]), "hipEventElapsedTime");
+      hip_check(hipEventElapsedTime(&b, ctx->tev[i][1], ctx->tev[i][2]), "hipEventElapsedTime");
+      f += a;
+      t += b;
+    }
+    if (count) *count = (int64_t)ctx->tcount;
+    if (fold_ms) *fold_ms = f;
+    if (tail_ms) *tail_ms = t;
+    if (reset) ctx->tcount = 0;
+    return NF_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+// Event fold: step 1 of the signal calculation (paper, "Structure of the
+// framework"; offload of the oscillation weighting, "GPU accelerated
+// computation"), re-designed for gfx950.
+//
+// The survival probability is a fixed linear combination of cos(x_ab) terms,
+// x_ab = 2 k dm2_ab L/E (sin^2(x/2) = (1 - cos x)/2), with coefficients that
+// depend only on the mixing angles. So, per (dataset, source, fine bin)
+// segment, the fold streams the sorted events once and accumulates
+//   eq1 (Eq. 1):   C_ee, C_21, Q_ee, Q_21
+//   3nu (exact):   C_21, C_31, C_32, Q_21, Q_31, Q_32
+// with C_ab = sum_e w_e cos x_ab,e and Q_ab = sum_e w_e u_e sin x_ab,e,
+// u_e = L/E. The bin-stage kernel turns these moments into the oscillated
+// spectrum sum_e w_e P_e and its derivatives with respect to every
+// oscillation parameter (forward-mode Jacobian, exact), so mixing-angle
+// changes never re-read events. x_32 = x_31 - x_21 comes from the two
+// computed sin/cos pairs by angle subtraction.
+//
+// Layout: u[] and w[] are SoA, sorted by segment, every segment padded with
+// zero-weight events to a multiple of 4, so each lane reads 4 consecutive
+// events with 16-byte loads. One wavefront (64 lanes) reduces one work item
+// (<= chunk events of one segment) and writes one partial per moment;
+// partials of a segment are summed in a fixed order by the bin-stage kernel,
+// so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "fastmath.hpp"
+#include "kernels.hpp"
+
+namespace nufold {
+
+
+__device__ __forceinline__ double slot_val(const OscPlan& o, const double* th, int j) {
+  const int p = o.slot_param[j];
+  return p >= 0 ? th[p] : o.slot_value[j];
+}
+
+// Angular frequencies a (rad per m/MeV) of the two computed phases x = a * u.
+template <int FORM>
+__device__ __forceinline__ void fold_freqs(const OscPlan& o, const double* th, double& a1, double& a2) {
+  if (FORM == FORM_EQ1) {
+    a1 = TWO_PHASE_K * UNIT_1EM3 * slot_val(o, th, 1);   // dm2_ee
+    a2 = TWO_PHASE_K * UNIT_1EM5 * slot_val(o, th, 3);   // dm2_21
+  } else {
+    a1 = TWO_PHASE_K * UNIT_1EM5 * slot_val(o, th, 2);   // dm2_21
+    a2 = TWO_PHASE_K * UNIT_1EM3 * slot_val(o, th, 3);   // dm2_31
+  }
+}
+
+
+template <int FORM>
+__device__ __forceinline__ void accum64(double u, float wf, double a1, double a2, double* m) {
+  const double w = (double)wf;
+  const double wu = w * u;
+  double s1, c1, s2, c2;
+  sincos_fold(a1 * u, s1, c1);
+  sincos_fold(a2 * u, s2, c2);
+  if (FORM == FORM_EQ1) {
+    m[0] = fma(w, c1, m[0]);
+    m[1] = fma(w, c2, m[1]);
+    m[2] = fma(wu, s1, m[2]);
+    m[3] = fma(wu, s2, m[3]);
+  } else {
+    // 1 = 21, 2 = 31, 32 = 31 - 21
+    const double c3 = fma(c2, c1, s2 * s1);
+    const double s3 = fma(s2, c1, -(c2 * s1));
+    m[0] = fma(w, c1, m[0]);
+    m[1] = fma(w, c2, m[1]);
+    m[2] = fma(w, c3, m[2]);
+    m[3] = fma(wu, s1, m[3]);
+    m[4] = fma(wu, s2, m[4]);
+    m[5] = fma(wu, s3, m[5]);
+  }
+}
+
+// FP32 path: phases in revolutions t = x / 2pi, computed as a two-float
+// product so the fractional part keeps ~2^-24 relative accuracy of x even
+// when x reaches hundreds of radians; hardware sin/cos take revolutions.
+__device__ __forceinline__ float phase_rev(float u, float bh, float bl) {
+  const float p = bh * u;
+  const float e = fmaf(bh, u, -p);           // exact low part of bh*u
+  const float fr = p - floorf(p);            // exact for |p| < 2^23
+  return fr + fmaf(bl, u, e);
+}
+
+template <int FORM>
+__device__ __forceinline__ void accum32(float u, float w, float b1h, float b1l, float b2h, float b2l,
+                                        float* m) {
+  const float wu = w * u;
+  const float t1 = phase_rev(u, b1h, b1l);
+  const float t2 = phase_rev(u, b2h, b2l);
+  const float s1 = __builtin_amdgcn_sinf(t1), c1 = __builtin_amdgcn_cosf(t1);
+  const float s2 = __builtin_amdgcn_sinf(t2), c2 = __builtin_amdgcn_cosf(t2);
+  if (FORM == FORM_EQ1) {
+    m[0] = fmaf(w, c1, m[0]);
+    m[1] = fmaf(w, c2, m[1]);
+    m[2] = fmaf(wu, s1, m[2]);
+    m[3] = fmaf(wu, s2, m[3]);
+  } else {
+    const float c3 = fmaf(c2, c1, s2 * s1);
+    const float s3 = fmaf(s2, c1, -(c2 * s1));
+    m[0] = fmaf(w, c1, m[0]);
+    m[1] = fmaf(w, c2, m[1]);
+    m[2] = fmaf(w, c3, m[2]);
+    m[3] = fmaf(wu, s1, m[3]);
+    m[4] = fmaf(wu, s2, m[4]);
+    m[5] = fmaf(wu, s3, m[5]);
+  }
+}
+
+template <int NM>
+__device__ __forceinline__ void wave_sum_store(double* m, double* part, int nitems, int item, int lane) {
+#pragma unroll
+  for (int c = 0; c < NM; ++c) {
+    double v = m[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    m[c] = v;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NM; ++c) part[(int64_t)c * nitems + item] = m[c];
+  }
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
+  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
+  const int lane = threadIdx.x & 63;
+  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  if (item >= a.nitems) return;  // whole wavefronts leave together
+  double a1, a2;
+  fold_freqs<FORM>(a.osc, a.theta, a1, a2);
+  const WorkItem it = a.items[item];
+  const double* __restrict__ u = static_cast<const double*>(a.u) + it.begin;
+  const float* __restrict__ w = a.w + it.begin;
+  double m[NM];
+#pragma unroll
+  for (int c = 0; c < NM; ++c) m[c] = 0.0;
+  for (int j = lane * 4; j < it.count; j += 256) {
+    const double2 u01 = *reinterpret_cast<const double2*>(u + j);
+    const double2 u23 = *reinterpret_cast<const double2*>(u + j + 2);
+    const float4 w4 = *reinterpret_cast<const float4*>(w + j);
+    accum64<FORM>(u01.x, w4.x, a1, a2, m);
+    accum64<FORM>(u01.y, w4.y, a1, a2, m);
+    accum64<FORM>(u23.x, w4.z, a1, a2, m);
+    accum64<FORM>(u23.y, w4.w, a1, a2, m);
+  }
+  wave_sum_store<NM>(m, a.part, a.nitems, item, lane);
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
+  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
+  constexpr double INV_2PI = 0.15915494309189533577;
+  const int lane = threadIdx.x & 63;
+  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  if (item >= a.nitems) return;
+  double a1, a2;
+  fold_freqs<FORM>(a.osc, a.theta, a1, a2);
+  const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
+  const float b1h = (float)r1, b1l = (float)(r1 - (double)b1h);
+  const float b2h = (float)r2, b2l = (float)(r2 - (double)b2h);
+  const WorkItem it = a.items[item];
+  const float* __restrict__ u = static_cast<const float*>(a.u) + it.begin;
+  const float* __restrict__ w = a.w + it.begin;
+  float mf[NM];
+#pragma unroll
+  for (int c = 0; c < NM; ++c) mf[c] = 0.0f;
+  for (int j = lane * 4; j < it.count; j += 256) {
+    const float4 u4 = *reinterpret_cast<const float4*>(u + j);
+    const float4 w4 = *reinterpret_cast<const float4*>(w + j);
+    accum32<FORM>(u4.x, w4.x, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(u4.y, w4.y, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(u4.z, w4.z, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(u4.w, w4.w, b1h, b1l, b2h, b2l, mf);
+  }
+  double m[NM];
+#pragma unroll
+  for (int c = 0; c < NM; ++c) m[c] = (double)mf[c];
+  wave_sum_store<NM>(m, a.part, a.nitems, item, lane);
+}
+
+// Host-side launcher (same translation unit as the kernels).
+hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream) {
+  if (a.nitems <= 0) return hipSuccess;
+  const int waves_per_block = block / 64;
+  const int grid = (a.nitems + waves_per_block - 1) / waves_per_block;
+  if (mode == 0) {
+    if (a.osc.formula == FORM_EQ1)
+      hipLaunchKernelGGL(fold_m64_kernel<FORM_EQ1>, dim3(grid), dim3(block), 0, stream, a);
+    else
+      hipLaunchKernelGGL(fold_m64_kernel<FORM_3NU>, dim3(grid), dim3(block), 0, stream, a);
+  } else {
+    if (a.osc.formula == FORM_EQ1)
+      hipLaunchKernelGGL(fold_m32_kernel<FORM_EQ1>, dim3(grid), dim3(block), 0, stream, a);
+    else
+      hipLaunchKernelGGL(fold_m32_kernel<FORM_3NU>, dim3(grid), dim3(block), 0, stream, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nufold

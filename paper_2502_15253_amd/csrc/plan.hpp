@@ -1,0 +1,86 @@
+// Flat, device-readable description of a model (built once by the host
+// runtime from the JSON description) and of the sorted event stream.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace nufold {
+
+constexpr int FORM_EQ1 = 0;  // Eq. 1: slots sin2_2t13, dm2_ee, sin2_t12, dm2_21
+constexpr int FORM_3NU = 1;  // exact vacuum 3-flavour: sin2_t12, sin2_t13, dm2_21, dm2_31
+constexpr int NSLOT = 4;
+constexpr int MAX_MOM = 6;   // per-segment moments produced by the fold
+constexpr int MAX_SOURCES = 64;
+
+// 2 k, k = 1/(4 hbar c) in MeV/(eV^2 m) with the exact SI-2019 value of hbar c;
+// the fold phase x = 2 k dm2 L/E is twice the phase of Eq. 1.
+constexpr double TWO_PHASE_K = 2.0 * 1.266932679039099;
+constexpr double UNIT_1EM3 = 1e-3;
+constexpr double UNIT_1EM5 = 1e-5;
+
+__host__ __device__ inline int num_moments(int formula) { return formula == FORM_EQ1 ? 4 : 6; }
+
+struct OscPlan {
+  int formula;
+  int slot_param[NSLOT];   // parameter index, or -1 for a constant
+  double slot_value[NSLOT];
+};
+
+// A contiguous run of sorted events that all belong to one segment
+// (dataset, source, fine bin). begin and count are multiples of 4.
+struct WorkItem {
+  int64_t begin;
+  int32_t count;
+  int32_t seg;
+};
+
+struct BkgPlan {
+  double scale;
+  int rate;    // parameter index or -1 (rate fixed at 1)
+  int tmpl;    // dpool offset of Nb template values
+  int shape;   // ipool offset of Nb parameter indices (-1 entries: none), or -1
+  int pad_;
+};
+
+struct DsPlan {
+  double y0, wf;
+  int K, Nb, S, M, nbkg;
+  int seg0;         // global segment index of (source 0, fine bin 0)
+  int edges;        // dpool: Nb + 1 analysis edges
+  int data;         // offset into the data vector (Nb counts)
+  int bins0;        // offset into concatenated analysis bins (same as data)
+  int srcnorm_ptr;  // ipool: S + 1 absolute ipool offsets of each source's norm list
+  int fx_row;       // ipool: K + 1 absolute offsets into fx_mode / dpool fx_coef (CSR over k)
+  int fx_mode;      // ipool base of CSR mode indices (0..M-1)
+  int fx_coef;      // dpool base of CSR coefficients
+  int md_col;       // ipool: M + 1 absolute offsets (CSC over modes)
+  int md_k;         // ipool base of CSC fine-bin indices
+  int md_coef;      // dpool base of CSC coefficients
+  int md_param;     // ipool: M parameter indices
+  int cidx[3];      // energy-scale parameters c0, c1, c2 (-1: fixed at 0)
+  int bkg0;         // index of the first BkgPlan
+};
+
+struct DevPlan {
+  int P, D, G, nitems, nbins_total;
+  int max_K, max_Nb, max_S;
+  OscPlan osc;
+  const DsPlan* ds;
+  const BkgPlan* bkg;
+  const double* dpool;
+  const int* ipool;
+  const int* seg_item;   // G + 1: work-item range of each segment
+  const double* Wseg;    // G: sum of weights of each segment (static)
+  // priors
+  int ngauss;
+  int gidx, gmean, ginv;        // ipool / dpool / dpool offsets (ginv = 1/sigma^2)
+  int nblk;
+  int blk_ptr;                  // ipool: nblk + 1 offsets into blk_idx (and blk_mean)
+  int blk_idx;                  // ipool base
+  int blk_mean;                 // dpool base (aligned with blk_idx)
+  int blk_inv;                  // ipool: nblk offsets into dpool of row-major V^-1
+};
+
+}  // namespace nufold

@@ -1,0 +1,194 @@
+"""ctypes binding of libnufold (the C-ABI declared in include/nufold.h).
+
+Argument marshalling only: every step of an evaluation runs in the library's
+HIP kernels. Functions keep the C names; `Engine` is a thin convenience
+wrapper. There is no fallback: if the shared library is missing the import of
+any entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+NF_OK, NF_WDOMAIN, NF_WNOCONV = 0, 1, 2
+NF_EINVAL, NF_ESTATE, NF_ENOMEM, NF_EDEVICE, NF_EPARSE = -1, -2, -3, -4, -5
+NF_M64, NF_M32 = 0, 1
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnufold.so")
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_u8p = C.POINTER(C.c_uint8)
+_i32p = C.POINTER(C.c_int32)
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "nf_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_char_p, C.c_int, C.c_void_p]),
+    "nf_destroy": (None, [C.c_void_p]),
+    "nf_last_error": (C.c_char_p, [C.c_void_p]),
+    "nf_num_params": (C.c_int, [C.c_void_p]),
+    "nf_num_datasets": (C.c_int, [C.c_void_p]),
+    "nf_num_bins": (C.c_int, [C.c_void_p, C.c_int]),
+    "nf_param_index": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "nf_set_events": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_int]),
+    "nf_dropped_events": (C.c_int64, [C.c_void_p, C.c_int]),
+    "nf_set_data": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int]),
+    "nf_eval_nll": (C.c_int, [C.c_void_p, _dp, _dp]),
+    "nf_eval_nll_grad": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
+    "nf_eval_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "nf_expected": (C.c_int, [C.c_void_p, _dp, _dp]),
+    "nf_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
+    "nf_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp, _dp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libnufold.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        # PyTorch ships its own HIP runtime with the same SONAME as ROCm's
+        # (libamdhip64.so.7). Loading torch first makes the engine bind to that
+        # already-loaded runtime, so torch streams and device pointers are valid
+        # in the engine; without torch the system ROCm runtime is used.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libnufold.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class NufoldError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nufold error {code}: {msg}")
+        self.code = code
+
+
+def _err(ctx):
+    m = load().nf_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def _check(ctx, code, allow_warn=True):
+    if code < 0 or (code > 0 and not allow_warn):
+        raise NufoldError(code, _err(ctx))
+    return code
+
+
+def _ptr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _is_cuda(t):
+    return hasattr(t, "is_cuda") and t.is_cuda
+
+
+class Engine:
+    """One nf_ctx: model description, events, data; evaluations on the device."""
+
+    def __init__(self, model, mode="m64", stream=None):
+        text = model if isinstance(model, str) else json.dumps(model)
+        self.mode = NF_M64 if mode in ("m64", NF_M64) else NF_M32
+        h = C.c_void_p()
+        code = load().nf_create(C.byref(h), text.encode(), self.mode,
+                                C.c_void_p(stream) if stream else None)
+        if code != NF_OK:
+            raise NufoldError(code, _err(None))
+        self.ctx = h
+        self.P = load().nf_num_params(h)
+        self.D = load().nf_num_datasets(h)
+        self.nbins = [load().nf_num_bins(h, d) for d in range(self.D)]
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().nf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return _err(self.ctx)
+
+    def param_index(self, name):
+        return load().nf_param_index(self.ctx, name.encode())
+
+    def set_option(self, key, value):
+        _check(self.ctx, load().nf_set_option(self.ctx, key.encode(), int(value)))
+
+    def set_events(self, d, e_true, e_reco, source=None, weight=None):
+        if _is_cuda(e_true):
+            n = int(e_true.numel())
+            ptrs = [t.data_ptr() if t is not None else None for t in (e_true, e_reco, source, weight)]
+            return _check(self.ctx, load().nf_set_events(self.ctx, d, n, *ptrs, 1))
+        et, pe = _ptr(e_true, np.float64)
+        er, pr = _ptr(e_reco, np.float64)
+        ps = pw = None
+        if source is not None:
+            src, ps = _ptr(source, np.uint8)
+        if weight is not None:
+            wt, pw = _ptr(weight, np.float32)
+        return _check(self.ctx, load().nf_set_events(self.ctx, d, len(et), pe, pr, ps, pw, 0))
+
+    def dropped(self, d):
+        return load().nf_dropped_events(self.ctx, d)
+
+    def set_data(self, d, counts):
+        if _is_cuda(counts):
+            return _check(self.ctx, load().nf_set_data(self.ctx, d, int(counts.numel()),
+                                                       counts.data_ptr(), 1))
+        c, p = _ptr(counts, np.float64)
+        return _check(self.ctx, load().nf_set_data(self.ctx, d, len(c), p, 0))
+
+    def eval_nll(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        out = C.c_double()
+        code = _check(self.ctx, load().nf_eval_nll(self.ctx, th.ctypes.data_as(_dp), C.byref(out)))
+        return out.value, code
+
+    def eval_nll_grad(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        g = np.zeros(self.P)
+        out = C.c_double()
+        code = _check(self.ctx, load().nf_eval_nll_grad(self.ctx, th.ctypes.data_as(_dp), C.byref(out),
+                                                        g.ctypes.data_as(_dp)))
+        return out.value, g, code
+
+    def expected(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        mu = np.zeros(sum(self.nbins))
+        code = _check(self.ctx, load().nf_expected(self.ctx, th.ctypes.data_as(_dp), mu.ctypes.data_as(_dp)))
+        out, o = [], 0
+        for nb in self.nbins:
+            out.append(mu[o:o + nb].copy())
+            o += nb
+        return out, code
+
+    def eval_device(self, theta_ptr, out_ptr, status_ptr=None, want_grad=True):
+        """Enqueue an evaluation on device pointers (ints); returns immediately."""
+        return _check(self.ctx, load().nf_eval_device(self.ctx, C.c_void_p(theta_ptr), C.c_void_p(out_ptr),
+                                                      C.c_void_p(status_ptr) if status_ptr else None,
+                                                      1 if want_grad else 0))
+
+    def timing(self, reset=True):
+        """(evaluations, summed fold ms, summed bin-stage ms) since the last reset."""
+        n, f, t = C.c_int64(), C.c_double(), C.c_double()
+        _check(self.ctx, load().nf_timing(self.ctx, 1 if reset else 0, C.byref(n), C.byref(f), C.byref(t)))
+        return n.value, f.value, t.value

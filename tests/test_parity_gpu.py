@@ -1,0 +1,253 @@
+"""Parity of the HIP engine (through the C-ABI) with the FP64 oracle.
+
+Tolerances (relative, with a floor of 1 for NLL and gradient):
+  M64: 1e-9 on every expectation mu_{d,i}, on the NLL and on the gradient
+  M32: 1e-5 on the same quantities
+  NLL: |dNLL| <= tol * max(1, |NLL|);  gradient: max|dg| <= tol * max(1, max|g|).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.model import Model
+from oracle import likelihood as LK
+from oracle import fold as OF
+from paper_2502_15253_amd import nufold as nf
+from paper_2502_15253_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"m64": 1e-9, "m32": 1e-5}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def make_engine(desc, events, data=None, mode="m64", chunk=None):
+    eng = nf.Engine(desc, mode)
+    if chunk:
+        eng.set_option("chunk", chunk)
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+    if data is not None:
+        for d, n in enumerate(data):
+            eng.set_data(d, n)
+    return eng
+
+
+def oracle_data(desc, events, seed):
+    m = Model(desc)
+    mus, ok = LK.expected(m, events, synth.start_vector(desc))
+    assert ok
+    return synth.poisson_data(mus, seed)
+
+
+def compare(eng, desc, events, data, theta, tol, what=""):
+    m = Model(desc)
+    mus_o, _ = LK.expected(m, events, theta)
+    f_o, g_o = LK.nll_grad(m, events, data, theta)
+    mus_g, code = eng.expected(theta)
+    assert code == nf.NF_OK
+    for mo, mg in zip(mus_o, mus_g):
+        rel = np.max(np.abs(mg - mo) / np.maximum(np.abs(mo), 1e-300))
+        assert rel <= tol, f"{what}: mu rel err {rel:.3e}"
+    f_g, g_g, code = eng.eval_nll_grad(theta)
+    assert code == nf.NF_OK
+    assert abs(f_g - f_o) <= tol * max(1.0, abs(f_o)), f"{what}: NLL {f_g!r} vs {f_o!r}"
+    scale = max(1.0, np.max(np.abs(g_o)))
+    err = np.max(np.abs(g_g - g_o))
+    assert err <= tol * scale, f"{what}: grad err {err:.3e} (scale {scale:.3e}) at {np.argmax(np.abs(g_g - g_o))}"
+    f_n, code = eng.eval_nll(theta)
+    assert f_n == f_g
+    return f_g, g_g
+
+
+def displaced(desc, seed, scale=0.3):
+    """Start vector moved by a fraction of each prior width (or 1% of the value)."""
+    rng = np.random.default_rng(seed)
+    th = synth.start_vector(desc).copy()
+    for i, p in enumerate(desc["params"]):
+        s = p["prior"][1] if p["prior"] else max(abs(p["start"]) * 0.01, 1e-3)
+        th[i] += scale * s * rng.standard_normal()
+    return th
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+@pytest.mark.parametrize("formula", ["eq1", "3nu"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_models(mode, formula, seed):
+    say("tiny", mode, formula, seed)
+    desc = synth.tiny_model(10 + seed, formula=formula, n_datasets=2 + seed % 2, n_sources=1 + seed)
+    events = synth.tiny_events(desc, 5000 + 1111 * seed, 50 + seed)
+    data = oracle_data(desc, events, 60 + seed)
+    eng = make_engine(desc, events, data, mode)
+    for j in range(3):
+        compare(eng, desc, events, data, displaced(desc, 70 + j), TOL[mode], f"tiny {formula} {seed} {j}")
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_config1_full_size(mode):
+    say("config1", mode)
+    desc, events = synth.model_and_events(1)
+    data = oracle_data(desc, events, synth.data_seed(1))
+    eng = make_engine(desc, events, data, mode)
+    assert eng.dropped(0) == OF.dropped_events(Model(desc), events)[0]
+    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c1 start")
+    for j in range(3):
+        compare(eng, desc, events, data, displaced(desc, 100 + j), TOL[mode], f"c1 displaced {j}")
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_config2_full_size(mode):
+    say("config2", mode)
+    desc, events = synth.model_and_events(2)
+    data = oracle_data(desc, events, synth.data_seed(2))
+    eng = make_engine(desc, events, data, mode)
+    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c2 start")
+    compare(eng, desc, events, data, displaced(desc, 200), TOL[mode], "c2 displaced")
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_config3_full_size(mode):
+    say("config3", mode)
+    desc, events = synth.model_and_events(3)
+    m = Model(desc)
+    mus, _ = LK.expected(m, events, synth.start_vector(desc))
+    data = [mu.copy() for mu in mus]  # Asimov, as in the medium-baseline study
+    eng = make_engine(desc, events, data, mode)
+    compare(eng, desc, events, data, displaced(desc, 300), TOL[mode], "c3 displaced")
+
+
+def test_work_item_chunking_does_not_change_results():
+    say("chunking")
+    desc = synth.tiny_model(21, formula="3nu", n_datasets=2, n_sources=3)
+    events = synth.tiny_events(desc, 40000, 5)
+    data = oracle_data(desc, events, 6)
+    th = displaced(desc, 7)
+    ref = None
+    for chunk in (256, 512, 2048, 65536):
+        eng = make_engine(desc, events, data, "m64", chunk=chunk)
+        f, g, _ = eng.eval_nll_grad(th)
+        if ref is None:
+            ref = (f, g)
+            compare(eng, desc, events, data, th, 1e-9, "chunk")
+        else:
+            assert abs(f - ref[0]) <= 1e-12 * max(1, abs(f))
+            assert np.max(np.abs(g - ref[1])) <= 1e-12 * max(1, np.max(np.abs(g)))
+
+
+def test_repeated_evaluations_are_bitwise_identical():
+    say("determinism")
+    desc, events = synth.model_and_events(1)
+    data = oracle_data(desc, events, 3)
+    eng = make_engine(desc, events, data)
+    th = displaced(desc, 8)
+    f0, g0, _ = eng.eval_nll_grad(th)
+    for _ in range(5):
+        f, g, _ = eng.eval_nll_grad(th)
+        assert f == f0 and np.array_equal(g, g0)
+
+
+def test_gradient_matches_central_differences_on_device():
+    say("central differences")
+    desc, events = synth.model_and_events(1)
+    data = oracle_data(desc, events, 4)
+    eng = make_engine(desc, events, data)
+    th = displaced(desc, 9)
+    f, g, _ = eng.eval_nll_grad(th)
+    h = 1e-6
+    for j in range(len(th)):
+        e = np.zeros_like(th); e[j] = h
+        fp, _ = eng.eval_nll(th + e)
+        fm, _ = eng.eval_nll(th - e)
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-5 * max(1.0, np.max(np.abs(g))), (j, fd, g[j])
+
+
+def test_edge_cases_empty_single_bin_out_of_range_defaults():
+    say("edge cases")
+    desc = synth.tiny_model(31, formula="eq1", n_datasets=3, n_sources=2)
+    ev = synth.tiny_events(desc, 3000, 9)
+    # dataset 0: no events at all (background-only expectation)
+    ev[0] = {k: v[:0] for k, v in ev[0].items()}
+    # dataset 1: every event in one fine bin, a few exactly on edges and out of range
+    f = desc["datasets"][1]["fine"]
+    n1 = len(ev[1]["e_reco"])
+    er = np.full(n1, f["y0"] + 3.5 * f["width"])
+    er[:5] = f["y0"] + 3 * f["width"]              # on an edge: upper bin
+    er[5:9] = f["y0"] + f["n"] * f["width"]        # top edge: dropped
+    er[9:12] = f["y0"] - 1e-9                      # below: dropped
+    ev[1]["e_reco"] = er
+    # dataset 2: default source (all 0) and unit weights
+    ev[2]["source"] = np.zeros_like(ev[2]["source"])
+    ev[2]["weight"] = np.ones_like(ev[2]["weight"])
+    data = oracle_data(desc, ev, 10)
+    eng = nf.Engine(desc, "m64")
+    eng.set_events(0, ev[0]["e_true"], ev[0]["e_reco"], ev[0]["source"], ev[0]["weight"])
+    eng.set_events(1, ev[1]["e_true"], ev[1]["e_reco"], ev[1]["source"], ev[1]["weight"])
+    eng.set_events(2, ev[2]["e_true"], ev[2]["e_reco"], None, None)
+    for d in range(3):
+        eng.set_data(d, data[d])
+    assert eng.dropped(1) == 7
+    compare(eng, desc, ev, data, displaced(desc, 11), 1e-9, "edge cases")
+
+
+def test_error_paths():
+    say("error paths")
+    desc = synth.tiny_model(41, formula="eq1", n_datasets=1)
+    ev = synth.tiny_events(desc, 2000, 3)
+    eng = nf.Engine(desc, "m64")
+    th = synth.start_vector(desc)
+    with pytest.raises(nf.NufoldError) as e:
+        eng.eval_nll(th)
+    assert e.value.code == nf.NF_ESTATE
+    eng.set_events(0, ev[0]["e_true"], ev[0]["e_reco"], ev[0]["source"], ev[0]["weight"])
+    with pytest.raises(nf.NufoldError) as e:
+        eng.eval_nll(th)
+    assert e.value.code == nf.NF_ESTATE  # data missing
+    data = oracle_data(desc, ev, 4)
+    eng.set_data(0, data[0])
+    bad = th.copy(); bad[0] = np.nan
+    with pytest.raises(nf.NufoldError) as e:
+        eng.eval_nll(bad)
+    assert e.value.code == nf.NF_EINVAL
+    with pytest.raises(nf.NufoldError) as e:
+        eng.set_data(0, data[0][:-1])
+    assert e.value.code == nf.NF_EINVAL
+    # mu <= 0 -> domain warning, NLL = +inf, gradient 0
+    neg = th.copy()
+    neg[eng.param_index("ds0.norm")] = -1.0
+    neg[eng.param_index("ds0.bkg.rate")] = -1.0
+    f, g, code = eng.eval_nll_grad(neg)
+    assert code == nf.NF_WDOMAIN and f == np.inf and np.all(g == 0)
+    # energy map not monotone on the fine range -> domain warning
+    bad_c = th.copy()
+    bad_c[eng.param_index("ds0.c1")] = -1.5
+    f, code = eng.eval_nll(bad_c)
+    assert code == nf.NF_WDOMAIN and f == np.inf
+    # and the engine keeps working afterwards
+    f, g, code = eng.eval_nll_grad(th)
+    assert code == nf.NF_OK and np.isfinite(f)
+
+
+def test_device_pointer_entry_point_matches_host_path():
+    say("device entry point")
+    import torch
+    desc, events = synth.model_and_events(1)
+    data = oracle_data(desc, events, 5)
+    eng = nf.Engine(desc, "m64", stream=torch.cuda.current_stream().cuda_stream)
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+        eng.set_data(d, torch.tensor(data[d], dtype=torch.float64, device="cuda"))
+    th = displaced(desc, 12)
+    theta_t = torch.tensor(th, dtype=torch.float64, device="cuda")
+    out_t = torch.zeros(1 + len(th), dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    eng.eval_device(theta_t.data_ptr(), out_t.data_ptr(), st.data_ptr(), True)
+    torch.cuda.synchronize()
+    f, g, _ = eng.eval_nll_grad(th)
+    o = out_t.cpu().numpy()
+    assert o[0] == f and np.array_equal(o[1:], g) and int(st.item()) == 0
