@@ -157,7 +157,10 @@ struct nf_ctx {
   DevBuf<int32_t> d_status;
   DevBuf<double> d_data;
   DevBuf<double> d_mu;
-  DevBuf<double> d_scratch;
+  DevBuf<double> d_Sseg;
+  DevBuf<double> d_bin;
+  DevBuf<double> d_prior;
+  DevBuf<int> d_counter;
   double* h_stage = nullptr;  // pinned: theta, out, mu
   int32_t* h_status = nullptr;
   int nitems = 0;
@@ -173,7 +176,7 @@ struct nf_ctx {
     d_dpool.release(); d_ipool.release(); d_ds.release(); d_bkg.release();
     d_u64.release(); d_u32.release(); d_w.release(); d_items.release(); d_seg_item.release();
     d_Wseg.release(); d_part.release(); d_theta.release(); d_out.release(); d_status.release();
-    d_data.release(); d_mu.release(); d_scratch.release();
+    d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release(); d_prior.release(); d_counter.release();
     if (h_stage) (void)hipHostFree(h_stage);
     if (h_status) (void)hipHostFree(h_status);
     for (auto& t : tev)
@@ -259,6 +262,8 @@ void parse_model(nf_ctx* c, const char* text) {
     if (dsj.empty()) fail(NF_EPARSE, "datasets: empty");
     int seg0 = 0, bins0 = 0;
     for (const auto& dj : dsj) {
+      if (!dj.get("backgrounds").is_null() && (int)dj.at("backgrounds").array().size() > MAX_BKG)
+        fail(NF_EPARSE, "at most 8 backgrounds per dataset");
       HostDataset d;
       d.name = dj.get("name").kind == Json::String ? dj.get("name").string() : "";
       const Json& fine = dj.at("fine");
@@ -284,6 +289,7 @@ void parse_model(nf_ctx* c, const char* text) {
         std::vector<int> lst = dnorm;
         if (!s.get("norm").is_null())
           for (const auto& n : s.at("norm").array()) lst.push_back(param_ref(c, n, false, "source norm"));
+        if ((int)lst.size() > NLMAX) fail(NF_EPARSE, "at most 8 norm parameters per source");
         d.srcnorm.push_back(lst);
       }
       const Json& fl = dj.get("flux");
@@ -336,9 +342,14 @@ void parse_model(nf_ctx* c, const char* text) {
     pl.G = seg0;
     pl.nbins_total = bins0;
     pl.osc = c->osc;
-    pl.max_K = pl.max_Nb = pl.max_S = 0;
+    pl.max_K = pl.max_Nb = pl.max_S = pl.max_B = pl.max_M = pl.max_nnz = pl.max_nl = 0;
+    int kt = 0, fs = 0;
     for (auto& d : c->ds) {
       DsPlan q{};
+      q.kt0 = kt;
+      q.fs0 = fs;
+      kt += d.K;
+      fs += d.S;
       q.y0 = d.y0; q.wf = d.wf; q.K = d.K; q.Nb = d.Nb; q.S = d.S; q.M = d.M;
       q.nbkg = (int)d.bkgs.size();
       q.seg0 = d.seg0;
@@ -354,6 +365,8 @@ void parse_model(nf_ctx* c, const char* text) {
         ip.insert(ip.end(), d.srcnorm[s].begin(), d.srcnorm[s].end());
       }
       ip[q.srcnorm_ptr + d.S] = (int)ip.size();
+      q.nl0 = ip[q.srcnorm_ptr];
+      q.nl = ip[q.srcnorm_ptr + d.S] - q.nl0;
       // flux basis: CSR over fine bins, CSC over modes (exact zeros dropped)
       q.md_param = (int)ip.size();
       ip.insert(ip.end(), d.flux_param.begin(), d.flux_param.end());
@@ -375,6 +388,7 @@ void parse_model(nf_ctx* c, const char* text) {
         }
       }
       cptr[d.M] = (int)ck.size();
+      q.nnz = (int)ck.size();
       q.fx_coef = (int)dp.size();
       dp.insert(dp.end(), rcoef.begin(), rcoef.end());
       q.fx_mode = (int)ip.size();
@@ -408,6 +422,98 @@ void parse_model(nf_ctx* c, const char* text) {
       pl.max_K = std::max(pl.max_K, d.K);
       pl.max_Nb = std::max(pl.max_Nb, d.Nb);
       pl.max_S = std::max(pl.max_S, d.S);
+      pl.max_B = std::max(pl.max_B, q.nbkg);
+      pl.max_M = std::max(pl.max_M, q.M);
+      pl.max_nnz = std::max(pl.max_nnz, q.nnz);
+      pl.max_nl = std::max(pl.max_nl, q.nl);
+    }
+    pl.KT = kt;
+    pl.FS = fs;
+    // static blobs (one per dataset) for the serial bin stages
+    pl.max_blob = 0;
+    for (size_t di = 0; di < c->dsplan.size(); ++di) {
+      DsPlan& q = c->dsplan[di];
+      const HostDataset& d = c->ds[di];
+      const BlobLayout B = blob_layout(q.Nb + 1, q.nbkg, q.Nb, q.nnz, q.M, q.S, q.nl);
+      std::vector<double> blob(B.total, 0.0);
+      for (int i = 0; i <= q.Nb; ++i) blob[B.edges + i] = d.edges[i];
+      for (int b = 0; b < q.nbkg; ++b) {
+        const HostBkg& hb = d.bkgs[b];
+        blob[B.bsc + b] = hb.scale;
+        blob[B.brt + b] = hb.rate;
+        for (int i = 0; i < q.Nb; ++i) {
+          blob[B.tmpl + b * q.Nb + i] = hb.tmpl[i];
+          blob[B.shp + b * q.Nb + i] = hb.shape.empty() ? -1.0 : (double)hb.shape[i];
+        }
+      }
+      for (int e = 0; e < q.nnz; ++e) {
+        blob[B.mdc + e] = dp[q.md_coef + e];
+        blob[B.mdk + e] = ip[q.md_k + e];
+      }
+      for (int m = 0; m <= q.M; ++m) blob[B.mdcol + m] = ip[q.md_col + m];
+      for (int m = 0; m < q.M; ++m) blob[B.mdp + m] = ip[q.md_param + m];
+      for (int s = 0; s <= q.S; ++s) blob[B.nlp + s] = ip[q.srcnorm_ptr + s] - q.nl0;
+      for (int j = 0; j < q.nl; ++j) blob[B.nli + j] = ip[q.nl0 + j];
+      q.blob = (int)dp.size();
+      q.blob_n = B.total;
+      dp.insert(dp.end(), blob.begin(), blob.end());
+      pl.max_blob = std::max(pl.max_blob, B.total);
+    }
+    // per global fine bin: first segment, stride, sources, first flat source
+    pl.kt_info = (int)ip.size();
+    for (const auto& q : c->dsplan)
+      for (int k = 0; k < q.K; ++k) {
+        ip.push_back(q.seg0 + k);
+        ip.push_back(q.K);
+        ip.push_back(q.S);
+        ip.push_back(q.fs0);
+        ip.push_back(q.kt0);
+      }
+    // per flat source: fixed-width norm list
+    pl.fs_nl = (int)ip.size();
+    for (size_t di = 0; di < c->ds.size(); ++di)
+      for (int s = 0; s < c->ds[di].S; ++s)
+        for (int j = 0; j < NLMAX; ++j)
+          ip.push_back(j < (int)c->ds[di].srcnorm[s].size() ? c->ds[di].srcnorm[s][j] : -1);
+    // per-segment flat source, per-fine-bin dataset, per-flat-source norm-list range
+    pl.seg_fs = (int)ip.size();
+    for (size_t di = 0; di < c->dsplan.size(); ++di) {
+      const DsPlan& q = c->dsplan[di];
+      for (int s = 0; s < q.S; ++s)
+        for (int k = 0; k < q.K; ++k) ip.push_back(q.fs0 + s);
+    }
+    pl.kt_ds = (int)ip.size();
+    for (size_t di = 0; di < c->dsplan.size(); ++di)
+      for (int k = 0; k < c->dsplan[di].K; ++k) ip.push_back((int)di);
+    // flux basis rows per global fine bin with parameter indices (for phase A)
+    {
+      std::vector<int> rows(1, 0), par;
+      std::vector<double> cf;
+      for (const auto& d : c->ds)
+        for (int k = 0; k < d.K; ++k) {
+          for (int m = 0; m < d.M; ++m) {
+            const double v = d.basis[(size_t)m * d.K + k];
+            if (v != 0.0) {
+              par.push_back(d.flux_param[m]);
+              cf.push_back(v);
+            }
+          }
+          rows.push_back((int)par.size());
+        }
+      pl.kt_row = (int)ip.size();
+      ip.insert(ip.end(), rows.begin(), rows.end());
+      pl.kt_par = (int)ip.size();
+      ip.insert(ip.end(), par.begin(), par.end());
+      pl.kt_coef = (int)dp.size();
+      dp.insert(dp.end(), cf.begin(), cf.end());
+    }
+    pl.fs_ptr = (int)ip.size();
+    for (size_t di = 0; di < c->dsplan.size(); ++di) {
+      const DsPlan& q = c->dsplan[di];
+      for (int s = 0; s < q.S; ++s) {
+        ip.push_back(ip[q.srcnorm_ptr + s]);
+        ip.push_back(ip[q.srcnorm_ptr + s + 1]);
+      }
     }
     // priors
     pl.ngauss = (int)gidx.size();
@@ -454,6 +560,10 @@ void parse_model(nf_ctx* c, const char* text) {
     dp.insert(dp.end(), bmean.begin(), bmean.end());
     pl.blk_inv = (int)ip.size();
     ip.insert(ip.end(), binv.begin(), binv.end());
+    pl.NR = pl.ngauss + (int)bidx.size();
+    pl.prow_blk = (int)ip.size();
+    for (int b = 0; b < pl.nblk; ++b)
+      for (int r = bptr[b]; r < bptr[b + 1]; ++r) ip.push_back(b);
   } catch (const JsonError& e) {
     fail(NF_EPARSE, e.what());
   }
@@ -475,7 +585,11 @@ void upload_plan(nf_ctx* c) {
   c->d_status.alloc(1);
   c->d_data.alloc(std::max(1, c->nbins_total));
   c->d_mu.alloc(std::max(1, c->nbins_total));
-  c->d_scratch.alloc((size_t)std::max(1, c->plan.max_S) * std::max(1, c->plan.max_K));
+  c->d_Sseg.alloc((size_t)std::max(1, c->plan.G));
+  c->d_bin.alloc((size_t)6 * std::max(1, c->plan.KT));
+  c->d_prior.alloc((size_t)2 * std::max(1, c->plan.NR));
+  c->d_counter.alloc(1);
+  hip_check(hipMemsetAsync(c->d_counter.p, 0, sizeof(int), c->stream), "hipMemsetAsync");
   hip_check(hipHostMalloc((void**)&c->h_stage, sizeof(double) * (2 + 2 * c->P + c->nbins_total)),
             "hipHostMalloc");
   hip_check(hipHostMalloc((void**)&c->h_status, sizeof(int32_t) * 4), "hipHostMalloc");
@@ -646,7 +760,10 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   ta.out = out_dev;
   ta.status = status_dev;
   ta.mu_out = mu_dev;
-  ta.scratch = c->d_scratch.p;
+  ta.Sseg = c->d_Sseg.p;
+  ta.bin = c->d_bin.p;
+  ta.prior = c->d_prior.p;
+  ta.counter = c->d_counter.p;
   ta.want_grad = want_grad;
   ta.want_nll = want_nll;
   hipEvent_t* ev = nullptr;

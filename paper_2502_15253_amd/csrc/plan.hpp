@@ -47,11 +47,14 @@ struct BkgPlan {
 struct DsPlan {
   double y0, wf;
   int K, Nb, S, M, nbkg;
-  int seg0;         // global segment index of (source 0, fine bin 0)
+  int seg0;         // global segment index of (source 0, fine bin 0); segment = seg0 + s*K + k
+  int kt0;          // global index of fine bin 0 of this dataset
+  int fs0;          // flat (all-dataset) index of source 0
   int edges;        // dpool: Nb + 1 analysis edges
   int data;         // offset into the data vector (Nb counts)
   int bins0;        // offset into concatenated analysis bins (same as data)
   int srcnorm_ptr;  // ipool: S + 1 absolute ipool offsets of each source's norm list
+  int nl0, nl;      // ipool offset and total length of this dataset's norm lists
   int fx_row;       // ipool: K + 1 absolute offsets into fx_mode / dpool fx_coef (CSR over k)
   int fx_mode;      // ipool base of CSR mode indices (0..M-1)
   int fx_coef;      // dpool base of CSR coefficients
@@ -59,18 +62,57 @@ struct DsPlan {
   int md_k;         // ipool base of CSC fine-bin indices
   int md_coef;      // dpool base of CSC coefficients
   int md_param;     // ipool: M parameter indices
+  int nnz;          // number of non-zero basis entries
   int cidx[3];      // energy-scale parameters c0, c1, c2 (-1: fixed at 0)
   int bkg0;         // index of the first BkgPlan
+  int blob, blob_n; // dpool offset and length of the static blob (layout: blob_layout)
 };
+
+constexpr int NLMAX = 8;  // norm parameters multiplying one source
+
+// Per-dataset static inputs of the bin stages, packed contiguously (integers
+// stored as exact doubles) so one batched copy stages them in LDS.
+struct BlobLayout {
+  int edges, tmpl, mdc, bsc, brt, shp, mdcol, mdk, mdp, nlp, nli, total;
+};
+__host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl) {
+  BlobLayout L;
+  int o = 0;
+  L.edges = o; o += E;
+  L.tmpl = o; o += B * Nb;
+  L.mdc = o; o += nnz;
+  L.bsc = o; o += B;
+  L.brt = o; o += B;
+  L.shp = o; o += B * Nb;
+  L.mdcol = o; o += M + 1;
+  L.mdk = o; o += nnz;
+  L.mdp = o; o += M;
+  L.nlp = o; o += S + 1;
+  L.nli = o; o += nl;
+  L.total = o;
+  return L;
+}
 
 struct DevPlan {
   int P, D, G, nitems, nbins_total;
-  int max_K, max_Nb, max_S;
+  int KT, FS;            // total fine bins, total sources over all datasets
+  int max_K, max_Nb, max_S, max_B, max_M, max_nnz, max_nl;
   OscPlan osc;
   const DsPlan* ds;
   const BkgPlan* bkg;
   const double* dpool;
   const int* ipool;
+  int seg_fs;            // ipool: G flat source index of each segment
+  int kt_ds;             // ipool: KT dataset index of each global fine bin
+  int fs_ptr;            // ipool: 2 FS, [begin, end) absolute ipool offsets of each source's norm list
+  int max_blob;          // largest static blob
+  int kt_info;           // ipool: 5 KT: first segment, stride K, sources S, first flat source, kt0
+  int fs_nl;             // ipool: NLMAX FS norm-list parameter indices per flat source (-1 padded)
+  int kt_row;            // ipool: KT + 1 flux-basis row pointers per global fine bin (relative)
+  int kt_par;            // ipool base: parameter index of each row entry
+  int kt_coef;           // dpool base: coefficient of each row entry
+  int NR;                // prior rows: ngauss Gaussian rows, then one row per block-prior entry
+  int prow_blk;          // ipool: NR - ngauss block index of each block-prior row
   const int* seg_item;   // G + 1: work-item range of each segment
   const double* Wseg;    // G: sum of weights of each segment (static)
   // priors

@@ -1,20 +1,30 @@
-// Bin stages, NLL and adjoint gradient for one model evaluation, executed by a
-// single workgroup (they are latency-bound: a few hundred bins per dataset).
+// Bin stages, NLL and adjoint gradient of one model evaluation.
 //
-// Forward, per dataset (paper, "Structure of the framework", steps 2 and 3,
-// and Eq. 3-6, 9):
-//   S[s][k]  = W a0 + sum_c a_c M_c           oscillated fine spectrum from the
-//                                              fold moments M (linear in M)
-//   Hs[k]    = sum_s A_s S[s][k],  A_s = product of its norm parameters
-//   H[k]     = Hs[k] (1 + F_k),    F_k = sum_m f_m phi_m(k)   (flux shape)
+// Phase A (many workgroups, one wavefront per fine bin, lane s = source):
+// sum the fold's partial moments of each (dataset, source, fine-bin) segment
+// in a fixed order, turn them into the oscillated fine spectrum S and its
+// derivatives with respect to the four oscillation slots (linear in the
+// moments), apply the source normalisation A_s and reduce over sources; the
+// same wavefront evaluates the flux-shape factor 1 + F_k. Further wavefronts
+// evaluate the prior rows (Gaussian and correlated-Gaussian, independent of
+// the fold). Phase A results are written with agent-scope (write-through)
+// atomic stores; each workgroup waits for its stores to complete and then
+// bumps a counter; the last workgroup runs the serial part, reading those
+// results with agent-scope atomic loads, and resets the counter. No L2
+// write-back is needed for the hand-off.
+//
+// Serial part (one workgroup; bin stages are latency-bound), per dataset
+// (paper, "Structure of the framework", steps 2 and 3, and Eq. 3-6, 9):
+//   Hs[k] = sum_s A_s S[s][k],  H[k] = Hs[k] (1 + F_k)
 //   m_k = H_k/w, d_k = harmonic mean of neighbouring m (ends: m_0, m_{K-1}),
 //   C(y) = C_k + w [d_k (t - t^2/2) + d_{k+1} t^2/2 + 6 (m_k - (d_k+d_{k+1})/2)(t^2/2 - t^3/3)]
 //   X_i = C(g(x_i)),  g = inverse of f(E) = c0 + (1+c1) E + c2 E^2
 //   s_i = X_{i+1} - X_i,  mu_i = s_i + sum_b scale_b R_b T_bi (1 + beta_bi)
 //   NLL += sum_i [mu - n + n ln(n/mu)]   (n = 0: mu)
-// then Gaussian and correlated-Gaussian priors.
+// then the prior rows. A dataset's static inputs (one packed blob) and its
+// dynamic inputs are staged in LDS with two batched copies.
 //
-// Reverse pass (exact adjoint of the above; replaces numerical gradients):
+// Reverse pass (exact adjoint; replaces numerical gradients):
 //   lambda_mu = 1 - n/mu -> background rates and shapes; lambda_X from
 //   s_i = X_{i+1} - X_i; each X_i depends on C_k, m_k, d_k, d_{k+1} of its
 //   fine bin and on y = g(x; c) (energy-scale coefficients, dC/dy = rho);
@@ -22,8 +32,8 @@
 //   lambda_H -> flux modes, source norms, and, through the forward-mode
 //   derivative rows of the fold moments, the oscillation parameters.
 //
-// All arithmetic is FP64. Gradient contributions are gathered in a fixed order
-// except where several contributions can hit one shared parameter within a
+// All arithmetic is FP64. Gradient contributions are gathered in a fixed
+// order except where contributions can hit one shared parameter within a
 // phase (LDS atomics), which only affects the last bits.
 #include <hip/hip_runtime.h>
 
@@ -31,56 +41,63 @@
 
 namespace nufold {
 
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <int NT>
 struct Lds {
-  double* theta;  // P
+  double* th;     // P
   double* grad;   // P
-  double* coef;   // 5 x 8
-  double* A;      // max_S
-  double* Hs;     // K
-  double* F1;     // K
-  double* Gs;     // 4 K
-  double* D;      // K + 1  edge densities
-  double* C;      // K + 1  cumulative, later lambda_C, then lambda_H
-  double* Ld;     // K + 1  lambda_d, later lambda_F
-  double* LH;     // K      H (scan input), lambda_m (direct), later lambda_Hs
-  double* Suf;    // K + 1  suffix sums of lambda_C
-  double* eT;     // E      t, later e_m
-  double* eY;     // E      y, later e_dlo
-  double* eX;     // E      X, later lambda_X
-  double* eH;     // E      e_dhi
-  double* mu;     // Nb     mu, later lambda_mu
-  double* red;    // 8 * NT/64 + 8
+  double* coef;   // 40
+  double* red;    // reduction scratch
+  double* dyn;    // 6K + S*K + Nb: Hs, G0..G3, F1, Ss (per-source spectra), observed counts
+  double* Hs;
+  double* Gs;     // 4K
+  double* F1;
+  double* Ss;
+  double* nD;
+  double* D;      // K+1  edge densities
+  double* C;      // K+1  cumulative, later lambda_C, then lambda_H
+  double* Ld;     // K+1  lambda_d, later lambda_F
+  double* Suf;    // K+1  suffix sums of lambda_C
+  double* LH;     // K    H (scan input), lambda_m (direct), later lambda_Hs
+  double* eT;     // E    t, later e_m
+  double* eY;     // E    y, later e_dlo
+  double* eH;     // E    e_dhi
+  double* mu;     // Nb   lambda_mu
+  double* st;     // static blob of the current dataset (edges become X, then lambda_X)
   int* kidx;      // E
-  int* flag;      // 1
+  int* flag;      // 2
 };
 
 template <int NT>
 __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   Lds<NT> L;
-  const int K = p.max_K, E = p.max_Nb + 1;
+  const int K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
   double* q = base;
-  L.theta = q; q += p.P;
+  L.th = q; q += p.P;
   L.grad = q; q += p.P;
   L.coef = q; q += 40;
-  L.A = q; q += p.max_S;
-  L.Hs = q; q += K;
-  L.F1 = q; q += K;
-  L.Gs = q; q += 4 * K;
+  L.red = q; q += 16 * (NT / 64) + 16;
+  L.dyn = q; q += 6 * K + p.max_S * K + Nb;
   L.D = q; q += K + 1;
   L.C = q; q += K + 1;
   L.Ld = q; q += K + 1;
-  L.LH = q; q += K;
   L.Suf = q; q += K + 1;
+  L.LH = q; q += K;
   L.eT = q; q += E;
   L.eY = q; q += E;
-  L.eX = q; q += E;
   L.eH = q; q += E;
-  L.mu = q; q += p.max_Nb;
-  L.red = q; q += 8 * (NT / 64) + 8;
-  L.kidx = reinterpret_cast<int*>(q);
-  L.flag = L.kidx + E;
+  L.mu = q; q += Nb;
+  L.st = q; q += p.max_blob;
+  int* r = reinterpret_cast<int*>(q);
+  L.kidx = r; r += E;
+  L.flag = r;
+  L.Hs = L.Gs = L.F1 = L.Ss = L.nD = nullptr;
   return L;
 }
 
@@ -90,38 +107,41 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of N values over the workgroup; every thread gets the totals.
+// Sum of N values over the workgroup; every thread gets the totals. Wave
+// partials go to red[j*NW + w]; groups of NW lanes finish them with shuffles.
 template <int NT, int N>
 __device__ __forceinline__ void block_sum(double* v, double* red) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  static_assert(N <= 16, "reduction scratch too small");
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 #pragma unroll
   for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
-  __syncthreads();
   if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) red[j * (NT / 64) + wid] = v[j];
+    for (int j = 0; j < N; ++j) red[j * NW + wid] = v[j];
+  }
+  __syncthreads();
+  if (wid < (N * NW + 63) / 64) {  // whole wavefronts take part in the shuffles
+    double x = tid < N * NW ? red[tid] : 0.0;
+#pragma unroll
+    for (int off = NW / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (tid < N * NW && (tid % NW) == 0) red[16 * NW + tid / NW] = x;
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    double t = 0.0;
-    for (int i = 0; i < NT / 64; ++i) t += red[j * (NT / 64) + i];
-    v[j] = t;
-  }
-  __syncthreads();
+  for (int j = 0; j < N; ++j) v[j] = red[16 * NW + j];
 }
 
 // out[i] = sum of x[j] for j < i (i = 0..n), or, with reverse, out[i] = sum of
 // x[j] for j > i (i = 0..n-1). Contiguous chunks per thread, fixed order.
 template <int NT>
 __device__ void block_scan(const double* x, double* out, int n, bool reverse, double* red) {
+  constexpr int NW = NT / 64;
   const int per = (n + NT - 1) / NT;
   const int lo = threadIdx.x * per;
   const int hi = min(lo + per, n);
-  auto at = [&](int i) { return reverse ? x[n - 1 - i] : x[i]; };
   double s = 0.0;
-  for (int i = lo; i < hi; ++i) s += at(i);
-  // inclusive scan of s over threads
+  for (int i = lo; i < hi; ++i) s += reverse ? x[n - 1 - i] : x[i];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double v = s;
 #pragma unroll
@@ -129,12 +149,20 @@ __device__ void block_scan(const double* x, double* out, int n, bool reverse, do
     const double t = __shfl_up(v, off, 64);
     if (lane >= off) v += t;
   }
-  __syncthreads();
   if (lane == 63) red[wid] = v;
   __syncthreads();
-  double base = 0.0;
-  for (int i = 0; i < wid; ++i) base += red[i];
-  double acc = base + v - s;  // exclusive prefix of this thread's chunk
+  if (wid == 0) {  // exclusive scan of the wave totals
+    const double w = lane < NW ? red[lane] : 0.0;
+    double incl = w;
+#pragma unroll
+    for (int off = 1; off < NW; off <<= 1) {
+      const double t = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += t;
+    }
+    if (lane < NW) red[NW + lane] = incl - w;
+  }
+  __syncthreads();
+  double acc = red[NW + wid] + v - s;  // exclusive prefix of this thread's chunk
   if (!reverse) {
     for (int i = lo; i < hi; ++i) {
       out[i] = acc;
@@ -143,13 +171,30 @@ __device__ void block_scan(const double* x, double* out, int n, bool reverse, do
     if (hi == n && lo < hi) out[n] = acc;
     if (n == 0 && threadIdx.x == 0) out[0] = 0.0;
   } else {
-    // position i in reversed order is element n-1-i; out[e] = sum over j > e
     for (int i = lo; i < hi; ++i) {
       out[n - 1 - i] = acc;
       acc += x[n - 1 - i];
     }
   }
   __syncthreads();
+}
+
+// Cooperative copy global -> LDS with U independent loads in flight per thread.
+template <int NT, int U>
+__device__ __forceinline__ void stage(double* dst, const double* src, int n) {
+  for (int base = 0; base < n; base += NT * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + (int)threadIdx.x;
+      v[u] = i < n ? src[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + (int)threadIdx.x;
+      if (i < n) dst[i] = v[u];
+    }
+  }
 }
 
 __device__ __forceinline__ int lower_bound_int(const int* a, int n, int key) {
@@ -165,12 +210,14 @@ __device__ __forceinline__ double pval(const double* th, int idx, double dflt) {
   return idx >= 0 ? th[idx] : dflt;
 }
 
-// Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j) as linear
-// combinations of (W, M_1..M_NM). Returns false outside the parameter domain.
+// Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
+// linear combination of (W, M_1..M_NM). Returns false outside the domain.
 __device__ bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {
   double v[NSLOT];
   for (int j = 0; j < NSLOT; ++j) v[j] = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];
   for (int i = 0; i < 40; ++i) cf[i] = 0.0;
+  bool ok = true;
+  for (int j = 0; j < NSLOT; ++j) ok = ok && isfinite(v[j]);
   if (o.formula == FORM_EQ1) {
     // moments: 1 C_ee, 2 C_21, 3 Q_ee, 4 Q_21
     const double s = v[0], s12 = v[2];
@@ -185,7 +232,7 @@ __device__ bool osc_coefficients(const OscPlan& o, const double* th, double* cf)
     const double aee = TWO_PHASE_K * UNIT_1EM3, a21 = TWO_PHASE_K * UNIT_1EM5;
     double* r0 = cf;
     r0[0] = 1.0 - 0.5 * s - 0.5 * A; r0[1] = 0.5 * s; r0[2] = 0.5 * A;
-    double* r1 = cf + 8;  // d/d sin^2(2 th13)
+    double* r1 = cf + 8;   // d/d sin^2(2 th13)
     r1[0] = -0.5 - 0.5 * dA_ds; r1[1] = 0.5; r1[2] = 0.5 * dA_ds;
     double* r2 = cf + 16;  // d/d dm2_ee
     r2[3] = -0.5 * s * aee;
@@ -220,7 +267,81 @@ __device__ bool osc_coefficients(const OscPlan& o, const double* th, double* cf)
     double* r4 = cf + 32;  // d/d dm2_31
     r4[5] = -0.5 * K31 * a31; r4[6] = -0.5 * K32 * a31;
   }
-  return true;
+  return ok;
+}
+
+// ---------------------------------------------------------------- phase A
+// Wavefront w < KT: global fine bin w. Wavefront KT + r: prior rows 64 r .. 64 r + 63.
+template <int NT>
+__device__ void phase_a(const TailArgs& a, const Lds<NT>& L) {
+  const DevPlan& p = a.plan;
+  const int lane = threadIdx.x & 63;
+  const int w = (int)((blockIdx.x * NT + threadIdx.x) >> 6);
+  const int NMOM = num_moments(p.osc.formula);
+  if (w < p.KT) {
+    const int* info = p.ipool + p.kt_info + 5 * w;
+    const int g0 = info[0], K = info[1], S = info[2], fs0 = info[3], kt0 = info[4];
+    const int k = w - kt0;
+    double hs = 0.0, gsum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = lane; s < S; s += 64) {
+      const int g = g0 + s * K;
+      double M[MAX_MOM + 1];
+      M[0] = p.Wseg[g];
+      for (int c = 1; c <= MAX_MOM; ++c) M[c] = 0.0;
+      const int ib = p.seg_item[g], ie = p.seg_item[g + 1];
+      for (int it = ib; it < ie; ++it)
+        for (int c = 0; c < NMOM; ++c) M[1 + c] += a.part[(int64_t)c * p.nitems + it];
+      const int* nl = p.ipool + p.fs_nl + NLMAX * (fs0 + s);
+      double A = 1.0;
+#pragma unroll
+      for (int q = 0; q < NLMAX; ++q)
+        if (nl[q] >= 0) A *= L.th[nl[q]];
+      double Sv = 0.0;
+      for (int c = 0; c <= NMOM; ++c) Sv += L.coef[c] * M[c];
+      store_agent(&a.Sseg[g], Sv);
+      hs += A * Sv;
+      for (int j = 0; j < 4; ++j) {
+        double gj = 0.0;
+        for (int c = 0; c <= NMOM; ++c) gj += L.coef[8 * (j + 1) + c] * M[c];
+        gsum[j] += A * gj;
+      }
+    }
+    // flux-shape factor of this fine bin
+    double F = 0.0;
+    const int rb = p.ipool[p.kt_row + w], re = p.ipool[p.kt_row + w + 1];
+    for (int e = rb + lane; e < re; e += 64) F += L.th[p.ipool[p.kt_par + e]] * p.dpool[p.kt_coef + e];
+    hs = wave_sum(hs);
+    for (int j = 0; j < 4; ++j) gsum[j] = wave_sum(gsum[j]);
+    F = wave_sum(F);
+    if (lane == 0) {
+      double* b = a.bin + 6 * (int64_t)kt0;
+      store_agent(&b[k], hs);
+      for (int j = 0; j < 4; ++j) store_agent(&b[(1 + j) * K + k], gsum[j]);
+      store_agent(&b[5 * K + k], 1.0 + F);
+    }
+  } else {
+    const int r = (w - p.KT) * 64 + lane;
+    if (r < p.NR) {
+      double v, e;
+      if (r < p.ngauss) {
+        const double z = L.th[p.ipool[p.gidx + r]] - p.dpool[p.gmean + r];
+        v = z * p.dpool[p.ginv + r];
+        e = 0.5 * z * v;
+      } else {
+        const int bl = p.ipool[p.prow_blk + r - p.ngauss];
+        const int b = p.ipool[p.blk_ptr + bl], n = p.ipool[p.blk_ptr + bl + 1] - b;
+        const int row = r - p.ngauss - b;
+        const double* Vi = p.dpool + p.ipool[p.blk_inv + bl] + (int64_t)row * n;
+        v = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < n; ++c)
+          v += Vi[c] * (L.th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
+        e = 0.5 * (L.th[p.ipool[p.blk_idx + b + row]] - p.dpool[p.blk_mean + b + row]) * v;
+      }
+      store_agent(&a.prior[r], v);
+      store_agent(&a.prior[p.NR + r], e);
+    }
+  }
 }
 
 template <int NT>
@@ -229,67 +350,72 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   const DevPlan& p = a.plan;
   Lds<NT> L = carve<NT>(smem, p);
   const int tid = threadIdx.x;
-  const int NMOM = num_moments(p.osc.formula);
 
   for (int i = tid; i < p.P; i += NT) {
-    L.theta[i] = a.theta[i];
+    L.th[i] = a.theta[i];
     L.grad[i] = 0.0;
   }
-  if (tid == 0) *L.flag = 0;
-  __syncthreads();
   if (tid == 0) {
-    bool ok = osc_coefficients(p.osc, L.theta, L.coef);
-    for (int i = 0; i < p.P; ++i)
-      if (!isfinite(L.theta[i])) ok = false;
-    if (!ok) *L.flag |= ST_DOMAIN;
+    L.flag[0] = 0;
+    bool ok = osc_coefficients(p.osc, L.th, L.coef);
+    if (!ok) L.flag[0] |= ST_DOMAIN;
   }
   __syncthreads();
+  phase_a<NT>(a, L);
 
-  double nll_total = 0.0;  // meaningful in every thread (block sums broadcast)
+  // ---- hand-off: our write-through stores are complete before we count
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    const int done = __hip_atomic_fetch_add(a.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    L.flag[1] = (done == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!L.flag[1]) return;
+  if (tid == 0) __hip_atomic_store(a.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  for (int i = tid; i < p.P; i += NT)
+    if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
+
+  double nll_total = 0.0;  // identical in every thread (block sums broadcast)
 
   for (int d = 0; d < p.D; ++d) {
-    const DsPlan ds = p.ds[d];
-    const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1;
+    const DsPlan& ds = p.ds[d];
+    const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
     const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
+    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl);
+    double* X = L.st + BL.edges;  // edges, then X, then lambda_X
+    const double* tmpl = L.st + BL.tmpl;
+    const double* shp = L.st + BL.shp;
+    const double* bsc = L.st + BL.bsc;
+    const double* brt = L.st + BL.brt;
+    L.Hs = L.dyn;
+    L.Gs = L.dyn + K;
+    L.F1 = L.dyn + 5 * K;
+    L.Ss = L.dyn + 6 * K;
+    L.nD = L.dyn + 6 * K + S * K;
 
-    // ---- source normalisations
-    for (int s = tid; s < S; s += NT) {
-      const int b = p.ipool[ds.srcnorm_ptr + s], e = p.ipool[ds.srcnorm_ptr + s + 1];
-      double A = 1.0;
-      for (int q = b; q < e; ++q) A *= L.theta[p.ipool[q]];
-      L.A[s] = A;
-    }
-    __syncthreads();
-
-    // ---- moments -> S[s][k], Hs, Gs, flux factor
-    for (int k = tid; k < K; k += NT) {
-      double hs = 0.0, g[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int s = 0; s < S; ++s) {
-        const int gseg = ds.seg0 + s * K + k;
-        double M[MAX_MOM + 1];
-        M[0] = p.Wseg[gseg];
-        for (int c = 1; c <= MAX_MOM; ++c) M[c] = 0.0;
-        const int ib = p.seg_item[gseg], ie = p.seg_item[gseg + 1];
-        for (int it = ib; it < ie; ++it)
-          for (int c = 0; c < NMOM; ++c) M[1 + c] += a.part[(int64_t)c * p.nitems + it];
-        double Sv = 0.0;
-        for (int c = 0; c <= NMOM; ++c) Sv += L.coef[c] * M[c];
-        a.scratch[s * K + k] = Sv;
-        const double As = L.A[s];
-        hs += As * Sv;
-        for (int j = 0; j < 4; ++j) {
-          double gj = 0.0;
-          for (int c = 0; c <= NMOM; ++c) gj += L.coef[8 * (j + 1) + c] * M[c];
-          g[j] += As * gj;
+    // ---- stage: static blob (plain loads), phase-A results and data
+    stage<NT, 8>(L.st, p.dpool + ds.blob, ds.blob_n);
+    {
+      const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (a.want_nll ? Nb : 0);
+      const double* b = a.bin + 6 * (int64_t)ds.kt0;
+      const double* sg = a.Sseg + ds.seg0;
+      const double* dt = a.data + ds.data;
+      constexpr int U = 8;
+      for (int base = 0; base < n3; base += NT * U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = base + u * NT + tid;
+          v[u] = i < n1 ? load_agent(b + i) : i < n2 ? load_agent(sg + (i - n1)) : i < n3 ? dt[i - n2] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = base + u * NT + tid;
+          if (i < n3) L.dyn[i] = v[u];
         }
       }
-      double F = 0.0;
-      const int rb = p.ipool[ds.fx_row + k], re = p.ipool[ds.fx_row + k + 1];
-      for (int e = rb; e < re; ++e)
-        F += L.theta[p.ipool[ds.md_param + p.ipool[ds.fx_mode + e]]] * p.dpool[ds.fx_coef + e];
-      L.Hs[k] = hs;
-      L.F1[k] = 1.0 + F;
-      for (int j = 0; j < 4; ++j) L.Gs[j * K + k] = g[j];
     }
     __syncthreads();
 
@@ -303,34 +429,32 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
         dk = (ma * mb > 0.0) ? 2.0 * ma * mb / (ma + mb) : 0.0;
       }
       L.D[k] = dk;
+      if (k < K) L.LH[k] = L.Hs[k] * L.F1[k];  // H (scan input)
     }
-    for (int k = tid; k < K; k += NT) L.LH[k] = L.Hs[k] * L.F1[k];  // H, temporarily
     __syncthreads();
     block_scan<NT>(L.LH, L.C, K, false, L.red);
 
     // ---- energy scale and analysis edges
-    const double c0 = pval(L.theta, ds.cidx[0], 0.0);
-    const double c1 = pval(L.theta, ds.cidx[1], 0.0);
-    const double c2 = pval(L.theta, ds.cidx[2], 0.0);
+    const double c0 = pval(L.th, ds.cidx[0], 0.0);
+    const double c1 = pval(L.th, ds.cidx[1], 0.0);
+    const double c2 = pval(L.th, ds.cidx[2], 0.0);
     const double bb = 1.0 + c1;
-    if (tid == 0) {
-      if (!(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0)) *L.flag |= ST_DOMAIN;
-    }
+    if (tid == 0 && !(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0))
+      atomicOr(&L.flag[0], ST_DOMAIN);
     for (int i = tid; i < E; i += NT) {
-      const double x = p.dpool[ds.edges + i];
-      const double z = x - c0;
+      const double z = X[i] - c0;
       const double disc = bb * bb + 4.0 * c2 * z;
       double y;
       if (disc < 0.0) y = c2 < 0.0 ? INFINITY : -INFINITY;
       else y = 2.0 * z / (bb + sqrt(disc));
       int k;
-      double t = 0.0, X;
+      double t = 0.0, Xi;
       if (!(y >= y0)) {
         k = -1;
-        X = 0.0;
+        Xi = 0.0;
       } else if (y >= yK) {
         k = K;
-        X = L.C[K];
+        Xi = L.C[K];
       } else {
         k = (int)floor((y - y0) / wf);
         k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
@@ -338,64 +462,55 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
         const double mk = L.Hs[k] * L.F1[k] / wf;
         const double dl = L.D[k], dh = L.D[k + 1];
         const double q = 0.5 * t * t - t * t * t / 3.0;
-        X = L.C[k] + wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + 6.0 * (mk - 0.5 * (dl + dh)) * q);
+        Xi = L.C[k] + wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + 6.0 * (mk - 0.5 * (dl + dh)) * q);
       }
       L.kidx[i] = k;
       L.eT[i] = t;
       L.eY[i] = y;
-      L.eX[i] = X;
+      X[i] = Xi;
     }
     __syncthreads();
 
-    // ---- expectations, deviance, lambda_mu
-    double nll_loc = 0.0;
+    // ---- expectations, deviance, lambda_mu; background rate/shape gradients
+    double acc[1 + MAX_BKG];
+    for (int j = 0; j <= MAX_BKG; ++j) acc[j] = 0.0;
     for (int i = tid; i < Nb; i += NT) {
       double B = 0.0;
-      for (int b = 0; b < ds.nbkg; ++b) {
-        const BkgPlan bk = p.bkg[ds.bkg0 + b];
-        const double R = pval(L.theta, bk.rate, 1.0);
-        const double beta = bk.shape >= 0 ? pval(L.theta, p.ipool[bk.shape + i], 0.0) : 0.0;
-        B += bk.scale * R * p.dpool[bk.tmpl + i] * (1.0 + beta);
+      for (int b = 0; b < NB; ++b) {
+        const double beta = pval(L.th, (int)shp[b * Nb + i], 0.0);
+        B += bsc[b] * pval(L.th, (int)brt[b], 1.0) * tmpl[b * Nb + i] * (1.0 + beta);
       }
-      const double mu = (L.eX[i + 1] - L.eX[i]) + B;
+      const double mu = (X[i + 1] - X[i]) + B;
       if (a.mu_out) a.mu_out[ds.bins0 + i] = mu;
       double lam = 0.0;
       if (a.want_nll) {
-        const double n = a.data[ds.data + i];
-        if (!(mu > 0.0)) atomicOr(L.flag, ST_DOMAIN);
-        nll_loc += (n > 0.0) ? (mu - n + n * log(n / mu)) : mu;
+        const double n = L.nD[i];
+        if (!(mu > 0.0)) atomicOr(&L.flag[0], ST_DOMAIN);
+        acc[0] += (n > 0.0) ? (mu - n + n * log(n / mu)) : mu;
         lam = 1.0 - n / mu;
+        if (a.want_grad) {
+          for (int b = 0; b < NB; ++b) {
+            const int sp = (int)shp[b * Nb + i];
+            const double stv = bsc[b] * tmpl[b * Nb + i];
+            acc[1 + b] += lam * stv * (1.0 + pval(L.th, sp, 0.0));
+            if (sp >= 0) atomicAdd(&L.grad[sp], lam * stv * pval(L.th, (int)brt[b], 1.0));
+          }
+        }
       }
       L.mu[i] = lam;
     }
-    {
-      double v[1] = {nll_loc};
-      block_sum<NT, 1>(v, L.red);
-      nll_total += v[0];
+    block_sum<NT, 1 + MAX_BKG>(acc, L.red);
+    nll_total += acc[0];
+    if (!a.want_grad) {
+      __syncthreads();
+      continue;
     }
-    if (!a.want_grad) continue;
+    if (tid == 0)
+      for (int b = 0; b < NB; ++b)
+        if ((int)brt[b] >= 0) L.grad[(int)brt[b]] += acc[1 + b];
 
-    // ---- adjoint: backgrounds
-    for (int b = 0; b < ds.nbkg; ++b) {
-      const BkgPlan bk = p.bkg[ds.bkg0 + b];
-      const double R = pval(L.theta, bk.rate, 1.0);
-      double gr = 0.0;
-      for (int i = tid; i < Nb; i += NT) {
-        const double beta = bk.shape >= 0 ? pval(L.theta, p.ipool[bk.shape + i], 0.0) : 0.0;
-        const double st = bk.scale * p.dpool[bk.tmpl + i];
-        gr += L.mu[i] * st * (1.0 + beta);
-        if (bk.shape >= 0) {
-          const int pi = p.ipool[bk.shape + i];
-          if (pi >= 0) atomicAdd(&L.grad[pi], L.mu[i] * st * R);
-        }
-      }
-      double v[1] = {gr};
-      block_sum<NT, 1>(v, L.red);
-      if (tid == 0 && bk.rate >= 0) L.grad[bk.rate] += v[0];
-    }
-
-    // ---- adjoint: per edge (lambda_X, energy-scale coefficients, spline pieces)
-    double gc[4] = {0.0, 0.0, 0.0, 0.0};  // c0, c1, c2, top
+    // ---- adjoint per edge: lambda_X, energy-scale coefficients, spline pieces
+    double gc[4] = {0.0, 0.0, 0.0, 0.0};  // c0, c1, c2, out-of-range-above total
     for (int i = tid; i < E; i += NT) {
       const double lx = (i >= 1 ? L.mu[i - 1] : 0.0) - (i < Nb ? L.mu[i] : 0.0);
       const int k = L.kidx[i];
@@ -417,16 +532,15 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
         elo = lx * wf * (t - 0.5 * t * t - 3.0 * q);
         ehi = lx * wf * (0.5 * t * t - 3.0 * q);
       }
-      L.eX[i] = (k >= 0 && k < K) ? lx : 0.0;  // lambda_X of in-range edges
+      X[i] = (k >= 0 && k < K) ? lx : 0.0;
       L.eT[i] = em;
       L.eY[i] = elo;
       L.eH[i] = ehi;
     }
-    block_sum<NT, 4>(gc, L.red);  // contains the needed barrier
-    if (tid == 0) {
+    block_sum<NT, 4>(gc, L.red);
+    if (tid == 0)
       for (int j = 0; j < 3; ++j)
         if (ds.cidx[j] >= 0) L.grad[ds.cidx[j]] += gc[j];
-    }
     const double top = gc[3];
 
     // ---- gather per fine bin: lambda_C -> C, lambda_m (direct) -> LH, lambda_d -> Ld
@@ -436,7 +550,7 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
       double lc = 0.0, lm = 0.0, ld = 0.0;
       if (k < K) {
         for (int i = b0; i < b1; ++i) {
-          lc += L.eX[i];
+          lc += X[i];
           lm += L.eT[i];
           ld += L.eY[i];
         }
@@ -452,7 +566,7 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
       }
     }
     __syncthreads();
-    // C_k = sum_{j<k} H_j: lambda_H[j] collects sum_{k>j} lambda_C[k] (suffix sums -> Suf)
+    // C_k = sum_{j<k} H_j: lambda_H[j] collects sum_{k>j} lambda_C[k]
     block_scan<NT>(L.C, L.Suf, K, true, L.red);
 
     // ---- lambda_H per fine bin -> C
@@ -489,32 +603,39 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
       for (int j = 0; j < 4; ++j) go[j] += lhs * L.Gs[j * K + k];
     }
     block_sum<NT, 4>(go, L.red);
-    if (tid == 0) {
+    if (tid == 0)
       for (int j = 0; j < NSLOT; ++j)
         if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += go[j];
-    }
 
     // ---- flux modes (CSC gather per mode)
-    for (int m = tid; m < ds.M; m += NT) {
-      const int cb = p.ipool[ds.md_col + m], ce = p.ipool[ds.md_col + m + 1];
-      double gm = 0.0;
-      for (int e = cb; e < ce; ++e) gm += L.Ld[p.ipool[ds.md_k + e]] * p.dpool[ds.md_coef + e];
-      atomicAdd(&L.grad[p.ipool[ds.md_param + m]], gm);
+    {
+      const double* mdcol = L.st + BL.mdcol;
+      const double* mdk = L.st + BL.mdk;
+      const double* mdc = L.st + BL.mdc;
+      const double* mdp = L.st + BL.mdp;
+      for (int m = tid; m < M; m += NT) {
+        double gm = 0.0;
+        const int e1 = (int)mdcol[m + 1];
+        for (int e = (int)mdcol[m]; e < e1; ++e) gm += L.Ld[(int)mdk[e]] * mdc[e];
+        atomicAdd(&L.grad[(int)mdp[m]], gm);
+      }
     }
     // ---- source norms: one wavefront per source
     {
+      const double* nlp = L.st + BL.nlp;
+      const double* nli = L.st + BL.nli;
       const int lane = tid & 63, wid = tid >> 6;
       for (int s = wid; s < S; s += NT / 64) {
         double gA = 0.0;
-        for (int k = lane; k < K; k += 64) gA += L.LH[k] * a.scratch[s * K + k];
+        for (int k = lane; k < K; k += 64) gA += L.LH[k] * L.Ss[s * K + k];
         gA = wave_sum(gA);
         if (lane == 0) {
-          const int b = p.ipool[ds.srcnorm_ptr + s], e = p.ipool[ds.srcnorm_ptr + s + 1];
+          const int b = (int)nlp[s], e = (int)nlp[s + 1];
           for (int q = b; q < e; ++q) {
             double prod = 1.0;
             for (int r = b; r < e; ++r)
-              if (r != q) prod *= L.theta[p.ipool[r]];
-            atomicAdd(&L.grad[p.ipool[q]], gA * prod);
+              if (r != q) prod *= L.th[(int)nli[r]];
+            atomicAdd(&L.grad[(int)nli[q]], gA * prod);
           }
         }
       }
@@ -522,53 +643,46 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
     __syncthreads();
   }
 
-  // ---- priors (Eq. 6; third line of Eq. 9)
-  double pr = 0.0;
-  for (int j = tid; j < p.ngauss; j += NT) {
-    const int i = p.ipool[p.gidx + j];
-    const double z = L.theta[i] - p.dpool[p.gmean + j];
-    const double inv = p.dpool[p.ginv + j];
-    pr += 0.5 * z * z * inv;
-    if (a.want_grad) atomicAdd(&L.grad[i], z * inv);
-  }
-  for (int bl = 0; bl < p.nblk; ++bl) {
-    const int b = p.ipool[p.blk_ptr + bl], e = p.ipool[p.blk_ptr + bl + 1];
-    const int n = e - b;
-    const double* Vi = p.dpool + p.ipool[p.blk_inv + bl];
-    for (int r = tid; r < n; r += NT) {
-      double v = 0.0;
-      for (int c = 0; c < n; ++c)
-        v += Vi[(int64_t)r * n + c] * (L.theta[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
-      const double rr = L.theta[p.ipool[p.blk_idx + b + r]] - p.dpool[p.blk_mean + b + r];
-      pr += 0.5 * rr * v;
-      if (a.want_grad) atomicAdd(&L.grad[p.ipool[p.blk_idx + b + r]], v);
-    }
-  }
+  // ---- priors (Eq. 6; third line of Eq. 9), rows evaluated in phase A
   {
-    double v[1] = {pr};
-    block_sum<NT, 1>(v, L.red);
-    nll_total += v[0];
+    double pr[1] = {0.0};
+    for (int r = tid; r < p.NR; r += NT) {
+      pr[0] += load_agent(&a.prior[p.NR + r]);
+      if (a.want_grad) {
+        const int i = r < p.ngauss ? p.ipool[p.gidx + r] : p.ipool[p.blk_idx + (r - p.ngauss)];
+        atomicAdd(&L.grad[i], load_agent(&a.prior[r]));
+      }
+    }
+    block_sum<NT, 1>(pr, L.red);
+    nll_total += pr[0];
   }
+  __syncthreads();
 
-  const bool bad = (*L.flag & ST_DOMAIN) || !isfinite(nll_total);
+  const bool bad = (L.flag[0] & ST_DOMAIN) || !isfinite(nll_total);
   if (a.want_nll && tid == 0) a.out[0] = bad ? INFINITY : nll_total;
-  if (a.want_grad && a.want_nll) {
+  if (a.want_grad && a.want_nll)
     for (int i = tid; i < p.P; i += NT) a.out[1 + i] = bad ? 0.0 : L.grad[i];
-  }
   if (a.status && tid == 0) *a.status = bad ? ST_DOMAIN : 0;
+}
+
+int tail_blocks(const DevPlan& p, int nt) {
+  const int waves = p.KT + (p.NR + 63) / 64;
+  const int b = (waves + nt / 64 - 1) / (nt / 64);
+  return b < 1 ? 1 : b;
 }
 
 hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream) {
   const size_t lds = tail_lds_bytes(a.plan, nt);
+  const dim3 grid(tail_blocks(a.plan, nt));
   switch (nt) {
     case 256:
-      hipLaunchKernelGGL(tail_kernel<256>, dim3(1), dim3(256), lds, stream, a);
+      hipLaunchKernelGGL(tail_kernel<256>, grid, dim3(256), lds, stream, a);
       break;
     case 512:
-      hipLaunchKernelGGL(tail_kernel<512>, dim3(1), dim3(512), lds, stream, a);
+      hipLaunchKernelGGL(tail_kernel<512>, grid, dim3(512), lds, stream, a);
       break;
     default:
-      hipLaunchKernelGGL(tail_kernel<1024>, dim3(1), dim3(1024), lds, stream, a);
+      hipLaunchKernelGGL(tail_kernel<1024>, grid, dim3(1024), lds, stream, a);
       break;
   }
   return hipGetLastError();
