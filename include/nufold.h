@@ -152,6 +152,80 @@ int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
 int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
 
 /*
+ * Fit options and result (paper: "Structure of the framework" -- minimise
+ * -ln L until the estimated distance to the minimum is below a threshold).
+ */
+typedef struct {
+  double edm_tol;   /* stop when EDM = 1/2 g^T H g < edm_tol; <= 0 selects 1e-7     */
+  int max_iter;     /* accepted iterations; <= 0 selects 1000                        */
+  int want_cov;     /* 1: covariance = inverse of the central-difference Hessian of
+                       the adjoint gradient at the minimum (2 evaluations per free
+                       parameter), written to result->cov                           */
+} nf_fit_opts;
+
+typedef struct {
+  double nll;       /* NLL at the returned point (deviance form, see nf_eval_nll)    */
+  double edm;       /* estimated distance to the minimum at the returned point       */
+  int status;       /* 0 converged, 2 iteration limit, 3 line search failed,
+                       4 start point out of domain                                   */
+  int iters;        /* accepted iterations                                           */
+  int evals;        /* model evaluations (fold + bin stages + gradient)              */
+  int pad_;
+  double* theta;    /* caller-owned, nf_num_params() values, or NULL                 */
+  double* cov;      /* caller-owned P x P row-major, or NULL; zero rows/columns for
+                       fixed parameters; NaN when the Hessian is not positive
+                       definite                                                      */
+} nf_fit_result;
+
+/*
+ * Minimise NLL(theta) over the free parameters from `start` (host, P values).
+ * fixed: NULL (use the model's "fixed" flags) or P bytes, nonzero = fixed.
+ * The minimiser is limited-memory BFGS with a strong-Wolfe line search and
+ * runs on the device: each iteration is one evaluation (fold, bin stages,
+ * adjoint gradient) followed by the step, captured in a HIP graph and
+ * replayed until the device reports convergence. Returns NF_OK (converged),
+ * NF_WNOCONV (iteration limit or line-search failure; result filled),
+ * NF_WDOMAIN (start point out of domain), or an error. Needs events and data.
+ */
+int nf_fit(nf_ctx* ctx, const double* start, const uint8_t* fixed, const nf_fit_opts* opts,
+           nf_fit_result* result);
+
+/*
+ * Batched pseudo-experiments and scans (paper: parallel fits with individual
+ * settings and start values for ensembles and profile-likelihood scans).
+ *
+ * nf_set_data_batch: nsets observed-count vectors, each the concatenation of
+ * all datasets' analysis bins (sum_d nf_num_bins(d) values), row-major.
+ * Replaces any previous batch data. Copied; on_device as in nf_set_events.
+ */
+int nf_set_data_batch(nf_ctx* ctx, int nsets, const double* counts, int on_device);
+
+/*
+ * B evaluations in one batched fold (events read once per tile of fits) and
+ * one workgroup per fit for the bin stages. theta: B x P (host). data_idx:
+ * B rows of the batch data (NULL: row f for fit f). nll: B values (host);
+ * grad: B x P (host) or NULL. NF_WDOMAIN when some evaluation is out of domain
+ * (its NLL is +inf).
+ */
+int nf_eval_batch(nf_ctx* ctx, int B, const double* theta, const int* data_idx, double* nll, double* grad);
+
+/*
+ * B independent fits (pseudo-experiments or scan points) advanced together:
+ * every iteration is one batched fold (fits whose oscillation parameters did
+ * not change since their last fold reuse it, so scan points with fixed
+ * oscillation parameters fold once), one workgroup per fit for the bin
+ * stages, adjoint gradient and L-BFGS step, captured in a HIP graph and
+ * replayed until every fit has stopped. start: B x P. fixed: NULL (model's
+ * flags) or P bytes shared by all fits. data_idx: as in nf_eval_batch.
+ * Outputs (host, each nullable): theta_out B x P, nll_out, edm_out B,
+ * status_out, iters_out, evals_out B (status codes as in nf_fit_result).
+ * opts->want_cov is ignored. NF_OK when every fit converged, else NF_WNOCONV.
+ */
+int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, const int* data_idx,
+                 const nf_fit_opts* opts, double* theta_out, double* nll_out, double* edm_out,
+                 int* status_out, int* iters_out, int* evals_out);
+
+/*
  * Per-kernel device time, measured with HIP events recorded on the context
  * stream around the fold and the bin-stage kernels of every evaluation while
  * option "timing" is 1. nf_timing synchronises the stream and returns, for the

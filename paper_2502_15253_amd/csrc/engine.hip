@@ -129,6 +129,7 @@ struct nf_ctx {
 
   int P = 0;
   std::vector<std::string> names;
+  std::vector<char> fixed_default;
   std::map<std::string, int> index;
   OscPlan osc{};
   std::vector<HostDataset> ds;
@@ -169,6 +170,22 @@ struct nf_ctx {
   int fold_block = 256;
   int tail_threads = 512;
   int timing = 0;
+  // minimiser buffers (allocated at the first fit) and the captured iteration graph
+  int fit_m = 8;
+  DevBuf<FitHeader> f_hdr;
+  DevBuf<double> f_x, f_g, f_p, f_d2, f_fr, f_S, f_Y, f_rho, f_gam;
+  FitHeader* h_hdr = nullptr;  // pinned
+  hipGraphExec_t fit_graph = nullptr;
+  // batched evaluations and fits (capacity bt_cap fits)
+  int bt_cap = 0, bt_nsets = 0;
+  DevBuf<double> bt_theta, bt_part, bt_out, bt_Sseg, bt_bin, bt_prior, bt_segtmp, bt_osc_last, bt_data;
+  DevBuf<int32_t> bt_status;
+  DevBuf<int> bt_didx;
+  DevBuf<FitHeader> bf_hdr;
+  DevBuf<double> bf_x, bf_g, bf_p, bf_d2, bf_fr, bf_S, bf_Y, bf_rho, bf_gam;
+  std::vector<FitHeader> bh_hdr;
+  hipGraphExec_t bf_graph = nullptr;
+  int bf_graph_B = 0;
   std::vector<std::array<hipEvent_t, 3>> tev;  // per-evaluation timing events
   size_t tcount = 0;
 
@@ -179,6 +196,15 @@ struct nf_ctx {
     d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release(); d_prior.release(); d_counter.release();
     if (h_stage) (void)hipHostFree(h_stage);
     if (h_status) (void)hipHostFree(h_status);
+    if (h_hdr) (void)hipHostFree(h_hdr);
+    if (fit_graph) (void)hipGraphExecDestroy(fit_graph);
+    f_hdr.release(); f_x.release(); f_g.release(); f_p.release(); f_d2.release(); f_fr.release();
+    f_S.release(); f_Y.release(); f_rho.release(); f_gam.release();
+    if (bf_graph) (void)hipGraphExecDestroy(bf_graph);
+    for (auto* b : {&bt_theta, &bt_part, &bt_out, &bt_Sseg, &bt_bin, &bt_prior, &bt_segtmp, &bt_osc_last, &bt_data,
+                    &bf_x, &bf_g, &bf_p, &bf_d2, &bf_fr, &bf_S, &bf_Y, &bf_rho, &bf_gam})
+      b->release();
+    bt_status.release(); bt_didx.release(); bf_hdr.release();
     for (auto& t : tev)
       for (auto& e : t)
         if (e) (void)hipEventDestroy(e);
@@ -227,6 +253,10 @@ void parse_model(nf_ctx* c, const char* text) {
       c->names.push_back(n);
     }
     c->P = (int)c->names.size();
+    for (const auto& p : params) {
+      const Json& fx = p.get("fixed");
+      c->fixed_default.push_back(fx.kind == Json::Bool && fx.b ? 1 : 0);
+    }
     std::vector<int> gidx;
     std::vector<double> gmean, ginv;
     for (int i = 0; i < c->P; ++i) {
@@ -429,6 +459,8 @@ void parse_model(nf_ctx* c, const char* text) {
     }
     pl.KT = kt;
     pl.FS = fs;
+    c->fit_m = std::min(std::max(c->P, 8), 24);  // L-BFGS history; reduced below if LDS is short
+    pl.fit_m = c->fit_m;
     // static blobs (one per dataset) for the serial bin stages
     pl.max_blob = 0;
     for (size_t di = 0; di < c->dsplan.size(); ++di) {
@@ -618,7 +650,17 @@ int fine_bin(double E, double y0, double wf, int K) {
 }
 #pragma clang fp contract(on)
 
+void drop_fit_graph(nf_ctx* c) {
+  if (c->fit_graph) (void)hipGraphExecDestroy(c->fit_graph);
+  c->fit_graph = nullptr;
+  if (c->bf_graph) (void)hipGraphExecDestroy(c->bf_graph);
+  c->bf_graph = nullptr;
+  c->bf_graph_B = 0;
+}
+
 void rebuild_events(nf_ctx* c) {
+  drop_fit_graph(c);
+  c->bt_cap = 0;  // batch partials depend on the work-item count
   std::vector<int> seg_item(c->plan.G + 1, 0);
   std::vector<double> Wseg(c->plan.G, 0.0);
   std::vector<WorkItem> items;
@@ -742,8 +784,25 @@ void require_ready(nf_ctx* c, bool need_data) {
   }
 }
 
+FitArgs fit_args(nf_ctx* c) {
+  FitArgs f{};
+  f.hdr = c->f_hdr.p;
+  f.x = c->f_x.p;
+  f.g = c->f_g.p;
+  f.p = c->f_p.p;
+  f.d2 = c->f_d2.p;
+  f.freem = c->f_fr.p;
+  f.S = c->f_S.p;
+  f.Y = c->f_Y.p;
+  f.rho = c->f_rho.p;
+  f.gam = c->f_gam.p;
+  f.theta_next = c->d_theta.p;
+  f.m = c->fit_m;
+  return f;
+}
+
 void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* status_dev, double* mu_dev,
-                  int want_nll, int want_grad) {
+                  int want_nll, int want_grad, bool fit = false) {
   FoldArgs fa{};
   fa.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
   fa.w = c->d_w.p;
@@ -766,8 +825,14 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   ta.counter = c->d_counter.p;
   ta.want_grad = want_grad;
   ta.want_nll = want_nll;
+  if (fit) {
+    ta.has_fit = 1;
+    ta.fit = fit_args(c);
+    ta.skip = &c->f_hdr.p->status;
+    fa.skip = &c->f_hdr.p->status;
+  }
   hipEvent_t* ev = nullptr;
-  if (c->timing) {
+  if (c->timing && !fit) {
     if (c->tcount == c->tev.size()) {
       std::array<hipEvent_t, 3> t{};
       for (auto& e : t) hip_check(hipEventCreate(&e), "hipEventCreate");
@@ -817,6 +882,347 @@ int eval_host(nf_ctx* c, const double* theta, double* nll, double* grad, double*
   return NF_OK;
 }
 
+constexpr int FIT_CHUNK = 8;  // iterations per graph launch
+
+// Public fit status: 0 converged, 2 iteration limit, 3 line search failed, 4 domain.
+int public_status(int s) { return s == FIT_CONVERGED ? 0 : s; }
+
+void ensure_fit_buffers(nf_ctx* c) {
+  if (c->f_hdr.p) return;
+  const size_t P = c->P, m = c->fit_m;
+  c->f_hdr.alloc(1);
+  c->f_x.alloc(P); c->f_g.alloc(P); c->f_p.alloc(P); c->f_d2.alloc(P); c->f_fr.alloc(P);
+  c->f_S.alloc(m * P); c->f_Y.alloc(m * P); c->f_rho.alloc(m); c->f_gam.alloc(m);
+  hip_check(hipHostMalloc((void**)&c->h_hdr, sizeof(FitHeader)), "hipHostMalloc");
+}
+
+void ensure_fit_graph(nf_ctx* c) {
+  if (c->fit_graph) return;
+  hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  try {
+    for (int i = 0; i < FIT_CHUNK; ++i)
+      enqueue_eval(c, c->d_theta.p, c->d_out.p, c->d_status.p, nullptr, 1, 1, true);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(c->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamEndCapture(c->stream, &g), "hipStreamEndCapture");
+  const hipError_t e = hipGraphInstantiate(&c->fit_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e, "hipGraphInstantiate");
+}
+
+// Diagonal preconditioner: prior variance, else covariance-block diagonal,
+// else (5% of the start value, at least 1e-3)^2.
+std::vector<double> preconditioner(nf_ctx* c, const double* start) {
+  std::vector<double> d2(c->P, -1.0);
+  const DevPlan& pl = c->plan;
+  for (int j = 0; j < pl.ngauss; ++j) d2[c->ipool[pl.gidx + j]] = 1.0 / c->dpool[pl.ginv + j];
+  for (int b = 0; b < pl.nblk; ++b) {
+    const int b0 = c->ipool[pl.blk_ptr + b], b1 = c->ipool[pl.blk_ptr + b + 1], n = b1 - b0;
+    const double* Vi = c->dpool.data() + c->ipool[pl.blk_inv + b];
+    for (int r = 0; r < n; ++r) {
+      const int i = c->ipool[pl.blk_idx + b0 + r];
+      if (d2[i] < 0) d2[i] = 1.0 / Vi[(size_t)r * n + r];  // conditional variance scale
+    }
+  }
+  for (int i = 0; i < c->P; ++i)
+    if (d2[i] < 0) {
+      const double s = 0.05 * std::max(std::fabs(start[i]), 0.02);
+      d2[i] = s * s;
+    }
+  return d2;
+}
+
+int fit_impl(nf_ctx* c, const double* start, const uint8_t* fixed, const nf_fit_opts* opts,
+             nf_fit_result* res) {
+  require_ready(c, true);
+  if (!start || !res) fail(NF_EINVAL, "start and result are required");
+  for (int i = 0; i < c->P; ++i)
+    if (!std::isfinite(start[i])) fail(NF_EINVAL, "start[" + std::to_string(i) + "] is not finite");
+  const double tol = (opts && opts->edm_tol > 0) ? opts->edm_tol : 1e-7;
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 1000;
+  ensure_fit_buffers(c);
+  const std::vector<double> d2 = preconditioner(c, start);
+  std::vector<double> fr(c->P, 1.0);
+  for (int i = 0; i < c->P; ++i)
+    if (fixed ? fixed[i] != 0 : c->fixed_default[i]) fr[i] = 0.0;
+  FitHeader h{};
+  h.status = FIT_RUNNING;
+  h.phase = 0;
+  h.max_iter = max_iter;
+  h.edm_tol = tol;
+  h.alpha = 1.0;
+  *c->h_hdr = h;
+  hip_check(hipMemcpyAsync(c->f_hdr.p, c->h_hdr, sizeof(FitHeader), hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->d_theta.p, start, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->f_d2.p, d2.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->f_fr.p, fr.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  ensure_fit_graph(c);
+  const int64_t max_evals = (int64_t)max_iter * 50 + 200;
+  for (int64_t launched = 0;; launched += FIT_CHUNK) {
+    hip_check(hipGraphLaunch(c->fit_graph, c->stream), "hipGraphLaunch");
+    hip_check(hipMemcpyAsync(c->h_hdr, c->f_hdr.p, sizeof(FitHeader), hipMemcpyDeviceToHost, c->stream), "D2H");
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (c->h_hdr->status != FIT_RUNNING) break;
+    if (launched + FIT_CHUNK >= max_evals) {
+      c->h_hdr->status = FIT_MAXITER;
+      break;
+    }
+  }
+  const FitHeader fh = *c->h_hdr;
+  std::vector<double> x(c->P);
+  hip_check(hipMemcpy(x.data(), c->f_x.p, sizeof(double) * c->P, hipMemcpyDeviceToHost), "D2H");
+  res->nll = fh.f;
+  res->edm = fh.edm;
+  res->status = public_status(fh.status);
+  res->iters = fh.iter;
+  res->evals = fh.nevals;
+  if (res->theta) std::memcpy(res->theta, x.data(), sizeof(double) * c->P);
+  if (fh.status == FIT_DOMAIN) {
+    c->err = "start point out of the model's domain";
+    return NF_WDOMAIN;
+  }
+  int code = fh.status == FIT_CONVERGED ? NF_OK : NF_WNOCONV;
+  if (code != NF_OK) c->err = fh.status == FIT_MAXITER ? "iteration limit reached" : "line search failed";
+  if (opts && opts->want_cov && res->cov) {
+    std::vector<int> fi;
+    for (int i = 0; i < c->P; ++i)
+      if (fr[i] != 0.0) fi.push_back(i);
+    const int n = (int)fi.size();
+    std::vector<double> Hm((size_t)n * n), th(x), gp(c->P), gm(c->P);
+    double fdum;
+    for (int a = 0; a < n; ++a) {
+      const int j = fi[a];
+      const double hstep = 1e-3 * std::sqrt(d2[j]);
+      th[j] = x[j] + hstep;
+      eval_host(c, th.data(), &fdum, gp.data(), nullptr);
+      th[j] = x[j] - hstep;
+      eval_host(c, th.data(), &fdum, gm.data(), nullptr);
+      th[j] = x[j];
+      for (int b = 0; b < n; ++b) Hm[(size_t)b * n + a] = (gp[fi[b]] - gm[fi[b]]) / (2.0 * hstep);
+    }
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double v = 0.5 * (Hm[(size_t)a * n + b] + Hm[(size_t)b * n + a]);
+        Hm[(size_t)a * n + b] = Hm[(size_t)b * n + a] = v;
+      }
+    std::vector<double> inv;
+    std::fill(res->cov, res->cov + (size_t)c->P * c->P, 0.0);
+    if (spd_inverse(Hm, n, inv)) {
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) res->cov[(size_t)fi[a] * c->P + fi[b]] = inv[(size_t)a * n + b];
+    } else {
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) res->cov[(size_t)fi[a] * c->P + fi[b]] = NAN;
+      c->err = "Hessian at the minimum is not positive definite";
+      if (code == NF_OK) code = NF_WNOCONV;
+    }
+  }
+  return code;
+}
+
+// ---------------------------------------------------------------- batches
+void ensure_batch(nf_ctx* c, int B) {
+  if (B <= c->bt_cap) return;
+  drop_fit_graph(c);
+  const size_t P = c->P, m = c->fit_m, G = std::max(1, c->plan.G), KT = std::max(1, c->plan.KT);
+  const size_t NR = std::max(1, c->plan.NR), NM = MAX_MOM, NI = std::max(1, c->nitems);
+  c->bt_theta.alloc(B * P);
+  c->bt_part.alloc(B * NM * NI);
+  c->bt_out.alloc(B * (1 + P));
+  c->bt_Sseg.alloc(B * G);
+  c->bt_bin.alloc(B * 6 * KT);
+  c->bt_prior.alloc(B * 2 * NR);
+  c->bt_segtmp.alloc(B * 5 * G);
+  c->bt_osc_last.alloc(B * 4);
+  c->bt_status.alloc(B);
+  c->bt_didx.alloc(B);
+  c->bf_hdr.alloc(B);
+  c->bf_x.alloc(B * P); c->bf_g.alloc(B * P); c->bf_p.alloc(B * P); c->bf_d2.alloc(B * P); c->bf_fr.alloc(B * P);
+  c->bf_S.alloc(B * m * P); c->bf_Y.alloc(B * m * P); c->bf_rho.alloc(B * m); c->bf_gam.alloc(B * m);
+  c->bh_hdr.resize(B);
+  c->bt_cap = B;
+}
+
+BatchFoldArgs batch_fold_args(nf_ctx* c, int B, bool fit) {
+  BatchFoldArgs a{};
+  a.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
+  a.w = c->d_w.p;
+  a.items = c->d_items.p;
+  a.nitems = c->nitems;
+  a.P = c->P;
+  a.B = B;
+  a.theta = c->bt_theta.p;
+  a.osc = c->osc;
+  a.part = c->bt_part.p;
+  a.hdr = fit ? c->bf_hdr.p : nullptr;
+  a.osc_last = fit ? c->bt_osc_last.p : nullptr;
+  return a;
+}
+
+BatchTailArgs batch_tail_args(nf_ctx* c, int B, bool fit, bool want_grad, bool use_didx) {
+  BatchTailArgs a{};
+  a.plan = c->plan;
+  a.B = B;
+  a.theta = c->bt_theta.p;
+  a.part = c->bt_part.p;
+  a.data = c->bt_data.p;
+  a.data_idx = use_didx ? c->bt_didx.p : nullptr;
+  a.out = c->bt_out.p;
+  a.status = c->bt_status.p;
+  a.Sseg = c->bt_Sseg.p;
+  a.bin = c->bt_bin.p;
+  a.prior = c->bt_prior.p;
+  a.segtmp = c->bt_segtmp.p;
+  a.osc_last = fit ? c->bt_osc_last.p : nullptr;
+  a.want_grad = want_grad ? 1 : 0;
+  a.has_fit = fit ? 1 : 0;
+  if (fit) {
+    FitArgs f{};
+    f.hdr = c->bf_hdr.p;
+    f.x = c->bf_x.p; f.g = c->bf_g.p; f.p = c->bf_p.p; f.d2 = c->bf_d2.p; f.freem = c->bf_fr.p;
+    f.S = c->bf_S.p; f.Y = c->bf_Y.p; f.rho = c->bf_rho.p; f.gam = c->bf_gam.p;
+    f.theta_next = c->bt_theta.p;
+    f.m = c->fit_m;
+    a.fit = f;
+  }
+  return a;
+}
+
+int batch_threads(nf_ctx* c) { return c->plan.G > 2048 ? 512 : 256; }
+
+void check_didx(nf_ctx* c, int B, const int* didx) {
+  if (c->bt_nsets <= 0) fail(NF_ESTATE, "batch data not set (nf_set_data_batch)");
+  for (int f = 0; f < B; ++f) {
+    const int r = didx ? didx[f] : f;
+    if (r < 0 || r >= c->bt_nsets) fail(NF_EINVAL, "data index out of range for fit " + std::to_string(f));
+  }
+}
+
+int eval_batch_impl(nf_ctx* c, int B, const double* theta, const int* didx, double* nll, double* grad) {
+  require_ready(c, false);
+  if (B <= 0 || !theta || !nll) fail(NF_EINVAL, "B > 0, theta and nll are required");
+  check_didx(c, B, didx);
+  for (int64_t i = 0; i < (int64_t)B * c->P; ++i)
+    if (!std::isfinite(theta[i])) fail(NF_EINVAL, "theta contains a non-finite value");
+  ensure_batch(c, B);
+  hip_check(hipMemcpyAsync(c->bt_theta.p, theta, sizeof(double) * B * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
+  if (didx) hip_check(hipMemcpyAsync(c->bt_didx.p, didx, sizeof(int) * B, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(launch_fold_batch(c->mode, batch_fold_args(c, B, false), c->stream), "batch fold");
+  hip_check(launch_batch_tail(batch_tail_args(c, B, false, grad != nullptr, didx != nullptr), batch_threads(c),
+                              c->stream), "batch tail");
+  std::vector<double> out((size_t)B * (1 + c->P));
+  std::vector<int32_t> st(B);
+  hip_check(hipMemcpyAsync(out.data(), c->bt_out.p, sizeof(double) * out.size(), hipMemcpyDeviceToHost, c->stream), "D2H");
+  hip_check(hipMemcpyAsync(st.data(), c->bt_status.p, sizeof(int32_t) * B, hipMemcpyDeviceToHost, c->stream), "D2H");
+  hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  bool dom = false;
+  for (int f = 0; f < B; ++f) {
+    nll[f] = out[(size_t)f * (1 + c->P)];
+    if (grad) std::memcpy(grad + (size_t)f * c->P, &out[(size_t)f * (1 + c->P) + 1], sizeof(double) * c->P);
+    dom = dom || (st[f] & ST_DOMAIN);
+  }
+  if (dom) {
+    c->err = "some evaluations are out of domain (NLL = +inf)";
+    return NF_WDOMAIN;
+  }
+  return NF_OK;
+}
+
+void ensure_batch_fit_graph(nf_ctx* c, int B) {
+  if (c->bf_graph && c->bf_graph_B == B) return;
+  if (c->bf_graph) (void)hipGraphExecDestroy(c->bf_graph);
+  c->bf_graph = nullptr;
+  hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < FIT_CHUNK && e == hipSuccess; ++i) {
+    e = launch_fold_batch(c->mode, batch_fold_args(c, B, true), c->stream);
+    if (e == hipSuccess)
+      e = launch_batch_tail(batch_tail_args(c, B, true, true, true), batch_threads(c), c->stream);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  hip_check(e, "batch capture launch");
+  hip_check(e2, "hipStreamEndCapture");
+  const hipError_t e3 = hipGraphInstantiate(&c->bf_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e3, "hipGraphInstantiate");
+  c->bf_graph_B = B;
+}
+
+int fit_batch_impl(nf_ctx* c, int B, const double* start, const uint8_t* fixed, const int* didx,
+                   const nf_fit_opts* opts, double* theta_out, double* nll_out, double* edm_out, int* status_out,
+                   int* iters_out, int* evals_out) {
+  require_ready(c, false);
+  if (B <= 0 || !start) fail(NF_EINVAL, "B > 0 and start are required");
+  check_didx(c, B, didx);
+  for (int64_t i = 0; i < (int64_t)B * c->P; ++i)
+    if (!std::isfinite(start[i])) fail(NF_EINVAL, "start contains a non-finite value");
+  const double tol = (opts && opts->edm_tol > 0) ? opts->edm_tol : 1e-7;
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 1000;
+  ensure_batch(c, B);
+  const size_t P = c->P;
+  std::vector<double> d2(B * P), fr(B * P);
+  for (int f = 0; f < B; ++f) {
+    const std::vector<double> d = preconditioner(c, start + (size_t)f * P);
+    std::memcpy(&d2[(size_t)f * P], d.data(), sizeof(double) * P);
+    for (size_t i = 0; i < P; ++i) fr[(size_t)f * P + i] = (fixed ? fixed[i] != 0 : c->fixed_default[i]) ? 0.0 : 1.0;
+  }
+  std::vector<int> rows(B);
+  for (int f = 0; f < B; ++f) rows[f] = didx ? didx[f] : f;
+  FitHeader h{};
+  h.status = FIT_RUNNING;
+  h.max_iter = max_iter;
+  h.edm_tol = tol;
+  h.alpha = 1.0;
+  std::fill(c->bh_hdr.begin(), c->bh_hdr.begin() + B, h);
+  std::vector<double> nanv((size_t)B * 4, NAN);
+  hip_check(hipMemcpyAsync(c->bf_hdr.p, c->bh_hdr.data(), sizeof(FitHeader) * B, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bt_theta.p, start, sizeof(double) * B * P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bf_d2.p, d2.data(), sizeof(double) * B * P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bf_fr.p, fr.data(), sizeof(double) * B * P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bt_osc_last.p, nanv.data(), sizeof(double) * B * 4, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bt_didx.p, rows.data(), sizeof(int) * B, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  ensure_batch_fit_graph(c, B);
+  const int64_t max_evals = (int64_t)max_iter * 50 + 200;
+  for (int64_t launched = 0;; launched += FIT_CHUNK) {
+    hip_check(hipGraphLaunch(c->bf_graph, c->stream), "hipGraphLaunch");
+    hip_check(hipMemcpyAsync(c->bh_hdr.data(), c->bf_hdr.p, sizeof(FitHeader) * B, hipMemcpyDeviceToHost, c->stream), "D2H");
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    int running = 0;
+    for (int f = 0; f < B; ++f) running += c->bh_hdr[f].status == FIT_RUNNING;
+    if (!running) break;
+    if (launched + FIT_CHUNK >= max_evals) {
+      for (int f = 0; f < B; ++f)
+        if (c->bh_hdr[f].status == FIT_RUNNING) c->bh_hdr[f].status = FIT_MAXITER;
+      break;
+    }
+  }
+  if (theta_out)
+    hip_check(hipMemcpy(theta_out, c->bf_x.p, sizeof(double) * B * P, hipMemcpyDeviceToHost), "D2H");
+  bool all_ok = true;
+  for (int f = 0; f < B; ++f) {
+    const FitHeader& fh = c->bh_hdr[f];
+    if (nll_out) nll_out[f] = fh.f;
+    if (edm_out) edm_out[f] = fh.edm;
+    if (status_out) status_out[f] = public_status(fh.status);
+    if (iters_out) iters_out[f] = fh.iter;
+    if (evals_out) evals_out[f] = fh.nevals;
+    all_ok = all_ok && fh.status == FIT_CONVERGED;
+  }
+  if (!all_ok) {
+    c->err = "some fits did not converge (see status)";
+    return NF_WNOCONV;
+  }
+  return NF_OK;
+}
+
 template <typename F>
 int guarded(nf_ctx* c, F&& f) {
   if (!c) return NF_EINVAL;
@@ -861,6 +1267,8 @@ int nf_create(nf_ctx** out, const char* model_json, int mode, void* hip_stream) 
     hip_check(hipGetDevice(&dev), "hipGetDevice");
     int maxlds = 0;
     hip_check(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
+    while (c->plan.fit_m > 4 && tail_lds_bytes(c->plan, 1024) > (size_t)maxlds) c->plan.fit_m -= 2;
+    c->fit_m = c->plan.fit_m;
     const size_t need = tail_lds_bytes(c->plan, 1024);
     if (need > (size_t)maxlds)
       fail(NF_EINVAL, "model too large for one workgroup's LDS (" + std::to_string(need) + " > " +
@@ -981,9 +1389,11 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
     } else if (k == "fold_block") {
       if (value != 64 && value != 128 && value != 256) fail(NF_EINVAL, "fold_block must be 64, 128 or 256");
       ctx->fold_block = (int)value;
+      drop_fit_graph(ctx);
     } else if (k == "tail_threads") {
       if (value != 256 && value != 512 && value != 1024) fail(NF_EINVAL, "tail_threads must be 256, 512 or 1024");
       ctx->tail_threads = (int)value;
+      drop_fit_graph(ctx);
     } else if (k == "timing") {
       ctx->timing = value ? 1 : 0;
       ctx->tcount = 0;
@@ -992,6 +1402,41 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
     }
     return NF_OK;
   });
+}
+
+int nf_set_data_batch(nf_ctx* ctx, int nsets, const double* counts, int on_device) {
+  return guarded(ctx, [&] {
+    if (nsets <= 0 || !counts) fail(NF_EINVAL, "nsets > 0 and counts are required");
+    const size_t n = (size_t)nsets * ctx->nbins_total;
+    std::vector<double> v(n);
+    hip_check(hipMemcpy(v.data(), counts, sizeof(double) * n, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost),
+              "copy counts");
+    for (double x : v)
+      if (!(std::isfinite(x) && x >= 0.0)) fail(NF_EINVAL, "counts must be finite and >= 0");
+    ctx->bt_data.upload(v, ctx->stream);
+    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    ctx->bt_nsets = nsets;
+    drop_fit_graph(ctx);
+    return NF_OK;
+  });
+}
+
+int nf_eval_batch(nf_ctx* ctx, int B, const double* theta, const int* data_idx, double* nll, double* grad) {
+  return guarded(ctx, [&] { return eval_batch_impl(ctx, B, theta, data_idx, nll, grad); });
+}
+
+int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, const int* data_idx,
+                 const nf_fit_opts* opts, double* theta_out, double* nll_out, double* edm_out, int* status_out,
+                 int* iters_out, int* evals_out) {
+  return guarded(ctx, [&] {
+    return fit_batch_impl(ctx, B, start, fixed, data_idx, opts, theta_out, nll_out, edm_out, status_out, iters_out,
+                          evals_out);
+  });
+}
+
+int nf_fit(nf_ctx* ctx, const double* start, const uint8_t* fixed, const nf_fit_opts* opts,
+           nf_fit_result* result) {
+  return guarded(ctx, [&] { return fit_impl(ctx, start, fixed, opts, result); });
 }
 
 int nf_timing(nf_ctx* ctx, int reset, int64_t* count, double* fold_ms, double* tail_ms) {

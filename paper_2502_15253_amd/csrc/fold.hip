@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   if (item >= a.nitems) return;  // whole wavefronts leave together
+  if (a.skip && *a.skip != FIT_RUNNING) return;
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const WorkItem it = a.items[item];
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   if (item >= a.nitems) return;
+  if (a.skip && *a.skip != FIT_RUNNING) return;
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
@@ -178,6 +180,135 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
 #pragma unroll
   for (int c = 0; c < NM; ++c) m[c] = (double)mf[c];
   wave_sum_store<NM>(m, a.part, a.nitems, item, lane);
+}
+
+// ---------------------------------------------------------------- batched
+// One wavefront per (work item, tile of FOLD_FT fits): the events are read
+// once and folded for every active fit of the tile. A fit is skipped when its
+// minimiser has stopped or when its oscillation slot values equal those of
+// its previous fold (its partials are still valid).
+template <int FORM>
+__device__ __forceinline__ bool batch_fit_active(const BatchFoldArgs& a, int f, double& a1, double& a2) {
+  if (f >= a.B) return false;
+  if (a.hdr && a.hdr[f].status != FIT_RUNNING) return false;
+  const double* th = a.theta + (int64_t)f * a.P;
+  if (a.osc_last) {
+    bool same = true;
+    for (int j = 0; j < NSLOT; ++j) same = same && (slot_val(a.osc, th, j) == a.osc_last[4 * f + j]);
+    if (same) return false;
+  }
+  fold_freqs<FORM>(a.osc, th, a1, a2);
+  return true;
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
+  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
+  constexpr int FT = FOLD_FT;
+  const int lane = threadIdx.x & 63;
+  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  if (item >= a.nitems) return;
+  const int f0 = blockIdx.y * FT;
+  double a1[FT], a2[FT];
+  bool act[FT];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < FT; ++j) {
+    a1[j] = a2[j] = 0.0;
+    act[j] = batch_fit_active<FORM>(a, f0 + j, a1[j], a2[j]);
+    any = any || act[j];
+  }
+  if (!any) return;
+  const WorkItem it = a.items[item];
+  const double* __restrict__ u = static_cast<const double*>(a.u) + it.begin;
+  const float* __restrict__ w = a.w + it.begin;
+  double m[FT][NM];
+#pragma unroll
+  for (int j = 0; j < FT; ++j)
+#pragma unroll
+    for (int c = 0; c < NM; ++c) m[j][c] = 0.0;
+  for (int e = lane * 4; e < it.count; e += 256) {
+    const double2 u01 = *reinterpret_cast<const double2*>(u + e);
+    const double2 u23 = *reinterpret_cast<const double2*>(u + e + 2);
+    const float4 w4 = *reinterpret_cast<const float4*>(w + e);
+#pragma unroll
+    for (int j = 0; j < FT; ++j) {
+      if (!act[j]) continue;
+      accum64<FORM>(u01.x, w4.x, a1[j], a2[j], m[j]);
+      accum64<FORM>(u01.y, w4.y, a1[j], a2[j], m[j]);
+      accum64<FORM>(u23.x, w4.z, a1[j], a2[j], m[j]);
+      accum64<FORM>(u23.y, w4.w, a1[j], a2[j], m[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < FT; ++j)
+    if (act[j]) wave_sum_store<NM>(m[j], a.part + (int64_t)(f0 + j) * NM * a.nitems, a.nitems, item, lane);
+}
+
+template <int FORM>
+__global__ __launch_bounds__(256) void fold_batch_m32_kernel(BatchFoldArgs a) {
+  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
+  constexpr int FT = FOLD_FT;
+  constexpr double INV_2PI = 0.15915494309189533577;
+  const int lane = threadIdx.x & 63;
+  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  if (item >= a.nitems) return;
+  const int f0 = blockIdx.y * FT;
+  float bh1[FT], bl1[FT], bh2[FT], bl2[FT];
+  bool act[FT];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < FT; ++j) {
+    double a1 = 0.0, a2 = 0.0;
+    act[j] = batch_fit_active<FORM>(a, f0 + j, a1, a2);
+    any = any || act[j];
+    const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
+    bh1[j] = (float)r1; bl1[j] = (float)(r1 - (double)bh1[j]);
+    bh2[j] = (float)r2; bl2[j] = (float)(r2 - (double)bh2[j]);
+  }
+  if (!any) return;
+  const WorkItem it = a.items[item];
+  const float* __restrict__ u = static_cast<const float*>(a.u) + it.begin;
+  const float* __restrict__ w = a.w + it.begin;
+  float mf[FT][NM];
+#pragma unroll
+  for (int j = 0; j < FT; ++j)
+#pragma unroll
+    for (int c = 0; c < NM; ++c) mf[j][c] = 0.0f;
+  for (int e = lane * 4; e < it.count; e += 256) {
+    const float4 u4 = *reinterpret_cast<const float4*>(u + e);
+    const float4 w4 = *reinterpret_cast<const float4*>(w + e);
+#pragma unroll
+    for (int j = 0; j < FT; ++j) {
+      if (!act[j]) continue;
+      accum32<FORM>(u4.x, w4.x, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
+      accum32<FORM>(u4.y, w4.y, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
+      accum32<FORM>(u4.z, w4.z, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
+      accum32<FORM>(u4.w, w4.w, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < FT; ++j) {
+    if (!act[j]) continue;
+    double m[NM];
+#pragma unroll
+    for (int c = 0; c < NM; ++c) m[c] = (double)mf[j][c];
+    wave_sum_store<NM>(m, a.part + (int64_t)(f0 + j) * NM * a.nitems, a.nitems, item, lane);
+  }
+}
+
+hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream) {
+  if (a.nitems <= 0 || a.B <= 0) return hipSuccess;
+  const dim3 grid((a.nitems + 3) / 4, (a.B + FOLD_FT - 1) / FOLD_FT);
+  const dim3 block(256);
+  if (mode == 0) {
+    if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL(fold_batch_m64_kernel<FORM_EQ1>, grid, block, 0, stream, a);
+    else hipLaunchKernelGGL(fold_batch_m64_kernel<FORM_3NU>, grid, block, 0, stream, a);
+  } else {
+    if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL(fold_batch_m32_kernel<FORM_EQ1>, grid, block, 0, stream, a);
+    else hipLaunchKernelGGL(fold_batch_m32_kernel<FORM_3NU>, grid, block, 0, stream, a);
+  }
+  return hipGetLastError();
 }
 
 // Host-side launcher (same translation unit as the kernels).

@@ -8,6 +8,35 @@
 
 namespace nufold {
 
+// Minimiser state of one fit (device memory).
+constexpr int FIT_RUNNING = 0, FIT_CONVERGED = 1, FIT_MAXITER = 2, FIT_LSFAIL = 3, FIT_DOMAIN = 4;
+struct FitHeader {
+  int status, phase, iter, nevals, ls_steps, hist_n, hist_head, resets, max_iter, pad_;
+  double f, edm, alpha, dphi0;
+  double a_prev, f_prev, d_prev;
+  double a_lo, f_lo, d_lo, a_hi, f_hi, d_hi;
+  double edm_tol;
+  double df;        // decrease of f in the last accepted step
+};
+struct FitArgs {
+  FitHeader* hdr;
+  double* x;           // accepted point [P]
+  double* g;           // masked gradient at x [P]
+  double* p;           // search direction [P]
+  const double* d2;    // diagonal preconditioner D [P]
+  const double* freem; // 1 free, 0 fixed [P]
+  double* S;           // history s [m][P]
+  double* Y;           // history y [m][P]
+  double* rho;         // 1 / s^T y [m]
+  double* gam;         // s^T y / y^T D y [m]
+  double* theta_next;  // the evaluation input buffer, written with the next trial point
+  int m;
+};
+// LDS doubles used by the minimiser step (matches lbfgs_step's carve).
+__host__ __device__ inline size_t fit_lds_doubles(int P, int m) {
+  return 2 * (size_t)m * P + 7 * (size_t)P + 3 * (size_t)m + 16;
+}
+
 struct FoldArgs {
   const void* u;        // double (M64) or float (M32), padded, sorted
   const float* w;       // f32 weights (0 for padding)
@@ -16,6 +45,35 @@ struct FoldArgs {
   const double* theta;  // device parameter vector
   OscPlan osc;
   double* part;         // [num_moments][nitems]
+  const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
+};
+
+// Batched fold: FT fits per wavefront, each event read once per tile.
+constexpr int FOLD_FT = 4;
+struct BatchFoldArgs {
+  const void* u;
+  const float* w;
+  const WorkItem* items;
+  int nitems;
+  int P, B;
+  const double* theta;     // [B][P] trial points
+  OscPlan osc;
+  double* part;            // [B][NM][nitems]
+  const FitHeader* hdr;    // [B] nullable: fits that are not RUNNING are skipped
+  const double* osc_last;  // [B][4] nullable: fits whose slot values equal these are skipped
+};
+
+// Pointers of one evaluation (the single evaluation, or one fit of a batch).
+struct EvalIO {
+  const double* theta;  // P trial point
+  const double* part;   // [NM][nitems] fold partials of this evaluation
+  const double* data;   // concatenated observed counts
+  double* out;          // 1 + P: NLL, gradient (nullable)
+  int32_t* status;      // nullable
+  double* mu_out;       // nullable
+  double* Sseg;         // G
+  double* bin;          // 6 KT
+  double* prior;        // 2 NR
 };
 
 struct TailArgs {
@@ -32,6 +90,28 @@ struct TailArgs {
   int* counter;         // workgroup completion counter (0 between launches)
   int want_grad;
   int want_nll;         // 0: only mu_out (no data needed)
+  int has_fit;          // run the minimiser step after the evaluation
+  FitArgs fit;
+  const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
+};
+
+struct BatchTailArgs {
+  DevPlan plan;
+  int B;
+  const double* theta;    // [B][P] trial points
+  const double* part;     // [B][NM][nitems]
+  const double* data;     // [nsets][nbins_total]
+  const int* data_idx;    // [B] data row of each fit (nullable: row f)
+  double* out;            // [B][1+P] (nullable)
+  int32_t* status;        // [B] (nullable)
+  double* Sseg;           // [B][G]
+  double* bin;            // [B][6 KT]
+  double* prior;          // [B][2 NR]
+  double* segtmp;         // [B][5 G] in-block phase A scratch
+  double* osc_last;       // [B][4] (nullable): slot values of each fit's last fold
+  int want_grad;
+  int has_fit;
+  FitArgs fit;            // base pointers; fit f uses hdr + f, vectors + f P, history + f m P
 };
 
 constexpr int ST_DOMAIN = 1;
@@ -43,12 +123,14 @@ __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
   const size_t nd = 2 * (size_t)p.P + 40 + 16 * (nt / 64) + 16 + 6 * K + (size_t)p.max_S * K + Nb +
                     4 * (K + 1) + K + 3 * E + Nb + p.max_blob;
   const size_t ni = E + 2;
-  return nd * sizeof(double) + ni * sizeof(int);
+  return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }
 
 int tail_blocks(const DevPlan& p, int nt);
 hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream);
+hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream);
 hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream);
 hipError_t tail_set_lds_limit(size_t bytes);
+hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream);
 
 }  // namespace nufold

@@ -106,6 +106,7 @@ struct DevPlan {
   int kt_ds;             // ipool: KT dataset index of each global fine bin
   int fs_ptr;            // ipool: 2 FS, [begin, end) absolute ipool offsets of each source's norm list
   int max_blob;          // largest static blob
+  int fit_m;             // minimiser history length (LDS is reserved for it)
   int kt_info;           // ipool: 5 KT: first segment, stride K, sources S, first flat source, kt0
   int fs_nl;             // ipool: NLMAX FS norm-list parameter indices per flat source (-1 padded)
   int kt_row;            // ipool: KT + 1 flux-basis row pointers per global fine bin (relative)

@@ -70,6 +70,7 @@ struct Lds {
   double* eH;     // E    e_dhi
   double* mu;     // Nb   lambda_mu
   double* st;     // static blob of the current dataset (edges become X, then lambda_X)
+  double* fit;    // minimiser scratch
   int* kidx;      // E
   int* flag;      // 2
 };
@@ -94,6 +95,7 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.eH = q; q += E;
   L.mu = q; q += Nb;
   L.st = q; q += p.max_blob;
+  L.fit = q; q += fit_lds_doubles(p.P, p.fit_m);
   int* r = reinterpret_cast<int*>(q);
   L.kidx = r; r += E;
   L.flag = r;
@@ -270,13 +272,15 @@ __device__ bool osc_coefficients(const OscPlan& o, const double* th, double* cf)
   return ok;
 }
 
+}  // namespace nufold
+#include "minimize.hpp"
+namespace nufold {
+
 // ---------------------------------------------------------------- phase A
 // Wavefront w < KT: global fine bin w. Wavefront KT + r: prior rows 64 r .. 64 r + 63.
 template <int NT>
-__device__ void phase_a(const TailArgs& a, const Lds<NT>& L) {
-  const DevPlan& p = a.plan;
+__device__ void phase_a(const DevPlan& p, const EvalIO& io, const Lds<NT>& L, int w) {
   const int lane = threadIdx.x & 63;
-  const int w = (int)((blockIdx.x * NT + threadIdx.x) >> 6);
   const int NMOM = num_moments(p.osc.formula);
   if (w < p.KT) {
     const int* info = p.ipool + p.kt_info + 5 * w;
@@ -290,7 +294,7 @@ __device__ void phase_a(const TailArgs& a, const Lds<NT>& L) {
       for (int c = 1; c <= MAX_MOM; ++c) M[c] = 0.0;
       const int ib = p.seg_item[g], ie = p.seg_item[g + 1];
       for (int it = ib; it < ie; ++it)
-        for (int c = 0; c < NMOM; ++c) M[1 + c] += a.part[(int64_t)c * p.nitems + it];
+        for (int c = 0; c < NMOM; ++c) M[1 + c] += io.part[(int64_t)c * p.nitems + it];
       const int* nl = p.ipool + p.fs_nl + NLMAX * (fs0 + s);
       double A = 1.0;
 #pragma unroll
@@ -298,7 +302,7 @@ __device__ void phase_a(const TailArgs& a, const Lds<NT>& L) {
         if (nl[q] >= 0) A *= L.th[nl[q]];
       double Sv = 0.0;
       for (int c = 0; c <= NMOM; ++c) Sv += L.coef[c] * M[c];
-      store_agent(&a.Sseg[g], Sv);
+      store_agent(&io.Sseg[g], Sv);
       hs += A * Sv;
       for (int j = 0; j < 4; ++j) {
         double gj = 0.0;
@@ -314,7 +318,7 @@ __device__ void phase_a(const TailArgs& a, const Lds<NT>& L) {
     for (int j = 0; j < 4; ++j) gsum[j] = wave_sum(gsum[j]);
     F = wave_sum(F);
     if (lane == 0) {
-      double* b = a.bin + 6 * (int64_t)kt0;
+      double* b = io.bin + 6 * (int64_t)kt0;
       store_agent(&b[k], hs);
       for (int j = 0; j < 4; ++j) store_agent(&b[(1 + j) * K + k], gsum[j]);
       store_agent(&b[5 * K + k], 1.0 + F);
@@ -338,42 +342,17 @@ __device__ void phase_a(const TailArgs& a, const Lds<NT>& L) {
           v += Vi[c] * (L.th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
         e = 0.5 * (L.th[p.ipool[p.blk_idx + b + row]] - p.dpool[p.blk_mean + b + row]) * v;
       }
-      store_agent(&a.prior[r], v);
-      store_agent(&a.prior[p.NR + r], e);
+      store_agent(&io.prior[r], v);
+      store_agent(&io.prior[p.NR + r], e);
     }
   }
 }
 
+// Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
+// NLL (+inf when out of domain) to every thread; the gradient is in L.grad.
 template <int NT>
-__global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
-  extern __shared__ double smem[];
-  const DevPlan& p = a.plan;
-  Lds<NT> L = carve<NT>(smem, p);
+__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int want_nll, int want_grad) {
   const int tid = threadIdx.x;
-
-  for (int i = tid; i < p.P; i += NT) {
-    L.th[i] = a.theta[i];
-    L.grad[i] = 0.0;
-  }
-  if (tid == 0) {
-    L.flag[0] = 0;
-    bool ok = osc_coefficients(p.osc, L.th, L.coef);
-    if (!ok) L.flag[0] |= ST_DOMAIN;
-  }
-  __syncthreads();
-  phase_a<NT>(a, L);
-
-  // ---- hand-off: our write-through stores are complete before we count
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (tid == 0) {
-    const int done = __hip_atomic_fetch_add(a.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    L.flag[1] = (done == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!L.flag[1]) return;
-  if (tid == 0) __hip_atomic_store(a.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
   for (int i = tid; i < p.P; i += NT)
     if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
 
@@ -398,10 +377,10 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
     // ---- stage: static blob (plain loads), phase-A results and data
     stage<NT, 8>(L.st, p.dpool + ds.blob, ds.blob_n);
     {
-      const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (a.want_nll ? Nb : 0);
-      const double* b = a.bin + 6 * (int64_t)ds.kt0;
-      const double* sg = a.Sseg + ds.seg0;
-      const double* dt = a.data + ds.data;
+      const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
+      const double* b = io.bin + 6 * (int64_t)ds.kt0;
+      const double* sg = io.Sseg + ds.seg0;
+      const double* dt = io.data + ds.data;
       constexpr int U = 8;
       for (int base = 0; base < n3; base += NT * U) {
         double v[U];
@@ -481,14 +460,14 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
         B += bsc[b] * pval(L.th, (int)brt[b], 1.0) * tmpl[b * Nb + i] * (1.0 + beta);
       }
       const double mu = (X[i + 1] - X[i]) + B;
-      if (a.mu_out) a.mu_out[ds.bins0 + i] = mu;
+      if (io.mu_out) io.mu_out[ds.bins0 + i] = mu;
       double lam = 0.0;
-      if (a.want_nll) {
+      if (want_nll) {
         const double n = L.nD[i];
         if (!(mu > 0.0)) atomicOr(&L.flag[0], ST_DOMAIN);
         acc[0] += (n > 0.0) ? (mu - n + n * log(n / mu)) : mu;
         lam = 1.0 - n / mu;
-        if (a.want_grad) {
+        if (want_grad) {
           for (int b = 0; b < NB; ++b) {
             const int sp = (int)shp[b * Nb + i];
             const double stv = bsc[b] * tmpl[b * Nb + i];
@@ -501,7 +480,7 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
     }
     block_sum<NT, 1 + MAX_BKG>(acc, L.red);
     nll_total += acc[0];
-    if (!a.want_grad) {
+    if (!want_grad) {
       __syncthreads();
       continue;
     }
@@ -647,10 +626,10 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   {
     double pr[1] = {0.0};
     for (int r = tid; r < p.NR; r += NT) {
-      pr[0] += load_agent(&a.prior[p.NR + r]);
-      if (a.want_grad) {
+      pr[0] += load_agent(&io.prior[p.NR + r]);
+      if (want_grad) {
         const int i = r < p.ngauss ? p.ipool[p.gidx + r] : p.ipool[p.blk_idx + (r - p.ngauss)];
-        atomicAdd(&L.grad[i], load_agent(&a.prior[r]));
+        atomicAdd(&L.grad[i], load_agent(&io.prior[r]));
       }
     }
     block_sum<NT, 1>(pr, L.red);
@@ -659,10 +638,188 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   __syncthreads();
 
   const bool bad = (L.flag[0] & ST_DOMAIN) || !isfinite(nll_total);
-  if (a.want_nll && tid == 0) a.out[0] = bad ? INFINITY : nll_total;
-  if (a.want_grad && a.want_nll)
-    for (int i = tid; i < p.P; i += NT) a.out[1 + i] = bad ? 0.0 : L.grad[i];
-  if (a.status && tid == 0) *a.status = bad ? ST_DOMAIN : 0;
+  if (io.out && want_nll && tid == 0) io.out[0] = bad ? INFINITY : nll_total;
+  if (io.out && want_grad && want_nll)
+    for (int i = tid; i < p.P; i += NT) io.out[1 + i] = bad ? 0.0 : L.grad[i];
+  if (io.status && tid == 0) *io.status = bad ? ST_DOMAIN : 0;
+  return bad ? INFINITY : nll_total;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
+  extern __shared__ double smem[];
+  if (a.skip && *a.skip != FIT_RUNNING) return;
+  const DevPlan& p = a.plan;
+  Lds<NT> L = carve<NT>(smem, p);
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < p.P; i += NT) {
+    L.th[i] = a.theta[i];
+    L.grad[i] = 0.0;
+  }
+  if (tid == 0) {
+    L.flag[0] = 0;
+    bool ok = osc_coefficients(p.osc, L.th, L.coef);
+    if (!ok) L.flag[0] |= ST_DOMAIN;
+  }
+  __syncthreads();
+  const EvalIO io{a.theta, a.part, a.data, a.out, a.status, a.mu_out, a.Sseg, a.bin, a.prior};
+  phase_a<NT>(p, io, L, (int)((blockIdx.x * NT + threadIdx.x) >> 6));
+
+  // ---- hand-off: our write-through stores are complete before we count
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    const int done = __hip_atomic_fetch_add(a.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    L.flag[1] = (done == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!L.flag[1]) return;
+  if (tid == 0) __hip_atomic_store(a.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  const double f = serial_stages<NT>(p, io, L, a.want_nll, a.want_grad);
+  if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
+}
+
+// ---------------------------------------------------------------- batched
+// One workgroup per fit: phase A inside the workgroup (thread per segment,
+// then per fine bin), the same serial stages, then the fit's minimiser step.
+__device__ inline FitArgs fit_of(const FitArgs& F, int f, int P) {
+  FitArgs r = F;
+  const int64_t o = (int64_t)f * P, oh = (int64_t)f * F.m * P, om = (int64_t)f * F.m;
+  r.hdr = F.hdr + f;
+  r.x = F.x + o;
+  r.g = F.g + o;
+  r.p = F.p + o;
+  r.d2 = F.d2 + o;
+  r.freem = F.freem + o;
+  r.S = F.S + oh;
+  r.Y = F.Y + oh;
+  r.rho = F.rho + om;
+  r.gam = F.gam + om;
+  r.theta_next = F.theta_next + o;
+  return r;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
+  extern __shared__ double smem[];
+  const int f = blockIdx.x;
+  if (f >= a.B) return;
+  if (a.has_fit && a.fit.hdr[f].status != FIT_RUNNING) return;
+  const DevPlan& p = a.plan;
+  Lds<NT> L = carve<NT>(smem, p);
+  const int tid = threadIdx.x;
+  const int P = p.P, G = p.G, KT = p.KT, NR = p.NR;
+  const int NMOM = num_moments(p.osc.formula);
+  const double* th = a.theta + (int64_t)f * P;
+  for (int i = tid; i < P; i += NT) {
+    L.th[i] = th[i];
+    L.grad[i] = 0.0;
+  }
+  if (tid == 0) {
+    L.flag[0] = 0;
+    if (!osc_coefficients(p.osc, L.th, L.coef)) L.flag[0] |= ST_DOMAIN;
+  }
+  __syncthreads();
+  const int drow = a.data_idx ? a.data_idx[f] : f;
+  const EvalIO io{th,
+                  a.part + (int64_t)f * NMOM * p.nitems,
+                  a.data + (int64_t)drow * p.nbins_total,
+                  a.out ? a.out + (int64_t)f * (1 + P) : nullptr,
+                  a.status ? a.status + f : nullptr,
+                  nullptr,
+                  a.Sseg + (int64_t)f * G,
+                  a.bin + (int64_t)f * 6 * KT,
+                  a.prior + (int64_t)f * 2 * NR};
+  double* tmp = a.segtmp + (int64_t)f * 5 * G;
+  // phase A, per segment
+  for (int g = tid; g < G; g += NT) {
+    double M[MAX_MOM + 1];
+    M[0] = p.Wseg[g];
+    for (int c = 1; c <= MAX_MOM; ++c) M[c] = 0.0;
+    const int ib = p.seg_item[g], ie = p.seg_item[g + 1];
+    for (int it = ib; it < ie; ++it)
+      for (int c = 0; c < NMOM; ++c) M[1 + c] += io.part[(int64_t)c * p.nitems + it];
+    const int* nl = p.ipool + p.fs_nl + NLMAX * p.ipool[p.seg_fs + g];
+    double A = 1.0;
+#pragma unroll
+    for (int q = 0; q < NLMAX; ++q)
+      if (nl[q] >= 0) A *= L.th[nl[q]];
+    double Sv = 0.0;
+    for (int c = 0; c <= NMOM; ++c) Sv += L.coef[c] * M[c];
+    store_agent(&io.Sseg[g], Sv);
+    tmp[g] = A * Sv;
+    for (int j = 0; j < 4; ++j) {
+      double gj = 0.0;
+      for (int c = 0; c <= NMOM; ++c) gj += L.coef[8 * (j + 1) + c] * M[c];
+      tmp[(int64_t)(1 + j) * G + g] = A * gj;
+    }
+  }
+  // prior rows
+  for (int r = tid; r < NR; r += NT) {
+    double v, e;
+    if (r < p.ngauss) {
+      const double z = L.th[p.ipool[p.gidx + r]] - p.dpool[p.gmean + r];
+      v = z * p.dpool[p.ginv + r];
+      e = 0.5 * z * v;
+    } else {
+      const int bl = p.ipool[p.prow_blk + r - p.ngauss];
+      const int b = p.ipool[p.blk_ptr + bl], n = p.ipool[p.blk_ptr + bl + 1] - b;
+      const int row = r - p.ngauss - b;
+      const double* Vi = p.dpool + p.ipool[p.blk_inv + bl] + (int64_t)row * n;
+      v = 0.0;
+      for (int c = 0; c < n; ++c)
+        v += Vi[c] * (L.th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
+      e = 0.5 * (L.th[p.ipool[p.blk_idx + b + row]] - p.dpool[p.blk_mean + b + row]) * v;
+    }
+    store_agent(&io.prior[r], v);
+    store_agent(&io.prior[NR + r], e);
+  }
+  __syncthreads();
+  // per fine bin: sum over sources, flux factor
+  for (int kt = tid; kt < KT; kt += NT) {
+    const int* info = p.ipool + p.kt_info + 5 * kt;
+    const int g0 = info[0], K = info[1], S = info[2], kt0 = info[4];
+    const int k = kt - kt0;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < S; ++s)
+      for (int j = 0; j < 5; ++j) v[j] += tmp[(int64_t)j * G + g0 + s * K];
+    double F = 0.0;
+    const int rb = p.ipool[p.kt_row + kt], re = p.ipool[p.kt_row + kt + 1];
+    for (int e = rb; e < re; ++e) F += L.th[p.ipool[p.kt_par + e]] * p.dpool[p.kt_coef + e];
+    double* bb = io.bin + 6 * (int64_t)kt0;
+    for (int j = 0; j < 5; ++j) store_agent(&bb[j * K + k], v[j]);
+    store_agent(&bb[5 * K + k], 1.0 + F);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const double fval = serial_stages<NT>(p, io, L, 1, a.want_grad);
+  if (a.has_fit) {
+    if (a.osc_last && tid < NSLOT) {
+      const int q = p.osc.slot_param[tid];
+      a.osc_last[4 * f + tid] = q >= 0 ? L.th[q] : p.osc.slot_value[tid];
+    }
+    lbfgs_step<NT>(fit_of(a.fit, f, P), P, L.th, fval, L.grad, L.fit, L.red);
+  }
+}
+
+hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream) {
+  if (a.B <= 0) return hipSuccess;
+  const size_t lds = tail_lds_bytes(a.plan, nt);
+  const dim3 grid(a.B);
+  switch (nt) {
+    case 256:
+      hipLaunchKernelGGL(batch_tail_kernel<256>, grid, dim3(256), lds, stream, a);
+      break;
+    case 512:
+      hipLaunchKernelGGL(batch_tail_kernel<512>, grid, dim3(512), lds, stream, a);
+      break;
+    default:
+      hipLaunchKernelGGL(batch_tail_kernel<1024>, grid, dim3(1024), lds, stream, a);
+      break;
+  }
+  return hipGetLastError();
 }
 
 int tail_blocks(const DevPlan& p, int nt) {
@@ -695,7 +852,16 @@ hipError_t tail_set_lds_limit(size_t bytes) {
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<512>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<1024>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel<1024>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(batch_tail_kernel<256>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(batch_tail_kernel<512>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(batch_tail_kernel<1024>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

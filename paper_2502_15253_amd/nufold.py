@@ -45,6 +45,22 @@ SIGNATURES = {
     "nf_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp, _dp]),
 }
 
+class FitOpts(C.Structure):
+    _fields_ = [("edm_tol", C.c_double), ("max_iter", C.c_int), ("want_cov", C.c_int)]
+
+
+class FitResult(C.Structure):
+    _fields_ = [("nll", C.c_double), ("edm", C.c_double), ("status", C.c_int), ("iters", C.c_int),
+                ("evals", C.c_int), ("pad_", C.c_int), ("theta", C.c_void_p), ("cov", C.c_void_p)]
+
+
+SIGNATURES["nf_fit"] = (C.c_int, [C.c_void_p, _dp, C.c_void_p, C.POINTER(FitOpts), C.POINTER(FitResult)])
+SIGNATURES["nf_set_data_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int])
+SIGNATURES["nf_eval_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+SIGNATURES["nf_fit_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.POINTER(FitOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p])
+
 _lib = None
 
 
@@ -186,6 +202,58 @@ class Engine:
         return _check(self.ctx, load().nf_eval_device(self.ctx, C.c_void_p(theta_ptr), C.c_void_p(out_ptr),
                                                       C.c_void_p(status_ptr) if status_ptr else None,
                                                       1 if want_grad else 0))
+
+    def fit(self, start, fixed=None, edm_tol=1e-7, max_iter=1000, want_cov=False):
+        """Device L-BFGS fit from `start`; returns a dict (theta, nll, edm, status, iters,
+        evals, cov, code)."""
+        st = np.ascontiguousarray(start, dtype=np.float64)
+        th = np.zeros(self.P)
+        cov = np.zeros((self.P, self.P)) if want_cov else None
+        fx = None
+        if fixed is not None:
+            fx = np.ascontiguousarray(np.asarray(fixed, dtype=bool).astype(np.uint8))
+        opts = FitOpts(edm_tol, max_iter, 1 if want_cov else 0)
+        res = FitResult()
+        res.theta = th.ctypes.data
+        res.cov = cov.ctypes.data if cov is not None else None
+        code = _check(self.ctx, load().nf_fit(self.ctx, st.ctypes.data_as(_dp),
+                                              fx.ctypes.data if fx is not None else None,
+                                              C.byref(opts), C.byref(res)))
+        return dict(theta=th, nll=res.nll, edm=res.edm, status=res.status, iters=res.iters,
+                    evals=res.evals, cov=cov, code=code)
+
+    def set_data_batch(self, counts):
+        """counts: nsets x (sum of analysis bins) observed counts."""
+        c = np.ascontiguousarray(counts, dtype=np.float64)
+        if c.ndim != 2 or c.shape[1] != sum(self.nbins):
+            raise ValueError("counts must be nsets x total bins")
+        return _check(self.ctx, load().nf_set_data_batch(self.ctx, c.shape[0], c.ctypes.data, 0))
+
+    def eval_batch(self, theta, data_idx=None, want_grad=True):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        B = th.shape[0]
+        nll = np.zeros(B)
+        g = np.zeros((B, self.P)) if want_grad else None
+        di = None if data_idx is None else np.ascontiguousarray(data_idx, dtype=np.int32)
+        code = _check(self.ctx, load().nf_eval_batch(self.ctx, B, th.ctypes.data,
+                                                     di.ctypes.data if di is not None else None,
+                                                     nll.ctypes.data, g.ctypes.data if g is not None else None))
+        return nll, g, code
+
+    def fit_batch(self, start, fixed=None, data_idx=None, edm_tol=1e-7, max_iter=1000):
+        st = np.ascontiguousarray(start, dtype=np.float64)
+        B = st.shape[0]
+        th = np.zeros((B, self.P))
+        nll, edm = np.zeros(B), np.zeros(B)
+        status, iters, evals = (np.zeros(B, dtype=np.int32) for _ in range(3))
+        fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=bool).astype(np.uint8))
+        di = None if data_idx is None else np.ascontiguousarray(data_idx, dtype=np.int32)
+        opts = FitOpts(edm_tol, max_iter, 0)
+        code = _check(self.ctx, load().nf_fit_batch(
+            self.ctx, B, st.ctypes.data, fx.ctypes.data if fx is not None else None,
+            di.ctypes.data if di is not None else None, C.byref(opts), th.ctypes.data, nll.ctypes.data,
+            edm.ctypes.data, status.ctypes.data, iters.ctypes.data, evals.ctypes.data))
+        return dict(theta=th, nll=nll, edm=edm, status=status, iters=iters, evals=evals, code=code)
 
     def timing(self, reset=True):
         """(evaluations, summed fold ms, summed bin-stage ms) since the last reset."""

@@ -1,0 +1,155 @@
+"""Batched evaluations and fits (nf_eval_batch, nf_fit_batch) against the oracle
+and against the single-fit path."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.model import Model
+from oracle import likelihood as LK
+from paper_2502_15253_amd import nufold as nf
+from paper_2502_15253_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = {"m64": 1e-9, "m32": 1e-5}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def engine(desc, events, mode="m64"):
+    eng = nf.Engine(desc, mode)
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+    return eng
+
+
+def displaced(desc, rng, frac=0.3):
+    th = synth.start_vector(desc).copy()
+    for i, p in enumerate(desc["params"]):
+        s = p["prior"][1] if p["prior"] else max(abs(p["start"]) * 0.01, 1e-3)
+        th[i] += frac * s * rng.standard_normal()
+    return th
+
+
+def pseudo_data(desc, events, n, seed0=3000):
+    m = Model(desc)
+    mus = LK.expected(m, events, synth.start_vector(desc))[0]
+    rows = []
+    for j in range(n):
+        rows.append(np.concatenate(synth.poisson_data(mus, seed0 + j)))
+    return np.array(rows)
+
+
+def split(desc, row):
+    out, o = [], 0
+    for ds in desc["datasets"]:
+        nb = len(ds["edges"]) - 1
+        out.append(row[o:o + nb])
+        o += nb
+    return out
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+@pytest.mark.parametrize("config,B,nev", [(1, 37, None), (2, 9, 200_000), (3, 5, 1_000_000)])
+def test_eval_batch_matches_oracle(mode, config, B, nev):
+    say("eval_batch", mode, config, B)
+    desc, events = synth.model_and_events(config, nev)
+    m = Model(desc)
+    rng = np.random.default_rng(10 + config)
+    data = pseudo_data(desc, events, 4)
+    eng = engine(desc, events, mode)
+    eng.set_data_batch(data)
+    thetas = np.array([displaced(desc, rng) for _ in range(B)])
+    didx = rng.integers(0, 4, B).astype(np.int32)
+    nll, grad, code = eng.eval_batch(thetas, didx)
+    assert code == nf.NF_OK
+    tol = TOL[mode]
+    folds = None
+    for f in range(B):
+        dat = split(desc, data[didx[f]])
+        f_o, g_o = LK.nll_grad(m, events, dat, thetas[f])
+        assert abs(nll[f] - f_o) <= tol * max(1.0, abs(f_o)), (f, nll[f], f_o)
+        assert np.max(np.abs(grad[f] - g_o)) <= tol * max(1.0, np.max(np.abs(g_o))), f
+        if config == 3 and f >= 1:
+            break  # the oracle gradient at 1e6 events is slow; two fits suffice
+
+
+def test_eval_batch_agrees_with_single_evaluation_path():
+    say("eval_batch vs single")
+    desc, events = synth.model_and_events(1)
+    rng = np.random.default_rng(5)
+    data = pseudo_data(desc, events, 3)
+    eng = engine(desc, events)
+    eng.set_data_batch(data)
+    thetas = np.array([displaced(desc, rng) for _ in range(6)])
+    nll, grad, _ = eng.eval_batch(thetas, np.array([0, 1, 2, 0, 1, 2], np.int32))
+    for f in range(6):
+        for d, dat in enumerate(split(desc, data[f % 3])):
+            eng.set_data(d, dat)
+        f1, g1, _ = eng.eval_nll_grad(thetas[f])
+        assert abs(f1 - nll[f]) <= 1e-12 * max(1, abs(f1))
+        assert np.max(np.abs(g1 - grad[f])) <= 1e-12 * max(1, np.max(np.abs(g1)))
+
+
+def test_fit_batch_pseudo_experiments_match_single_fits():
+    say("fit_batch c1 pseudo-experiments")
+    desc, events = synth.model_and_events(1)
+    B = 24
+    data = pseudo_data(desc, events, B)
+    eng = engine(desc, events)
+    eng.set_data_batch(data)
+    start = np.tile(synth.start_vector(desc), (B, 1))
+    rb = eng.fit_batch(start, edm_tol=1e-9)
+    assert rb["code"] == nf.NF_OK, rb["status"]
+    for f in range(0, B, 5):
+        for d, dat in enumerate(split(desc, data[f])):
+            eng.set_data(d, dat)
+        r1 = eng.fit(start[f], edm_tol=1e-9)
+        assert r1["status"] == 0
+        # best-fit Delta chi^2 = 2 dNLL agrees far below 1e-3
+        assert abs(rb["nll"][f] - r1["nll"]) < 1e-6, (f, rb["nll"][f], r1["nll"])
+
+
+def test_fit_batch_scan_points_fold_once_and_match_single_fits():
+    say("fit_batch scan")
+    desc, events = synth.model_and_events(1)
+    m = Model(desc)
+    data = pseudo_data(desc, events, 1, seed0=synth.data_seed(1))
+    eng = engine(desc, events)
+    eng.set_data_batch(data)
+    i13, iee = m.index["osc.sin2_2t13"], m.index["osc.dm2_ee"]
+    grid = [(s, d) for s in np.linspace(0.0, 0.2, 4) for d in np.linspace(1.5, 3.5, 4)]
+    start = np.tile(synth.start_vector(desc), (len(grid), 1))
+    start[:, i13] = [g[0] for g in grid]
+    start[:, iee] = [g[1] for g in grid]
+    fixed = m.fixed.copy()
+    fixed[[i13, iee]] = True
+    rb = eng.fit_batch(start, fixed=fixed, data_idx=np.zeros(len(grid), np.int32), edm_tol=1e-9)
+    assert rb["code"] == nf.NF_OK, rb["status"]
+    assert np.all(rb["theta"][:, i13] == start[:, i13])
+    for d, dat in enumerate(split(desc, data[0])):
+        eng.set_data(d, dat)
+    for f in (0, 5, 10, 15):
+        r1 = eng.fit(start[f], fixed=fixed, edm_tol=1e-9)
+        assert abs(rb["nll"][f] - r1["nll"]) < 1e-6
+
+
+def test_fit_batch_config2_pseudo_experiments_converge():
+    say("fit_batch c2")
+    desc, events = synth.model_and_events(2, 300_000)
+    m = Model(desc)
+    B = 8
+    data = pseudo_data(desc, events, B)
+    eng = engine(desc, events)
+    eng.set_data_batch(data)
+    start = np.tile(synth.start_vector(desc), (B, 1))
+    rb = eng.fit_batch(start, edm_tol=1e-8, max_iter=3000)
+    assert np.all(rb["status"] == 0), rb["status"]
+    f = 3
+    f_o, g_o = LK.nll_grad(m, events, split(desc, data[f]), rb["theta"][f])
+    assert abs(f_o - rb["nll"][f]) < 1e-9 * max(1, f_o)
+    scale = np.array([p["prior"][1] if p["prior"] else 0.01 for p in desc["params"]])
+    assert np.max(np.abs(g_o * scale)) < 5e-3
