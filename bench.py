@@ -71,6 +71,20 @@ def cpu_baseline(desc, events, theta):
                        f"numpy FP64, single thread, {dt:.1f} s")
 
 
+COPY_BYTES = 512 << 20
+
+
+def copy_probe(torch, reps=8):
+    """Plain device-to-device copies of COPY_BYTES each: the reference that
+    scales the memory counters of a profiled run to bytes."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: {reps} copies of {COPY_BYTES} B")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +94,10 @@ def main():
     ap.add_argument("--events", type=float, default=1e7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--both-modes", action="store_true", help="also measure the other precision mode")
+    ap.add_argument("--replicas", type=int, default=6,
+                    help="event-set replicas cycled for the cold (HBM) figure; 0 skips it")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a device copy of known size (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the event fold shards over "
@@ -92,6 +110,9 @@ def main():
     from paper_2502_15253_amd import synth
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     stream = torch.cuda.current_stream()
     n_events = int(args.events)
     log(f"generating {n_events:.0e} events")
@@ -147,7 +168,49 @@ def main():
         log(f"{mode}: {json.dumps(res)}")
         return res
 
+    def run_cold(mode, R, steps):
+        """The same evaluations cycled over R engines that each hold their own
+        copy of the event set, so that consecutive folds read different
+        buffers whose total exceeds the 256 MB Infinity Cache."""
+        engs = []
+        for r in range(R):
+            e = nf.Engine(desc, mode, stream=stream.cuda_stream)
+            for d, ev in enumerate(events):
+                e.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+            for d, mu in enumerate(e.expected(start)[0]):
+                e.set_data(d, mu)
+            engs.append(e)
+        n_in = sum(len(ev["weight"]) for ev in events) - sum(engs[0].dropped(d) for d in range(engs[0].D))
+        th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
+        out_dev = torch.zeros((len(thetas), 1 + engs[0].P), dtype=torch.float64, device="cuda")
+        for k in range(2 * R):
+            engs[k % R].eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
+        torch.cuda.synchronize()
+        for e in engs:
+            e.set_option("timing", 1)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            engs[k % R].eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cnt = fold_ms = tail_ms = 0
+        for e in engs:
+            c_, f_, t_ = e.timing(reset=True)
+            cnt, fold_ms, tail_ms = cnt + c_, fold_ms + f_, tail_ms + t_
+            e.close()
+        assert cnt == steps and bool(torch.isfinite(out_dev).all())
+        bpe = 12 if mode == "m64" else 8
+        achieved = n_in * bpe / (fold_ms / cnt / 1e3) / 1e9
+        res = dict(replicas=R, resident_bytes=R * n_in * bpe, evals_per_s=steps / (t1 - t0),
+                   fold_us=fold_ms / cnt * 1e3, tail_us=tail_ms / cnt * 1e3,
+                   achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS)
+        log(f"{mode} cold: {json.dumps(res)}")
+        return res
+
     main_res = run(args.mode)
+    cold = None
+    if args.replicas > 0:
+        cold = run_cold(args.mode, args.replicas, max(args.steps, 4 * args.replicas))
     other = None
     if args.both_modes:
         other = run("m64" if args.mode == "m32" else "m32")
@@ -170,7 +233,7 @@ def main():
         "dtype": "f32+f64" if args.mode == "m32" else "f64",
         "data": "synthetic (seeded MC events and Asimov data)",
         "config": {
-            "workload": "config-3 medium-baseline three-flavour fold: 1e7 MC events, 10 cores at "
+            "workload": "medium-baseline three-flavour fold: 1e7 MC events, 10 cores at "
                         "52-53 km, 400 bins on 0.8-12 MeV, 120 parameters, NLL + adjoint gradient",
             "events": n_events, "bins": 400, "params": len(start),
             "mode": args.mode,
@@ -179,6 +242,7 @@ def main():
         "tail_us": main_res["tail_us"],
         "host_path_evals_per_s": main_res["host_path_evals_per_s"],
         "roofline": main_res["roofline"],
+        "cold": cold,
         "cpu_baseline": cpu,
     }
     if other is not None:

@@ -226,6 +226,17 @@ int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, 
                  int* status_out, int* iters_out, int* evals_out);
 
 /*
+ * Expected counts mu (Eq. 3-5: signal from the fold and bin stages plus
+ * backgrounds) for B parameter vectors in one batched launch. Rows whose
+ * oscillation parameters are equal share one event fold, so a set of
+ * nuisance-parameter draws at one oscillation point reads the events once.
+ * theta: B x P (host); mu: B x (sum_d nf_num_bins(d)) (host), datasets
+ * concatenated. Needs events (not data). NF_WDOMAIN when some row is out of
+ * domain (its mu is not meaningful).
+ */
+int nf_expected_batch(nf_ctx* ctx, int B, const double* theta, double* mu);
+
+/*
  * Per-kernel device time, measured with HIP events recorded on the context
  * stream around the fold and the bin-stage kernels of every evaluation while
  * option "timing" is 1. nf_timing synchronises the stream and returns, for the
@@ -233,6 +244,59 @@ int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, 
  * time and the summed bin-stage time (ms). reset != 0 starts a new window.
  */
 int nf_timing(nf_ctx* ctx, int reset, int64_t* count, double* fold_ms, double* tail_ms);
+
+/*
+ * ---------------------------------------------------------------------------
+ * Surrogate: a dense network  x (n_in) -> [Linear -> GELU] x depth -> Linear
+ * -> y (n_out)  that maps a subset of the parameters to the (standardised)
+ * log expectations of the analysis bins. It only proposes start points for
+ * fits; every NLL the library reports comes from the exact fold above.
+ * Layer l has weights W_l (d_in x d_out, row-major) and bias b_l (d_out);
+ * the flat parameter vector is W_0, b_0, W_1, b_1, ... in that order.
+ * GELU(z) = z Phi(z) with the exact normal CDF. Matrix products run on the
+ * matrix cores with BF16 operands (weights, activations and back-propagated
+ * gradients rounded to BF16, round-to-nearest-even) and FP32 accumulation;
+ * biases, pre-activations, master weights and optimiser state are FP32.
+ * Each handle owns its device memory and is used by one host thread at a time.
+ * Host-pointer calls are synchronous. Return codes as above.
+ */
+typedef struct nf_mlp nf_mlp;
+
+/* Create a network; parameters start at zero (set them with nf_mlp_set_params).
+ * max_batch bounds B in every call. hip_stream as in nf_create. */
+int nf_mlp_create(nf_mlp** out, int n_in, int width, int depth, int n_out, int max_batch, void* hip_stream);
+void nf_mlp_destroy(nf_mlp* net);
+const char* nf_mlp_last_error(const nf_mlp* net);  /* NULL net: error of the last failed create */
+int64_t nf_mlp_num_params(const nf_mlp* net);
+
+/* Copy the flat FP32 parameter vector in (also resets the optimiser state) or out. */
+int nf_mlp_set_params(nf_mlp* net, const float* params);
+int nf_mlp_get_params(nf_mlp* net, float* params);
+
+/* y = f(x) for B rows: x B x n_in, y B x n_out, FP32, host (on_device = 0)
+ * or device pointers (on_device = 1). */
+int nf_mlp_forward(nf_mlp* net, int B, const float* x, float* y, int on_device);
+
+/* Back-propagation of dy = dL/dy (B x n_out) at x: grad (nullable) receives
+ * dL/d(parameters) in the flat layout, dx (nullable) dL/dx (B x n_in). */
+int nf_mlp_grad(nf_mlp* net, int B, const float* x, const float* dy, float* grad, float* dx, int on_device);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * mean squared error  L = sum (y - t)^2 / (B n_out)  of the batch x -> t.
+ * loss (nullable, host) receives L before the step. With device pointers and
+ * loss NULL the step is only enqueued on the network's stream. */
+int nf_mlp_train_step(nf_mlp* net, int B, const float* x, const float* t, float lr, float* loss, int on_device);
+
+/* Warm start: for each of B rows, minimise over the inputs x the surrogate
+ * Poisson deviance  sum_j [mu_j - n_j + n_j ln(n_j / mu_j)],
+ * mu_j = exp(y_j out_std_j + out_mean_j), plus the Gaussian input prior
+ * 1/2 sum_i x_weight_i (x_i - x_prior_i)^2, by `iters` Adam steps of size lr
+ * on all rows at once. x: B x n_in (host, in: start, out: result); nobs: B x
+ * n_out observed counts; out_mean, out_std: n_out; x_prior, x_weight: n_in;
+ * nll (nullable): B values of the objective at the returned x. */
+int nf_mlp_fit_inputs(nf_mlp* net, int B, float* x, const float* nobs, const float* out_mean,
+                      const float* out_std, const float* x_prior, const float* x_weight, int iters, float lr,
+                      float* nll);
 
 #ifdef __cplusplus
 }

@@ -179,8 +179,9 @@ struct nf_ctx {
   // batched evaluations and fits (capacity bt_cap fits)
   int bt_cap = 0, bt_nsets = 0;
   DevBuf<double> bt_theta, bt_part, bt_out, bt_Sseg, bt_bin, bt_prior, bt_segtmp, bt_osc_last, bt_data;
+  DevBuf<double> bt_fold_theta, bt_mu;  // distinct oscillation points; expectations (nf_expected_batch)
   DevBuf<int32_t> bt_status;
-  DevBuf<int> bt_didx;
+  DevBuf<int> bt_didx, bt_pidx;
   DevBuf<FitHeader> bf_hdr;
   DevBuf<double> bf_x, bf_g, bf_p, bf_d2, bf_fr, bf_S, bf_Y, bf_rho, bf_gam;
   std::vector<FitHeader> bh_hdr;
@@ -202,9 +203,9 @@ struct nf_ctx {
     f_S.release(); f_Y.release(); f_rho.release(); f_gam.release();
     if (bf_graph) (void)hipGraphExecDestroy(bf_graph);
     for (auto* b : {&bt_theta, &bt_part, &bt_out, &bt_Sseg, &bt_bin, &bt_prior, &bt_segtmp, &bt_osc_last, &bt_data,
-                    &bf_x, &bf_g, &bf_p, &bf_d2, &bf_fr, &bf_S, &bf_Y, &bf_rho, &bf_gam})
+                    &bt_fold_theta, &bt_mu, &bf_x, &bf_g, &bf_p, &bf_d2, &bf_fr, &bf_S, &bf_Y, &bf_rho, &bf_gam})
       b->release();
-    bt_status.release(); bt_didx.release(); bf_hdr.release();
+    bt_status.release(); bt_didx.release(); bt_pidx.release(); bf_hdr.release();
     for (auto& t : tev)
       for (auto& e : t)
         if (e) (void)hipEventDestroy(e);
@@ -1042,6 +1043,9 @@ void ensure_batch(nf_ctx* c, int B) {
   c->bt_osc_last.alloc(B * 4);
   c->bt_status.alloc(B);
   c->bt_didx.alloc(B);
+  c->bt_pidx.alloc(B);
+  c->bt_fold_theta.alloc(B * P);
+  c->bt_mu.alloc(B * (size_t)std::max(1, c->nbins_total));
   c->bf_hdr.alloc(B);
   c->bf_x.alloc(B * P); c->bf_g.alloc(B * P); c->bf_p.alloc(B * P); c->bf_d2.alloc(B * P); c->bf_fr.alloc(B * P);
   c->bf_S.alloc(B * m * P); c->bf_Y.alloc(B * m * P); c->bf_rho.alloc(B * m); c->bf_gam.alloc(B * m);
@@ -1081,6 +1085,7 @@ BatchTailArgs batch_tail_args(nf_ctx* c, int B, bool fit, bool want_grad, bool u
   a.segtmp = c->bt_segtmp.p;
   a.osc_last = fit ? c->bt_osc_last.p : nullptr;
   a.want_grad = want_grad ? 1 : 0;
+  a.want_nll = 1;
   a.has_fit = fit ? 1 : 0;
   if (fit) {
     FitArgs f{};
@@ -1102,6 +1107,60 @@ void check_didx(nf_ctx* c, int B, const int* didx) {
     const int r = didx ? didx[f] : f;
     if (r < 0 || r >= c->bt_nsets) fail(NF_EINVAL, "data index out of range for fit " + std::to_string(f));
   }
+}
+
+// Expectations for B parameter vectors. Rows whose oscillation slots are equal
+// share one fold: the batched fold runs over the distinct oscillation points
+// only, and each row's bin stages read the partials of its point.
+int expected_batch_impl(nf_ctx* c, int B, const double* theta, double* mu) {
+  require_ready(c, false);
+  if (B <= 0 || !theta || !mu) fail(NF_EINVAL, "B > 0, theta and mu are required");
+  const int P = c->P;
+  for (int64_t i = 0; i < (int64_t)B * P; ++i)
+    if (!std::isfinite(theta[i])) fail(NF_EINVAL, "theta contains a non-finite value");
+  std::map<std::array<double, NSLOT>, int> points;
+  std::vector<int> pidx(B);
+  std::vector<double> ftheta;
+  for (int f = 0; f < B; ++f) {
+    std::array<double, NSLOT> key{};
+    for (int q = 0; q < NSLOT; ++q) {
+      const int i = c->osc.slot_param[q];
+      key[q] = i >= 0 ? theta[(size_t)f * P + i] : c->osc.slot_value[q];
+    }
+    auto it = points.find(key);
+    if (it == points.end()) {
+      it = points.emplace(key, (int)points.size()).first;
+      ftheta.insert(ftheta.end(), theta + (size_t)f * P, theta + (size_t)(f + 1) * P);
+    }
+    pidx[f] = it->second;
+  }
+  const int U = (int)points.size();
+  ensure_batch(c, B);
+  hip_check(hipMemcpyAsync(c->bt_fold_theta.p, ftheta.data(), sizeof(double) * U * P, hipMemcpyHostToDevice,
+                           c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bt_theta.p, theta, sizeof(double) * B * P, hipMemcpyHostToDevice, c->stream), "H2D");
+  hip_check(hipMemcpyAsync(c->bt_pidx.p, pidx.data(), sizeof(int) * B, hipMemcpyHostToDevice, c->stream), "H2D");
+  BatchFoldArgs fa = batch_fold_args(c, U, false);
+  fa.theta = c->bt_fold_theta.p;
+  hip_check(launch_fold_batch(c->mode, fa, c->stream), "batch fold");
+  BatchTailArgs ta = batch_tail_args(c, B, false, false, false);
+  ta.part_idx = c->bt_pidx.p;
+  ta.data = nullptr;
+  ta.want_nll = 0;
+  ta.out = nullptr;
+  ta.mu_out = c->bt_mu.p;
+  hip_check(launch_batch_tail(ta, batch_threads(c), c->stream), "batch tail");
+  std::vector<int32_t> st(B);
+  hip_check(hipMemcpyAsync(mu, c->bt_mu.p, sizeof(double) * (size_t)B * c->nbins_total, hipMemcpyDeviceToHost,
+                           c->stream), "D2H");
+  hip_check(hipMemcpyAsync(st.data(), c->bt_status.p, sizeof(int32_t) * B, hipMemcpyDeviceToHost, c->stream), "D2H");
+  hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  for (int f = 0; f < B; ++f)
+    if (st[f] & ST_DOMAIN) {
+      c->err = "some parameter vectors are out of domain";
+      return NF_WDOMAIN;
+    }
+  return NF_OK;
 }
 
 int eval_batch_impl(nf_ctx* c, int B, const double* theta, const int* didx, double* nll, double* grad) {
@@ -1419,6 +1478,10 @@ int nf_set_data_batch(nf_ctx* ctx, int nsets, const double* counts, int on_devic
     drop_fit_graph(ctx);
     return NF_OK;
   });
+}
+
+int nf_expected_batch(nf_ctx* ctx, int B, const double* theta, double* mu) {
+  return guarded(ctx, [&] { return expected_batch_impl(ctx, B, theta, mu); });
 }
 
 int nf_eval_batch(nf_ctx* ctx, int B, const double* theta, const int* data_idx, double* nll, double* grad) {

@@ -100,8 +100,10 @@ struct BatchTailArgs {
   int B;
   const double* theta;    // [B][P] trial points
   const double* part;     // [B][NM][nitems]
-  const double* data;     // [nsets][nbins_total]
+  const int* part_idx;    // [B] fold partials row of each fit (nullable: row f)
+  const double* data;     // [nsets][nbins_total] (unused when want_nll == 0)
   const int* data_idx;    // [B] data row of each fit (nullable: row f)
+  double* mu_out;         // [B][nbins_total] expectations (nullable)
   double* out;            // [B][1+P] (nullable)
   int32_t* status;        // [B] (nullable)
   double* Sseg;           // [B][G]
@@ -110,6 +112,7 @@ struct BatchTailArgs {
   double* segtmp;         // [B][5 G] in-block phase A scratch
   double* osc_last;       // [B][4] (nullable): slot values of each fit's last fold
   int want_grad;
+  int want_nll;
   int has_fit;
   FitArgs fit;            // base pointers; fit f uses hdr + f, vectors + f P, history + f m P
 };

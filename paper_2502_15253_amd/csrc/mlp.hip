@@ -1,0 +1,580 @@
+// MLP surrogate of the folded spectrum: dense layers with GELU, BF16 operands
+// on the matrix cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation, FP32
+// master weights with Adam. Used only to propose fit start points; every
+// reported NLL comes from the exact fold.
+//
+// GEMM: C (M x N) = op(A) (M x K) * op(B) (K x N). A workgroup of 256 threads
+// computes a 64 x 64 tile; each wavefront a 32 x 32 quarter as 2 x 2 MFMA
+// 16 x 16 blocks; K advances by 32. Operands are staged in LDS as bf16 with
+// the contraction index contiguous (A as [m][k], B as [n][k]) so every lane
+// reads its 8 consecutive k values with one 16-byte LDS load. Out-of-range
+// rows, columns and k are zero-filled, so any shape is accepted.
+// MFMA lane layout (16x16x32): lane l holds A[l % 16][8 (l / 16) + 0..7] and
+// B[8 (l / 16) + 0..7][l % 16]; the result lane holds D[4 (l / 16) + i][l % 16].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nufold.h"
+
+namespace nufold {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// float -> bf16 bits, round to nearest even (NaN kept quiet)
+__host__ __device__ inline uint16_t f2bf(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_prime(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_DGELU = 3 };
+
+struct GemmArgs {
+  int M, N, K;
+  const uint16_t* A;  // bf16
+  int lda;
+  const uint16_t* B;  // bf16
+  int ldb;
+  float* Cf;          // fp32 output (EPI_F32, EPI_BIAS_F32, EPI_BIAS_GELU: pre-activation, EPI_DGELU: dz)
+  uint16_t* Cb;       // bf16 output (EPI_BIAS_GELU: activation, EPI_DGELU: dz)
+  int ldc;
+  const float* bias;  // N (EPI_BIAS_*)
+  const float* Zin;   // EPI_DGELU: pre-activation of this layer (M x N, ldc)
+};
+
+constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;  // LDS row pitch padded against bank conflicts
+
+template <int TA, int TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    // stage A tile: TM x TK, and B tile: TN x TK (k contiguous)
+    for (int e = tid; e < TM * TK; e += 256) {
+      int mm, kk;
+      if (TA == 0) { mm = e / TK; kk = e % TK; } else { kk = e / TM; mm = e % TM; }
+      const int m = m0 + mm, k = k0 + kk;
+      uint16_t v = 0;
+      if (m < g.M && k < g.K) v = TA == 0 ? g.A[(int64_t)m * g.lda + k] : g.A[(int64_t)k * g.lda + m];
+      As[mm][kk] = v;
+    }
+    for (int e = tid; e < TN * TK; e += 256) {
+      int nn, kk;
+      if (TB == 0) { kk = e / TN; nn = e % TN; } else { nn = e / TK; kk = e % TK; }
+      const int n = n0 + nn, k = k0 + kk;
+      uint16_t v = 0;
+      if (n < g.N && k < g.K) v = TB == 0 ? g.B[(int64_t)k * g.ldb + n] : g.B[(int64_t)n * g.ldb + k];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    bf16x8 af[2], bfr[2];
+    for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + r][kq]);
+    for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + r][kq]);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  const int col = lane & 15, rq = (lane >> 4) * 4;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + i * 16 + rq + q, n = n0 + wn + j * 16 + col;
+        if (m >= g.M || n >= g.N) continue;
+        const float v = acc[i][j][q];
+        const int64_t o = (int64_t)m * g.ldc + n;
+        if (EPI == EPI_F32) {
+          g.Cf[o] = v;
+        } else if (EPI == EPI_BIAS_F32) {
+          g.Cf[o] = v + g.bias[n];
+        } else if (EPI == EPI_BIAS_GELU) {
+          const float z = v + g.bias[n];
+          g.Cf[o] = z;
+          g.Cb[o] = f2bf(gelu(z));
+        } else {  // EPI_DGELU: v is dL/dh
+          const float dz = v * gelu_prime(g.Zin[o]);
+          g.Cf[o] = dz;
+          g.Cb[o] = f2bf(dz);
+        }
+      }
+}
+
+template <int TA, int TB, int EPI>
+hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+  const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+__global__ void to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// column sums of an M x N fp32 matrix (bias gradients), fixed order
+__global__ void colsum_kernel(const float* x, int M, int N, float* out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int m = 0; m < M; ++m) s += x[(int64_t)m * N + n];
+  out[n] = s;
+}
+
+// MSE over B x N: dy = 2 (y - t) / (B N) as fp32 and bf16; per-block loss partials
+__global__ void mse_kernel(const float* y, const float* t, int64_t n, float scale, float* dyf, uint16_t* dyb,
+                           float* partial) {
+  __shared__ float red[256];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (i < n) {
+    const float d = y[i] - t[i];
+    l = d * d;
+    const float g = 2.f * d * scale;
+    dyf[i] = g;
+    dyb[i] = f2bf(g);
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Surrogate Poisson deviance per row with Gaussian input priors, and dL/dy:
+// mu = exp(y std + mean), L = sum [mu - n + n ln(n/mu)] + 1/2 sum w_j (x_j - xbar_j)^2
+__global__ void surrogate_nll_kernel(const float* y, const float* nobs, const float* mean, const float* stdv,
+                                     int N, const float* x, const float* xbar, const float* xw, int Nin,
+                                     float* dyf, uint16_t* dyb, float* dxp, float* nll) {
+  __shared__ float red[256];
+  const int row = blockIdx.x;
+  float l = 0.f;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const int64_t o = (int64_t)row * N + j;
+    const float lm = y[o] * stdv[j] + mean[j];
+    const float mu = expf(lm);
+    const float n = nobs[o];
+    l += n > 0.f ? (mu - n + n * (logf(n) - lm)) : mu;
+    const float g = (mu - n) * stdv[j];
+    dyf[o] = g;
+    dyb[o] = f2bf(g);
+  }
+  for (int j = threadIdx.x; j < Nin; j += blockDim.x) {
+    const int64_t o = (int64_t)row * Nin + j;
+    const float d = x[o] - xbar[j];
+    l += 0.5f * xw[j] * d * d;
+    dxp[o] = xw[j] * d;
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nll[row] = red[0];
+}
+
+// Adam on the inputs of every row (warm start), gradient = MLP input gradient + prior term
+__global__ void input_adam_kernel(float* x, const float* dx, const float* dxp, float* m, float* v, int64_t n,
+                                  float lr, float c1, float c2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = dx[i] + dxp[i];
+  const float mi = 0.9f * m[i] + 0.1f * g;
+  const float vi = 0.999f * v[i] + 0.001f * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  x[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+}  // namespace nufold
+
+using namespace nufold;
+
+namespace {
+
+template <typename T>
+T* dalloc(size_t n) {
+  T* p = nullptr;
+  if (n && hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+  return p;
+}
+
+}  // namespace
+
+struct nf_mlp {
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n_in = 0, width = 0, depth = 0, n_out = 0, max_batch = 0;
+  int L = 0;                          // number of weight layers = depth + 1
+  std::vector<int> din, dout;         // per layer
+  std::vector<int64_t> woff, boff;    // offsets into the flat parameter vector
+  int64_t nparam = 0;
+  float *w = nullptr, *g = nullptr, *am = nullptr, *av = nullptr;  // master params, grads, Adam moments
+  uint16_t* wb = nullptr;             // bf16 copy of the parameters (weights used)
+  float* xf = nullptr;                // B x n_in staging (fp32)
+  uint16_t* xb = nullptr;             // B x n_in bf16
+  std::vector<float*> Z;              // pre-activations per hidden layer (B x width)
+  std::vector<uint16_t*> H;           // activations bf16 per hidden layer
+  float* Y = nullptr;                 // B x n_out
+  float* T = nullptr;                 // targets / observed counts B x n_out
+  float* dYf = nullptr;               // B x max(width, n_out)
+  uint16_t* dYb = nullptr;
+  float* dZf = nullptr;               // B x width
+  uint16_t* dZb = nullptr;
+  float* dX = nullptr;                // B x n_in
+  float* partial = nullptr;           // loss partials
+  int adam_t = 0;
+  ~nf_mlp() {
+    for (void* p : {(void*)w, (void*)g, (void*)am, (void*)av, (void*)wb, (void*)xf, (void*)xb, (void*)Y, (void*)T,
+                    (void*)dYf, (void*)dYb, (void*)dZf, (void*)dZb, (void*)dX, (void*)partial})
+      if (p) (void)hipFree(p);
+    for (auto* p : Z) (void)hipFree(p);
+    for (auto* p : H) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+thread_local std::string g_mlp_create_error;
+
+struct MlpError : std::runtime_error {
+  int code;
+  MlpError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void mck(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw MlpError(NF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+int mguard(nf_mlp* n, F&& f) {
+  if (!n) return NF_EINVAL;
+  try {
+    n->err.clear();
+    return f();
+  } catch (const MlpError& e) {
+    n->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    n->err = "device allocation failed";
+    return NF_ENOMEM;
+  }
+}
+
+void upload_x(nf_mlp* n, int B, const float* x, int on_device) {
+  mck(hipMemcpyAsync(n->xf, x, sizeof(float) * B * n->n_in, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                     n->stream), "x copy");
+  const int64_t cnt = (int64_t)B * n->n_in;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((cnt + 255) / 256), dim3(256), 0, n->stream, n->xf, n->xb, cnt);
+}
+
+void refresh_bf16(nf_mlp* n) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((n->nparam + 255) / 256), dim3(256), 0, n->stream, n->w, n->wb, n->nparam);
+}
+
+// forward pass of B rows already in n->xb; output fp32 in n->Y
+void forward(nf_mlp* n, int B) {
+  const uint16_t* in = n->xb;
+  for (int l = 0; l < n->L; ++l) {
+    GemmArgs a{};
+    a.M = B; a.N = n->dout[l]; a.K = n->din[l];
+    a.A = in; a.lda = n->din[l];
+    a.B = n->wb + n->woff[l]; a.ldb = n->dout[l];
+    a.ldc = n->dout[l];
+    a.bias = n->w + n->boff[l];
+    if (l < n->L - 1) {
+      a.Cf = n->Z[l];
+      a.Cb = n->H[l];
+      mck(gemm<0, 0, EPI_BIAS_GELU>(a, n->stream), "gemm");
+      in = n->H[l];
+    } else {
+      a.Cf = n->Y;
+      mck(gemm<0, 0, EPI_BIAS_F32>(a, n->stream), "gemm");
+    }
+  }
+}
+
+// backward from dY (fp32 in n->dYf, bf16 in n->dYb, B x n_out): parameter
+// gradients into n->g when want_dw; input gradient into n->dX when want_dx
+void backward(nf_mlp* n, int B, bool want_dx, bool want_dw = true) {
+  float* dcur_f = n->dYf;
+  uint16_t* dcur_b = n->dYb;
+  for (int l = n->L - 1; l >= 0; --l) {
+    const uint16_t* inp = l == 0 ? n->xb : n->H[l - 1];
+    if (want_dw) {
+      // dW_l = inp^T dcur (din x dout), db_l = colsum(dcur)
+      GemmArgs gw{};
+      gw.M = n->din[l]; gw.N = n->dout[l]; gw.K = B;
+      gw.A = inp; gw.lda = n->din[l];
+      gw.B = dcur_b; gw.ldb = n->dout[l];
+      gw.Cf = n->g + n->woff[l]; gw.ldc = n->dout[l];
+      mck(gemm<1, 0, EPI_F32>(gw, n->stream), "gemm dW");
+      hipLaunchKernelGGL(colsum_kernel, dim3((n->dout[l] + 255) / 256), dim3(256), 0, n->stream, dcur_f, B,
+                         n->dout[l], n->g + n->boff[l]);
+    }
+    if (l == 0 && !want_dx) break;
+    // d(inp) = dcur W_l^T (B x din); through GELU of the previous layer
+    GemmArgs gd{};
+    gd.M = B; gd.N = n->din[l]; gd.K = n->dout[l];
+    gd.A = dcur_b; gd.lda = n->dout[l];
+    gd.B = n->wb + n->woff[l]; gd.ldb = n->dout[l];
+    gd.ldc = n->din[l];
+    if (l > 0) {
+      // write into the buffer not currently being read
+      float* nf = (dcur_f == n->dZf) ? n->dYf : n->dZf;
+      uint16_t* nb = (dcur_b == n->dZb) ? n->dYb : n->dZb;
+      gd.Cf = nf; gd.Cb = nb; gd.Zin = n->Z[l - 1];
+      mck(gemm<0, 1, EPI_DGELU>(gd, n->stream), "gemm dH");
+      dcur_f = nf;
+      dcur_b = nb;
+    } else {
+      gd.Cf = n->dX;
+      mck(gemm<0, 1, EPI_F32>(gd, n->stream), "gemm dX");
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nf_mlp_create(nf_mlp** out, int n_in, int width, int depth, int n_out, int max_batch, void* hip_stream) {
+  if (!out) return NF_EINVAL;
+  *out = nullptr;
+  g_mlp_create_error.clear();
+  if (n_in < 1 || width < 1 || depth < 1 || n_out < 1 || max_batch < 1 || depth > 64) {
+    g_mlp_create_error = "invalid MLP shape";
+    return NF_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    g_mlp_create_error = "no HIP device available";
+    return NF_EDEVICE;
+  }
+  nf_mlp* n = new nf_mlp();
+  try {
+    n->n_in = n_in; n->width = width; n->depth = depth; n->n_out = n_out; n->max_batch = max_batch;
+    n->L = depth + 1;
+    int64_t off = 0;
+    for (int l = 0; l < n->L; ++l) {
+      const int a = l == 0 ? n_in : width, b = l == n->L - 1 ? n_out : width;
+      n->din.push_back(a);
+      n->dout.push_back(b);
+      n->woff.push_back(off);
+      off += (int64_t)a * b;
+      n->boff.push_back(off);
+      off += b;
+    }
+    n->nparam = off;
+    if (hip_stream) n->stream = (hipStream_t)hip_stream;
+    else {
+      mck(hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking), "hipStreamCreate");
+      n->own_stream = true;
+    }
+    const size_t B = max_batch, wmax = std::max(width, n_out);
+    n->w = dalloc<float>(off); n->g = dalloc<float>(off); n->am = dalloc<float>(off); n->av = dalloc<float>(off);
+    n->wb = dalloc<uint16_t>(off);
+    n->xf = dalloc<float>(B * n_in); n->xb = dalloc<uint16_t>(B * n_in);
+    for (int l = 0; l < depth; ++l) {
+      n->Z.push_back(dalloc<float>(B * width));
+      n->H.push_back(dalloc<uint16_t>(B * width));
+    }
+    n->Y = dalloc<float>(B * n_out); n->T = dalloc<float>(B * n_out);
+    n->dYf = dalloc<float>(B * wmax); n->dYb = dalloc<uint16_t>(B * wmax);
+    n->dZf = dalloc<float>(B * wmax); n->dZb = dalloc<uint16_t>(B * wmax);
+    n->dX = dalloc<float>(B * n_in);
+    n->partial = dalloc<float>((B * n_out + 255) / 256 + 1);
+    mck(hipMemsetAsync(n->w, 0, sizeof(float) * off, n->stream), "memset");
+    mck(hipMemsetAsync(n->am, 0, sizeof(float) * off, n->stream), "memset");
+    mck(hipMemsetAsync(n->av, 0, sizeof(float) * off, n->stream), "memset");
+    refresh_bf16(n);
+    mck(hipStreamSynchronize(n->stream), "sync");
+  } catch (const std::exception& e) {
+    g_mlp_create_error = e.what();
+    delete n;
+    return NF_ENOMEM;
+  }
+  *out = n;
+  return NF_OK;
+}
+
+void nf_mlp_destroy(nf_mlp* n) {
+  if (!n) return;
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  delete n;
+}
+
+const char* nf_mlp_last_error(const nf_mlp* n) { return n ? n->err.c_str() : g_mlp_create_error.c_str(); }
+
+int64_t nf_mlp_num_params(const nf_mlp* n) { return n ? n->nparam : NF_EINVAL; }
+
+int nf_mlp_set_params(nf_mlp* n, const float* params) {
+  return mguard(n, [&] {
+    if (!params) throw MlpError(NF_EINVAL, "params is null");
+    mck(hipMemcpyAsync(n->w, params, sizeof(float) * n->nparam, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemsetAsync(n->am, 0, sizeof(float) * n->nparam, n->stream), "memset");
+    mck(hipMemsetAsync(n->av, 0, sizeof(float) * n->nparam, n->stream), "memset");
+    n->adam_t = 0;
+    refresh_bf16(n);
+    mck(hipStreamSynchronize(n->stream), "sync");
+    return NF_OK;
+  });
+}
+
+int nf_mlp_get_params(nf_mlp* n, float* params) {
+  return mguard(n, [&] {
+    if (!params) throw MlpError(NF_EINVAL, "params is null");
+    mck(hipMemcpy(params, n->w, sizeof(float) * n->nparam, hipMemcpyDeviceToHost), "D2H");
+    return NF_OK;
+  });
+}
+
+int nf_mlp_forward(nf_mlp* n, int B, const float* x, float* y, int on_device) {
+  return mguard(n, [&] {
+    if (B < 1 || B > n->max_batch || !x || !y) throw MlpError(NF_EINVAL, "bad batch or null pointer");
+    upload_x(n, B, x, on_device);
+    forward(n, B);
+    mck(hipMemcpyAsync(y, n->Y, sizeof(float) * B * n->n_out,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, n->stream), "y copy");
+    mck(hipStreamSynchronize(n->stream), "sync");
+    return NF_OK;
+  });
+}
+
+int nf_mlp_grad(nf_mlp* n, int B, const float* x, const float* dy, float* grad, float* dx, int on_device) {
+  return mguard(n, [&] {
+    if (B < 1 || B > n->max_batch || !x || !dy) throw MlpError(NF_EINVAL, "bad batch or null pointer");
+    const hipMemcpyKind k_in = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind k_out = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    upload_x(n, B, x, on_device);
+    forward(n, B);
+    const int64_t cnt = (int64_t)B * n->n_out;
+    mck(hipMemcpyAsync(n->dYf, dy, sizeof(float) * cnt, k_in, n->stream), "dy copy");
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((cnt + 255) / 256), dim3(256), 0, n->stream, n->dYf, n->dYb, cnt);
+    backward(n, B, dx != nullptr);
+    if (grad) mck(hipMemcpyAsync(grad, n->g, sizeof(float) * n->nparam, k_out, n->stream), "grad copy");
+    if (dx) mck(hipMemcpyAsync(dx, n->dX, sizeof(float) * B * n->n_in, k_out, n->stream), "dx copy");
+    mck(hipStreamSynchronize(n->stream), "sync");
+    return NF_OK;
+  });
+}
+
+int nf_mlp_train_step(nf_mlp* n, int B, const float* x, const float* t, float lr, float* loss, int on_device) {
+  return mguard(n, [&] {
+    if (B < 1 || B > n->max_batch || !x || !t || !(lr > 0.f)) throw MlpError(NF_EINVAL, "bad arguments");
+    upload_x(n, B, x, on_device);
+    const int64_t cnt = (int64_t)B * n->n_out;
+    mck(hipMemcpyAsync(n->T, t, sizeof(float) * cnt, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       n->stream), "t copy");
+    forward(n, B);
+    const int nb = (int)((cnt + 255) / 256);
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, n->stream, n->Y, n->T, cnt, 1.0f / (float)cnt, n->dYf,
+                       n->dYb, n->partial);
+    backward(n, B, false);
+    n->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
+    hipLaunchKernelGGL(adam_kernel, dim3((n->nparam + 255) / 256), dim3(256), 0, n->stream, n->w, n->g, n->am, n->av,
+                       n->nparam, lr, b1, b2, 1e-8f, c1, c2);
+    refresh_bf16(n);
+    if (loss) {
+      std::vector<float> part(nb);
+      mck(hipMemcpyAsync(part.data(), n->partial, sizeof(float) * nb, hipMemcpyDeviceToHost, n->stream), "D2H");
+      mck(hipStreamSynchronize(n->stream), "sync");
+      double s = 0.0;
+      for (float v : part) s += v;
+      *loss = (float)(s / (double)cnt);
+    } else if (!on_device) {
+      mck(hipStreamSynchronize(n->stream), "sync");
+    }
+    return NF_OK;
+  });
+}
+
+int nf_mlp_fit_inputs(nf_mlp* n, int B, float* x, const float* nobs, const float* out_mean, const float* out_std,
+                      const float* x_prior, const float* x_weight, int iters, float lr, float* nll) {
+  return mguard(n, [&] {
+    if (B < 1 || B > n->max_batch || !x || !nobs || !out_mean || !out_std || !x_prior || !x_weight || iters < 1)
+      throw MlpError(NF_EINVAL, "bad arguments");
+    const int Ni = n->n_in, No = n->n_out;
+    float* xd = dalloc<float>((size_t)B * Ni);
+    float* mom = dalloc<float>((size_t)B * Ni * 3);  // m, v, prior gradient
+    float* aux = dalloc<float>((size_t)No * 2 + (size_t)Ni * 2 + B);
+    float* nd = dalloc<float>((size_t)B * No);
+    struct Free {
+      std::vector<void*> p;
+      ~Free() { for (void* q : p) (void)hipFree(q); }
+    } fr{{xd, mom, aux, nd}};
+    float *mean = aux, *sd = aux + No, *xbar = aux + 2 * No, *xw = xbar + Ni, *nllv = xw + Ni;
+    mck(hipMemcpyAsync(xd, x, sizeof(float) * B * Ni, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemcpyAsync(nd, nobs, sizeof(float) * B * No, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemcpyAsync(mean, out_mean, sizeof(float) * No, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemcpyAsync(sd, out_std, sizeof(float) * No, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemcpyAsync(xbar, x_prior, sizeof(float) * Ni, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemcpyAsync(xw, x_weight, sizeof(float) * Ni, hipMemcpyHostToDevice, n->stream), "H2D");
+    mck(hipMemsetAsync(mom, 0, sizeof(float) * B * Ni * 2, n->stream), "memset");
+    const int64_t cx = (int64_t)B * Ni;
+    for (int it = 1; it <= iters; ++it) {
+      hipLaunchKernelGGL(to_bf16_kernel, dim3((cx + 255) / 256), dim3(256), 0, n->stream, xd, n->xb, cx);
+      forward(n, B);
+      hipLaunchKernelGGL(surrogate_nll_kernel, dim3(B), dim3(256), 0, n->stream, n->Y, nd, mean, sd, No, xd, xbar, xw,
+                         Ni, n->dYf, n->dYb, mom + 2 * cx, nllv);
+      backward(n, B, true, false);
+      const float c1 = 1.f - std::pow(0.9f, (float)it), c2 = 1.f - std::pow(0.999f, (float)it);
+      hipLaunchKernelGGL(input_adam_kernel, dim3((cx + 255) / 256), dim3(256), 0, n->stream, xd, n->dX, mom + 2 * cx,
+                         mom, mom + cx, cx, lr, c1, c2);
+    }
+    // final NLL at the returned inputs
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((cx + 255) / 256), dim3(256), 0, n->stream, xd, n->xb, cx);
+    forward(n, B);
+    hipLaunchKernelGGL(surrogate_nll_kernel, dim3(B), dim3(256), 0, n->stream, n->Y, nd, mean, sd, No, xd, xbar, xw, Ni,
+                       n->dYf, n->dYb, mom + 2 * cx, nllv);
+    mck(hipMemcpyAsync(x, xd, sizeof(float) * B * Ni, hipMemcpyDeviceToHost, n->stream), "D2H");
+    if (nll) mck(hipMemcpyAsync(nll, nllv, sizeof(float) * B, hipMemcpyDeviceToHost, n->stream), "D2H");
+    mck(hipStreamSynchronize(n->stream), "sync");
+    return NF_OK;
+  });
+}
+
+}  // extern "C"

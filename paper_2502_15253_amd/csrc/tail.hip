@@ -723,12 +723,13 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   }
   __syncthreads();
   const int drow = a.data_idx ? a.data_idx[f] : f;
+  const int prow = a.part_idx ? a.part_idx[f] : f;
   const EvalIO io{th,
-                  a.part + (int64_t)f * NMOM * p.nitems,
-                  a.data + (int64_t)drow * p.nbins_total,
+                  a.part + (int64_t)prow * NMOM * p.nitems,
+                  a.want_nll ? a.data + (int64_t)drow * p.nbins_total : nullptr,
                   a.out ? a.out + (int64_t)f * (1 + P) : nullptr,
                   a.status ? a.status + f : nullptr,
-                  nullptr,
+                  a.mu_out ? a.mu_out + (int64_t)f * p.nbins_total : nullptr,
                   a.Sseg + (int64_t)f * G,
                   a.bin + (int64_t)f * 6 * KT,
                   a.prior + (int64_t)f * 2 * NR};
@@ -794,7 +795,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const double fval = serial_stages<NT>(p, io, L, 1, a.want_grad);
+  const double fval = serial_stages<NT>(p, io, L, a.want_nll, a.want_nll ? a.want_grad : 0);
   if (a.has_fit) {
     if (a.osc_last && tid < NSLOT) {
       const int q = p.osc.slot_param[tid];

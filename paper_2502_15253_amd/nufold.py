@@ -61,6 +61,22 @@ SIGNATURES["nf_fit_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_voi
                                         C.POINTER(FitOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p])
 
+SIGNATURES["nf_expected_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
+SIGNATURES["nf_mlp_create"] = (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_void_p])
+SIGNATURES["nf_mlp_destroy"] = (None, [C.c_void_p])
+SIGNATURES["nf_mlp_last_error"] = (C.c_char_p, [C.c_void_p])
+SIGNATURES["nf_mlp_num_params"] = (C.c_int64, [C.c_void_p])
+SIGNATURES["nf_mlp_set_params"] = (C.c_int, [C.c_void_p, C.c_void_p])
+SIGNATURES["nf_mlp_get_params"] = (C.c_int, [C.c_void_p, C.c_void_p])
+SIGNATURES["nf_mlp_forward"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
+SIGNATURES["nf_mlp_grad"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_int])
+SIGNATURES["nf_mlp_train_step"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_float,
+                                             C.POINTER(C.c_float), C.c_int])
+SIGNATURES["nf_mlp_fit_inputs"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.c_void_p])
+
 _lib = None
 
 
@@ -255,8 +271,101 @@ class Engine:
             edm.ctypes.data, status.ctypes.data, iters.ctypes.data, evals.ctypes.data))
         return dict(theta=th, nll=nll, edm=edm, status=status, iters=iters, evals=evals, code=code)
 
+    def expected_batch(self, theta):
+        """Expected counts for B parameter vectors: B x (all analysis bins)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        mu = np.zeros((th.shape[0], sum(self.nbins)))
+        code = _check(self.ctx, load().nf_expected_batch(self.ctx, th.shape[0], th.ctypes.data, mu.ctypes.data))
+        return mu, code
+
     def timing(self, reset=True):
         """(evaluations, summed fold ms, summed bin-stage ms) since the last reset."""
         n, f, t = C.c_int64(), C.c_double(), C.c_double()
         _check(self.ctx, load().nf_timing(self.ctx, 1 if reset else 0, C.byref(n), C.byref(f), C.byref(t)))
         return n.value, f.value, t.value
+
+
+def _mlp_err(h):
+    m = load().nf_mlp_last_error(h)
+    return m.decode() if m else ""
+
+
+class Mlp:
+    """One nf_mlp: dense GELU network on the matrix cores (BF16 in, FP32 out)."""
+
+    def __init__(self, n_in, width, depth, n_out, max_batch, stream=None):
+        h = C.c_void_p()
+        code = load().nf_mlp_create(C.byref(h), n_in, width, depth, n_out, max_batch,
+                                    C.c_void_p(stream) if stream else None)
+        if code != NF_OK:
+            raise NufoldError(code, _mlp_err(None))
+        self.h = h
+        self.n_in, self.width, self.depth, self.n_out, self.max_batch = n_in, width, depth, n_out, max_batch
+        self.nparam = load().nf_mlp_num_params(h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().nf_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, code):
+        if code < 0:
+            raise NufoldError(code, _mlp_err(self.h))
+        return code
+
+    def layer_shapes(self):
+        dims = [self.n_in] + [self.width] * self.depth + [self.n_out]
+        return [(dims[i], dims[i + 1]) for i in range(len(dims) - 1)]
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.nparam
+        self._check(load().nf_mlp_set_params(self.h, a.ctypes.data))
+
+    def get_params(self):
+        a = np.zeros(self.nparam, dtype=np.float32)
+        self._check(load().nf_mlp_get_params(self.h, a.ctypes.data))
+        return a
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((x.shape[0], self.n_out), dtype=np.float32)
+        self._check(load().nf_mlp_forward(self.h, x.shape[0], x.ctypes.data, y.ctypes.data, 0))
+        return y
+
+    def grad(self, x, dy, want_dx=True):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        dy = np.ascontiguousarray(dy, dtype=np.float32)
+        g = np.zeros(self.nparam, dtype=np.float32)
+        dx = np.zeros_like(x) if want_dx else None
+        self._check(load().nf_mlp_grad(self.h, x.shape[0], x.ctypes.data, dy.ctypes.data, g.ctypes.data,
+                                       dx.ctypes.data if want_dx else None, 0))
+        return g, dx
+
+    def train_step(self, x, t, lr, want_loss=True):
+        """Host arrays, or device tensors (torch, float32, contiguous). Without
+        want_loss a device-tensor step is enqueued and returns at once (None)."""
+        loss = C.c_float()
+        lp = C.byref(loss) if want_loss else None
+        if _is_cuda(x):
+            self._check(load().nf_mlp_train_step(self.h, x.shape[0], C.c_void_p(x.data_ptr()),
+                                                 C.c_void_p(t.data_ptr()), lr, lp, 1))
+        else:
+            x = np.ascontiguousarray(x, dtype=np.float32)
+            t = np.ascontiguousarray(t, dtype=np.float32)
+            self._check(load().nf_mlp_train_step(self.h, x.shape[0], x.ctypes.data, t.ctypes.data, lr, lp, 0))
+        return loss.value if want_loss else None
+
+    def fit_inputs(self, x, nobs, out_mean, out_std, x_prior, x_weight, iters, lr):
+        x = np.array(x, dtype=np.float32, order="C")
+        args = [np.ascontiguousarray(a, dtype=np.float32) for a in (nobs, out_mean, out_std, x_prior, x_weight)]
+        nll = np.zeros(x.shape[0], dtype=np.float32)
+        self._check(load().nf_mlp_fit_inputs(self.h, x.shape[0], x.ctypes.data, *[a.ctypes.data for a in args],
+                                             iters, lr, nll.ctypes.data))
+        return x, nll

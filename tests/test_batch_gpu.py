@@ -153,3 +153,31 @@ def test_fit_batch_config2_pseudo_experiments_converge():
     assert abs(f_o - rb["nll"][f]) < 1e-9 * max(1, f_o)
     scale = np.array([p["prior"][1] if p["prior"] else 0.01 for p in desc["params"]])
     assert np.max(np.abs(g_o * scale)) < 5e-3
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_expected_batch_shares_folds_and_matches_oracle(mode):
+    say("expected_batch", mode)
+    desc, events = synth.model_and_events(3, 200_000)
+    m = Model(desc)
+    rng = np.random.default_rng(21)
+    eng = engine(desc, events, mode)
+    osc = [synth.param_index(desc, n) for n in ("osc.sin2_t13", "osc.dm2_31")]
+    # 3 oscillation points x 4 nuisance draws, interleaved
+    pts = [(0.020, 2.40), (0.025, 2.60), (0.0218, 2.53)]
+    rows = []
+    for j in range(12):
+        th = displaced(desc, rng)
+        th[osc[0]], th[osc[1]] = pts[j % 3]
+        rows.append(th)
+    rows = np.array(rows)
+    mu, code = eng.expected_batch(rows)
+    assert code == nf.NF_OK and mu.shape == (12, 400)
+    tol = TOL[mode]
+    for f in (0, 1, 2, 5, 11):
+        ref = np.concatenate(LK.expected(m, events, rows[f])[0])
+        assert np.max(np.abs(mu[f] - ref)) <= tol * np.max(ref), f
+    # the single-evaluation path gives the same expectations
+    for f in (3, 7):
+        one = np.concatenate(eng.expected(rows[f])[0])
+        assert np.max(np.abs(one - mu[f])) <= 1e-12 * np.max(one)
