@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fold_c3_traffic.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fold_juno_like_1e7_traffic.json")
 
 
 def log(*a):
@@ -37,7 +37,7 @@ def log(*a):
 
 def fold_source_hash():
     h = hashlib.sha256()
-    for f in ("fold.hip", "fastmath.hpp", "sincos_coeffs.hpp", "kernels.hpp", "plan.hpp"):
+    for f in ("fold.hip", "fastmath.hpp", "sincos_coeffs.hpp"):
         with open(os.path.join(ROOT, "paper_2502_15253_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -85,6 +85,182 @@ def copy_probe(torch, reps=8):
     log(f"copy probe: {reps} copies of {COPY_BYTES} B")
 
 
+def pseudo_data(eng, desc, n, seed0=3000):
+    """n Poisson pseudo-experiments around the expectations at the start point."""
+    from paper_2502_15253_amd import synth
+    mus, _ = eng.expected(synth.start_vector(desc))
+    return np.array([np.concatenate(synth.poisson_data(mus, seed0 + j)) for j in range(n)])
+
+
+def engine_for(nf, synth, config, stream, n_events=None):
+    desc, events = synth.model_and_events(config, n_events)
+    eng = nf.Engine(desc, "m64", stream=stream.cuda_stream)
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+    return desc, events, eng
+
+
+def plain_fit(eng, start, h=1e-6):
+    """The paper's method on the GPU: one fit at a time, BFGS on the host with
+    central finite-difference gradients, every function value one GPU
+    evaluation (fold + bin stages + NLL). Returns (NLL, evaluations)."""
+    from scipy.optimize import minimize
+    n = [0]
+
+    def f(x):
+        n[0] += 1
+        return eng.eval_nll(x)[0]
+
+    def g(x):
+        out = np.zeros_like(x)
+        for i in range(len(x)):
+            e = np.zeros_like(x)
+            e[i] = h
+            out[i] = (eng.eval_nll(x + e)[0] - eng.eval_nll(x - e)[0]) / (2 * h)
+        n[0] += 2 * len(x)
+        return out
+
+    r = minimize(f, start, jac=g, method="BFGS", options=dict(gtol=1e-5, maxiter=5000))
+    return r.fun, n[0]
+
+
+def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
+    """Pseudo-experiment fits/s: batched adjoint fits (2048 + 2048 pseudo-experiments
+    of the 1050 m single-detector and three-detector models, and a 200 x 200
+    profile scan) against the plain per-fit GPU path; and the learned warm start
+    on medium-baseline pseudo-experiments."""
+    out = {}
+    t_all = 0.0
+    n_all = 0
+    for config, label in ((1, "single_detector"), (2, "three_detector")):
+        desc, _, eng = engine_for(nf, synth, config, stream)
+        data = pseudo_data(eng, desc, 2048)
+        eng.set_data_batch(data)
+        start = np.tile(synth.start_vector(desc), (2048, 1))
+        eng.fit_batch(start[:8], edm_tol=1e-7, max_iter=3000)  # graph capture and buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = eng.fit_batch(start, edm_tol=1e-7, max_iter=3000)
+        dt = time.perf_counter() - t0
+        t_all += dt
+        n_all += 2048
+        ent = dict(fits=2048, seconds=dt, fits_per_s=2048 / dt, params=len(start[0]),
+                   converged=int(np.sum(r["status"] == 0)), mean_iters=float(r["iters"].mean()))
+        log(f"batched {label}: {json.dumps(ent)}")
+        if config == 1:
+            # the plain per-fit GPU path on the first n_plain pseudo-experiments
+            nb = np.cumsum([0] + [len(ds["edges"]) - 1 for ds in desc["datasets"]])
+            t0 = time.perf_counter()
+            dmax, nev = 0.0, 0
+            for j in range(n_plain):
+                for d in range(len(desc["datasets"])):
+                    eng.set_data(d, data[j][nb[d]:nb[d + 1]])
+                fmin, ne = plain_fit(eng, start[j])
+                nev += ne
+                dmax = max(dmax, 2.0 * abs(fmin - r["nll"][j]))
+            tp = time.perf_counter() - t0
+            ent["plain"] = dict(fits=n_plain, seconds=tp, fits_per_s=n_plain / tp, evals_per_fit=nev / n_plain,
+                                max_delta_chi2_vs_batched=dmax)
+            ent["batched_over_plain"] = ent["fits_per_s"] / ent["plain"]["fits_per_s"]
+            log(f"plain single_detector: {json.dumps(ent['plain'])}")
+            # 200 x 200 profile scan of (sin2_2t13, dm2_ee) on one Poisson data set
+            scan_data = np.concatenate(synth.poisson_data(eng.expected(synth.start_vector(desc))[0],
+                                                          synth.data_seed(1)))
+            eng.set_data_batch(scan_data[None, :])
+            i13, iee = synth.param_index(desc, "osc.sin2_2t13"), synth.param_index(desc, "osc.dm2_ee")
+            fixed = np.array([p["fixed"] for p in desc["params"]], dtype=bool)
+            fixed[[i13, iee]] = True
+            s13, dee = np.linspace(0.0, 0.2, 200), np.linspace(1.5, 3.5, 200)
+            grid = np.array([(a, b) for a in s13 for b in dee])
+            nll = np.empty(len(grid))
+            t0 = time.perf_counter()
+            conv = 0
+            for o in range(0, len(grid), 4096):
+                g = grid[o:o + 4096]
+                st = np.tile(synth.start_vector(desc), (len(g), 1))
+                st[:, i13], st[:, iee] = g[:, 0], g[:, 1]
+                rs = eng.fit_batch(st, fixed=fixed, data_idx=np.zeros(len(g), np.int32), edm_tol=1e-7,
+                                   max_iter=3000)
+                nll[o:o + len(g)] = rs["nll"]
+                conv += int(np.sum(rs["status"] == 0))
+            ts = time.perf_counter() - t0
+            t_all += ts
+            n_all += len(grid)
+            k = int(np.argmin(nll))
+            out["scan_200x200"] = dict(fits=len(grid), seconds=ts, fits_per_s=len(grid) / ts, converged=conv,
+                                       best=[float(grid[k, 0]), float(grid[k, 1])],
+                                       delta_chi2_max=float(2 * (nll.max() - nll.min())))
+            log(f"scan: {json.dumps(out['scan_200x200'])}")
+        out[label] = ent
+        eng.close()
+    out["ensemble_fits_per_s"] = n_all / t_all
+    if surrogate_samples > 0:
+        out["warm_start"] = warm_start_section(nf, synth, torch, stream, surrogate_samples)
+    return out
+
+
+def warm_start_section(nf, synth, torch, stream, n_samples, E=256):
+    """Medium-baseline pseudo-experiments at random points of the training box:
+    exact batched fits from the box centre (cold) and from the surrogate's
+    proposal (warm). A third fit from the generating point gives the reference
+    minimum; success = final NLL within 5e-4 of the best of the three."""
+    from paper_2502_15253_amd import surrogate as SG
+    desc, _, eng = engine_for(nf, synth, 3, stream)
+    space = SG.Space(desc)
+    t0 = time.perf_counter()
+    X, Y = SG.generate(eng, space, n_samples // 100, 100, seed=11)
+    t_gen = time.perf_counter() - t0
+    sur = SG.Surrogate(space, Y.shape[1], stream=stream, max_batch=4096)
+    t0 = time.perf_counter()
+    losses = sur.train(X, Y, epochs=12, batch=1024, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = 12 * (len(X) // 1024)
+    Xv, Yv = SG.generate(eng, space, 200, 5, seed=12)
+    err = sur.predict_log_mu(space.to_theta(Xv)) - Yv
+    rng = np.random.default_rng(5)
+    base = synth.start_vector(desc)
+    truths = np.tile(base, (E, 1))
+    for i, p in enumerate(desc["params"]):
+        if p["prior"]:
+            truths[:, i] = p["prior"][0] + p["prior"][1] * rng.standard_normal(E)
+    i13, i31 = synth.param_index(desc, "osc.sin2_t13"), synth.param_index(desc, "osc.dm2_31")
+    truths[:, i13] = rng.uniform(0.017, 0.028, E)
+    truths[:, i31] = rng.uniform(2.33, 2.77, E)
+    mu, _ = eng.expected_batch(truths)
+    data = rng.poisson(mu).astype(np.float64)
+    eng.set_data_batch(data)
+    cold = np.tile(base, (E, 1))
+    for i, p in enumerate(desc["params"]):
+        if p["prior"]:
+            cold[:, i] = p["prior"][0]
+    cold[:, i13], cold[:, i31] = 0.0225, 2.55
+    eng.fit_batch(cold[:4], edm_tol=1e-6, max_iter=2000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc = eng.fit_batch(cold, edm_tol=1e-6, max_iter=2000)
+    tc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    warm, _ = sur.warm_start(data.astype(np.float32), base=cold[0])
+    tsur = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rw = eng.fit_batch(warm, edm_tol=1e-6, max_iter=2000)
+    tw = time.perf_counter() - t0
+    rt = eng.fit_batch(truths, edm_tol=1e-6, max_iter=2000)
+    best = np.minimum(np.minimum(rc["nll"], rw["nll"]), rt["nll"])
+    res = dict(pseudo_experiments=E, training_spectra=len(X), generate_s=t_gen, train_s=t_train,
+               train_tflops=6.0 * sur.net.nparam * 1024 * steps / t_train / 1e12,
+               heldout_rms_dlogmu=float(np.sqrt(np.mean(err ** 2))),
+               cold=dict(seconds=tc, fits_per_s=E / tc, found_global_min=float(np.mean(rc["nll"] - best < 5e-4)),
+                         mean_iters=float(rc["iters"].mean())),
+               warm=dict(seconds=tsur + tw, surrogate_s=tsur, fits_per_s=E / (tsur + tw),
+                         found_global_min=float(np.mean(rw["nll"] - best < 5e-4)),
+                         mean_iters=float(rw["iters"].mean())))
+    eng.close()
+    log(f"warm start: {json.dumps(res)}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +272,10 @@ def main():
     ap.add_argument("--both-modes", action="store_true", help="also measure the other precision mode")
     ap.add_argument("--replicas", type=int, default=6,
                     help="event-set replicas cycled for the cold (HBM) figure; 0 skips it")
+    ap.add_argument("--no-fits", action="store_true", help="skip the pseudo-experiment fits/s section")
+    ap.add_argument("--plain-fits", type=int, default=16, help="fits of the plain per-fit GPU path")
+    ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
+                    help="training spectra for the warm-start section (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device copy of known size (counter calibration) and exit")
     args = ap.parse_args()
@@ -113,7 +293,8 @@ def main():
     if args.copy_probe:
         copy_probe(torch)
         return
-    stream = torch.cuda.current_stream()
+    # one explicit stream (default priority) that every engine enqueues on
+    stream = torch.cuda.Stream()
     n_events = int(args.events)
     log(f"generating {n_events:.0e} events")
     desc, events = synth.model_and_events(3, n_events)
@@ -132,6 +313,7 @@ def main():
         out_dev = torch.zeros((len(thetas), 1 + eng.P), dtype=torch.float64, device="cuda")
         ptr_t = [th_dev[i].data_ptr() for i in range(len(thetas))]
         ptr_o = [out_dev[i].data_ptr() for i in range(len(thetas))]
+        torch.cuda.synchronize()  # the inputs were written on torch's default stream
         for k in range(args.warmup):
             eng.eval_device(ptr_t[k % 64], ptr_o[k % 64])
         torch.cuda.synchronize()
@@ -183,6 +365,7 @@ def main():
         n_in = sum(len(ev["weight"]) for ev in events) - sum(engs[0].dropped(d) for d in range(engs[0].D))
         th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
         out_dev = torch.zeros((len(thetas), 1 + engs[0].P), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
         for k in range(2 * R):
             engs[k % R].eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
         torch.cuda.synchronize()
@@ -214,6 +397,9 @@ def main():
     other = None
     if args.both_modes:
         other = run("m64" if args.mode == "m32" else "m32")
+    fits = None
+    if not args.no_fits:
+        fits = fits_section(nf, synth, torch, stream, args.plain_fits, args.surrogate_samples)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (one evaluation)")
@@ -243,6 +429,7 @@ def main():
         "host_path_evals_per_s": main_res["host_path_evals_per_s"],
         "roofline": main_res["roofline"],
         "cold": cold,
+        "fits": fits,
         "cpu_baseline": cpu,
     }
     if other is not None:

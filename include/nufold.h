@@ -143,13 +143,28 @@ int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev,
 int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
 
 /*
- * Tuning knobs (autotuner hooks). key: "chunk" (events per fold work item,
- * multiple of 256, default 2048), "fold_block" (threads per fold workgroup:
- * 64, 128, 256, 512), "tail_threads" (256, 512 or 1024). Changing "chunk"
- * rebuilds the work-item list. "timing" (0/1) turns per-kernel event timing
- * on or off (see nf_timing). Returns NF_EINVAL for unknown keys/values.
+ * Tuning knobs. key: "chunk" (events per fold work item, multiple of 256,
+ * default 2048), "fold_block" (threads per fold workgroup: 64, 128 or 256),
+ * "tail_threads" (bin-stage threads of the single evaluation: 256, 512 or
+ * 1024), "batch_threads" (bin-stage threads per fit in batched launches: 256,
+ * 512, 1024, or 0 = chosen from the model size). Changing "chunk" rebuilds
+ * the work-item list. "timing" (0/1) turns per-kernel event timing on or off
+ * (see nf_timing). Returns NF_EINVAL for unknown keys/values.
  */
 int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
+
+/*
+ * Autotuner: times the launch choices above on this context's model, events
+ * and data (evaluations at theta, P host values, `evals` timed evaluations
+ * per candidate, device time from HIP events) and keeps the fastest:
+ * tail_threads first, then chunk x fold_block; then, if batch > 0 and batch
+ * data are set (nf_set_data_batch), batch_threads for batched launches of
+ * `batch` fits. best (nullable): 4 values chunk, fold_block, tail_threads,
+ * batch_threads. best_us (nullable): 2 values, the mean device time of one
+ * evaluation and of one batched evaluation (0 if not tuned), microseconds.
+ * Needs events and data. Replaces the options in place.
+ */
+int nf_autotune(nf_ctx* ctx, const double* theta, int evals, int batch, int64_t* best, double* best_us);
 
 /*
  * Fit options and result (paper: "Structure of the framework" -- minimise

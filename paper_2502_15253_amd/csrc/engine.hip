@@ -165,6 +165,8 @@ struct nf_ctx {
   double* h_stage = nullptr;  // pinned: theta, out, mu
   int32_t* h_status = nullptr;
   int nitems = 0;
+  int64_t zpad = 0;  // first of the 4 zero-weight events after all datasets' events
+  int batch_threads_opt = 0;  // bin-stage threads per fit in batched launches (0: by model size)
 
   int64_t chunk = 2048;
   int fold_block = 256;
@@ -669,8 +671,8 @@ void rebuild_events(nf_ctx* c) {
   for (auto& d : c->ds) total += (int64_t)d.w.size();
   std::vector<double> u64;
   std::vector<float> u32, w;
-  if (c->mode == NF_M64) u64.reserve(total); else u32.reserve(total);
-  w.reserve(total);
+  if (c->mode == NF_M64) u64.reserve(total + 4); else u32.reserve(total + 4);
+  w.reserve(total + 4);
   const int64_t chunk = c->chunk;
   for (auto& d : c->ds) {
     int64_t local = 0;
@@ -698,6 +700,11 @@ void rebuild_events(nf_ctx* c) {
   }
   seg_item[c->plan.G] = (int)items.size();
   if (items.size() > (size_t)0x7fffffff) fail(NF_EINVAL, "too many work items");
+  // 4 zero-weight events after the last one: the fold's prefetching loads of
+  // positions past an item's end are redirected here
+  c->zpad = (int64_t)w.size();
+  if (c->mode == NF_M64) u64.insert(u64.end(), 4, 0.0); else u32.insert(u32.end(), 4, 0.0f);
+  w.insert(w.end(), 4, 0.0f);
   c->nitems = (int)items.size();
   if (c->mode == NF_M64) c->d_u64.upload(u64, c->stream); else c->d_u32.upload(u32, c->stream);
   c->d_w.upload(w, c->stream);
@@ -809,6 +816,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.w = c->d_w.p;
   fa.items = c->d_items.p;
   fa.nitems = c->nitems;
+  fa.zpad = c->zpad;
   fa.theta = theta_dev;
   fa.osc = c->osc;
   fa.part = c->d_part.p;
@@ -836,7 +844,9 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   if (c->timing && !fit) {
     if (c->tcount == c->tev.size()) {
       std::array<hipEvent_t, 3> t{};
-      for (auto& e : t) hip_check(hipEventCreate(&e), "hipEventCreate");
+      // timing-only events: no system-scope fence (no cache write-back or
+      // invalidation around the timed kernels)
+      for (auto& e : t) hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
       c->tev.push_back(t);
     }
     ev = c->tev[c->tcount++].data();
@@ -1099,7 +1109,10 @@ BatchTailArgs batch_tail_args(nf_ctx* c, int B, bool fit, bool want_grad, bool u
   return a;
 }
 
-int batch_threads(nf_ctx* c) { return c->plan.G > 2048 ? 512 : 256; }
+int batch_threads(nf_ctx* c) {
+  if (c->batch_threads_opt) return c->batch_threads_opt;
+  return c->plan.G > 2048 ? 512 : 256;
+}
 
 void check_didx(nf_ctx* c, int B, const int* didx) {
   if (c->bt_nsets <= 0) fail(NF_ESTATE, "batch data not set (nf_set_data_batch)");
@@ -1107,6 +1120,121 @@ void check_didx(nf_ctx* c, int B, const int* didx) {
     const int r = didx ? didx[f] : f;
     if (r < 0 || r >= c->bt_nsets) fail(NF_EINVAL, "data index out of range for fit " + std::to_string(f));
   }
+}
+
+// ---------------------------------------------------------------- autotuner
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    hip_check(hipEventCreateWithFlags(&a, hipEventDisableSystemFence), "hipEventCreate");
+    hip_check(hipEventCreateWithFlags(&b, hipEventDisableSystemFence), "hipEventCreate");
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  double us_per(int n) {
+    hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+    return 1e3 * ms / n;
+  }
+};
+
+// mean device time of one evaluation (fold + bin stages + NLL + gradient) at d_theta
+double time_single(nf_ctx* c, int n) {
+  EventPair ev;
+  for (int i = 0; i < 2; ++i) enqueue_eval(c, c->d_theta.p, c->d_out.p, c->d_status.p, nullptr, 1, 1);
+  hip_check(hipEventRecord(ev.a, c->stream), "hipEventRecord");
+  for (int i = 0; i < n; ++i) enqueue_eval(c, c->d_theta.p, c->d_out.p, c->d_status.p, nullptr, 1, 1);
+  hip_check(hipEventRecord(ev.b, c->stream), "hipEventRecord");
+  return ev.us_per(n);
+}
+
+// mean device time of one batched evaluation of B fits (bt_theta, data row 0)
+double time_batch(nf_ctx* c, int B, int n) {
+  EventPair ev;
+  auto once = [&] {
+    hip_check(launch_fold_batch(c->mode, batch_fold_args(c, B, false), c->stream), "batch fold");
+    hip_check(launch_batch_tail(batch_tail_args(c, B, false, true, true), batch_threads(c), c->stream),
+              "batch tail");
+  };
+  once();
+  hip_check(hipEventRecord(ev.a, c->stream), "hipEventRecord");
+  for (int i = 0; i < n; ++i) once();
+  hip_check(hipEventRecord(ev.b, c->stream), "hipEventRecord");
+  return ev.us_per(n);
+}
+
+// Sweep the launch choices on this context's model and events and keep the
+// fastest: bin-stage threads, then work-item size x fold workgroup size for
+// the single evaluation; bin-stage threads per fit for batched launches of
+// `batch` fits when batch data are set (batch > 0).
+int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t* best, double* best_us) {
+  require_ready(c, true);
+  if (!theta || evals < 1 || batch < 0) fail(NF_EINVAL, "theta, evals >= 1 and batch >= 0 are required");
+  for (int i = 0; i < c->P; ++i)
+    if (!std::isfinite(theta[i])) fail(NF_EINVAL, "theta contains a non-finite value");
+  const int timing = c->timing;
+  c->timing = 0;
+  hip_check(hipMemcpy(c->d_theta.p, theta, sizeof(double) * c->P, hipMemcpyHostToDevice), "H2D");
+  double t_best = 1e300;
+  int nt_best = c->tail_threads;
+  for (int nt : {256, 512, 1024}) {
+    c->tail_threads = nt;
+    const double t = time_single(c, evals);
+    if (t < t_best) { t_best = t; nt_best = nt; }
+  }
+  c->tail_threads = nt_best;
+  t_best = 1e300;
+  int64_t ch_best = c->chunk;
+  int fb_best = c->fold_block;
+  for (int64_t ch : {1024, 2048, 4096, 8192}) {
+    if (ch != c->chunk) {
+      c->chunk = ch;
+      rebuild_events(c);
+    }
+    for (int fb : {64, 128, 256}) {
+      c->fold_block = fb;
+      const double t = time_single(c, evals);
+      if (t < t_best) { t_best = t; ch_best = ch; fb_best = fb; }
+    }
+  }
+  if (ch_best != c->chunk) {
+    c->chunk = ch_best;
+    rebuild_events(c);
+  }
+  c->fold_block = fb_best;
+  int bt_best = c->batch_threads_opt;
+  double tb_best = 0.0;
+  if (batch > 0 && c->bt_nsets > 0) {
+    ensure_batch(c, batch);
+    std::vector<double> th((size_t)batch * c->P);
+    for (int f = 0; f < batch; ++f) std::memcpy(&th[(size_t)f * c->P], theta, sizeof(double) * c->P);
+    std::vector<int> didx(batch, 0);
+    hip_check(hipMemcpy(c->bt_theta.p, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice), "H2D");
+    hip_check(hipMemcpy(c->bt_didx.p, didx.data(), sizeof(int) * batch, hipMemcpyHostToDevice), "H2D");
+    tb_best = 1e300;
+    for (int nt : {256, 512, 1024}) {
+      c->batch_threads_opt = nt;
+      const double t = time_batch(c, batch, std::max(1, evals / 4));
+      if (t < tb_best) { tb_best = t; bt_best = nt; }
+    }
+    c->batch_threads_opt = bt_best;
+  }
+  drop_fit_graph(c);
+  c->timing = timing;
+  if (best) {
+    best[0] = c->chunk;
+    best[1] = c->fold_block;
+    best[2] = c->tail_threads;
+    best[3] = c->batch_threads_opt;
+  }
+  if (best_us) {
+    best_us[0] = t_best;
+    best_us[1] = tb_best;
+  }
+  return NF_OK;
 }
 
 // Expectations for B parameter vectors. Rows whose oscillation slots are equal
@@ -1453,6 +1581,11 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
       if (value != 256 && value != 512 && value != 1024) fail(NF_EINVAL, "tail_threads must be 256, 512 or 1024");
       ctx->tail_threads = (int)value;
       drop_fit_graph(ctx);
+    } else if (k == "batch_threads") {
+      if (value != 0 && value != 256 && value != 512 && value != 1024)
+        fail(NF_EINVAL, "batch_threads must be 0, 256, 512 or 1024");
+      ctx->batch_threads_opt = (int)value;
+      drop_fit_graph(ctx);
     } else if (k == "timing") {
       ctx->timing = value ? 1 : 0;
       ctx->tcount = 0;
@@ -1478,6 +1611,10 @@ int nf_set_data_batch(nf_ctx* ctx, int nsets, const double* counts, int on_devic
     drop_fit_graph(ctx);
     return NF_OK;
   });
+}
+
+int nf_autotune(nf_ctx* ctx, const double* theta, int evals, int batch, int64_t* best, double* best_us) {
+  return guarded(ctx, [&] { return autotune_impl(ctx, theta, evals, batch, best, best_us); });
 }
 
 int nf_expected_batch(nf_ctx* ctx, int B, const double* theta, double* mu) {

@@ -122,29 +122,53 @@ __device__ __forceinline__ void wave_sum_store(double* m, double* part, int nite
   }
 }
 
+// One wavefront folds one work item. Each lane takes 4 consecutive events
+// per step (16-byte loads) and the loop is software-pipelined two steps deep:
+// the loads of step t+1 are issued before step t is folded, so every wave
+// keeps its next loads in flight. Positions past the item's end load the 4
+// zero-weight events at zpad, which add nothing (so the second half of the
+// last step may fold zeros); the loop is uniform over the wave and no load
+// sits under a branch.
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
   const int lane = threadIdx.x & 63;
-  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;  // whole wavefronts leave together
   if (a.skip && *a.skip != FIT_RUNNING) return;
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const WorkItem it = a.items[item];
-  const double* __restrict__ u = static_cast<const double*>(a.u) + it.begin;
-  const float* __restrict__ w = a.w + it.begin;
+  const double* __restrict__ u = static_cast<const double*>(a.u);
+  const float* __restrict__ w = a.w;
+  const int cnt = it.count;
+  const int niter = (cnt + 255) >> 8;
   double m[NM];
 #pragma unroll
   for (int c = 0; c < NM; ++c) m[c] = 0.0;
-  for (int j = lane * 4; j < it.count; j += 256) {
-    const double2 u01 = *reinterpret_cast<const double2*>(u + j);
-    const double2 u23 = *reinterpret_cast<const double2*>(u + j + 2);
-    const float4 w4 = *reinterpret_cast<const float4*>(w + j);
-    accum64<FORM>(u01.x, w4.x, a1, a2, m);
-    accum64<FORM>(u01.y, w4.y, a1, a2, m);
-    accum64<FORM>(u23.x, w4.z, a1, a2, m);
-    accum64<FORM>(u23.y, w4.w, a1, a2, m);
+  int j = lane * 4;
+  int64_t o = j < cnt ? it.begin + j : a.zpad;
+  double2 pa = *reinterpret_cast<const double2*>(u + o);
+  double2 qa = *reinterpret_cast<const double2*>(u + o + 2);
+  float4 wa = *reinterpret_cast<const float4*>(w + o);
+  for (int t = 0; t < niter; t += 2) {
+    const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
+    const double2 pb = *reinterpret_cast<const double2*>(u + ob);
+    const double2 qb = *reinterpret_cast<const double2*>(u + ob + 2);
+    const float4 wb = *reinterpret_cast<const float4*>(w + ob);
+    accum64<FORM>(pa.x, wa.x, a1, a2, m);
+    accum64<FORM>(pa.y, wa.y, a1, a2, m);
+    accum64<FORM>(qa.x, wa.z, a1, a2, m);
+    accum64<FORM>(qa.y, wa.w, a1, a2, m);
+    const int64_t on = j + 512 < cnt ? it.begin + j + 512 : a.zpad;
+    pa = *reinterpret_cast<const double2*>(u + on);
+    qa = *reinterpret_cast<const double2*>(u + on + 2);
+    wa = *reinterpret_cast<const float4*>(w + on);
+    accum64<FORM>(pb.x, wb.x, a1, a2, m);
+    accum64<FORM>(pb.y, wb.y, a1, a2, m);
+    accum64<FORM>(qb.x, wb.z, a1, a2, m);
+    accum64<FORM>(qb.y, wb.w, a1, a2, m);
+    j += 512;
   }
   wave_sum_store<NM>(m, a.part, a.nitems, item, lane);
 }
@@ -154,7 +178,7 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
   constexpr double INV_2PI = 0.15915494309189533577;
   const int lane = threadIdx.x & 63;
-  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;
   if (a.skip && *a.skip != FIT_RUNNING) return;
   double a1, a2;
@@ -163,18 +187,33 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   const float b1h = (float)r1, b1l = (float)(r1 - (double)b1h);
   const float b2h = (float)r2, b2l = (float)(r2 - (double)b2h);
   const WorkItem it = a.items[item];
-  const float* __restrict__ u = static_cast<const float*>(a.u) + it.begin;
-  const float* __restrict__ w = a.w + it.begin;
+  const float* __restrict__ u = static_cast<const float*>(a.u);
+  const float* __restrict__ w = a.w;
+  const int cnt = it.count;
+  const int niter = (cnt + 255) >> 8;
   float mf[NM];
 #pragma unroll
   for (int c = 0; c < NM; ++c) mf[c] = 0.0f;
-  for (int j = lane * 4; j < it.count; j += 256) {
-    const float4 u4 = *reinterpret_cast<const float4*>(u + j);
-    const float4 w4 = *reinterpret_cast<const float4*>(w + j);
-    accum32<FORM>(u4.x, w4.x, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(u4.y, w4.y, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(u4.z, w4.z, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(u4.w, w4.w, b1h, b1l, b2h, b2l, mf);
+  int j = lane * 4;
+  int64_t o = j < cnt ? it.begin + j : a.zpad;
+  float4 ua = *reinterpret_cast<const float4*>(u + o);
+  float4 wa = *reinterpret_cast<const float4*>(w + o);
+  for (int t = 0; t < niter; t += 2) {
+    const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
+    const float4 ub = *reinterpret_cast<const float4*>(u + ob);
+    const float4 wb = *reinterpret_cast<const float4*>(w + ob);
+    accum32<FORM>(ua.x, wa.x, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(ua.y, wa.y, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(ua.z, wa.z, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(ua.w, wa.w, b1h, b1l, b2h, b2l, mf);
+    const int64_t on = j + 512 < cnt ? it.begin + j + 512 : a.zpad;
+    ua = *reinterpret_cast<const float4*>(u + on);
+    wa = *reinterpret_cast<const float4*>(w + on);
+    accum32<FORM>(ub.x, wb.x, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(ub.y, wb.y, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(ub.z, wb.z, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(ub.w, wb.w, b1h, b1l, b2h, b2l, mf);
+    j += 512;
   }
   double m[NM];
 #pragma unroll

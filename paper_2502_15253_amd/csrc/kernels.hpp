@@ -42,6 +42,7 @@ struct FoldArgs {
   const float* w;       // f32 weights (0 for padding)
   const WorkItem* items;
   int nitems;
+  int64_t zpad;         // index of 4 trailing zero-weight events (loads past an item's end read these)
   const double* theta;  // device parameter vector
   OscPlan osc;
   double* part;         // [num_moments][nitems]

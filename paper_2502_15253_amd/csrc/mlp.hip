@@ -4,11 +4,13 @@
 // reported NLL comes from the exact fold.
 //
 // GEMM: C (M x N) = op(A) (M x K) * op(B) (K x N). A workgroup of 256 threads
-// computes a 64 x 64 tile; each wavefront a 32 x 32 quarter as 2 x 2 MFMA
-// 16 x 16 blocks; K advances by 32. Operands are staged in LDS as bf16 with
-// the contraction index contiguous (A as [m][k], B as [n][k]) so every lane
-// reads its 8 consecutive k values with one 16-byte LDS load. Out-of-range
-// rows, columns and k are zero-filled, so any shape is accepted.
+// computes a 128 x 128 tile (64 x 64 when that leaves too few workgroups to
+// fill the chip); each wavefront a quarter of it as MFMA 16 x 16 blocks; K
+// advances by 32. Operands are staged in LDS as bf16 with the contraction
+// index contiguous (A as [m][k], B as [n][k]) so every lane reads its 8
+// consecutive k values with one 16-byte LDS load; operands stored the other
+// way round are transposed on the way into LDS. Out-of-range rows, columns
+// and k are zero-filled, so any shape is accepted.
 // MFMA lane layout (16x16x32): lane l holds A[l % 16][8 (l / 16) + 0..7] and
 // B[8 (l / 16) + 0..7][l % 16]; the result lane holds D[4 (l / 16) + i][l % 16].
 #include <hip/hip_runtime.h>
@@ -61,48 +63,119 @@ struct GemmArgs {
   const float* Zin;   // EPI_DGELU: pre-activation of this layer (M x N, ldc)
 };
 
-constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;  // LDS row pitch padded against bank conflicts
+constexpr int TK = 32, LDK = TK + 8;  // LDS row pitch (bf16) padded against bank conflicts
 
-template <int TA, int TB, int EPI>
+// One operand tile, ROWS x TK, into registers. KC: the operand is stored with
+// k contiguous (row r at src + r ld); otherwise with rows contiguous (k at
+// src + k ld). Out-of-range elements are zero.
+template <int ROWS, bool KC>
+struct TileRegs {
+  static constexpr int NV = ROWS * TK / 8 / 256;  // 16-byte vectors per thread
+  bf16x8 v[NV];
+
+  __device__ void load(const uint16_t* __restrict__ src, int ld, int r0, int R, int k0, int K, int tid) {
+    const bool vec_ok = (ld & 7) == 0 && ((uintptr_t)src & 15) == 0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int e = tid + 256 * j;
+      int r, k;
+      if (KC) { r = e / (TK / 8); k = (e % (TK / 8)) * 8; }
+      else { k = e / (ROWS / 8); r = (e % (ROWS / 8)) * 8; }
+      const int gr = r0 + r, gk = k0 + k;
+      if (KC) {
+        if (vec_ok && gr < R && gk + 8 <= K) {
+          v[j] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
+        } else {
+          union { bf16x8 b; uint16_t u[8]; } t;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) t.u[i] = (gr < R && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : 0;
+          v[j] = t.b;
+        }
+      } else {
+        if (vec_ok && gk < K && gr + 8 <= R) {
+          v[j] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
+        } else {
+          union { bf16x8 b; uint16_t u[8]; } t;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) t.u[i] = (gk < K && gr + i < R) ? src[(int64_t)gk * ld + gr + i] : 0;
+          v[j] = t.b;
+        }
+      }
+    }
+  }
+
+  // to LDS laid out [row][k] (k contiguous, pitch LDK)
+  __device__ void store(uint16_t (*lds)[LDK], int tid) const {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int e = tid + 256 * j;
+      if (KC) {
+        const int r = e / (TK / 8), k = (e % (TK / 8)) * 8;
+        *reinterpret_cast<bf16x8*>(&lds[r][k]) = v[j];
+      } else {
+        const int k = e / (ROWS / 8), r = (e % (ROWS / 8)) * 8;
+        union { bf16x8 b; uint16_t u[8]; } t;
+        t.b = v[j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[r + i][k] = t.u[i];
+      }
+    }
+  }
+};
+
+// C tile BM x BN per workgroup of 4 wavefronts (2 x 2), each wavefront
+// (BM/2) x (BN/2) as FM x FN blocks of 16 x 16; K advances by 32 with the next
+// tile's global loads in flight during the current tile's products (two LDS
+// buffers, one barrier per step).
+template <int BM, int BN, int TA, int TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
+  constexpr int FM = BM / 32, FN = BN / 32;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
-    // stage A tile: TM x TK, and B tile: TN x TK (k contiguous)
-    for (int e = tid; e < TM * TK; e += 256) {
-      int mm, kk;
-      if (TA == 0) { mm = e / TK; kk = e % TK; } else { kk = e / TM; mm = e % TM; }
-      const int m = m0 + mm, k = k0 + kk;
-      uint16_t v = 0;
-      if (m < g.M && k < g.K) v = TA == 0 ? g.A[(int64_t)m * g.lda + k] : g.A[(int64_t)k * g.lda + m];
-      As[mm][kk] = v;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  TileRegs<BM, TA == 0> ra;
+  TileRegs<BN, TB == 1> rb;
+  const int nk = (g.K + TK - 1) / TK;
+  ra.load(g.A, g.lda, m0, g.M, 0, g.K, tid);
+  rb.load(g.B, g.ldb, n0, g.N, 0, g.K, tid);
+  ra.store(As[0], tid);
+  rb.store(Bs[0], tid);
+  __syncthreads();
+  const int r = lane & 15, kq = (lane >> 4) * 8;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      ra.load(g.A, g.lda, m0, g.M, (kt + 1) * TK, g.K, tid);
+      rb.load(g.B, g.ldb, n0, g.N, (kt + 1) * TK, g.K, tid);
     }
-    for (int e = tid; e < TN * TK; e += 256) {
-      int nn, kk;
-      if (TB == 0) { kk = e / TN; nn = e % TN; } else { nn = e / TK; kk = e % TK; }
-      const int n = n0 + nn, k = k0 + kk;
-      uint16_t v = 0;
-      if (n < g.N && k < g.K) v = TB == 0 ? g.B[(int64_t)k * g.ldb + n] : g.B[(int64_t)n * g.ldb + k];
-      Bs[nn][kk] = v;
+    bf16x8 af[FM], bfr[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + i * 16 + r][kq]);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + j * 16 + r][kq]);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    if (kt + 1 < nk) {
+      ra.store(As[cur ^ 1], tid);
+      rb.store(Bs[cur ^ 1], tid);
     }
-    __syncthreads();
-    const int r = lane & 15, kq = (lane >> 4) * 8;
-    bf16x8 af[2], bfr[2];
-    for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + r][kq]);
-    for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + j * 16 + r][kq]);
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
   const int col = lane & 15, rq = (lane >> 4) * 4;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm + i * 16 + rq + q, n = n0 + wn + j * 16 + col;
         if (m >= g.M || n >= g.N) continue;
@@ -126,8 +199,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 
 template <int TA, int TB, int EPI>
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
+  if (t128 >= 512) {
+    const dim3 grid((g.N + 127) / 128, (g.M + 127) / 128);
+    hipLaunchKernelGGL((gemm_kernel<128, 128, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  } else {
+    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    hipLaunchKernelGGL((gemm_kernel<64, 64, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }
 
@@ -136,12 +215,32 @@ __global__ void to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
   if (i < n) y[i] = f2bf(x[i]);
 }
 
-// column sums of an M x N fp32 matrix (bias gradients), fixed order
-__global__ void colsum_kernel(const float* x, int M, int N, float* out) {
+// Column sums of an M x N fp32 matrix (bias gradients) in a fixed order, two
+// passes: blocks of CS_ROWS rows x 64 columns write partial sums, then one
+// thread per column adds the partials in row-block order.
+constexpr int CS_ROWS = 64;
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ x, int M, int N,
+                                                            float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int m0 = blockIdx.y * CS_ROWS;
+  const int m1 = min(M, m0 + CS_ROWS);
+  float s = 0.f;
+  if (n < N) {
+#pragma unroll 4
+    for (int m = m0 + sl; m < m1; m += 4) s += x[(int64_t)m * N + n];
+  }
+  red[sl][c] = s;
+  __syncthreads();
+  if (sl == 0 && n < N) part[(int64_t)blockIdx.y * N + n] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ part, int nrb, int N, float* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += x[(int64_t)m * N + n];
+  for (int r = 0; r < nrb; ++r) s += part[(int64_t)r * N + n];
   out[n] = s;
 }
 
@@ -263,10 +362,11 @@ struct nf_mlp {
   uint16_t* dZb = nullptr;
   float* dX = nullptr;                // B x n_in
   float* partial = nullptr;           // loss partials
+  float* csum = nullptr;              // column-sum partials, ceil(max_batch / 64) x max(width, n_out)
   int adam_t = 0;
   ~nf_mlp() {
     for (void* p : {(void*)w, (void*)g, (void*)am, (void*)av, (void*)wb, (void*)xf, (void*)xb, (void*)Y, (void*)T,
-                    (void*)dYf, (void*)dYb, (void*)dZf, (void*)dZb, (void*)dX, (void*)partial})
+                    (void*)dYf, (void*)dYb, (void*)dZf, (void*)dZb, (void*)dX, (void*)partial, (void*)csum})
       if (p) (void)hipFree(p);
     for (auto* p : Z) (void)hipFree(p);
     for (auto* p : H) (void)hipFree(p);
@@ -350,7 +450,10 @@ void backward(nf_mlp* n, int B, bool want_dx, bool want_dw = true) {
       gw.B = dcur_b; gw.ldb = n->dout[l];
       gw.Cf = n->g + n->woff[l]; gw.ldc = n->dout[l];
       mck(gemm<1, 0, EPI_F32>(gw, n->stream), "gemm dW");
-      hipLaunchKernelGGL(colsum_kernel, dim3((n->dout[l] + 255) / 256), dim3(256), 0, n->stream, dcur_f, B,
+      const int nrb = (B + CS_ROWS - 1) / CS_ROWS;
+      hipLaunchKernelGGL(colsum_partial_kernel, dim3((n->dout[l] + 63) / 64, nrb), dim3(256), 0, n->stream, dcur_f,
+                         B, n->dout[l], n->csum);
+      hipLaunchKernelGGL(colsum_final_kernel, dim3((n->dout[l] + 255) / 256), dim3(256), 0, n->stream, n->csum, nrb,
                          n->dout[l], n->g + n->boff[l]);
     }
     if (l == 0 && !want_dx) break;
@@ -425,6 +528,7 @@ int nf_mlp_create(nf_mlp** out, int n_in, int width, int depth, int n_out, int m
     n->dZf = dalloc<float>(B * wmax); n->dZb = dalloc<uint16_t>(B * wmax);
     n->dX = dalloc<float>(B * n_in);
     n->partial = dalloc<float>((B * n_out + 255) / 256 + 1);
+    n->csum = dalloc<float>(((B + CS_ROWS - 1) / CS_ROWS) * wmax);
     mck(hipMemsetAsync(n->w, 0, sizeof(float) * off, n->stream), "memset");
     mck(hipMemsetAsync(n->am, 0, sizeof(float) * off, n->stream), "memset");
     mck(hipMemsetAsync(n->av, 0, sizeof(float) * off, n->stream), "memset");

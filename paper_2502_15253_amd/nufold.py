@@ -61,6 +61,7 @@ SIGNATURES["nf_fit_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_voi
                                         C.POINTER(FitOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p])
 
+SIGNATURES["nf_autotune"] = (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p])
 SIGNATURES["nf_expected_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
 SIGNATURES["nf_mlp_create"] = (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                          C.c_void_p])
@@ -270,6 +271,16 @@ class Engine:
             di.ctypes.data if di is not None else None, C.byref(opts), th.ctypes.data, nll.ctypes.data,
             edm.ctypes.data, status.ctypes.data, iters.ctypes.data, evals.ctypes.data))
         return dict(theta=th, nll=nll, edm=edm, status=status, iters=iters, evals=evals, code=code)
+
+    def autotune(self, theta, evals=50, batch=0):
+        """Run the library's autotuner; returns ({option: value}, (us/eval, us/batched eval))."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        best = np.zeros(4, dtype=np.int64)
+        us = np.zeros(2)
+        _check(self.ctx, load().nf_autotune(self.ctx, th.ctypes.data, evals, batch, best.ctypes.data,
+                                            us.ctypes.data))
+        keys = ("chunk", "fold_block", "tail_threads", "batch_threads")
+        return {k: int(v) for k, v in zip(keys, best)}, (float(us[0]), float(us[1]))
 
     def expected_batch(self, theta):
         """Expected counts for B parameter vectors: B x (all analysis bins)."""

@@ -119,10 +119,14 @@ def generate(eng, space, n_osc, n_nuis, seed, rows_per_call=4096, log=None):
 
 
 class Surrogate:
+    """stream: a torch.cuda.Stream (default priority) shared by the network's
+    kernels and the torch operations that feed it; None creates one."""
+
     def __init__(self, space, n_out, width=512, depth=4, max_batch=4096, seed=0, stream=None):
+        import torch
         self.space = space
-        self.net = nf.Mlp(space.n_in, width, depth, n_out, max_batch, stream=stream)
-        self.stream = stream
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.net = nf.Mlp(space.n_in, width, depth, n_out, max_batch, stream=self.stream.cuda_stream)
         rng = np.random.default_rng(seed)
         parts = []
         for a, b in self.net.layer_shapes():
@@ -139,6 +143,10 @@ class Surrogate:
         self.out_mean = Ylog.mean(axis=0).astype(np.float32)
         self.out_std = (Ylog.std(axis=0) + 1e-6).astype(np.float32)
         T = ((Ylog - self.out_mean) / self.out_std).astype(np.float32)
+        with torch.cuda.stream(self.stream):
+            return self._train(torch, X, T, epochs, batch, lr, lr_min, seed, log)
+
+    def _train(self, torch, X, T, epochs, batch, lr, lr_min, seed, log):
         Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
         Td = torch.from_numpy(np.ascontiguousarray(T)).cuda()
         n = X.shape[0]
@@ -163,7 +171,7 @@ class Surrogate:
                 step += 1
             if log:
                 log(f"epoch {ep}: loss {losses[-1]:.3e} ({time.perf_counter() - t0:.1f} s)")
-        torch.cuda.synchronize()
+        self.stream.synchronize()
         return losses
 
     def predict_log_mu(self, theta):

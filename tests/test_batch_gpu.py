@@ -181,3 +181,39 @@ def test_expected_batch_shares_folds_and_matches_oracle(mode):
     for f in (3, 7):
         one = np.concatenate(eng.expected(rows[f])[0])
         assert np.max(np.abs(one - mu[f])) <= 1e-12 * np.max(one)
+
+
+def test_autotuner_keeps_results_and_caches_its_choice(tmp_path):
+    from paper_2502_15253_amd import autotune as AT
+    say("autotune")
+    desc, events = synth.model_and_events(1)
+    m = Model(desc)
+    th = synth.start_vector(desc)
+    data = pseudo_data(desc, events, 2)
+    eng = engine(desc, events)
+    for d, dat in enumerate(split(desc, data[0])):
+        eng.set_data(d, dat)
+    eng.set_data_batch(data)
+    f0, g0, _ = eng.eval_nll_grad(th)
+    cache = str(tmp_path / "tune.json")
+    counts = [len(ev["weight"]) for ev in events]
+    rec = AT.tune(eng, desc, counts, th, cache_path=cache, evals=10, batch=64)
+    assert not rec["cached"]
+    o = rec["options"]
+    assert o["chunk"] in (1024, 2048, 4096, 8192) and o["fold_block"] in (64, 128, 256)
+    assert o["tail_threads"] in (256, 512, 1024) and o["batch_threads"] in (256, 512, 1024)
+    assert rec["us_per_eval"] > 0 and rec["us_per_batched_eval"] > 0
+    # the tuned engine computes the same NLL and gradient (only summation order may change)
+    f1, g1, _ = eng.eval_nll_grad(th)
+    assert abs(f1 - f0) <= 1e-11 * max(1, abs(f0))
+    assert np.max(np.abs(g1 - g0)) <= 1e-10 * max(1, np.max(np.abs(g0)))
+    f_o = LK.nll(m, events, split(desc, data[0]), th)
+    assert abs(f1 - f_o) <= 1e-9 * max(1, abs(f_o))
+    # a second engine takes the cached choice without timing
+    eng2 = engine(desc, events)
+    rec2 = AT.tune(eng2, desc, counts, th, cache_path=cache, evals=10, batch=64)
+    assert rec2["cached"] and rec2["options"] == o
+    for d, dat in enumerate(split(desc, data[0])):
+        eng2.set_data(d, dat)
+    f2, _, _ = eng2.eval_nll_grad(th)
+    assert f2 == f1
