@@ -144,7 +144,7 @@ int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
 
 /*
  * Tuning knobs. key: "chunk" (events per fold work item, multiple of 256,
- * default 2048), "fold_block" (threads per fold workgroup: 64, 128 or 256),
+ * default 4096), "fold_block" (threads per fold workgroup: 64, 128 or 256),
  * "tail_threads" (bin-stage threads of the single evaluation: 256, 512 or
  * 1024), "batch_threads" (bin-stage threads per fit in batched launches: 256,
  * 512, 1024, or 0 = chosen from the model size). Changing "chunk" rebuilds

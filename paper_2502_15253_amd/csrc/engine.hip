@@ -160,15 +160,15 @@ struct nf_ctx {
   DevBuf<double> d_mu;
   DevBuf<double> d_Sseg;
   DevBuf<double> d_bin;
-  DevBuf<double> d_prior;
-  DevBuf<int> d_counter;
+  DevBuf<int> d_seg_cnt, d_kt_cnt, d_seg_kt, d_kt_need;  // fused fine-bin reduction in the fold
+  DevBuf<double> d_segm;
   double* h_stage = nullptr;  // pinned: theta, out, mu
   int32_t* h_status = nullptr;
   int nitems = 0;
   int64_t zpad = 0;  // first of the 4 zero-weight events after all datasets' events
   int batch_threads_opt = 0;  // bin-stage threads per fit in batched launches (0: by model size)
 
-  int64_t chunk = 2048;
+  int64_t chunk = 4096;
   int fold_block = 256;
   int tail_threads = 512;
   int timing = 0;
@@ -180,7 +180,7 @@ struct nf_ctx {
   hipGraphExec_t fit_graph = nullptr;
   // batched evaluations and fits (capacity bt_cap fits)
   int bt_cap = 0, bt_nsets = 0;
-  DevBuf<double> bt_theta, bt_part, bt_out, bt_Sseg, bt_bin, bt_prior, bt_segtmp, bt_osc_last, bt_data;
+  DevBuf<double> bt_theta, bt_part, bt_out, bt_Sseg, bt_bin, bt_segtmp, bt_osc_last, bt_data;
   DevBuf<double> bt_fold_theta, bt_mu;  // distinct oscillation points; expectations (nf_expected_batch)
   DevBuf<int32_t> bt_status;
   DevBuf<int> bt_didx, bt_pidx;
@@ -196,7 +196,8 @@ struct nf_ctx {
     d_dpool.release(); d_ipool.release(); d_ds.release(); d_bkg.release();
     d_u64.release(); d_u32.release(); d_w.release(); d_items.release(); d_seg_item.release();
     d_Wseg.release(); d_part.release(); d_theta.release(); d_out.release(); d_status.release();
-    d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release(); d_prior.release(); d_counter.release();
+    d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release();
+    d_seg_cnt.release(); d_kt_cnt.release(); d_seg_kt.release(); d_kt_need.release(); d_segm.release();
     if (h_stage) (void)hipHostFree(h_stage);
     if (h_status) (void)hipHostFree(h_status);
     if (h_hdr) (void)hipHostFree(h_hdr);
@@ -204,7 +205,7 @@ struct nf_ctx {
     f_hdr.release(); f_x.release(); f_g.release(); f_p.release(); f_d2.release(); f_fr.release();
     f_S.release(); f_Y.release(); f_rho.release(); f_gam.release();
     if (bf_graph) (void)hipGraphExecDestroy(bf_graph);
-    for (auto* b : {&bt_theta, &bt_part, &bt_out, &bt_Sseg, &bt_bin, &bt_prior, &bt_segtmp, &bt_osc_last, &bt_data,
+    for (auto* b : {&bt_theta, &bt_part, &bt_out, &bt_Sseg, &bt_bin, &bt_segtmp, &bt_osc_last, &bt_data,
                     &bt_fold_theta, &bt_mu, &bf_x, &bf_g, &bf_p, &bf_d2, &bf_fr, &bf_S, &bf_Y, &bf_rho, &bf_gam})
       b->release();
     bt_status.release(); bt_didx.release(); bt_pidx.release(); bf_hdr.release();
@@ -622,9 +623,22 @@ void upload_plan(nf_ctx* c) {
   c->d_mu.alloc(std::max(1, c->nbins_total));
   c->d_Sseg.alloc((size_t)std::max(1, c->plan.G));
   c->d_bin.alloc((size_t)6 * std::max(1, c->plan.KT));
-  c->d_prior.alloc((size_t)2 * std::max(1, c->plan.NR));
-  c->d_counter.alloc(1);
-  hip_check(hipMemsetAsync(c->d_counter.p, 0, sizeof(int), c->stream), "hipMemsetAsync");
+  {
+    // fine bin of every segment (static), arrival counters and segment moments
+    const int G = std::max(1, c->plan.G), KT = std::max(1, c->plan.KT);
+    std::vector<int> seg_kt(G, 0);
+    for (int kt = 0; kt < c->plan.KT; ++kt) {
+      const int* info = &c->ipool[c->plan.kt_info + 5 * kt];
+      for (int s2 = 0; s2 < info[2]; ++s2) seg_kt[info[0] + s2 * info[1]] = kt;
+    }
+    c->d_seg_kt.upload(seg_kt, c->stream);
+    c->d_seg_cnt.alloc(G);
+    c->d_kt_cnt.alloc(KT);
+    c->d_kt_need.alloc(KT);
+    c->d_segm.alloc((size_t)(MAX_MOM + 1) * G);
+    hip_check(hipMemsetAsync(c->d_seg_cnt.p, 0, sizeof(int) * G, c->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(c->d_kt_cnt.p, 0, sizeof(int) * KT, c->stream), "hipMemsetAsync");
+  }
   hip_check(hipHostMalloc((void**)&c->h_stage, sizeof(double) * (2 + 2 * c->P + c->nbins_total)),
             "hipHostMalloc");
   hip_check(hipHostMalloc((void**)&c->h_status, sizeof(int32_t) * 4), "hipHostMalloc");
@@ -712,6 +726,23 @@ void rebuild_events(nf_ctx* c) {
   c->d_seg_item.upload(seg_item, c->stream);
   c->d_Wseg.upload(Wseg, c->stream);
   c->d_part.alloc((size_t)MAX_MOM * std::max(1, c->nitems));
+  {
+    // segments with work items per fine bin; fine bins and segments without
+    // events are never written by the fold, so they start (and stay) zero
+    std::vector<int> need(std::max(1, c->plan.KT), 0);
+    for (int kt = 0; kt < c->plan.KT; ++kt) {
+      const int* info = &c->ipool[c->plan.kt_info + 5 * kt];
+      for (int s2 = 0; s2 < info[2]; ++s2) {
+        const int g = info[0] + s2 * info[1];
+        if (seg_item[g + 1] > seg_item[g]) ++need[kt];
+      }
+    }
+    c->d_kt_need.upload(need, c->stream);
+    hip_check(hipMemsetAsync(c->d_Sseg.p, 0, sizeof(double) * std::max(1, c->plan.G), c->stream), "memset");
+    hip_check(hipMemsetAsync(c->d_bin.p, 0, sizeof(double) * 6 * std::max(1, c->plan.KT), c->stream), "memset");
+    hip_check(hipMemsetAsync(c->d_seg_cnt.p, 0, sizeof(int) * std::max(1, c->plan.G), c->stream), "memset");
+    hip_check(hipMemsetAsync(c->d_kt_cnt.p, 0, sizeof(int) * std::max(1, c->plan.KT), c->stream), "memset");
+  }
   c->plan.G = (int)Wseg.size();
   c->plan.nitems = c->nitems;
   c->plan.seg_item = c->d_seg_item.p;
@@ -820,18 +851,28 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.theta = theta_dev;
   fa.osc = c->osc;
   fa.part = c->d_part.p;
+  FoldFuse& fu = fa.fuse;
+  fu.seg_item = c->d_seg_item.p;
+  fu.Wseg = c->d_Wseg.p;
+  fu.seg_kt = c->d_seg_kt.p;
+  fu.kt_need = c->d_kt_need.p;
+  fu.kt_info = c->d_ipool.p + c->plan.kt_info;
+  fu.fs_nl = c->d_ipool.p + c->plan.fs_nl;
+  fu.seg_cnt = c->d_seg_cnt.p;
+  fu.kt_cnt = c->d_kt_cnt.p;
+  fu.segm = c->d_segm.p;
+  fu.Sseg = c->d_Sseg.p;
+  fu.bin = c->d_bin.p;
+  fu.G = c->plan.G;
   TailArgs ta{};
   ta.plan = c->plan;
   ta.theta = theta_dev;
-  ta.part = c->d_part.p;
   ta.data = c->d_data.p;
   ta.out = out_dev;
   ta.status = status_dev;
   ta.mu_out = mu_dev;
   ta.Sseg = c->d_Sseg.p;
   ta.bin = c->d_bin.p;
-  ta.prior = c->d_prior.p;
-  ta.counter = c->d_counter.p;
   ta.want_grad = want_grad;
   ta.want_nll = want_nll;
   if (fit) {
@@ -1042,13 +1083,12 @@ void ensure_batch(nf_ctx* c, int B) {
   if (B <= c->bt_cap) return;
   drop_fit_graph(c);
   const size_t P = c->P, m = c->fit_m, G = std::max(1, c->plan.G), KT = std::max(1, c->plan.KT);
-  const size_t NR = std::max(1, c->plan.NR), NM = MAX_MOM, NI = std::max(1, c->nitems);
+  const size_t NM = MAX_MOM, NI = std::max(1, c->nitems);
   c->bt_theta.alloc(B * P);
   c->bt_part.alloc(B * NM * NI);
   c->bt_out.alloc(B * (1 + P));
   c->bt_Sseg.alloc(B * G);
   c->bt_bin.alloc(B * 6 * KT);
-  c->bt_prior.alloc(B * 2 * NR);
   c->bt_segtmp.alloc(B * 5 * G);
   c->bt_osc_last.alloc(B * 4);
   c->bt_status.alloc(B);
@@ -1091,7 +1131,6 @@ BatchTailArgs batch_tail_args(nf_ctx* c, int B, bool fit, bool want_grad, bool u
   a.status = c->bt_status.p;
   a.Sseg = c->bt_Sseg.p;
   a.bin = c->bt_bin.p;
-  a.prior = c->bt_prior.p;
   a.segtmp = c->bt_segtmp.p;
   a.osc_last = fit ? c->bt_osc_last.p : nullptr;
   a.want_grad = want_grad ? 1 : 0;

@@ -18,13 +18,22 @@
 // Layout: u[] and w[] are SoA, sorted by segment, every segment padded with
 // zero-weight events to a multiple of 4, so each lane reads 4 consecutive
 // events with 16-byte loads. One wavefront (64 lanes) reduces one work item
-// (<= chunk events of one segment) and writes one partial per moment;
-// partials of a segment are summed in a fixed order by the bin-stage kernel,
-// so results are deterministic.
+// (<= chunk events of one segment) to one partial per moment.
+//
+// Single evaluation: the fold also finishes the reduction to fine bins. The
+// last wavefront to complete a segment sums the segment's partials (item
+// order); the last segment of a fine bin to complete applies the oscillation
+// coefficients (computed once per workgroup into LDS) and the source norms
+// and writes the bin's oscillated spectrum and its four slot derivatives
+// (source order). Hand-offs use write-through stores and device-scope
+// counters that the last arrival resets, so no extra launch or cache
+// write-back is needed and the results do not depend on arrival order.
+// Batched evaluations keep the raw partials; their bin stages reduce them.
 #include <hip/hip_runtime.h>
 
 #include "fastmath.hpp"
 #include "kernels.hpp"
+#include "osc.hpp"
 
 namespace nufold {
 
@@ -129,13 +138,130 @@ __device__ __forceinline__ void wave_sum_store(double* m, double* part, int nite
 // zero-weight events at zpad, which add nothing (so the second half of the
 // last step may fold zeros); the loop is uniform over the wave and no load
 // sits under a branch.
+// Fine-bin reduction by the last arrivals (see FoldFuse). m: this item's NM
+// moment sums, identical in every lane; cf: the coefficient rows (LDS).
+template <int NM>
+__device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const double* m, int item, int seg,
+                                  int lane) {
+  const FoldFuse& F = a.fuse;
+  const int ib = F.seg_item[seg], ie = F.seg_item[seg + 1];
+  double M[NM + 1];
+  M[0] = F.Wseg[seg];
+  if (ie - ib == 1) {
+#pragma unroll
+    for (int c = 0; c < NM; ++c) M[1 + c] = m[c];
+  } else {
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < NM; ++c) store_agent(&a.part[(int64_t)c * a.nitems + item], m[c]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    int last = 0;
+    if (lane == 0) {
+      const int done = __hip_atomic_fetch_add(&F.seg_cnt[seg], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = done == ie - ib - 1;
+      if (last) __hip_atomic_store(&F.seg_cnt[seg], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!__builtin_amdgcn_readlane(last, 0)) return;
+#pragma unroll
+    for (int c = 0; c < NM; ++c) M[1 + c] = 0.0;
+#pragma unroll 1
+    for (int it = ib; it < ie; ++it) {
+#pragma unroll
+      for (int c = 0; c < NM; ++c) M[1 + c] += load_agent(&a.part[(int64_t)c * a.nitems + it]);
+    }
+  }
+  const int kt = F.seg_kt[seg];
+  if (F.kt_need[kt] > 1) {
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c <= NM; ++c) store_agent(&F.segm[(int64_t)c * F.G + seg], M[c]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    int last = 0;
+    if (lane == 0) {
+      const int done = __hip_atomic_fetch_add(&F.kt_cnt[kt], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = done == F.kt_need[kt] - 1;
+      if (last) __hip_atomic_store(&F.kt_cnt[kt], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!__builtin_amdgcn_readlane(last, 0)) return;
+  }
+  // this wavefront holds the fine bin's last segment: lane s takes source s
+  const int* info = F.kt_info + 5 * kt;
+  const int g0 = info[0], K = info[1], S = info[2], fs0 = info[3], kt0 = info[4];
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int s = lane; s < S; s += 64) {
+    const int g = g0 + s * K;
+    const int src = g == seg ? 0 : (F.seg_item[g + 1] > F.seg_item[g] ? 1 : 2);  // registers, stored, empty
+    double Sv = 0.0, gj[4] = {0.0, 0.0, 0.0, 0.0};
+    if (src != 2) {
+      // an opaque zero offset keeps the coefficient loads inside this loop:
+      // hoisted, the 35 values would hold registers for the whole kernel
+      int z = 0;
+      asm volatile("" : "+v"(z));
+      const double* c0 = cf + z;
+#pragma unroll
+      for (int c = 0; c <= NM; ++c) {
+        const double Mc = src == 0 ? M[c] : load_agent(&F.segm[(int64_t)c * F.G + g]);
+        Sv += c0[c] * Mc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gj[j] += c0[8 * (j + 1) + c] * Mc;
+      }
+    }
+    const int* nl = F.fs_nl + NLMAX * (fs0 + s);
+    double A = 1.0;
+#pragma unroll
+    for (int q = 0; q < NLMAX; ++q)
+      if (nl[q] >= 0) A *= a.theta[nl[q]];
+    F.Sseg[g] = Sv;
+    v[0] += A * Sv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[1 + j] += A * gj[j];
+  }
+#pragma unroll
+  for (int r = 0; r < 5; ++r) v[r] = wave_sum_fixed(v[r]);
+  if (lane == 0) {
+    double* b = F.bin + 6 * (int64_t)kt0;
+    const int k = kt - kt0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) b[r * K + k] = v[r];
+  }
+}
+
+// Oscillation coefficients of this launch's parameters into LDS (fused
+// launches only). Called by every thread before any early return.
+__device__ __forceinline__ void fold_coefficients(const FoldArgs& a, double* cf) {
+  if (a.fuse.seg_cnt) {
+    if (threadIdx.x == 0) (void)osc_coefficients(a.osc, a.theta, cf);
+    __syncthreads();
+  }
+}
+
+template <int NM>
+__device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf, double* m, int item, int seg) {
+  // the lane id is recomputed here rather than kept live across the event
+  // loop (the register allocator would park it above the loop's registers)
+  const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+#pragma unroll
+  for (int c = 0; c < NM; ++c) m[c] = wave_sum_fixed(m[c]);
+  if (a.fuse.seg_cnt) {
+    fold_bin_epilogue<NM>(a, cf, m, item, seg, lane);
+  } else if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < NM; ++c) a.part[(int64_t)c * a.nitems + item] = m[c];
+  }
+}
+
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
+  __shared__ double cf[40];
+  if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
+  fold_coefficients(a, cf);
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;  // whole wavefronts leave together
-  if (a.skip && *a.skip != FIT_RUNNING) return;
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const WorkItem it = a.items[item];
@@ -170,17 +296,19 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
     accum64<FORM>(qb.y, wb.w, a1, a2, m);
     j += 512;
   }
-  wave_sum_store<NM>(m, a.part, a.nitems, item, lane);
+  fold_finish<NM>(a, cf, m, item, it.seg);
 }
 
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
   constexpr double INV_2PI = 0.15915494309189533577;
+  __shared__ double cf[40];
+  if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
+  fold_coefficients(a, cf);
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;
-  if (a.skip && *a.skip != FIT_RUNNING) return;
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
@@ -218,7 +346,7 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   double m[NM];
 #pragma unroll
   for (int c = 0; c < NM; ++c) m[c] = (double)mf[c];
-  wave_sum_store<NM>(m, a.part, a.nitems, item, lane);
+  fold_finish<NM>(a, cf, m, item, it.seg);
 }
 
 // ---------------------------------------------------------------- batched

@@ -37,6 +37,26 @@ __host__ __device__ inline size_t fit_lds_doubles(int P, int m) {
   return 2 * (size_t)m * P + 7 * (size_t)P + 3 * (size_t)m + 16;
 }
 
+// Reduction of the single evaluation's fold results to fine bins, done by the
+// fold kernel itself: the last wavefront to finish a segment sums the
+// segment's item partials (fixed item order); the last segment of a fine bin
+// to finish applies the oscillation coefficients and the source norms and
+// writes that bin's rows (fixed source order). Counters return to zero.
+struct FoldFuse {
+  const int* seg_item;  // [G+1] work-item range of each segment
+  const double* Wseg;   // [G] summed weights of each segment
+  const int* seg_kt;    // [G] global fine bin of each segment
+  const int* kt_need;   // [KT] segments with at least one work item, per fine bin
+  const int* kt_info;   // [5 KT] g0, K, S, fs0, kt0 of each fine bin
+  const int* fs_nl;     // [NLMAX per (dataset, source)] norm parameter indices (-1: none)
+  int* seg_cnt;         // [G] arrival counters
+  int* kt_cnt;          // [KT] arrival counters
+  double* segm;         // [MAX_MOM + 1][G] segment moments (W, M_1..M_NM), write-through
+  double* Sseg;         // [G] oscillated fine spectrum S per segment (before the source norm)
+  double* bin;          // per dataset at 6 kt0: rows Hs, dHs/dslot_0..3 over its K fine bins
+  int G;
+};
+
 struct FoldArgs {
   const void* u;        // double (M64) or float (M32), padded, sorted
   const float* w;       // f32 weights (0 for padding)
@@ -47,6 +67,7 @@ struct FoldArgs {
   OscPlan osc;
   double* part;         // [num_moments][nitems]
   const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
+  FoldFuse fuse;        // used when fuse.seg_cnt != nullptr
 };
 
 // Batched fold: FT fits per wavefront, each event read once per tile.
@@ -74,21 +95,20 @@ struct EvalIO {
   double* mu_out;       // nullable
   double* Sseg;         // G
   double* bin;          // 6 KT
-  double* prior;        // 2 NR
+  int fused;            // bin rows 0..4 and Sseg come from the fold kernel; row 5 (1 + F) is formed here
 };
 
+// Single evaluation: one workgroup, after the fold kernel has written Sseg and
+// bin rows 0..4.
 struct TailArgs {
   DevPlan plan;
   const double* theta;  // P
-  const double* part;   // [NM][nitems] fold partials
   const double* data;   // observed counts (concatenated bins)
   double* out;          // 1 + P: NLL, gradient
   int32_t* status;      // 1 int (may be null)
   double* mu_out;       // concatenated expectations (may be null)
-  double* Sseg;         // G: oscillated fine spectrum S per segment (before A_s)
-  double* bin;          // 6 KT: per dataset [Hs | dHs/dslot_0..3 | 1 + F] over its K fine bins, at 6 kt0
-  double* prior;        // 2 NR: per prior row v (gradient contribution) and NLL contribution
-  int* counter;         // workgroup completion counter (0 between launches)
+  const double* Sseg;   // G: oscillated fine spectrum S per segment (before A_s)
+  const double* bin;    // 6 KT: per dataset [Hs | dHs/dslot_0..3 | unused] over its K fine bins, at 6 kt0
   int want_grad;
   int want_nll;         // 0: only mu_out (no data needed)
   int has_fit;          // run the minimiser step after the evaluation
@@ -109,7 +129,6 @@ struct BatchTailArgs {
   int32_t* status;        // [B] (nullable)
   double* Sseg;           // [B][G]
   double* bin;            // [B][6 KT]
-  double* prior;          // [B][2 NR]
   double* segtmp;         // [B][5 G] in-block phase A scratch
   double* osc_last;       // [B][4] (nullable): slot values of each fit's last fold
   int want_grad;
@@ -130,7 +149,6 @@ __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
   return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }
 
-int tail_blocks(const DevPlan& p, int nt);
 hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream);
 hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream);
 hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream);

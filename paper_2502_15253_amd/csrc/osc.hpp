@@ -1,0 +1,104 @@
+// Oscillation coefficients and agent-scope memory helpers shared by the fold
+// and bin-stage kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace nufold {
+
+// Write-through store and coherent load at device (agent) scope: a value
+// stored this way by one workgroup and followed by s_waitcnt(0) is visible to
+// a load_agent of any other workgroup, on any XCD, that observes a later
+// counter update; no cache write-back is needed.
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of a double over the 64 lanes of a wavefront in a fixed order, returned
+// to every lane: pairs, quads, half-rows and rows by DPP lane swaps (every lane
+// of a group ends with the same group total), then the four row totals read
+// from lanes 0, 16, 32, 48 and added as (r0 + r1) + (r2 + r3). Needs all lanes
+// active; uses no address registers.
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+__device__ __forceinline__ double wave_sum_fixed(double x) {
+  x += dpp_swap<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_swap<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_swap<0x141>(x);  // row_half_mirror
+  x += dpp_swap<0x140>(x);  // row_mirror
+  return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
+}
+
+// Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
+// linear combination of (W, M_1..M_NM). Returns false outside the domain.
+__device__ inline bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {
+  double v[NSLOT];
+  for (int j = 0; j < NSLOT; ++j) v[j] = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];
+  for (int i = 0; i < 40; ++i) cf[i] = 0.0;
+  bool ok = true;
+  for (int j = 0; j < NSLOT; ++j) ok = ok && isfinite(v[j]);
+  if (o.formula == FORM_EQ1) {
+    // moments: 1 C_ee, 2 C_21, 3 Q_ee, 4 Q_21
+    const double s = v[0], s12 = v[2];
+    if (!(s < 1.0)) return false;
+    const double r = sqrt(1.0 - s);
+    const double c13sq = 0.5 * (1.0 + r);
+    const double c4 = c13sq * c13sq;
+    const double s2t12 = 4.0 * s12 * (1.0 - s12);
+    const double A = c4 * s2t12;
+    const double dA_ds = -s2t12 * c13sq / (2.0 * r);
+    const double dA_ds12 = c4 * 4.0 * (1.0 - 2.0 * s12);
+    const double aee = TWO_PHASE_K * UNIT_1EM3, a21 = TWO_PHASE_K * UNIT_1EM5;
+    double* r0 = cf;
+    r0[0] = 1.0 - 0.5 * s - 0.5 * A; r0[1] = 0.5 * s; r0[2] = 0.5 * A;
+    double* r1 = cf + 8;   // d/d sin^2(2 th13)
+    r1[0] = -0.5 - 0.5 * dA_ds; r1[1] = 0.5; r1[2] = 0.5 * dA_ds;
+    double* r2 = cf + 16;  // d/d dm2_ee
+    r2[3] = -0.5 * s * aee;
+    double* r3 = cf + 24;  // d/d sin^2 th12
+    r3[0] = -0.5 * dA_ds12; r3[2] = 0.5 * dA_ds12;
+    double* r4 = cf + 32;  // d/d dm2_21
+    r4[4] = -0.5 * A * a21;
+  } else {
+    // moments: 1 C_21, 2 C_31, 3 C_32, 4 Q_21, 5 Q_31, 6 Q_32
+    const double s12 = v[0], s13 = v[1];
+    const double c12 = 1.0 - s12, c13 = 1.0 - s13;
+    const double K21 = 4.0 * c12 * s12 * c13 * c13;
+    const double K31 = 4.0 * c12 * c13 * s13;
+    const double K32 = 4.0 * s12 * c13 * s13;
+    const double a21 = TWO_PHASE_K * UNIT_1EM5, a31 = TWO_PHASE_K * UNIT_1EM3;
+    double* r0 = cf;
+    r0[0] = 1.0 - 0.5 * (K21 + K31 + K32);
+    r0[1] = 0.5 * K21; r0[2] = 0.5 * K31; r0[3] = 0.5 * K32;
+    const double d12[3] = {4.0 * (1.0 - 2.0 * s12) * c13 * c13, -4.0 * c13 * s13, 4.0 * c13 * s13};
+    const double d13[3] = {-8.0 * c12 * s12 * c13, 4.0 * c12 * (1.0 - 2.0 * s13),
+                           4.0 * s12 * (1.0 - 2.0 * s13)};
+    double* r1 = cf + 8;
+    double* r2 = cf + 16;
+    r1[0] = -0.5 * (d12[0] + d12[1] + d12[2]);
+    r2[0] = -0.5 * (d13[0] + d13[1] + d13[2]);
+    for (int j = 0; j < 3; ++j) {
+      r1[1 + j] = 0.5 * d12[j];
+      r2[1 + j] = 0.5 * d13[j];
+    }
+    double* r3 = cf + 24;  // d/d dm2_21: x21 grows, x32 = x31 - x21 shrinks
+    r3[4] = -0.5 * K21 * a21; r3[6] = 0.5 * K32 * a21;
+    double* r4 = cf + 32;  // d/d dm2_31
+    r4[5] = -0.5 * K31 * a31; r4[6] = -0.5 * K32 * a31;
+  }
+  return ok;
+}
+
+}  // namespace nufold

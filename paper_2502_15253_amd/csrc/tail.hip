@@ -1,17 +1,11 @@
 // Bin stages, NLL and adjoint gradient of one model evaluation.
 //
-// Phase A (many workgroups, one wavefront per fine bin, lane s = source):
-// sum the fold's partial moments of each (dataset, source, fine-bin) segment
-// in a fixed order, turn them into the oscillated fine spectrum S and its
-// derivatives with respect to the four oscillation slots (linear in the
-// moments), apply the source normalisation A_s and reduce over sources; the
-// same wavefront evaluates the flux-shape factor 1 + F_k. Further wavefronts
-// evaluate the prior rows (Gaussian and correlated-Gaussian, independent of
-// the fold). Phase A results are written with agent-scope (write-through)
-// atomic stores; each workgroup waits for its stores to complete and then
-// bumps a counter; the last workgroup runs the serial part, reading those
-// results with agent-scope atomic loads, and resets the counter. No L2
-// write-back is needed for the hand-off.
+// Inputs per fine bin k of a dataset: Hs[k] = sum_s A_s S[s][k] (oscillated
+// spectrum with source norms) and its derivatives with respect to the four
+// oscillation slots, and S[s][k] per source. For a single evaluation the fold
+// kernel has produced them; for a batch of fits each fit's workgroup first
+// sums the fold's partial moments itself (phase A, one thread per segment,
+// then per fine bin).
 //
 // Serial part (one workgroup; bin stages are latency-bound), per dataset
 // (paper, "Structure of the framework", steps 2 and 3, and Eq. 3-6, 9):
@@ -38,15 +32,10 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "osc.hpp"
 
 namespace nufold {
 
-__device__ __forceinline__ void store_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <int NT>
 struct Lds {
@@ -212,139 +201,31 @@ __device__ __forceinline__ double pval(const double* th, int idx, double dflt) {
   return idx >= 0 ? th[idx] : dflt;
 }
 
-// Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
-// linear combination of (W, M_1..M_NM). Returns false outside the domain.
-__device__ bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {
-  double v[NSLOT];
-  for (int j = 0; j < NSLOT; ++j) v[j] = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];
-  for (int i = 0; i < 40; ++i) cf[i] = 0.0;
-  bool ok = true;
-  for (int j = 0; j < NSLOT; ++j) ok = ok && isfinite(v[j]);
-  if (o.formula == FORM_EQ1) {
-    // moments: 1 C_ee, 2 C_21, 3 Q_ee, 4 Q_21
-    const double s = v[0], s12 = v[2];
-    if (!(s < 1.0)) return false;
-    const double r = sqrt(1.0 - s);
-    const double c13sq = 0.5 * (1.0 + r);
-    const double c4 = c13sq * c13sq;
-    const double s2t12 = 4.0 * s12 * (1.0 - s12);
-    const double A = c4 * s2t12;
-    const double dA_ds = -s2t12 * c13sq / (2.0 * r);
-    const double dA_ds12 = c4 * 4.0 * (1.0 - 2.0 * s12);
-    const double aee = TWO_PHASE_K * UNIT_1EM3, a21 = TWO_PHASE_K * UNIT_1EM5;
-    double* r0 = cf;
-    r0[0] = 1.0 - 0.5 * s - 0.5 * A; r0[1] = 0.5 * s; r0[2] = 0.5 * A;
-    double* r1 = cf + 8;   // d/d sin^2(2 th13)
-    r1[0] = -0.5 - 0.5 * dA_ds; r1[1] = 0.5; r1[2] = 0.5 * dA_ds;
-    double* r2 = cf + 16;  // d/d dm2_ee
-    r2[3] = -0.5 * s * aee;
-    double* r3 = cf + 24;  // d/d sin^2 th12
-    r3[0] = -0.5 * dA_ds12; r3[2] = 0.5 * dA_ds12;
-    double* r4 = cf + 32;  // d/d dm2_21
-    r4[4] = -0.5 * A * a21;
-  } else {
-    // moments: 1 C_21, 2 C_31, 3 C_32, 4 Q_21, 5 Q_31, 6 Q_32
-    const double s12 = v[0], s13 = v[1];
-    const double c12 = 1.0 - s12, c13 = 1.0 - s13;
-    const double K21 = 4.0 * c12 * s12 * c13 * c13;
-    const double K31 = 4.0 * c12 * c13 * s13;
-    const double K32 = 4.0 * s12 * c13 * s13;
-    const double a21 = TWO_PHASE_K * UNIT_1EM5, a31 = TWO_PHASE_K * UNIT_1EM3;
-    double* r0 = cf;
-    r0[0] = 1.0 - 0.5 * (K21 + K31 + K32);
-    r0[1] = 0.5 * K21; r0[2] = 0.5 * K31; r0[3] = 0.5 * K32;
-    const double d12[3] = {4.0 * (1.0 - 2.0 * s12) * c13 * c13, -4.0 * c13 * s13, 4.0 * c13 * s13};
-    const double d13[3] = {-8.0 * c12 * s12 * c13, 4.0 * c12 * (1.0 - 2.0 * s13),
-                           4.0 * s12 * (1.0 - 2.0 * s13)};
-    double* r1 = cf + 8;
-    double* r2 = cf + 16;
-    r1[0] = -0.5 * (d12[0] + d12[1] + d12[2]);
-    r2[0] = -0.5 * (d13[0] + d13[1] + d13[2]);
-    for (int j = 0; j < 3; ++j) {
-      r1[1 + j] = 0.5 * d12[j];
-      r2[1 + j] = 0.5 * d13[j];
-    }
-    double* r3 = cf + 24;  // d/d dm2_21: x21 grows, x32 = x31 - x21 shrinks
-    r3[4] = -0.5 * K21 * a21; r3[6] = 0.5 * K32 * a21;
-    double* r4 = cf + 32;  // d/d dm2_31
-    r4[5] = -0.5 * K31 * a31; r4[6] = -0.5 * K32 * a31;
-  }
-  return ok;
-}
-
 }  // namespace nufold
 #include "minimize.hpp"
 namespace nufold {
 
-// ---------------------------------------------------------------- phase A
-// Wavefront w < KT: global fine bin w. Wavefront KT + r: prior rows 64 r .. 64 r + 63.
-template <int NT>
-__device__ void phase_a(const DevPlan& p, const EvalIO& io, const Lds<NT>& L, int w) {
-  const int lane = threadIdx.x & 63;
-  const int NMOM = num_moments(p.osc.formula);
-  if (w < p.KT) {
-    const int* info = p.ipool + p.kt_info + 5 * w;
-    const int g0 = info[0], K = info[1], S = info[2], fs0 = info[3], kt0 = info[4];
-    const int k = w - kt0;
-    double hs = 0.0, gsum[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int s = lane; s < S; s += 64) {
-      const int g = g0 + s * K;
-      double M[MAX_MOM + 1];
-      M[0] = p.Wseg[g];
-      for (int c = 1; c <= MAX_MOM; ++c) M[c] = 0.0;
-      const int ib = p.seg_item[g], ie = p.seg_item[g + 1];
-      for (int it = ib; it < ie; ++it)
-        for (int c = 0; c < NMOM; ++c) M[1 + c] += io.part[(int64_t)c * p.nitems + it];
-      const int* nl = p.ipool + p.fs_nl + NLMAX * (fs0 + s);
-      double A = 1.0;
-#pragma unroll
-      for (int q = 0; q < NLMAX; ++q)
-        if (nl[q] >= 0) A *= L.th[nl[q]];
-      double Sv = 0.0;
-      for (int c = 0; c <= NMOM; ++c) Sv += L.coef[c] * M[c];
-      store_agent(&io.Sseg[g], Sv);
-      hs += A * Sv;
-      for (int j = 0; j < 4; ++j) {
-        double gj = 0.0;
-        for (int c = 0; c <= NMOM; ++c) gj += L.coef[8 * (j + 1) + c] * M[c];
-        gsum[j] += A * gj;
-      }
-    }
-    // flux-shape factor of this fine bin
-    double F = 0.0;
-    const int rb = p.ipool[p.kt_row + w], re = p.ipool[p.kt_row + w + 1];
-    for (int e = rb + lane; e < re; e += 64) F += L.th[p.ipool[p.kt_par + e]] * p.dpool[p.kt_coef + e];
-    hs = wave_sum(hs);
-    for (int j = 0; j < 4; ++j) gsum[j] = wave_sum(gsum[j]);
-    F = wave_sum(F);
-    if (lane == 0) {
-      double* b = io.bin + 6 * (int64_t)kt0;
-      store_agent(&b[k], hs);
-      for (int j = 0; j < 4; ++j) store_agent(&b[(1 + j) * K + k], gsum[j]);
-      store_agent(&b[5 * K + k], 1.0 + F);
-    }
+// ---------------------------------------------------------------- priors
+// Prior row r (Eq. 6; third line of Eq. 9): v = its gradient contribution to
+// the row's parameter, e = its NLL contribution. Rows < ngauss are
+// independent Gaussians; the rest are rows of correlated blocks (V^-1 r).
+__device__ __forceinline__ void prior_row(const DevPlan& p, const double* th, int r, int& idx, double& v,
+                                          double& e) {
+  if (r < p.ngauss) {
+    idx = p.ipool[p.gidx + r];
+    const double z = th[idx] - p.dpool[p.gmean + r];
+    v = z * p.dpool[p.ginv + r];
+    e = 0.5 * z * v;
   } else {
-    const int r = (w - p.KT) * 64 + lane;
-    if (r < p.NR) {
-      double v, e;
-      if (r < p.ngauss) {
-        const double z = L.th[p.ipool[p.gidx + r]] - p.dpool[p.gmean + r];
-        v = z * p.dpool[p.ginv + r];
-        e = 0.5 * z * v;
-      } else {
-        const int bl = p.ipool[p.prow_blk + r - p.ngauss];
-        const int b = p.ipool[p.blk_ptr + bl], n = p.ipool[p.blk_ptr + bl + 1] - b;
-        const int row = r - p.ngauss - b;
-        const double* Vi = p.dpool + p.ipool[p.blk_inv + bl] + (int64_t)row * n;
-        v = 0.0;
+    const int bl = p.ipool[p.prow_blk + r - p.ngauss];
+    const int b = p.ipool[p.blk_ptr + bl], n = p.ipool[p.blk_ptr + bl + 1] - b;
+    const int row = r - p.ngauss - b;
+    const double* Vi = p.dpool + p.ipool[p.blk_inv + bl] + (int64_t)row * n;
+    v = 0.0;
 #pragma unroll 8
-        for (int c = 0; c < n; ++c)
-          v += Vi[c] * (L.th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
-        e = 0.5 * (L.th[p.ipool[p.blk_idx + b + row]] - p.dpool[p.blk_mean + b + row]) * v;
-      }
-      store_agent(&io.prior[r], v);
-      store_agent(&io.prior[p.NR + r], e);
-    }
+    for (int c = 0; c < n; ++c) v += Vi[c] * (th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
+    idx = p.ipool[p.blk_idx + b + row];
+    e = 0.5 * (th[idx] - p.dpool[p.blk_mean + b + row]) * v;
   }
 }
 
@@ -374,25 +255,41 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     L.Ss = L.dyn + 6 * K;
     L.nD = L.dyn + 6 * K + S * K;
 
-    // ---- stage: static blob (plain loads), phase-A results and data
+    // ---- stage: static blob (plain loads), fine-bin rows, per-segment S and data.
+    // Fused (single evaluation): rows 0..4 and S were written by the fold
+    // kernel (plain loads), row 5 = 1 + F is formed here. Otherwise they were
+    // written by this workgroup's phase A with agent-scope stores.
     stage<NT, 8>(L.st, p.dpool + ds.blob, ds.blob_n);
     {
+      const int nb = io.fused ? 5 * K : 6 * K;
       const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
       const double* b = io.bin + 6 * (int64_t)ds.kt0;
       const double* sg = io.Sseg + ds.seg0;
       const double* dt = io.data + ds.data;
-      constexpr int U = 8;
+      constexpr int U = 16;
       for (int base = 0; base < n3; base += NT * U) {
         double v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = base + u * NT + tid;
-          v[u] = i < n1 ? load_agent(b + i) : i < n2 ? load_agent(sg + (i - n1)) : i < n3 ? dt[i - n2] : 0.0;
+          if (io.fused)
+            v[u] = i < nb ? b[i] : i < n1 ? 0.0 : i < n2 ? sg[i - n1] : i < n3 ? dt[i - n2] : 0.0;
+          else
+            v[u] = i < n1 ? load_agent(b + i) : i < n2 ? load_agent(sg + (i - n1)) : i < n3 ? dt[i - n2] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = base + u * NT + tid;
-          if (i < n3) L.dyn[i] = v[u];
+          if (i < n3 && (i < nb || i >= n1)) L.dyn[i] = v[u];
+        }
+      }
+      if (io.fused) {
+        for (int k = tid; k < K; k += NT) {
+          const int kt = ds.kt0 + k;
+          double F = 0.0;
+          const int rb = p.ipool[p.kt_row + kt], re = p.ipool[p.kt_row + kt + 1];
+          for (int e = rb; e < re; ++e) F += L.th[p.ipool[p.kt_par + e]] * p.dpool[p.kt_coef + e];
+          L.F1[k] = 1.0 + F;
         }
       }
     }
@@ -622,15 +519,15 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     __syncthreads();
   }
 
-  // ---- priors (Eq. 6; third line of Eq. 9), rows evaluated in phase A
+  // ---- priors (Eq. 6; third line of Eq. 9)
   {
     double pr[1] = {0.0};
     for (int r = tid; r < p.NR; r += NT) {
-      pr[0] += load_agent(&io.prior[p.NR + r]);
-      if (want_grad) {
-        const int i = r < p.ngauss ? p.ipool[p.gidx + r] : p.ipool[p.blk_idx + (r - p.ngauss)];
-        atomicAdd(&L.grad[i], load_agent(&io.prior[r]));
-      }
+      int i;
+      double v, e;
+      prior_row(p, L.th, r, i, v, e);
+      pr[0] += e;
+      if (want_grad) atomicAdd(&L.grad[i], v);
     }
     block_sum<NT, 1>(pr, L.red);
     nll_total += pr[0];
@@ -645,6 +542,8 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   return bad ? INFINITY : nll_total;
 }
 
+// Single evaluation: one workgroup; the fold kernel has already reduced the
+// events to fine-bin rows 0..4 and per-segment S.
 template <int NT>
 __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   extern __shared__ double smem[];
@@ -663,20 +562,8 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
     if (!ok) L.flag[0] |= ST_DOMAIN;
   }
   __syncthreads();
-  const EvalIO io{a.theta, a.part, a.data, a.out, a.status, a.mu_out, a.Sseg, a.bin, a.prior};
-  phase_a<NT>(p, io, L, (int)((blockIdx.x * NT + threadIdx.x) >> 6));
-
-  // ---- hand-off: our write-through stores are complete before we count
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (tid == 0) {
-    const int done = __hip_atomic_fetch_add(a.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    L.flag[1] = (done == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!L.flag[1]) return;
-  if (tid == 0) __hip_atomic_store(a.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
+  const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
+                  const_cast<double*>(a.bin), 1};
   const double f = serial_stages<NT>(p, io, L, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
 }
@@ -710,7 +597,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   const DevPlan& p = a.plan;
   Lds<NT> L = carve<NT>(smem, p);
   const int tid = threadIdx.x;
-  const int P = p.P, G = p.G, KT = p.KT, NR = p.NR;
+  const int P = p.P, G = p.G, KT = p.KT;
   const int NMOM = num_moments(p.osc.formula);
   const double* th = a.theta + (int64_t)f * P;
   for (int i = tid; i < P; i += NT) {
@@ -732,7 +619,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
                   a.mu_out ? a.mu_out + (int64_t)f * p.nbins_total : nullptr,
                   a.Sseg + (int64_t)f * G,
                   a.bin + (int64_t)f * 6 * KT,
-                  a.prior + (int64_t)f * 2 * NR};
+                  0};
   double* tmp = a.segtmp + (int64_t)f * 5 * G;
   // phase A, per segment
   for (int g = tid; g < G; g += NT) {
@@ -756,26 +643,6 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
       for (int c = 0; c <= NMOM; ++c) gj += L.coef[8 * (j + 1) + c] * M[c];
       tmp[(int64_t)(1 + j) * G + g] = A * gj;
     }
-  }
-  // prior rows
-  for (int r = tid; r < NR; r += NT) {
-    double v, e;
-    if (r < p.ngauss) {
-      const double z = L.th[p.ipool[p.gidx + r]] - p.dpool[p.gmean + r];
-      v = z * p.dpool[p.ginv + r];
-      e = 0.5 * z * v;
-    } else {
-      const int bl = p.ipool[p.prow_blk + r - p.ngauss];
-      const int b = p.ipool[p.blk_ptr + bl], n = p.ipool[p.blk_ptr + bl + 1] - b;
-      const int row = r - p.ngauss - b;
-      const double* Vi = p.dpool + p.ipool[p.blk_inv + bl] + (int64_t)row * n;
-      v = 0.0;
-      for (int c = 0; c < n; ++c)
-        v += Vi[c] * (L.th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
-      e = 0.5 * (L.th[p.ipool[p.blk_idx + b + row]] - p.dpool[p.blk_mean + b + row]) * v;
-    }
-    store_agent(&io.prior[r], v);
-    store_agent(&io.prior[NR + r], e);
   }
   __syncthreads();
   // per fine bin: sum over sources, flux factor
@@ -823,15 +690,9 @@ hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream)
   return hipGetLastError();
 }
 
-int tail_blocks(const DevPlan& p, int nt) {
-  const int waves = p.KT + (p.NR + 63) / 64;
-  const int b = (waves + nt / 64 - 1) / (nt / 64);
-  return b < 1 ? 1 : b;
-}
-
 hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream) {
   const size_t lds = tail_lds_bytes(a.plan, nt);
-  const dim3 grid(tail_blocks(a.plan, nt));
+  const dim3 grid(1);
   switch (nt) {
     case 256:
       hipLaunchKernelGGL(tail_kernel<256>, grid, dim3(256), lds, stream, a);
