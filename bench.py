@@ -100,27 +100,38 @@ def engine_for(nf, synth, config, stream, n_events=None):
     return desc, events, eng
 
 
-def plain_fit(eng, start, h=1e-6):
+def plain_fit(eng, desc, start, h=1e-6):
     """The paper's method on the GPU: one fit at a time, BFGS on the host with
     central finite-difference gradients, every function value one GPU
-    evaluation (fold + bin stages + NLL). Returns (NLL, evaluations)."""
+    evaluation (fold + bin stages + NLL). Like Minuit's internal parameters,
+    the minimiser works in scaled variables z = (theta - start) / s, with s the
+    prior width (else 5% of the start value), so that its initial metric is
+    sensible; fixed parameters stay at their start. Returns (NLL, evaluations)."""
     from scipy.optimize import minimize
+    free = np.array([not p["fixed"] for p in desc["params"]])
+    scale = np.array([p["prior"][1] if p["prior"] else 0.05 * max(abs(p["start"]), 0.02)
+                      for p in desc["params"]])
+    idx = np.where(free)[0]
     n = [0]
 
-    def f(x):
-        n[0] += 1
-        return eng.eval_nll(x)[0]
+    def theta(z):
+        th = np.array(start, dtype=np.float64)
+        th[idx] += scale[idx] * z
+        return th
 
-    def g(x):
-        out = np.zeros_like(x)
-        for i in range(len(x)):
-            e = np.zeros_like(x)
-            e[i] = h
-            out[i] = (eng.eval_nll(x + e)[0] - eng.eval_nll(x - e)[0]) / (2 * h)
-        n[0] += 2 * len(x)
+    def f(z):
+        n[0] += 1
+        return eng.eval_nll(theta(z))[0]
+
+    def g(z):
+        out = np.zeros_like(z)
+        for j in range(len(z)):
+            e = np.zeros_like(z)
+            e[j] = h
+            out[j] = (f(z + e) - f(z - e)) / (2 * h)
         return out
 
-    r = minimize(f, start, jac=g, method="BFGS", options=dict(gtol=1e-5, maxiter=5000))
+    r = minimize(f, np.zeros(len(idx)), jac=g, method="BFGS", options=dict(gtol=1e-6, maxiter=5000))
     return r.fun, n[0]
 
 
@@ -155,7 +166,7 @@ def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
             for j in range(n_plain):
                 for d in range(len(desc["datasets"])):
                     eng.set_data(d, data[j][nb[d]:nb[d + 1]])
-                fmin, ne = plain_fit(eng, start[j])
+                fmin, ne = plain_fit(eng, desc, start[j])
                 nev += ne
                 dmax = max(dmax, 2.0 * abs(fmin - r["nll"][j]))
             tp = time.perf_counter() - t0
@@ -199,7 +210,7 @@ def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
     return out
 
 
-def warm_start_section(nf, synth, torch, stream, n_samples, E=256):
+def warm_start_section(nf, synth, torch, stream, n_samples, E=256, n_plain=2):
     """Medium-baseline pseudo-experiments at random points of the training box:
     exact batched fits from the box centre (cold) and from the surrogate's
     proposal (warm). A third fit from the generating point gives the reference
@@ -248,6 +259,19 @@ def warm_start_section(nf, synth, torch, stream, n_samples, E=256):
     tw = time.perf_counter() - t0
     rt = eng.fit_batch(truths, edm_tol=1e-6, max_iter=2000)
     best = np.minimum(np.minimum(rc["nll"], rw["nll"]), rt["nll"])
+    # the plain per-fit GPU path on the first pseudo-experiments, from the same
+    # surrogate starts (so both find the same minimum): host BFGS with central
+    # finite-difference gradients, every value one GPU evaluation
+    nb = np.cumsum([0] + [len(ds["edges"]) - 1 for ds in desc["datasets"]])
+    t0 = time.perf_counter()
+    dmax, nev = 0.0, 0
+    for j in range(n_plain):
+        for d in range(len(desc["datasets"])):
+            eng.set_data(d, data[j][nb[d]:nb[d + 1]])
+        fmin, ne = plain_fit(eng, desc, warm[j])
+        nev += ne
+        dmax = max(dmax, 2.0 * abs(fmin - rw["nll"][j]))
+    tp = time.perf_counter() - t0
     res = dict(pseudo_experiments=E, training_spectra=len(X), generate_s=t_gen, train_s=t_train,
                train_tflops=6.0 * sur.net.nparam * 1024 * steps / t_train / 1e12,
                heldout_rms_dlogmu=float(np.sqrt(np.mean(err ** 2))),
@@ -255,10 +279,29 @@ def warm_start_section(nf, synth, torch, stream, n_samples, E=256):
                          mean_iters=float(rc["iters"].mean())),
                warm=dict(seconds=tsur + tw, surrogate_s=tsur, fits_per_s=E / (tsur + tw),
                          found_global_min=float(np.mean(rw["nll"] - best < 5e-4)),
-                         mean_iters=float(rw["iters"].mean())))
+                         mean_iters=float(rw["iters"].mean())),
+               plain=dict(fits=n_plain, seconds=tp, fits_per_s=n_plain / tp, evals_per_fit=nev / max(1, n_plain),
+                          max_delta_chi2_vs_batched=dmax))
+    res["warm_over_plain"] = res["warm"]["fits_per_s"] / res["plain"]["fits_per_s"]
     eng.close()
     log(f"warm start: {json.dumps(res)}")
     return res
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Achievable device-memory bandwidth: a plain device-to-device copy
+    (bytes read + bytes written per second)."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return 2 * nbytes / dt / 1e9
 
 
 def main():
@@ -327,6 +370,9 @@ def main():
         cnt, fold_ms, tail_ms = eng.timing(reset=True)
         eng.set_option("timing", 0)
         assert cnt == args.steps
+        # fixed cost inside every event-timed region (event packets, dispatch
+        # and completion of the launch), measured on the same stream
+        ev_over_us = eng.timing_overhead(200)
         assert bool(torch.isfinite(out_dev).all()), "non-finite NLL/gradient in the timed loop"
         # host C-ABI path, synchronous, including H2D of theta and D2H of NLL + gradient
         th_np = thetas
@@ -336,16 +382,18 @@ def main():
             eng.eval_nll_grad(th_np[k % 64])
         h1 = time.perf_counter()
         bpe = 12 if mode == "m64" else 8
-        fold_avg_s = fold_ms / cnt / 1e3
-        achieved = n_in * bpe / fold_avg_s / 1e9
+        fold_us = fold_ms / cnt * 1e3
+        achieved = n_in * bpe / (fold_us * 1e-6) / 1e9
         traffic = measured_traffic(mode, n_in * bpe)
         res = dict(
             evals_per_s=args.steps / (t1 - t0), ms_per_step=(t1 - t0) * 1e3 / args.steps,
-            fold_us=fold_ms / cnt * 1e3, tail_us=tail_ms / cnt * 1e3,
+            fold_us=fold_us, tail_us=tail_ms / cnt * 1e3, event_pair_gap_us=ev_over_us,
             host_path_evals_per_s=nh / (h1 - h0), events_in_range=n_in,
             roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                          algorithmic_bytes_per_launch=n_in * bpe))
+                          algorithmic_bytes_per_launch=n_in * bpe,
+                          duration="mean fold duration from HIP events recorded around every fold "
+                                   "launch of the timed region on the engine stream"))
         eng.close()
         log(f"{mode}: {json.dumps(res)}")
         return res
@@ -383,14 +431,21 @@ def main():
             e.close()
         assert cnt == steps and bool(torch.isfinite(out_dev).all())
         bpe = 12 if mode == "m64" else 8
-        achieved = n_in * bpe / (fold_ms / cnt / 1e3) / 1e9
+        fold_us = fold_ms / cnt * 1e3
+        achieved = n_in * bpe / (fold_us * 1e-6) / 1e9
         res = dict(replicas=R, resident_bytes=R * n_in * bpe, evals_per_s=steps / (t1 - t0),
-                   fold_us=fold_ms / cnt * 1e3, tail_us=tail_ms / cnt * 1e3,
+                   fold_us=fold_us, tail_us=tail_ms / cnt * 1e3,
                    achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS)
         log(f"{mode} cold: {json.dumps(res)}")
         return res
 
+    copy_gbs = copy_bandwidth(torch)
+    log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
     main_res = run(args.mode)
+    main_res["roofline"]["frac_of_copy_bandwidth"] = main_res["roofline"]["achieved"] / copy_gbs
+    main_res["roofline"]["copy_bandwidth_gbs"] = copy_gbs
+    main_res["roofline"]["frac_whole_evaluation"] = (main_res["roofline"]["algorithmic_bytes_per_launch"]
+                                                     / (main_res["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
     cold = None
     if args.replicas > 0:
         cold = run_cold(args.mode, args.replicas, max(args.steps, 4 * args.replicas))

@@ -261,6 +261,14 @@ int nf_expected_batch(nf_ctx* ctx, int B, const double* theta, double* mu);
 int nf_timing(nf_ctx* ctx, int reset, int64_t* count, double* fold_ms, double* tail_ms);
 
 /*
+ * Mean time (microseconds, over n samples) between two timing events recorded
+ * back to back on the context stream with no work between them: the fixed
+ * cost (event packets, dispatch and completion of the timed launch) that is
+ * included in every per-kernel duration nf_timing reports. Synchronises.
+ */
+int nf_timing_overhead(nf_ctx* ctx, int n, double* us);
+
+/*
  * ---------------------------------------------------------------------------
  * Surrogate: a dense network  x (n_in) -> [Linear -> GELU] x depth -> Linear
  * -> y (n_out)  that maps a subset of the parameters to the (standardised)

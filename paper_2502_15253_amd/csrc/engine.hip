@@ -470,7 +470,7 @@ void parse_model(nf_ctx* c, const char* text) {
     for (size_t di = 0; di < c->dsplan.size(); ++di) {
       DsPlan& q = c->dsplan[di];
       const HostDataset& d = c->ds[di];
-      const BlobLayout B = blob_layout(q.Nb + 1, q.nbkg, q.Nb, q.nnz, q.M, q.S, q.nl);
+      const BlobLayout B = blob_layout(q.Nb + 1, q.nbkg, q.Nb, q.nnz, q.M, q.S, q.nl, q.K);
       std::vector<double> blob(B.total, 0.0);
       for (int i = 0; i <= q.Nb; ++i) blob[B.edges + i] = d.edges[i];
       for (int b = 0; b < q.nbkg; ++b) {
@@ -490,6 +490,11 @@ void parse_model(nf_ctx* c, const char* text) {
       for (int m = 0; m < q.M; ++m) blob[B.mdp + m] = ip[q.md_param + m];
       for (int s = 0; s <= q.S; ++s) blob[B.nlp + s] = ip[q.srcnorm_ptr + s] - q.nl0;
       for (int j = 0; j < q.nl; ++j) blob[B.nli + j] = ip[q.nl0 + j];
+      for (int k = 0; k <= q.K; ++k) blob[B.frow + k] = ip[q.fx_row + k];
+      for (int e = 0; e < q.nnz; ++e) {
+        blob[B.fpar + e] = d.flux_param[ip[q.fx_mode + e]];
+        blob[B.fcf + e] = dp[q.fx_coef + e];
+      }
       q.blob = (int)dp.size();
       q.blob_n = B.total;
       dp.insert(dp.end(), blob.begin(), blob.end());
@@ -1648,6 +1653,22 @@ int nf_set_data_batch(nf_ctx* ctx, int nsets, const double* counts, int on_devic
     hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     ctx->bt_nsets = nsets;
     drop_fit_graph(ctx);
+    return NF_OK;
+  });
+}
+
+int nf_timing_overhead(nf_ctx* ctx, int n, double* us) {
+  return guarded(ctx, [&] {
+    if (n < 1 || !us) fail(NF_EINVAL, "n >= 1 and us are required");
+    hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+      EventPair ev;
+      hip_check(hipEventRecord(ev.a, ctx->stream), "hipEventRecord");
+      hip_check(hipEventRecord(ev.b, ctx->stream), "hipEventRecord");
+      total += ev.us_per(1);
+    }
+    *us = total / n;
     return NF_OK;
   });
 }

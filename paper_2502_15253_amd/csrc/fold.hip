@@ -44,6 +44,22 @@ __device__ __forceinline__ double slot_val(const OscPlan& o, const double* th, i
 }
 
 // Angular frequencies a (rad per m/MeV) of the two computed phases x = a * u.
+
+// Streaming loads of the event arrays in the single evaluation: each event is
+// read once per evaluation, so the loads carry the non-temporal hint and do
+// not displace the bin-stage kernel's inputs and code from the caches. (The
+// batched fold re-reads events for every tile of fits and keeps plain loads.)
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 load_stream2(const double* p) {
+  const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+  return double2{v.x, v.y};
+}
+__device__ __forceinline__ float4 load_stream4(const float* p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  return float4{v.x, v.y, v.z, v.w};
+}
+
 template <int FORM>
 __device__ __forceinline__ void fold_freqs(const OscPlan& o, const double* th, double& a1, double& a2) {
   if (FORM == FORM_EQ1) {
@@ -274,22 +290,22 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   for (int c = 0; c < NM; ++c) m[c] = 0.0;
   int j = lane * 4;
   int64_t o = j < cnt ? it.begin + j : a.zpad;
-  double2 pa = *reinterpret_cast<const double2*>(u + o);
-  double2 qa = *reinterpret_cast<const double2*>(u + o + 2);
-  float4 wa = *reinterpret_cast<const float4*>(w + o);
+  double2 pa = load_stream2(u + o);
+  double2 qa = load_stream2(u + o + 2);
+  float4 wa = load_stream4(w + o);
   for (int t = 0; t < niter; t += 2) {
     const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
-    const double2 pb = *reinterpret_cast<const double2*>(u + ob);
-    const double2 qb = *reinterpret_cast<const double2*>(u + ob + 2);
-    const float4 wb = *reinterpret_cast<const float4*>(w + ob);
+    const double2 pb = load_stream2(u + ob);
+    const double2 qb = load_stream2(u + ob + 2);
+    const float4 wb = load_stream4(w + ob);
     accum64<FORM>(pa.x, wa.x, a1, a2, m);
     accum64<FORM>(pa.y, wa.y, a1, a2, m);
     accum64<FORM>(qa.x, wa.z, a1, a2, m);
     accum64<FORM>(qa.y, wa.w, a1, a2, m);
     const int64_t on = j + 512 < cnt ? it.begin + j + 512 : a.zpad;
-    pa = *reinterpret_cast<const double2*>(u + on);
-    qa = *reinterpret_cast<const double2*>(u + on + 2);
-    wa = *reinterpret_cast<const float4*>(w + on);
+    pa = load_stream2(u + on);
+    qa = load_stream2(u + on + 2);
+    wa = load_stream4(w + on);
     accum64<FORM>(pb.x, wb.x, a1, a2, m);
     accum64<FORM>(pb.y, wb.y, a1, a2, m);
     accum64<FORM>(qb.x, wb.z, a1, a2, m);
@@ -324,19 +340,19 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   for (int c = 0; c < NM; ++c) mf[c] = 0.0f;
   int j = lane * 4;
   int64_t o = j < cnt ? it.begin + j : a.zpad;
-  float4 ua = *reinterpret_cast<const float4*>(u + o);
-  float4 wa = *reinterpret_cast<const float4*>(w + o);
+  float4 ua = load_stream4(u + o);
+  float4 wa = load_stream4(w + o);
   for (int t = 0; t < niter; t += 2) {
     const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
-    const float4 ub = *reinterpret_cast<const float4*>(u + ob);
-    const float4 wb = *reinterpret_cast<const float4*>(w + ob);
+    const float4 ub = load_stream4(u + ob);
+    const float4 wb = load_stream4(w + ob);
     accum32<FORM>(ua.x, wa.x, b1h, b1l, b2h, b2l, mf);
     accum32<FORM>(ua.y, wa.y, b1h, b1l, b2h, b2l, mf);
     accum32<FORM>(ua.z, wa.z, b1h, b1l, b2h, b2l, mf);
     accum32<FORM>(ua.w, wa.w, b1h, b1l, b2h, b2l, mf);
     const int64_t on = j + 512 < cnt ? it.begin + j + 512 : a.zpad;
-    ua = *reinterpret_cast<const float4*>(u + on);
-    wa = *reinterpret_cast<const float4*>(w + on);
+    ua = load_stream4(u + on);
+    wa = load_stream4(w + on);
     accum32<FORM>(ub.x, wb.x, b1h, b1l, b2h, b2l, mf);
     accum32<FORM>(ub.y, wb.y, b1h, b1l, b2h, b2l, mf);
     accum32<FORM>(ub.z, wb.z, b1h, b1l, b2h, b2l, mf);

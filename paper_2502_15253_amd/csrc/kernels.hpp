@@ -145,7 +145,7 @@ __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
   const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
   const size_t nd = 2 * (size_t)p.P + 40 + 16 * (nt / 64) + 16 + 6 * K + (size_t)p.max_S * K + Nb +
                     4 * (K + 1) + K + 3 * E + Nb + p.max_blob;
-  const size_t ni = E + 2;
+  const size_t ni = E + 2 + K + 3;
   return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }
 

@@ -41,6 +41,36 @@ __device__ __forceinline__ double wave_sum_fixed(double x) {
   return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
 }
 
+// Inclusive prefix sum of a double over the 64 lanes of a wavefront in a
+// fixed order: Hillis-Steele steps within each 16-lane row (row_shr 1, 2, 4,
+// 8), then the row totals carried across rows (row_bcast 15 and 31).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_shift0(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_scan_incl(double x) {
+  x += dpp_shift0<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_shift0<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_shift0<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_shift0<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_shift0<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_shift0<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+// Sum over aligned groups of NW lanes (NW = 2, 4, 8 or 16); every lane of a
+// group gets its group's total.
+template <int NW>
+__device__ __forceinline__ double group_sum(double x) {
+  if (NW >= 2) x += dpp_swap<0xB1>(x);
+  if (NW >= 4) x += dpp_swap<0x4E>(x);
+  if (NW >= 8) x += dpp_swap<0x141>(x);
+  if (NW >= 16) x += dpp_swap<0x140>(x);
+  return x;
+}
+
 // Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
 // linear combination of (W, M_1..M_NM). Returns false outside the domain.
 __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {

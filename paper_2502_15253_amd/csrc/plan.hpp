@@ -73,9 +73,9 @@ constexpr int NLMAX = 8;  // norm parameters multiplying one source
 // Per-dataset static inputs of the bin stages, packed contiguously (integers
 // stored as exact doubles) so one batched copy stages them in LDS.
 struct BlobLayout {
-  int edges, tmpl, mdc, bsc, brt, shp, mdcol, mdk, mdp, nlp, nli, total;
+  int edges, tmpl, mdc, bsc, brt, shp, mdcol, mdk, mdp, nlp, nli, frow, fpar, fcf, total;
 };
-__host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl) {
+__host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K) {
   BlobLayout L;
   int o = 0;
   L.edges = o; o += E;
@@ -89,6 +89,9 @@ __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz,
   L.mdp = o; o += M;
   L.nlp = o; o += S + 1;
   L.nli = o; o += nl;
+  L.frow = o; o += K + 1;   // flux basis by fine bin (CSR): row pointers,
+  L.fpar = o; o += nnz;     // parameter index and
+  L.fcf = o; o += nnz;      // coefficient of each entry
   L.total = o;
   return L;
 }

@@ -60,7 +60,8 @@ struct Lds {
   double* mu;     // Nb   lambda_mu
   double* st;     // static blob of the current dataset (edges become X, then lambda_X)
   double* fit;    // minimiser scratch
-  int* kidx;      // E
+  int* kidx;      // E    fine bin of each mapped analysis edge (monotone)
+  int* first;     // K+3  first[k + 1] = first edge with kidx >= k, k = -1 .. K+1
   int* flag;      // 2
 };
 
@@ -87,16 +88,13 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.fit = q; q += fit_lds_doubles(p.P, p.fit_m);
   int* r = reinterpret_cast<int*>(q);
   L.kidx = r; r += E;
+  L.first = r; r += K + 3;
   L.flag = r;
   L.Hs = L.Gs = L.F1 = L.Ss = L.nD = nullptr;
   return L;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_fixed(v); }
 
 // Sum of N values over the workgroup; every thread gets the totals. Wave
 // partials go to red[j*NW + w]; groups of NW lanes finish them with shuffles.
@@ -112,10 +110,9 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
     for (int j = 0; j < N; ++j) red[j * NW + wid] = v[j];
   }
   __syncthreads();
-  if (wid < (N * NW + 63) / 64) {  // whole wavefronts take part in the shuffles
+  if (wid < (N * NW + 63) / 64) {  // whole wavefronts take part in the lane swaps
     double x = tid < N * NW ? red[tid] : 0.0;
-#pragma unroll
-    for (int off = NW / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    x = group_sum<NW>(x);
     if (tid < N * NW && (tid % NW) == 0) red[16 * NW + tid / NW] = x;
   }
   __syncthreads();
@@ -134,22 +131,12 @@ __device__ void block_scan(const double* x, double* out, int n, bool reverse, do
   double s = 0.0;
   for (int i = lo; i < hi; ++i) s += reverse ? x[n - 1 - i] : x[i];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double v = s;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double t = __shfl_up(v, off, 64);
-    if (lane >= off) v += t;
-  }
+  const double v = wave_scan_incl(s);
   if (lane == 63) red[wid] = v;
   __syncthreads();
   if (wid == 0) {  // exclusive scan of the wave totals
     const double w = lane < NW ? red[lane] : 0.0;
-    double incl = w;
-#pragma unroll
-    for (int off = 1; off < NW; off <<= 1) {
-      const double t = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += t;
-    }
+    const double incl = wave_scan_incl(w);
     if (lane < NW) red[NW + lane] = incl - w;
   }
   __syncthreads();
@@ -186,15 +173,6 @@ __device__ __forceinline__ void stage(double* dst, const double* src, int n) {
       if (i < n) dst[i] = v[u];
     }
   }
-}
-
-__device__ __forceinline__ int lower_bound_int(const int* a, int n, int key) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] < key) lo = mid + 1; else hi = mid;
-  }
-  return lo;
 }
 
 __device__ __forceinline__ double pval(const double* th, int idx, double dflt) {
@@ -243,7 +221,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     const DsPlan& ds = p.ds[d];
     const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
     const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
-    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl);
+    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
     double* X = L.st + BL.edges;  // edges, then X, then lambda_X
     const double* tmpl = L.st + BL.tmpl;
     const double* shp = L.st + BL.shp;
@@ -255,57 +233,75 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     L.Ss = L.dyn + 6 * K;
     L.nD = L.dyn + 6 * K + S * K;
 
-    // ---- stage: static blob (plain loads), fine-bin rows, per-segment S and data.
+    // ---- stage in one pass (every load in flight before the first LDS
+    // write): the static blob, the fine-bin rows, per-segment S and the data.
     // Fused (single evaluation): rows 0..4 and S were written by the fold
-    // kernel (plain loads), row 5 = 1 + F is formed here. Otherwise they were
-    // written by this workgroup's phase A with agent-scope stores.
-    stage<NT, 8>(L.st, p.dpool + ds.blob, ds.blob_n);
+    // kernel (plain loads) and row 5 = 1 + F is formed below from the blob's
+    // flux rows. Otherwise all six rows were written by this workgroup's
+    // phase A with agent-scope stores.
     {
+      const int nbl = ds.blob_n;
       const int nb = io.fused ? 5 * K : 6 * K;
       const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
+      const double* blob = p.dpool + ds.blob;
       const double* b = io.bin + 6 * (int64_t)ds.kt0;
       const double* sg = io.Sseg + ds.seg0;
       const double* dt = io.data + ds.data;
+      const int total = nbl + n3;
       constexpr int U = 16;
-      for (int base = 0; base < n3; base += NT * U) {
+      for (int base = 0; base < total; base += NT * U) {
         double v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = base + u * NT + tid;
-          if (io.fused)
-            v[u] = i < nb ? b[i] : i < n1 ? 0.0 : i < n2 ? sg[i - n1] : i < n3 ? dt[i - n2] : 0.0;
+          const int j = i - nbl;
+          if (i < nbl) v[u] = blob[i];
+          else if (io.fused)
+            v[u] = j < nb ? b[j] : j < n1 ? 0.0 : j < n2 ? sg[j - n1] : j < n3 ? dt[j - n2] : 0.0;
           else
-            v[u] = i < n1 ? load_agent(b + i) : i < n2 ? load_agent(sg + (i - n1)) : i < n3 ? dt[i - n2] : 0.0;
+            v[u] = j < n1 ? load_agent(b + j) : j < n2 ? load_agent(sg + (j - n1)) : j < n3 ? dt[j - n2] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = base + u * NT + tid;
-          if (i < n3 && (i < nb || i >= n1)) L.dyn[i] = v[u];
-        }
-      }
-      if (io.fused) {
-        for (int k = tid; k < K; k += NT) {
-          const int kt = ds.kt0 + k;
-          double F = 0.0;
-          const int rb = p.ipool[p.kt_row + kt], re = p.ipool[p.kt_row + kt + 1];
-          for (int e = rb; e < re; ++e) F += L.th[p.ipool[p.kt_par + e]] * p.dpool[p.kt_coef + e];
-          L.F1[k] = 1.0 + F;
+          const int j = i - nbl;
+          if (i < nbl) L.st[i] = v[u];
+          else if (j < n3 && (j < nb || j >= n1)) L.dyn[j] = v[u];
         }
       }
     }
     __syncthreads();
 
-    // ---- spline: edge densities and cumulative
-    for (int k = tid; k <= K; k += NT) {
-      double dk;
-      if (k == 0) dk = L.Hs[0] * L.F1[0] / wf;
-      else if (k == K) dk = L.Hs[K - 1] * L.F1[K - 1] / wf;
-      else {
-        const double ma = L.Hs[k - 1] * L.F1[k - 1] / wf, mb = L.Hs[k] * L.F1[k] / wf;
-        dk = (ma * mb > 0.0) ? 2.0 * ma * mb / (ma + mb) : 0.0;
+    // ---- spline: edge densities and cumulative. In fused evaluations each
+    // thread forms 1 + F of its own and the previous fine bin from the blob's
+    // flux rows (no extra barrier).
+    {
+      const double* frow = L.st + BL.frow;
+      const double* fpar = L.st + BL.fpar;
+      const double* fcf = L.st + BL.fcf;
+      auto f1 = [&](int k) {
+        if (!io.fused) return L.F1[k];
+        double F = 0.0;
+        const int e1 = (int)frow[k + 1];
+        for (int e = (int)frow[k]; e < e1; ++e) F += L.th[(int)fpar[e]] * fcf[e];
+        return 1.0 + F;
+      };
+      for (int k = tid; k <= K; k += NT) {
+        const double fa = k > 0 ? f1(k - 1) : 0.0;
+        const double fb = k < K ? f1(k) : 0.0;
+        double dk;
+        if (k == 0) dk = L.Hs[0] * fb / wf;
+        else if (k == K) dk = L.Hs[K - 1] * fa / wf;
+        else {
+          const double ma = L.Hs[k - 1] * fa / wf, mb = L.Hs[k] * fb / wf;
+          dk = (ma * mb > 0.0) ? 2.0 * ma * mb / (ma + mb) : 0.0;
+        }
+        L.D[k] = dk;
+        if (k < K) {
+          L.LH[k] = L.Hs[k] * fb;  // H (scan input)
+          if (io.fused) L.F1[k] = fb;
+        }
       }
-      L.D[k] = dk;
-      if (k < K) L.LH[k] = L.Hs[k] * L.F1[k];  // H (scan input)
     }
     __syncthreads();
     block_scan<NT>(L.LH, L.C, K, false, L.red);
@@ -412,6 +408,11 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       L.eT[i] = em;
       L.eY[i] = elo;
       L.eH[i] = ehi;
+      // edge-index table: first[k + 1] = i for kidx[i-1] < k <= kidx[i]
+      const int kp = i > 0 ? L.kidx[i - 1] : -2;
+      for (int q = kp + 1; q <= k; ++q) L.first[q + 1] = i;
+      if (i == E - 1)
+        for (int q = k + 1; q <= K + 1; ++q) L.first[q + 1] = E;
     }
     block_sum<NT, 4>(gc, L.red);
     if (tid == 0)
@@ -420,9 +421,11 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     const double top = gc[3];
 
     // ---- gather per fine bin: lambda_C -> C, lambda_m (direct) -> LH, lambda_d -> Ld
+    // (bounds clamped: with an invalid energy map, which is flagged as out of
+    // domain, the edge index need not be monotone)
     for (int k = tid; k <= K; k += NT) {
-      const int b0 = lower_bound_int(L.kidx, E, k);
-      const int b1 = lower_bound_int(L.kidx, E, k + 1);
+      const int b0 = min(max(L.first[k + 1], 0), E);
+      const int b1 = min(max(L.first[k + 2], b0), E);
       double lc = 0.0, lm = 0.0, ld = 0.0;
       if (k < K) {
         for (int i = b0; i < b1; ++i) {
@@ -432,7 +435,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         }
       }
       if (k >= 1) {
-        const int a0 = lower_bound_int(L.kidx, E, k - 1);
+        const int a0 = min(max(L.first[k], 0), b0);
         for (int i = a0; i < b0; ++i) ld += L.eH[i];
       }
       L.Ld[k] = ld;
@@ -496,23 +499,45 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         atomicAdd(&L.grad[(int)mdp[m]], gm);
       }
     }
-    // ---- source norms: one wavefront per source
+    // ---- source norms: dNLL/dA_s = sum_k lambda_Hs[k] S[s][k], then the
+    // product rule over each source's norm list
     {
       const double* nlp = L.st + BL.nlp;
       const double* nli = L.st + BL.nli;
-      const int lane = tid & 63, wid = tid >> 6;
-      for (int s = wid; s < S; s += NT / 64) {
-        double gA = 0.0;
-        for (int k = lane; k < K; k += 64) gA += L.LH[k] * L.Ss[s * K + k];
-        gA = wave_sum(gA);
-        if (lane == 0) {
-          const int b = (int)nlp[s], e = (int)nlp[s + 1];
-          for (int q = b; q < e; ++q) {
-            double prod = 1.0;
-            for (int r = b; r < e; ++r)
-              if (r != q) prod *= L.th[(int)nli[r]];
-            atomicAdd(&L.grad[(int)nli[q]], gA * prod);
-          }
+      auto apply = [&](int s, double gA) {
+        const int b = (int)nlp[s], e = (int)nlp[s + 1];
+        for (int q = b; q < e; ++q) {
+          double prod = 1.0;
+          for (int r = b; r < e; ++r)
+            if (r != q) prod *= L.th[(int)nli[r]];
+          atomicAdd(&L.grad[(int)nli[q]], gA * prod);
+        }
+      };
+      if (S <= 16) {  // all sources at once, one block reduction
+        double gA[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) gA[s] = 0.0;
+        for (int k = tid; k < K; k += NT) {
+          const double lh = L.LH[k];
+#pragma unroll
+          for (int s = 0; s < 16; ++s)
+            if (s < S) gA[s] += lh * L.Ss[s * K + k];
+        }
+        block_sum<NT, 16>(gA, L.red);
+        if (tid < S) {
+          double g = 0.0;
+#pragma unroll
+          for (int s = 0; s < 16; ++s)
+            if (s == tid) g = gA[s];
+          apply(tid, g);
+        }
+      } else {  // one wavefront per source
+        const int lane = tid & 63, wid = tid >> 6;
+        for (int s = wid; s < S; s += NT / 64) {
+          double gA = 0.0;
+          for (int k = lane; k < K; k += 64) gA += L.LH[k] * L.Ss[s * K + k];
+          gA = wave_sum(gA);
+          if (lane == 0) apply(s, gA);
         }
       }
     }

@@ -61,6 +61,7 @@ SIGNATURES["nf_fit_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_voi
                                         C.POINTER(FitOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p])
 
+SIGNATURES["nf_timing_overhead"] = (C.c_int, [C.c_void_p, C.c_int, _dp])
 SIGNATURES["nf_autotune"] = (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p])
 SIGNATURES["nf_expected_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
 SIGNATURES["nf_mlp_create"] = (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -271,6 +272,12 @@ class Engine:
             di.ctypes.data if di is not None else None, C.byref(opts), th.ctypes.data, nll.ctypes.data,
             edm.ctypes.data, status.ctypes.data, iters.ctypes.data, evals.ctypes.data))
         return dict(theta=th, nll=nll, edm=edm, status=status, iters=iters, evals=evals, code=code)
+
+    def timing_overhead(self, n=200):
+        """Mean gap (us) between two back-to-back timing events on the stream."""
+        us = C.c_double()
+        _check(self.ctx, load().nf_timing_overhead(self.ctx, n, C.byref(us)))
+        return us.value
 
     def autotune(self, theta, evals=50, batch=0):
         """Run the library's autotuner; returns ({option: value}, (us/eval, us/batched eval))."""
