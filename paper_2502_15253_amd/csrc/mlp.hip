@@ -3,18 +3,27 @@
 // master weights with Adam. Used only to propose fit start points; every
 // reported NLL comes from the exact fold.
 //
-// GEMM: C (M x N) = op(A) (M x K) * op(B) (K x N). A workgroup of 256 threads
+// GEMM: C (M x N) = A (M x K) * B^T, with both operands stored with the
+// contraction index contiguous (A as [m][k], B as [n][k]), so tiles go from
+// global memory to LDS with 16-byte loads and every lane reads its 8
+// consecutive k values with one 16-byte LDS load. A workgroup of 256 threads
 // computes a 128 x 128 tile (64 x 64 when that leaves too few workgroups to
 // fill the chip); each wavefront a quarter of it as MFMA 16 x 16 blocks; K
-// advances by 32. Operands are staged in LDS as bf16 with the contraction
-// index contiguous (A as [m][k], B as [n][k]) so every lane reads its 8
-// consecutive k values with one 16-byte LDS load; operands stored the other
-// way round are transposed on the way into LDS. Out-of-range rows, columns
-// and k are zero-filled, so any shape is accepted.
+// advances by 32 with the next step's global loads in flight. Out-of-range
+// rows, columns and k are zero-filled, so any shape is accepted.
+//
+// Layouts that make every product k-contiguous: the forward pass uses W^T
+// (kept as a second bf16 copy of the weights); the input gradient uses W as
+// stored; the weight gradient dW = H^T dZ contracts over the batch, so the
+// epilogues that produce activations H and back-propagated gradients dZ also
+// write bf16 transposed copies ([feature][batch]), one 8-byte store per lane
+// (the 4 consecutive rows an MFMA result lane holds). Weight gradients split
+// the batch (K) over workgroups and add the slices in a fixed order.
 // MFMA lane layout (16x16x32): lane l holds A[l % 16][8 (l / 16) + 0..7] and
 // B[8 (l / 16) + 0..7][l % 16]; the result lane holds D[4 (l / 16) + i][l % 16].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -36,39 +45,36 @@ __host__ __device__ inline uint16_t f2bf(float x) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-__host__ __device__ inline float bf2f(uint16_t b) {
-  const uint32_t u = (uint32_t)b << 16;
-  float x;
-  std::memcpy(&x, &u, 4);
-  return x;
-}
 
 __device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ inline float gelu_prime(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_DGELU = 3 };
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_DGELU = 3, EPI_PARTIAL = 4 };
 
 struct GemmArgs {
   int M, N, K;
-  const uint16_t* A;  // bf16
+  int kslice;          // contraction range per blockIdx.z (multiple of 32)
+  const uint16_t* A;   // [M][lda] bf16, k contiguous
   int lda;
-  const uint16_t* B;  // bf16
+  const uint16_t* B;   // [N][ldb] bf16, k contiguous
   int ldb;
-  float* Cf;          // fp32 output (EPI_F32, EPI_BIAS_F32, EPI_BIAS_GELU: pre-activation, EPI_DGELU: dz)
-  uint16_t* Cb;       // bf16 output (EPI_BIAS_GELU: activation, EPI_DGELU: dz)
+  float* Cf;           // fp32 [M][ldc]: C (F32, BIAS_F32), pre-activation (BIAS_GELU), dz (DGELU);
+                       // PARTIAL: slice z at Cf + z M ldc
   int ldc;
-  const float* bias;  // N (EPI_BIAS_*)
-  const float* Zin;   // EPI_DGELU: pre-activation of this layer (M x N, ldc)
+  uint16_t* Cb;        // bf16 [M][ldc] copy (BIAS_GELU: activation, DGELU: dz), nullable
+  uint16_t* Ct;        // bf16 [N][ldt] transposed copy of the same, nullable
+  int ldt;
+  const float* bias;   // N (BIAS_*)
+  const float* Zin;    // DGELU: pre-activation of the layer below, [M][ldc]
 };
 
 constexpr int TK = 32, LDK = TK + 8;  // LDS row pitch (bf16) padded against bank conflicts
 
-// One operand tile, ROWS x TK, into registers. KC: the operand is stored with
-// k contiguous (row r at src + r ld); otherwise with rows contiguous (k at
-// src + k ld). Out-of-range elements are zero.
-template <int ROWS, bool KC>
+// One operand tile (ROWS x TK, k contiguous in memory) into registers; rows
+// >= R and k >= K read as zero.
+template <int ROWS>
 struct TileRegs {
   static constexpr int NV = ROWS * TK / 8 / 256;  // 16-byte vectors per thread
   bf16x8 v[NV];
@@ -78,56 +84,29 @@ struct TileRegs {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int e = tid + 256 * j;
-      int r, k;
-      if (KC) { r = e / (TK / 8); k = (e % (TK / 8)) * 8; }
-      else { k = e / (ROWS / 8); r = (e % (ROWS / 8)) * 8; }
+      const int r = e / (TK / 8), k = (e % (TK / 8)) * 8;
       const int gr = r0 + r, gk = k0 + k;
-      if (KC) {
-        if (vec_ok && gr < R && gk + 8 <= K) {
-          v[j] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
-        } else {
-          union { bf16x8 b; uint16_t u[8]; } t;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) t.u[i] = (gr < R && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : 0;
-          v[j] = t.b;
-        }
+      if (vec_ok && gr < R && gk + 8 <= K) {
+        v[j] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
       } else {
-        if (vec_ok && gk < K && gr + 8 <= R) {
-          v[j] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gk * ld + gr);
-        } else {
-          union { bf16x8 b; uint16_t u[8]; } t;
+        union { bf16x8 b; uint16_t u[8]; } t;
 #pragma unroll
-          for (int i = 0; i < 8; ++i) t.u[i] = (gk < K && gr + i < R) ? src[(int64_t)gk * ld + gr + i] : 0;
-          v[j] = t.b;
-        }
+        for (int i = 0; i < 8; ++i) t.u[i] = (gr < R && gk + i < K) ? src[(int64_t)gr * ld + gk + i] : 0;
+        v[j] = t.b;
       }
     }
   }
 
-  // to LDS laid out [row][k] (k contiguous, pitch LDK)
   __device__ void store(uint16_t (*lds)[LDK], int tid) const {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int e = tid + 256 * j;
-      if (KC) {
-        const int r = e / (TK / 8), k = (e % (TK / 8)) * 8;
-        *reinterpret_cast<bf16x8*>(&lds[r][k]) = v[j];
-      } else {
-        const int k = e / (ROWS / 8), r = (e % (ROWS / 8)) * 8;
-        union { bf16x8 b; uint16_t u[8]; } t;
-        t.b = v[j];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) lds[r + i][k] = t.u[i];
-      }
+      *reinterpret_cast<bf16x8*>(&lds[e / (TK / 8)][(e % (TK / 8)) * 8]) = v[j];
     }
   }
 };
 
-// C tile BM x BN per workgroup of 4 wavefronts (2 x 2), each wavefront
-// (BM/2) x (BN/2) as FM x FN blocks of 16 x 16; K advances by 32 with the next
-// tile's global loads in flight during the current tile's products (two LDS
-// buffers, one barrier per step).
-template <int BM, int BN, int TA, int TB, int EPI>
+template <int BM, int BN, int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int FM = BM / 32, FN = BN / 32;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDK];
@@ -135,25 +114,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int wm = (wv >> 1) * (BM / 2), wn = (wv & 1) * (BN / 2);
+  const int kb = blockIdx.z * g.kslice;
+  const int ke = min(g.K, kb + g.kslice);
   f32x4 acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  TileRegs<BM, TA == 0> ra;
-  TileRegs<BN, TB == 1> rb;
-  const int nk = (g.K + TK - 1) / TK;
-  ra.load(g.A, g.lda, m0, g.M, 0, g.K, tid);
-  rb.load(g.B, g.ldb, n0, g.N, 0, g.K, tid);
-  ra.store(As[0], tid);
-  rb.store(Bs[0], tid);
+  TileRegs<BM> ra;
+  TileRegs<BN> rb;
+  const int nk = ke > kb ? (ke - kb + TK - 1) / TK : 0;
+  if (nk > 0) {
+    ra.load(g.A, g.lda, m0, g.M, kb, ke, tid);
+    rb.load(g.B, g.ldb, n0, g.N, kb, ke, tid);
+    ra.store(As[0], tid);
+    rb.store(Bs[0], tid);
+  }
   __syncthreads();
   const int r = lane & 15, kq = (lane >> 4) * 8;
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      ra.load(g.A, g.lda, m0, g.M, (kt + 1) * TK, g.K, tid);
-      rb.load(g.B, g.ldb, n0, g.N, (kt + 1) * TK, g.K, tid);
+      ra.load(g.A, g.lda, m0, g.M, kb + (kt + 1) * TK, ke, tid);
+      rb.load(g.B, g.ldb, n0, g.N, kb + (kt + 1) * TK, ke, tid);
     }
     bf16x8 af[FM], bfr[FN];
 #pragma unroll
@@ -171,43 +154,79 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     __syncthreads();
   }
   const int col = lane & 15, rq = (lane >> 4) * 4;
+  float* Cf = g.Cf;
+  if (EPI == EPI_PARTIAL) Cf += (int64_t)blockIdx.z * g.M * g.ldc;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn + j * 16 + col;
+      const int mb = m0 + wm + i * 16 + rq;
+      if (n >= g.N) continue;
+      uint16_t tb[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm + i * 16 + rq + q, n = n0 + wn + j * 16 + col;
-        if (m >= g.M || n >= g.N) continue;
+        const int m = mb + q;
+        tb[q] = 0;
+        if (m >= g.M) continue;
         const float v = acc[i][j][q];
         const int64_t o = (int64_t)m * g.ldc + n;
-        if (EPI == EPI_F32) {
-          g.Cf[o] = v;
+        if (EPI == EPI_F32 || EPI == EPI_PARTIAL) {
+          Cf[o] = v;
         } else if (EPI == EPI_BIAS_F32) {
-          g.Cf[o] = v + g.bias[n];
+          Cf[o] = v + g.bias[n];
         } else if (EPI == EPI_BIAS_GELU) {
           const float z = v + g.bias[n];
-          g.Cf[o] = z;
-          g.Cb[o] = f2bf(gelu(z));
+          Cf[o] = z;
+          tb[q] = f2bf(gelu(z));
+          if (g.Cb) g.Cb[o] = tb[q];
         } else {  // EPI_DGELU: v is dL/dh
           const float dz = v * gelu_prime(g.Zin[o]);
-          g.Cf[o] = dz;
-          g.Cb[o] = f2bf(dz);
+          Cf[o] = dz;
+          tb[q] = f2bf(dz);
+          if (g.Cb) g.Cb[o] = tb[q];
         }
       }
+      if ((EPI == EPI_BIAS_GELU || EPI == EPI_DGELU) && g.Ct) {
+        uint16_t* t = g.Ct + (int64_t)n * g.ldt + mb;
+        if (mb + 3 < g.M && (g.ldt & 3) == 0) {
+          *reinterpret_cast<uint2*>(t) =
+              uint2{(uint32_t)tb[0] | ((uint32_t)tb[1] << 16), (uint32_t)tb[2] | ((uint32_t)tb[3] << 16)};
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (mb + q < g.M) t[q] = tb[q];
+        }
+      }
+    }
 }
 
-template <int TA, int TB, int EPI>
-hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
+// K split into `splits` slices (only with EPI_PARTIAL, slice z written to
+// Cf + z M ldc); returns the number of slices launched in *slices.
+template <int EPI>
+hipError_t gemm(GemmArgs g, hipStream_t s, int splits = 1, int* slices = nullptr) {
+  splits = std::max(1, splits);
+  g.kslice = std::max(TK, ((g.K + splits - 1) / splits + TK - 1) / TK * TK);
+  const int z = std::max(1, (g.K + g.kslice - 1) / g.kslice);
+  if (slices) *slices = z;
+  const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * z;
   if (t128 >= 512) {
-    const dim3 grid((g.N + 127) / 128, (g.M + 127) / 128);
-    hipLaunchKernelGGL((gemm_kernel<128, 128, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    const dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, z);
+    hipLaunchKernelGGL((gemm_kernel<128, 128, EPI>), grid, dim3(256), 0, s, g);
   } else {
-    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-    hipLaunchKernelGGL((gemm_kernel<64, 64, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, z);
+    hipLaunchKernelGGL((gemm_kernel<64, 64, EPI>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
+}
+
+// weight-gradient slices added in slice order: out[i] = sum_z part[z][i]
+__global__ void slice_sum_kernel(const float* __restrict__ part, int Z, int64_t n, float* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < Z; ++z) s += part[(int64_t)z * n + i];
+  out[i] = s;
 }
 
 __global__ void to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
@@ -215,10 +234,38 @@ __global__ void to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
   if (i < n) y[i] = f2bf(x[i]);
 }
 
+// network input: fp32 [B][n_in] -> bf16 [B][kin] (zero-padded columns) and bf16 [n_in][B]
+__global__ void prep_input_kernel(const float* x, int B, int n_in, int kin, uint16_t* xb, uint16_t* xt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * kin) return;
+  const int row = (int)(i / kin), c = (int)(i % kin);
+  const uint16_t v = c < n_in ? f2bf(x[(int64_t)row * n_in + c]) : (uint16_t)0;
+  xb[i] = v;
+  if (c < n_in) xt[(int64_t)c * B + row] = v;
+}
+
+// gradient at the output: fp32 [B][N] -> bf16 [B][N] and bf16 [N][B]
+__global__ void prep_grad_kernel(const float* d, int B, int N, uint16_t* db, uint16_t* dt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * N) return;
+  const uint16_t v = f2bf(d[i]);
+  db[i] = v;
+  dt[(int64_t)(i % N) * B + i / N] = v;
+}
+
+// bf16 W^T of one layer: wt[c][r] = bf16(w[r][c]) for r < din (columns din..dinp
+// of wt stay zero)
+__global__ void transpose_bf16_kernel(const float* w, int din, int dout, int dinp, uint16_t* wt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)din * dout) return;
+  const int r = (int)(i / dout), c = (int)(i % dout);
+  wt[(int64_t)c * dinp + r] = f2bf(w[i]);
+}
+
 // Column sums of an M x N fp32 matrix (bias gradients) in a fixed order, two
 // passes: blocks of CS_ROWS rows x 64 columns write partial sums, then one
 // thread per column adds the partials in row-block order.
-constexpr int CS_ROWS = 64;
+constexpr int CS_ROWS = 256;
 __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ x, int M, int N,
                                                             float* __restrict__ part) {
   __shared__ float red[4][64];
@@ -228,7 +275,7 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __rest
   const int m1 = min(M, m0 + CS_ROWS);
   float s = 0.f;
   if (n < N) {
-#pragma unroll 4
+#pragma unroll 8
     for (int m = m0 + sl; m < m1; m += 4) s += x[(int64_t)m * N + n];
   }
   red[sl][c] = s;
@@ -244,18 +291,20 @@ __global__ void colsum_final_kernel(const float* __restrict__ part, int nrb, int
   out[n] = s;
 }
 
-// MSE over B x N: dy = 2 (y - t) / (B N) as fp32 and bf16; per-block loss partials
-__global__ void mse_kernel(const float* y, const float* t, int64_t n, float scale, float* dyf, uint16_t* dyb,
-                           float* partial) {
+// MSE over B x N: dy = 2 (y - t) / (B N) as fp32, bf16 and transposed bf16; per-block loss partials
+__global__ void mse_kernel(const float* y, const float* t, int B, int N, float scale, float* dyf, uint16_t* dyb,
+                           uint16_t* dyt, float* partial) {
   __shared__ float red[256];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   float l = 0.f;
-  if (i < n) {
+  if (i < (int64_t)B * N) {
     const float d = y[i] - t[i];
     l = d * d;
     const float g = 2.f * d * scale;
+    const uint16_t gb = f2bf(g);
     dyf[i] = g;
-    dyb[i] = f2bf(g);
+    dyb[i] = gb;
+    dyt[(int64_t)(i % N) * B + i / N] = gb;
   }
   red[threadIdx.x] = l;
   __syncthreads();
@@ -337,39 +386,46 @@ T* dalloc(size_t n) {
   return p;
 }
 
+constexpr int MAX_SPLITS = 32;  // batch slices of one weight-gradient product
+
 }  // namespace
 
 struct nf_mlp {
   std::string err;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  int n_in = 0, width = 0, depth = 0, n_out = 0, max_batch = 0;
+  int n_in = 0, kin = 0, width = 0, depth = 0, n_out = 0, max_batch = 0;
   int L = 0;                          // number of weight layers = depth + 1
-  std::vector<int> din, dout;         // per layer
+  std::vector<int> din, dout, dinp;   // per layer; dinp: contraction length of the forward product
   std::vector<int64_t> woff, boff;    // offsets into the flat parameter vector
-  int64_t nparam = 0;
+  std::vector<int64_t> toff;          // offsets of each layer's W^T in wbt
+  int64_t nparam = 0, nwt = 0, maxdw = 0;
   float *w = nullptr, *g = nullptr, *am = nullptr, *av = nullptr;  // master params, grads, Adam moments
-  uint16_t* wb = nullptr;             // bf16 copy of the parameters (weights used)
+  uint16_t* wb = nullptr;             // bf16 copy of the parameter vector (W as stored: input gradient)
+  uint16_t* wbt = nullptr;            // bf16 W^T per layer, [dout][dinp] (forward)
   float* xf = nullptr;                // B x n_in staging (fp32)
-  uint16_t* xb = nullptr;             // B x n_in bf16
+  uint16_t* xb = nullptr;             // B x kin bf16 (zero-padded)
+  uint16_t* xt = nullptr;             // n_in x B bf16
   std::vector<float*> Z;              // pre-activations per hidden layer (B x width)
-  std::vector<uint16_t*> H;           // activations bf16 per hidden layer
+  std::vector<uint16_t*> H, HT;       // activations bf16, B x width and width x B
   float* Y = nullptr;                 // B x n_out
-  float* T = nullptr;                 // targets / observed counts B x n_out
-  float* dYf = nullptr;               // B x max(width, n_out)
-  uint16_t* dYb = nullptr;
-  float* dZf = nullptr;               // B x width
-  uint16_t* dZb = nullptr;
+  float* T = nullptr;                 // targets B x n_out
+  float *dYf = nullptr, *dZf = nullptr;        // B x max(width, n_out): back-propagated gradients (ping-pong)
+  uint16_t *dYb = nullptr, *dZb = nullptr;     // the same in bf16
+  uint16_t *dYt = nullptr, *dZt = nullptr;     // the same transposed, max(width, n_out) x B
   float* dX = nullptr;                // B x n_in
   float* partial = nullptr;           // loss partials
-  float* csum = nullptr;              // column-sum partials, ceil(max_batch / 64) x max(width, n_out)
+  float* csum = nullptr;              // column-sum partials
+  float* kpart = nullptr;             // weight-gradient slices, MAX_SPLITS x maxdw
   int adam_t = 0;
   ~nf_mlp() {
-    for (void* p : {(void*)w, (void*)g, (void*)am, (void*)av, (void*)wb, (void*)xf, (void*)xb, (void*)Y, (void*)T,
-                    (void*)dYf, (void*)dYb, (void*)dZf, (void*)dZb, (void*)dX, (void*)partial, (void*)csum})
+    for (void* p : {(void*)w, (void*)g, (void*)am, (void*)av, (void*)wb, (void*)wbt, (void*)xf, (void*)xb,
+                    (void*)xt, (void*)Y, (void*)T, (void*)dYf, (void*)dZf, (void*)dYb, (void*)dZb, (void*)dYt,
+                    (void*)dZt, (void*)dX, (void*)partial, (void*)csum, (void*)kpart})
       if (p) (void)hipFree(p);
     for (auto* p : Z) (void)hipFree(p);
     for (auto* p : H) (void)hipFree(p);
+    for (auto* p : HT) (void)hipFree(p);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -402,78 +458,99 @@ int mguard(nf_mlp* n, F&& f) {
   }
 }
 
+inline dim3 blocks(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// x (fp32, B x n_in, already in n->xf) -> bf16 operand copies
+void prep_input(nf_mlp* n, int B) {
+  hipLaunchKernelGGL(prep_input_kernel, blocks((int64_t)B * n->kin), dim3(256), 0, n->stream, n->xf, B, n->n_in,
+                     n->kin, n->xb, n->xt);
+}
+
 void upload_x(nf_mlp* n, int B, const float* x, int on_device) {
   mck(hipMemcpyAsync(n->xf, x, sizeof(float) * B * n->n_in, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                      n->stream), "x copy");
-  const int64_t cnt = (int64_t)B * n->n_in;
-  hipLaunchKernelGGL(to_bf16_kernel, dim3((cnt + 255) / 256), dim3(256), 0, n->stream, n->xf, n->xb, cnt);
+  prep_input(n, B);
 }
 
 void refresh_bf16(nf_mlp* n) {
-  hipLaunchKernelGGL(to_bf16_kernel, dim3((n->nparam + 255) / 256), dim3(256), 0, n->stream, n->w, n->wb, n->nparam);
+  hipLaunchKernelGGL(to_bf16_kernel, blocks(n->nparam), dim3(256), 0, n->stream, n->w, n->wb, n->nparam);
+  for (int l = 0; l < n->L; ++l)
+    hipLaunchKernelGGL(transpose_bf16_kernel, blocks((int64_t)n->din[l] * n->dout[l]), dim3(256), 0, n->stream,
+                       n->w + n->woff[l], n->din[l], n->dout[l], n->dinp[l], n->wbt + n->toff[l]);
 }
 
-// forward pass of B rows already in n->xb; output fp32 in n->Y
-void forward(nf_mlp* n, int B) {
+// forward pass of B rows already in n->xb; output fp32 in n->Y. keep_t: also
+// write the transposed activations that the weight gradient needs.
+void forward(nf_mlp* n, int B, bool keep_t) {
   const uint16_t* in = n->xb;
   for (int l = 0; l < n->L; ++l) {
     GemmArgs a{};
-    a.M = B; a.N = n->dout[l]; a.K = n->din[l];
-    a.A = in; a.lda = n->din[l];
-    a.B = n->wb + n->woff[l]; a.ldb = n->dout[l];
+    a.M = B; a.N = n->dout[l]; a.K = n->dinp[l];
+    a.A = in; a.lda = n->dinp[l];
+    a.B = n->wbt + n->toff[l]; a.ldb = n->dinp[l];
     a.ldc = n->dout[l];
     a.bias = n->w + n->boff[l];
     if (l < n->L - 1) {
       a.Cf = n->Z[l];
       a.Cb = n->H[l];
-      mck(gemm<0, 0, EPI_BIAS_GELU>(a, n->stream), "gemm");
+      a.Ct = keep_t ? n->HT[l] : nullptr;
+      a.ldt = B;
+      mck(gemm<EPI_BIAS_GELU>(a, n->stream), "gemm");
       in = n->H[l];
     } else {
       a.Cf = n->Y;
-      mck(gemm<0, 0, EPI_BIAS_F32>(a, n->stream), "gemm");
+      mck(gemm<EPI_BIAS_F32>(a, n->stream), "gemm");
     }
   }
 }
 
-// backward from dY (fp32 in n->dYf, bf16 in n->dYb, B x n_out): parameter
-// gradients into n->g when want_dw; input gradient into n->dX when want_dx
-void backward(nf_mlp* n, int B, bool want_dx, bool want_dw = true) {
-  float* dcur_f = n->dYf;
-  uint16_t* dcur_b = n->dYb;
+// backward from the output gradient (fp32 n->dYf, bf16 n->dYb and, when
+// want_dw, transposed bf16 n->dYt, B x n_out): parameter gradients into n->g
+// when want_dw; input gradient into n->dX when want_dx
+void backward(nf_mlp* n, int B, bool want_dx, bool want_dw) {
+  float* cf = n->dYf;
+  uint16_t* cb = n->dYb;
+  uint16_t* ct = n->dYt;
   for (int l = n->L - 1; l >= 0; --l) {
-    const uint16_t* inp = l == 0 ? n->xb : n->H[l - 1];
     if (want_dw) {
-      // dW_l = inp^T dcur (din x dout), db_l = colsum(dcur)
+      // dW_l = inp^T dcur (din x dout), contraction over the batch in slices
       GemmArgs gw{};
       gw.M = n->din[l]; gw.N = n->dout[l]; gw.K = B;
-      gw.A = inp; gw.lda = n->din[l];
-      gw.B = dcur_b; gw.ldb = n->dout[l];
-      gw.Cf = n->g + n->woff[l]; gw.ldc = n->dout[l];
-      mck(gemm<1, 0, EPI_F32>(gw, n->stream), "gemm dW");
+      gw.A = l == 0 ? n->xt : n->HT[l - 1]; gw.lda = B;
+      gw.B = ct; gw.ldb = B;
+      gw.Cf = n->kpart; gw.ldc = n->dout[l];
+      const int tiles = ((gw.M + 127) / 128) * ((gw.N + 127) / 128);
+      const int splits = std::min(MAX_SPLITS, std::max(1, std::min(512 / tiles, B / 256)));
+      int zs = 1;
+      mck(gemm<EPI_PARTIAL>(gw, n->stream, splits, &zs), "gemm dW");
+      const int64_t mn = (int64_t)gw.M * gw.N;
+      hipLaunchKernelGGL(slice_sum_kernel, blocks(mn), dim3(256), 0, n->stream, n->kpart, zs, mn, n->g + n->woff[l]);
+      // db_l = column sums of dcur
       const int nrb = (B + CS_ROWS - 1) / CS_ROWS;
-      hipLaunchKernelGGL(colsum_partial_kernel, dim3((n->dout[l] + 63) / 64, nrb), dim3(256), 0, n->stream, dcur_f,
-                         B, n->dout[l], n->csum);
-      hipLaunchKernelGGL(colsum_final_kernel, dim3((n->dout[l] + 255) / 256), dim3(256), 0, n->stream, n->csum, nrb,
-                         n->dout[l], n->g + n->boff[l]);
+      hipLaunchKernelGGL(colsum_partial_kernel, dim3((n->dout[l] + 63) / 64, nrb), dim3(256), 0, n->stream, cf, B,
+                         n->dout[l], n->csum);
+      hipLaunchKernelGGL(colsum_final_kernel, blocks(n->dout[l]), dim3(256), 0, n->stream, n->csum, nrb, n->dout[l],
+                         n->g + n->boff[l]);
     }
     if (l == 0 && !want_dx) break;
-    // d(inp) = dcur W_l^T (B x din); through GELU of the previous layer
+    // d(inp) = dcur W_l^T (B x din): W_l as stored is [din][dout], k = dout contiguous
     GemmArgs gd{};
     gd.M = B; gd.N = n->din[l]; gd.K = n->dout[l];
-    gd.A = dcur_b; gd.lda = n->dout[l];
+    gd.A = cb; gd.lda = n->dout[l];
     gd.B = n->wb + n->woff[l]; gd.ldb = n->dout[l];
     gd.ldc = n->din[l];
     if (l > 0) {
-      // write into the buffer not currently being read
-      float* nf = (dcur_f == n->dZf) ? n->dYf : n->dZf;
-      uint16_t* nb = (dcur_b == n->dZb) ? n->dYb : n->dZb;
-      gd.Cf = nf; gd.Cb = nb; gd.Zin = n->Z[l - 1];
-      mck(gemm<0, 1, EPI_DGELU>(gd, n->stream), "gemm dH");
-      dcur_f = nf;
-      dcur_b = nb;
+      float* nf = (cf == n->dZf) ? n->dYf : n->dZf;
+      uint16_t* nb = (cb == n->dZb) ? n->dYb : n->dZb;
+      uint16_t* nt = (ct == n->dZt) ? n->dYt : n->dZt;
+      gd.Cf = nf; gd.Cb = nb; gd.Ct = want_dw ? nt : nullptr; gd.ldt = B; gd.Zin = n->Z[l - 1];
+      mck(gemm<EPI_DGELU>(gd, n->stream), "gemm dH");
+      cf = nf;
+      cb = nb;
+      ct = nt;
     } else {
       gd.Cf = n->dX;
-      mck(gemm<0, 1, EPI_F32>(gd, n->stream), "gemm dX");
+      mck(gemm<EPI_F32>(gd, n->stream), "gemm dX");
     }
   }
 }
@@ -498,18 +575,25 @@ int nf_mlp_create(nf_mlp** out, int n_in, int width, int depth, int n_out, int m
   nf_mlp* n = new nf_mlp();
   try {
     n->n_in = n_in; n->width = width; n->depth = depth; n->n_out = n_out; n->max_batch = max_batch;
+    n->kin = (n_in + 7) / 8 * 8;
     n->L = depth + 1;
-    int64_t off = 0;
+    int64_t off = 0, toff = 0;
     for (int l = 0; l < n->L; ++l) {
       const int a = l == 0 ? n_in : width, b = l == n->L - 1 ? n_out : width;
+      const int ap = l == 0 ? n->kin : width;
       n->din.push_back(a);
       n->dout.push_back(b);
+      n->dinp.push_back(ap);
       n->woff.push_back(off);
       off += (int64_t)a * b;
       n->boff.push_back(off);
       off += b;
+      n->toff.push_back(toff);
+      toff += (int64_t)b * ap;
+      n->maxdw = std::max<int64_t>(n->maxdw, (int64_t)a * b);
     }
     n->nparam = off;
+    n->nwt = toff;
     if (hip_stream) n->stream = (hipStream_t)hip_stream;
     else {
       mck(hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking), "hipStreamCreate");
@@ -518,20 +602,25 @@ int nf_mlp_create(nf_mlp** out, int n_in, int width, int depth, int n_out, int m
     const size_t B = max_batch, wmax = std::max(width, n_out);
     n->w = dalloc<float>(off); n->g = dalloc<float>(off); n->am = dalloc<float>(off); n->av = dalloc<float>(off);
     n->wb = dalloc<uint16_t>(off);
-    n->xf = dalloc<float>(B * n_in); n->xb = dalloc<uint16_t>(B * n_in);
+    n->wbt = dalloc<uint16_t>(toff);
+    n->xf = dalloc<float>(B * n_in); n->xb = dalloc<uint16_t>(B * n->kin); n->xt = dalloc<uint16_t>(B * n_in);
     for (int l = 0; l < depth; ++l) {
       n->Z.push_back(dalloc<float>(B * width));
       n->H.push_back(dalloc<uint16_t>(B * width));
+      n->HT.push_back(dalloc<uint16_t>(B * width));
     }
     n->Y = dalloc<float>(B * n_out); n->T = dalloc<float>(B * n_out);
-    n->dYf = dalloc<float>(B * wmax); n->dYb = dalloc<uint16_t>(B * wmax);
-    n->dZf = dalloc<float>(B * wmax); n->dZb = dalloc<uint16_t>(B * wmax);
+    n->dYf = dalloc<float>(B * wmax); n->dZf = dalloc<float>(B * wmax);
+    n->dYb = dalloc<uint16_t>(B * wmax); n->dZb = dalloc<uint16_t>(B * wmax);
+    n->dYt = dalloc<uint16_t>(B * wmax); n->dZt = dalloc<uint16_t>(B * wmax);
     n->dX = dalloc<float>(B * n_in);
     n->partial = dalloc<float>((B * n_out + 255) / 256 + 1);
     n->csum = dalloc<float>(((B + CS_ROWS - 1) / CS_ROWS) * wmax);
+    n->kpart = dalloc<float>((size_t)MAX_SPLITS * n->maxdw);
     mck(hipMemsetAsync(n->w, 0, sizeof(float) * off, n->stream), "memset");
     mck(hipMemsetAsync(n->am, 0, sizeof(float) * off, n->stream), "memset");
     mck(hipMemsetAsync(n->av, 0, sizeof(float) * off, n->stream), "memset");
+    mck(hipMemsetAsync(n->wbt, 0, sizeof(uint16_t) * toff, n->stream), "memset");  // padding columns stay zero
     refresh_bf16(n);
     mck(hipStreamSynchronize(n->stream), "sync");
   } catch (const std::exception& e) {
@@ -569,7 +658,8 @@ int nf_mlp_set_params(nf_mlp* n, const float* params) {
 int nf_mlp_get_params(nf_mlp* n, float* params) {
   return mguard(n, [&] {
     if (!params) throw MlpError(NF_EINVAL, "params is null");
-    mck(hipMemcpy(params, n->w, sizeof(float) * n->nparam, hipMemcpyDeviceToHost), "D2H");
+    mck(hipMemcpyAsync(params, n->w, sizeof(float) * n->nparam, hipMemcpyDeviceToHost, n->stream), "D2H");
+    mck(hipStreamSynchronize(n->stream), "sync");
     return NF_OK;
   });
 }
@@ -578,7 +668,7 @@ int nf_mlp_forward(nf_mlp* n, int B, const float* x, float* y, int on_device) {
   return mguard(n, [&] {
     if (B < 1 || B > n->max_batch || !x || !y) throw MlpError(NF_EINVAL, "bad batch or null pointer");
     upload_x(n, B, x, on_device);
-    forward(n, B);
+    forward(n, B, false);
     mck(hipMemcpyAsync(y, n->Y, sizeof(float) * B * n->n_out,
                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, n->stream), "y copy");
     mck(hipStreamSynchronize(n->stream), "sync");
@@ -592,11 +682,11 @@ int nf_mlp_grad(nf_mlp* n, int B, const float* x, const float* dy, float* grad, 
     const hipMemcpyKind k_in = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind k_out = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     upload_x(n, B, x, on_device);
-    forward(n, B);
+    forward(n, B, true);
     const int64_t cnt = (int64_t)B * n->n_out;
     mck(hipMemcpyAsync(n->dYf, dy, sizeof(float) * cnt, k_in, n->stream), "dy copy");
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((cnt + 255) / 256), dim3(256), 0, n->stream, n->dYf, n->dYb, cnt);
-    backward(n, B, dx != nullptr);
+    hipLaunchKernelGGL(prep_grad_kernel, blocks(cnt), dim3(256), 0, n->stream, n->dYf, B, n->n_out, n->dYb, n->dYt);
+    backward(n, B, dx != nullptr, true);
     if (grad) mck(hipMemcpyAsync(grad, n->g, sizeof(float) * n->nparam, k_out, n->stream), "grad copy");
     if (dx) mck(hipMemcpyAsync(dx, n->dX, sizeof(float) * B * n->n_in, k_out, n->stream), "dx copy");
     mck(hipStreamSynchronize(n->stream), "sync");
@@ -611,16 +701,16 @@ int nf_mlp_train_step(nf_mlp* n, int B, const float* x, const float* t, float lr
     const int64_t cnt = (int64_t)B * n->n_out;
     mck(hipMemcpyAsync(n->T, t, sizeof(float) * cnt, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                        n->stream), "t copy");
-    forward(n, B);
+    forward(n, B, true);
     const int nb = (int)((cnt + 255) / 256);
-    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, n->stream, n->Y, n->T, cnt, 1.0f / (float)cnt, n->dYf,
-                       n->dYb, n->partial);
-    backward(n, B, false);
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, n->stream, n->Y, n->T, B, n->n_out, 1.0f / (float)cnt,
+                       n->dYf, n->dYb, n->dYt, n->partial);
+    backward(n, B, false, true);
     n->adam_t += 1;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
-    hipLaunchKernelGGL(adam_kernel, dim3((n->nparam + 255) / 256), dim3(256), 0, n->stream, n->w, n->g, n->am, n->av,
-                       n->nparam, lr, b1, b2, 1e-8f, c1, c2);
+    hipLaunchKernelGGL(adam_kernel, blocks(n->nparam), dim3(256), 0, n->stream, n->w, n->g, n->am, n->av, n->nparam,
+                       lr, b1, b2, 1e-8f, c1, c2);
     refresh_bf16(n);
     if (loss) {
       std::vector<float> part(nb);
@@ -642,15 +732,15 @@ int nf_mlp_fit_inputs(nf_mlp* n, int B, float* x, const float* nobs, const float
     if (B < 1 || B > n->max_batch || !x || !nobs || !out_mean || !out_std || !x_prior || !x_weight || iters < 1)
       throw MlpError(NF_EINVAL, "bad arguments");
     const int Ni = n->n_in, No = n->n_out;
-    float* xd = dalloc<float>((size_t)B * Ni);
     float* mom = dalloc<float>((size_t)B * Ni * 3);  // m, v, prior gradient
     float* aux = dalloc<float>((size_t)No * 2 + (size_t)Ni * 2 + B);
     float* nd = dalloc<float>((size_t)B * No);
     struct Free {
       std::vector<void*> p;
       ~Free() { for (void* q : p) (void)hipFree(q); }
-    } fr{{xd, mom, aux, nd}};
+    } fr{{mom, aux, nd}};
     float *mean = aux, *sd = aux + No, *xbar = aux + 2 * No, *xw = xbar + Ni, *nllv = xw + Ni;
+    float* xd = n->xf;  // the inputs being fitted live in the network's input staging buffer
     mck(hipMemcpyAsync(xd, x, sizeof(float) * B * Ni, hipMemcpyHostToDevice, n->stream), "H2D");
     mck(hipMemcpyAsync(nd, nobs, sizeof(float) * B * No, hipMemcpyHostToDevice, n->stream), "H2D");
     mck(hipMemcpyAsync(mean, out_mean, sizeof(float) * No, hipMemcpyHostToDevice, n->stream), "H2D");
@@ -660,18 +750,18 @@ int nf_mlp_fit_inputs(nf_mlp* n, int B, float* x, const float* nobs, const float
     mck(hipMemsetAsync(mom, 0, sizeof(float) * B * Ni * 2, n->stream), "memset");
     const int64_t cx = (int64_t)B * Ni;
     for (int it = 1; it <= iters; ++it) {
-      hipLaunchKernelGGL(to_bf16_kernel, dim3((cx + 255) / 256), dim3(256), 0, n->stream, xd, n->xb, cx);
-      forward(n, B);
+      prep_input(n, B);
+      forward(n, B, false);
       hipLaunchKernelGGL(surrogate_nll_kernel, dim3(B), dim3(256), 0, n->stream, n->Y, nd, mean, sd, No, xd, xbar, xw,
                          Ni, n->dYf, n->dYb, mom + 2 * cx, nllv);
       backward(n, B, true, false);
       const float c1 = 1.f - std::pow(0.9f, (float)it), c2 = 1.f - std::pow(0.999f, (float)it);
-      hipLaunchKernelGGL(input_adam_kernel, dim3((cx + 255) / 256), dim3(256), 0, n->stream, xd, n->dX, mom + 2 * cx,
-                         mom, mom + cx, cx, lr, c1, c2);
+      hipLaunchKernelGGL(input_adam_kernel, blocks(cx), dim3(256), 0, n->stream, xd, n->dX, mom + 2 * cx, mom,
+                         mom + cx, cx, lr, c1, c2);
     }
     // final NLL at the returned inputs
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((cx + 255) / 256), dim3(256), 0, n->stream, xd, n->xb, cx);
-    forward(n, B);
+    prep_input(n, B);
+    forward(n, B, false);
     hipLaunchKernelGGL(surrogate_nll_kernel, dim3(B), dim3(256), 0, n->stream, n->Y, nd, mean, sd, No, xd, xbar, xw, Ni,
                        n->dYf, n->dYb, mom + 2 * cx, nllv);
     mck(hipMemcpyAsync(x, xd, sizeof(float) * B * Ni, hipMemcpyDeviceToHost, n->stream), "D2H");

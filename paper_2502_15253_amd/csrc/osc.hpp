@@ -20,9 +20,9 @@ __device__ __forceinline__ double load_agent(const double* p) {
 
 // Sum of a double over the 64 lanes of a wavefront in a fixed order, returned
 // to every lane: pairs, quads, half-rows and rows by DPP lane swaps (every lane
-// of a group ends with the same group total), then the four row totals read
-// from lanes 0, 16, 32, 48 and added as (r0 + r1) + (r2 + r3). Needs all lanes
-// active; uses no address registers.
+// of a group ends with the same group total), then the four row totals by two
+// row broadcasts, read from lane 63. Needs all lanes active; uses no address
+// registers.
 template <int CTRL>
 __device__ __forceinline__ double dpp_swap(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
@@ -37,8 +37,20 @@ __device__ __forceinline__ double wave_sum_fixed(double x) {
   x += dpp_swap<0xB1>(x);   // quad_perm [1,0,3,2]
   x += dpp_swap<0x4E>(x);   // quad_perm [2,3,0,1]
   x += dpp_swap<0x141>(x);  // row_half_mirror
-  x += dpp_swap<0x140>(x);  // row_mirror
-  return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
+  x += dpp_swap<0x140>(x);  // row_mirror: every lane holds its row total r_q
+  // rows 1 and 3 add the total of the row below (r0 + r1, r2 + r3), then row
+  // 3 adds row 1: lane 63 holds (r2 + r3) + (r0 + r1)
+  {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x142, 0xa, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x142, 0xa, 0xf, false);
+    x += __hiloint2double(hi, lo);
+  }
+  {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x143, 0xc, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x143, 0xc, 0xf, false);
+    x += __hiloint2double(hi, lo);
+  }
+  return lane_value(x, 63);
 }
 
 // Inclusive prefix sum of a double over the 64 lanes of a wavefront in a

@@ -251,15 +251,28 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       constexpr int U = 16;
       for (int base = 0; base < total; base += NT * U) {
         double v[U];
+        if (io.fused) {
+          // one unconditional load per slot from a selected address (no
+          // branches, so all U loads are in flight together)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = base + u * NT + tid;
-          const int j = i - nbl;
-          if (i < nbl) v[u] = blob[i];
-          else if (io.fused)
-            v[u] = j < nb ? b[j] : j < n1 ? 0.0 : j < n2 ? sg[j - n1] : j < n3 ? dt[j - n2] : 0.0;
-          else
-            v[u] = j < n1 ? load_agent(b + j) : j < n2 ? load_agent(sg + (j - n1)) : j < n3 ? dt[j - n2] : 0.0;
+          for (int u = 0; u < U; ++u) {
+            const int i = base + u * NT + tid;
+            const int j = i - nbl;
+            const double* src = i < nbl ? blob + i
+                              : j < nb ? b + j
+                              : (j >= n1 && j < n2) ? sg + (j - n1)
+                              : (j >= n2 && j < n3) ? dt + (j - n2)
+                              : blob;
+            v[u] = *src;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int i = base + u * NT + tid;
+            const int j = i - nbl;
+            v[u] = i < nbl ? blob[i]
+                 : j < n1 ? load_agent(b + j) : j < n2 ? load_agent(sg + (j - n1)) : j < n3 ? dt[j - n2] : 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -371,7 +384,8 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       }
       L.mu[i] = lam;
     }
-    block_sum<NT, 1 + MAX_BKG>(acc, L.red);
+    if (NB <= 2) block_sum<NT, 3>(acc, L.red);
+    else block_sum<NT, 1 + MAX_BKG>(acc, L.red);
     nll_total += acc[0];
     if (!want_grad) {
       __syncthreads();
@@ -513,25 +527,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
           atomicAdd(&L.grad[(int)nli[q]], gA * prod);
         }
       };
-      if (S <= 16) {  // all sources at once, one block reduction
-        double gA[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) gA[s] = 0.0;
-        for (int k = tid; k < K; k += NT) {
-          const double lh = L.LH[k];
-#pragma unroll
-          for (int s = 0; s < 16; ++s)
-            if (s < S) gA[s] += lh * L.Ss[s * K + k];
-        }
-        block_sum<NT, 16>(gA, L.red);
-        if (tid < S) {
-          double g = 0.0;
-#pragma unroll
-          for (int s = 0; s < 16; ++s)
-            if (s == tid) g = gA[s];
-          apply(tid, g);
-        }
-      } else {  // one wavefront per source
+      {  // one wavefront per source
         const int lane = tid & 63, wid = tid >> 6;
         for (int s = wid; s < S; s += NT / 64) {
           double gA = 0.0;
