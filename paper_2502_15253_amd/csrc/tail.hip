@@ -207,38 +207,17 @@ __device__ __forceinline__ void prior_row(const DevPlan& p, const double* th, in
   }
 }
 
-// Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
-// NLL (+inf when out of domain) to every thread; the gradient is in L.grad.
+// Stage dataset d's inputs in LDS in one pass (every load in flight before the
+// first LDS write): the static blob, the fine-bin rows, per-segment S and the
+// data. Fused (single evaluation): rows 0..4 and S were written by the fold
+// kernel (plain loads) and row 5 = 1 + F is formed later from the blob's flux
+// rows. Otherwise all six rows were written by this workgroup's phase A with
+// agent-scope stores. No barrier: the caller synchronises.
 template <int NT>
-__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int want_nll, int want_grad) {
+__device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int d, int want_nll) {
   const int tid = threadIdx.x;
-  for (int i = tid; i < p.P; i += NT)
-    if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
-
-  double nll_total = 0.0;  // identical in every thread (block sums broadcast)
-
-  for (int d = 0; d < p.D; ++d) {
-    const DsPlan& ds = p.ds[d];
-    const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
-    const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
-    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
-    double* X = L.st + BL.edges;  // edges, then X, then lambda_X
-    const double* tmpl = L.st + BL.tmpl;
-    const double* shp = L.st + BL.shp;
-    const double* bsc = L.st + BL.bsc;
-    const double* brt = L.st + BL.brt;
-    L.Hs = L.dyn;
-    L.Gs = L.dyn + K;
-    L.F1 = L.dyn + 5 * K;
-    L.Ss = L.dyn + 6 * K;
-    L.nD = L.dyn + 6 * K + S * K;
-
-    // ---- stage in one pass (every load in flight before the first LDS
-    // write): the static blob, the fine-bin rows, per-segment S and the data.
-    // Fused (single evaluation): rows 0..4 and S were written by the fold
-    // kernel (plain loads) and row 5 = 1 + F is formed below from the blob's
-    // flux rows. Otherwise all six rows were written by this workgroup's
-    // phase A with agent-scope stores.
+  const DsPlan& ds = p.ds[d];
+  const int K = ds.K, Nb = ds.Nb, S = ds.S;
     {
       const int nbl = ds.blob_n;
       const int nb = io.fused ? 5 * K : 6 * K;
@@ -283,6 +262,35 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         }
       }
     }
+}
+
+// Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
+// NLL (+inf when out of domain) to every thread; the gradient is in L.grad.
+template <int NT>
+__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int want_nll, int want_grad) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < p.P; i += NT)
+    if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
+
+  double nll_total = 0.0;  // identical in every thread (block sums broadcast)
+
+  for (int d = 0; d < p.D; ++d) {
+    const DsPlan& ds = p.ds[d];
+    const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
+    const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
+    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
+    double* X = L.st + BL.edges;  // edges, then X, then lambda_X
+    const double* tmpl = L.st + BL.tmpl;
+    const double* shp = L.st + BL.shp;
+    const double* bsc = L.st + BL.bsc;
+    const double* brt = L.st + BL.brt;
+    L.Hs = L.dyn;
+    L.Gs = L.dyn + K;
+    L.F1 = L.dyn + 5 * K;
+    L.Ss = L.dyn + 6 * K;
+    L.nD = L.dyn + 6 * K + S * K;
+
+    stage_dataset<NT>(p, io, L, d, want_nll);
     __syncthreads();
 
     // ---- spline: edge densities and cumulative. In fused evaluations each
@@ -573,18 +581,17 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   Lds<NT> L = carve<NT>(smem, p);
   const int tid = threadIdx.x;
 
+  const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
+                  const_cast<double*>(a.bin), 1};
   for (int i = tid; i < p.P; i += NT) {
     L.th[i] = a.theta[i];
     L.grad[i] = 0.0;
   }
   if (tid == 0) {
     L.flag[0] = 0;
-    bool ok = osc_coefficients(p.osc, L.th, L.coef);
-    if (!ok) L.flag[0] |= ST_DOMAIN;
+    if (!osc_coefficients(p.osc, a.theta, L.coef)) L.flag[0] |= ST_DOMAIN;
   }
   __syncthreads();
-  const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
-                  const_cast<double*>(a.bin), 1};
   const double f = serial_stages<NT>(p, io, L, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
 }
@@ -627,7 +634,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   }
   if (tid == 0) {
     L.flag[0] = 0;
-    if (!osc_coefficients(p.osc, L.th, L.coef)) L.flag[0] |= ST_DOMAIN;
+    if (!osc_coefficients(p.osc, th, L.coef)) L.flag[0] |= ST_DOMAIN;
   }
   __syncthreads();
   const int drow = a.data_idx ? a.data_idx[f] : f;
