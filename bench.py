@@ -359,21 +359,41 @@ def main():
         torch.cuda.synchronize()  # the inputs were written on torch's default stream
         for k in range(args.warmup):
             eng.eval_device(ptr_t[k % 64], ptr_o[k % 64])
-        torch.cuda.synchronize()
-        eng.set_option("timing", 1)
+        # timed region: the evaluations as replays of one captured HIP graph of
+        # n_graph consecutive evaluations (n_graph divides the step count, so
+        # exactly `steps` evaluations run); the graph is captured and run once
+        # before the clock starts
+        n_graph = max(d for d in range(1, 65) if args.steps % d == 0)
+        eng.eval_device_many(n_graph, th_dev.data_ptr(), out_dev.data_ptr())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for r in range(args.steps // n_graph):
+            eng.eval_device_many(n_graph, th_dev.data_ptr(), out_dev.data_ptr())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        assert bool(torch.isfinite(out_dev[:n_graph]).all()), "non-finite NLL/gradient in the timed loop"
+        # the same evaluations one launch pair at a time, without and with
+        # per-kernel HIP events (the events give the fold and bin-stage
+        # durations of the roofline figure)
+        s0 = time.perf_counter()
         for k in range(args.steps):
             eng.eval_device(ptr_t[k % 64], ptr_o[k % 64])
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        s1 = time.perf_counter()
+        eng.set_option("timing", 1)
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        for k in range(args.steps):
+            eng.eval_device(ptr_t[k % 64], ptr_o[k % 64])
+        torch.cuda.synchronize()
+        e1 = time.perf_counter()
         cnt, fold_ms, tail_ms = eng.timing(reset=True)
         eng.set_option("timing", 0)
         assert cnt == args.steps
         # fixed cost inside every event-timed region (event packets, dispatch
         # and completion of the launch), measured on the same stream
         ev_over_us = eng.timing_overhead(200)
-        assert bool(torch.isfinite(out_dev).all()), "non-finite NLL/gradient in the timed loop"
+        assert bool(torch.isfinite(out_dev).all()), "non-finite NLL/gradient in the stream loops"
         # host C-ABI path, synchronous, including H2D of theta and D2H of NLL + gradient
         th_np = thetas
         h0 = time.perf_counter()
@@ -387,13 +407,18 @@ def main():
         traffic = measured_traffic(mode, n_in * bpe)
         res = dict(
             evals_per_s=args.steps / (t1 - t0), ms_per_step=(t1 - t0) * 1e3 / args.steps,
+            graph_evals=n_graph,
+            stream_loop_evals_per_s=args.steps / (s1 - s0),
+            event_timed_evals_per_s=args.steps / (e1 - e0),
             fold_us=fold_us, tail_us=tail_ms / cnt * 1e3, event_pair_gap_us=ev_over_us,
             host_path_evals_per_s=nh / (h1 - h0), events_in_range=n_in,
             roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                           algorithmic_bytes_per_launch=n_in * bpe,
-                          duration="mean fold duration from HIP events recorded around every fold "
-                                   "launch of the timed region on the engine stream"))
+                          duration="mean fold duration from HIP start/stop events carried by every "
+                                   "fold dispatch (hipExtLaunchKernel) of an event-timed pass over the "
+                                   "same evaluations (same kernels and inputs) right after the timed "
+                                   "graph replays, on the engine stream"))
         eng.close()
         log(f"{mode}: {json.dumps(res)}")
         return res
@@ -417,13 +442,17 @@ def main():
         for k in range(2 * R):
             engs[k % R].eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
         torch.cuda.synchronize()
-        for e in engs:
-            e.set_option("timing", 1)
         t0 = time.perf_counter()
         for k in range(steps):
             engs[k % R].eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        # the same loop again with per-kernel dispatch events for the durations
+        for e in engs:
+            e.set_option("timing", 1)
+        for k in range(steps):
+            engs[k % R].eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
+        torch.cuda.synchronize()
         cnt = fold_ms = tail_ms = 0
         for e in engs:
             c_, f_, t_ = e.timing(reset=True)
@@ -479,8 +508,12 @@ def main():
             "events": n_events, "bins": 400, "params": len(start),
             "mode": args.mode,
         },
+        "timed_region": f"replays of one HIP graph of {main_res['graph_evals']} consecutive "
+                        "evaluations (nf_eval_device_many), parameters and outputs resident in HBM",
         "fold_us": main_res["fold_us"],
         "tail_us": main_res["tail_us"],
+        "stream_loop_evals_per_s": main_res["stream_loop_evals_per_s"],
+        "event_timed_evals_per_s": main_res["event_timed_evals_per_s"],
         "host_path_evals_per_s": main_res["host_path_evals_per_s"],
         "roofline": main_res["roofline"],
         "cold": cold,

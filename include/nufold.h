@@ -138,6 +138,22 @@ int nf_eval_nll_grad(nf_ctx* ctx, const double* theta, double* nll, double* grad
 int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev,
                    int32_t* status_dev, int want_grad);
 
+/*
+ * n device evaluations in order, launched as one HIP graph on the context's
+ * stream: evaluation i reads theta_dev + i*P and writes NLL and gradient to
+ * out_dev + i*(1+P) (and its status to status_dev[i] when status_dev is not
+ * NULL), exactly as nf_eval_device would. The graph is captured on the first
+ * call and replayed by later calls with the same n, pointers and want_grad
+ * (it reads the current contents of theta_dev); other arguments, new events
+ * or changed launch options capture a new one. 1 <= n <= NF_MAX_GRAPH_EVALS.
+ * Asynchronous like nf_eval_device; per-kernel timing (option "timing") does
+ * not cover these launches. Each evaluation is that of nf_eval_device
+ * (Eq. 3-6 and 9 with the adjoint gradient).
+ */
+#define NF_MAX_GRAPH_EVALS 4096
+int nf_eval_device_many(nf_ctx* ctx, int n, const double* theta_dev, double* out_dev,
+                        int32_t* status_dev, int want_grad);
+
 /* Expected counts mu_{d,i}(theta) for every dataset, concatenated in dataset
  * order (host buffer of sum_d nf_num_bins(d) doubles). Needs events only. */
 int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
@@ -252,9 +268,10 @@ int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, 
 int nf_expected_batch(nf_ctx* ctx, int B, const double* theta, double* mu);
 
 /*
- * Per-kernel device time, measured with HIP events recorded on the context
- * stream around the fold and the bin-stage kernels of every evaluation while
- * option "timing" is 1. nf_timing synchronises the stream and returns, for the
+ * Per-kernel device time, measured with HIP start and stop events carried by
+ * the fold and the bin-stage kernel dispatches themselves (hipExtLaunchKernel:
+ * the events take each kernel's own start and end times) for every
+ * evaluation enqueued by nf_eval_* while option "timing" is 1. nf_timing synchronises the stream and returns, for the
  * evaluations enqueued since the last reset: their count, the summed fold
  * time and the summed bin-stage time (ms). reset != 0 starts a new window.
  */

@@ -189,7 +189,14 @@ struct nf_ctx {
   std::vector<FitHeader> bh_hdr;
   hipGraphExec_t bf_graph = nullptr;
   int bf_graph_B = 0;
-  std::vector<std::array<hipEvent_t, 3>> tev;  // per-evaluation timing events
+  // graph of n consecutive device evaluations (nf_eval_device_many), keyed by
+  // its arguments
+  hipGraphExec_t ev_graph = nullptr;
+  int ev_n = 0, ev_grad = -1;
+  const double* ev_theta = nullptr;
+  double* ev_out = nullptr;
+  int32_t* ev_status = nullptr;
+  std::vector<std::array<hipEvent_t, 4>> tev;  // per-evaluation kernel start/stop events (fold, bin stages)
   size_t tcount = 0;
 
   ~nf_ctx() {
@@ -205,6 +212,7 @@ struct nf_ctx {
     f_hdr.release(); f_x.release(); f_g.release(); f_p.release(); f_d2.release(); f_fr.release();
     f_S.release(); f_Y.release(); f_rho.release(); f_gam.release();
     if (bf_graph) (void)hipGraphExecDestroy(bf_graph);
+    if (ev_graph) (void)hipGraphExecDestroy(ev_graph);
     for (auto* b : {&bt_theta, &bt_part, &bt_out, &bt_Sseg, &bt_bin, &bt_segtmp, &bt_osc_last, &bt_data,
                     &bt_fold_theta, &bt_mu, &bf_x, &bf_g, &bf_p, &bf_d2, &bf_fr, &bf_S, &bf_Y, &bf_rho, &bf_gam})
       b->release();
@@ -678,6 +686,9 @@ void drop_fit_graph(nf_ctx* c) {
   if (c->bf_graph) (void)hipGraphExecDestroy(c->bf_graph);
   c->bf_graph = nullptr;
   c->bf_graph_B = 0;
+  if (c->ev_graph) (void)hipGraphExecDestroy(c->ev_graph);
+  c->ev_graph = nullptr;
+  c->ev_n = 0;
 }
 
 void rebuild_events(nf_ctx* c) {
@@ -846,7 +857,7 @@ FitArgs fit_args(nf_ctx* c) {
 }
 
 void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* status_dev, double* mu_dev,
-                  int want_nll, int want_grad, bool fit = false) {
+                  int want_nll, int want_grad, bool fit = false, bool timed = true) {
   FoldArgs fa{};
   fa.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
   fa.w = c->d_w.p;
@@ -887,21 +898,20 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
     fa.skip = &c->f_hdr.p->status;
   }
   hipEvent_t* ev = nullptr;
-  if (c->timing && !fit) {
+  if (c->timing && !fit && timed) {
     if (c->tcount == c->tev.size()) {
-      std::array<hipEvent_t, 3> t{};
+      std::array<hipEvent_t, 4> t{};
       // timing-only events: no system-scope fence (no cache write-back or
       // invalidation around the timed kernels)
       for (auto& e : t) hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
       c->tev.push_back(t);
     }
     ev = c->tev[c->tcount++].data();
-    hip_check(hipEventRecord(ev[0], c->stream), "hipEventRecord");
   }
-  hip_check(launch_fold(c->mode, fa, c->fold_block, c->stream), "fold launch");
-  if (ev) hip_check(hipEventRecord(ev[1], c->stream), "hipEventRecord");
-  hip_check(launch_tail(ta, c->tail_threads, c->stream), "tail launch");
-  if (ev) hip_check(hipEventRecord(ev[2], c->stream), "hipEventRecord");
+  hip_check(launch_fold(c->mode, fa, c->fold_block, c->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr),
+            "fold launch");
+  hip_check(launch_tail(ta, c->tail_threads, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr),
+            "tail launch");
 }
 
 int eval_host(nf_ctx* c, const double* theta, double* nll, double* grad, double* mu) {
@@ -1607,6 +1617,46 @@ int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev, int32_
   });
 }
 
+int nf_eval_device_many(nf_ctx* ctx, int n, const double* theta_dev, double* out_dev, int32_t* status_dev,
+                        int want_grad) {
+  return guarded(ctx, [&] {
+    require_ready(ctx, true);
+    if (n < 1 || n > NF_MAX_GRAPH_EVALS) fail(NF_EINVAL, "n must be in 1.." + std::to_string(NF_MAX_GRAPH_EVALS));
+    if (!theta_dev || !out_dev) fail(NF_EINVAL, "null device pointer");
+    nf_ctx* c = ctx;
+    const int g = want_grad ? 1 : 0;
+    if (!(c->ev_graph && c->ev_n == n && c->ev_grad == g && c->ev_theta == theta_dev && c->ev_out == out_dev &&
+          c->ev_status == status_dev)) {
+      if (c->ev_graph) (void)hipGraphExecDestroy(c->ev_graph);
+      c->ev_graph = nullptr;
+      c->ev_n = 0;
+      hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      try {
+        for (int i = 0; i < n; ++i)
+          enqueue_eval(c, theta_dev + (size_t)i * c->P, out_dev + (size_t)i * (1 + c->P),
+                       status_dev ? status_dev + i : nullptr, nullptr, 1, g, false, false);
+      } catch (...) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(c->stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      hipGraph_t gr = nullptr;
+      hip_check(hipStreamEndCapture(c->stream, &gr), "hipStreamEndCapture");
+      const hipError_t e = hipGraphInstantiate(&c->ev_graph, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      hip_check(e, "hipGraphInstantiate");
+      c->ev_n = n;
+      c->ev_grad = g;
+      c->ev_theta = theta_dev;
+      c->ev_out = out_dev;
+      c->ev_status = status_dev;
+    }
+    hip_check(hipGraphLaunch(c->ev_graph, c->stream), "hipGraphLaunch");
+    return NF_OK;
+  });
+}
+
 int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
   return guarded(ctx, [&] {
     if (!key) fail(NF_EINVAL, "key is null");
@@ -1706,7 +1756,7 @@ int nf_timing(nf_ctx* ctx, int reset, int64_t* count, double* fold_ms, double* t
     for (size_t i = 0; i < ctx->tcount; ++i) {
       float a = 0.f, b = 0.f;
       hip_check(hipEventElapsedTime(&a, ctx->tev[i][0], ctx->tev[i][1]), "hipEventElapsedTime");
-      hip_check(hipEventElapsedTime(&b, ctx->tev[i][1], ctx->tev[i][2]), "hipEventElapsedTime");
+      hip_check(hipEventElapsedTime(&b, ctx->tev[i][2], ctx->tev[i][3]), "hipEventElapsedTime");
       f += a;
       t += b;
     }

@@ -30,6 +30,7 @@
 // write-back is needed and the results do not depend on arrival order.
 // Batched evaluations keep the raw partials; their bin stages reduce them.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "fastmath.hpp"
 #include "kernels.hpp"
@@ -494,21 +495,24 @@ hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t strea
   return hipGetLastError();
 }
 
-// Host-side launcher (same translation unit as the kernels).
-hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream) {
+// Host-side launcher (same translation unit as the kernels). With events, the
+// launch carries them in its dispatch (hipExtLaunchKernel), so they take the
+// kernel's own start and end times.
+hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream, hipEvent_t start,
+                       hipEvent_t stop) {
   if (a.nitems <= 0) return hipSuccess;
   const int waves_per_block = block / 64;
-  const int grid = (a.nitems + waves_per_block - 1) / waves_per_block;
+  const dim3 grid((a.nitems + waves_per_block - 1) / waves_per_block);
+  auto go = [&](auto kernel) {
+    if (start || stop) hipExtLaunchKernelGGL(kernel, grid, dim3(block), 0, stream, start, stop, 0, a);
+    else hipLaunchKernelGGL(kernel, grid, dim3(block), 0, stream, a);
+  };
   if (mode == 0) {
-    if (a.osc.formula == FORM_EQ1)
-      hipLaunchKernelGGL(fold_m64_kernel<FORM_EQ1>, dim3(grid), dim3(block), 0, stream, a);
-    else
-      hipLaunchKernelGGL(fold_m64_kernel<FORM_3NU>, dim3(grid), dim3(block), 0, stream, a);
+    if (a.osc.formula == FORM_EQ1) go(fold_m64_kernel<FORM_EQ1>);
+    else go(fold_m64_kernel<FORM_3NU>);
   } else {
-    if (a.osc.formula == FORM_EQ1)
-      hipLaunchKernelGGL(fold_m32_kernel<FORM_EQ1>, dim3(grid), dim3(block), 0, stream, a);
-    else
-      hipLaunchKernelGGL(fold_m32_kernel<FORM_3NU>, dim3(grid), dim3(block), 0, stream, a);
+    if (a.osc.formula == FORM_EQ1) go(fold_m32_kernel<FORM_EQ1>);
+    else go(fold_m32_kernel<FORM_3NU>);
   }
   return hipGetLastError();
 }

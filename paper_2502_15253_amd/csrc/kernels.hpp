@@ -143,15 +143,18 @@ constexpr int MAX_BKG = 8;  // backgrounds per dataset
 // Dynamic LDS bytes used by the bin-stage kernel for a plan (matches carve()).
 __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
   const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
-  const size_t nd = 2 * (size_t)p.P + 40 + 16 * (nt / 64) + 16 + 6 * K + (size_t)p.max_S * K + Nb +
+  const size_t nd = 2 * (size_t)p.P + 40 + (size_t)p.D * DSPLAN_DOUBLES + (size_t)nt + 16 + 6 * K +
+                    (size_t)p.max_S * K + Nb +
                     4 * (K + 1) + K + 3 * E + Nb + p.max_blob;
   const size_t ni = E + 2 + K + 3;
   return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }
 
-hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream);
+hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream, hipEvent_t start = nullptr,
+                       hipEvent_t stop = nullptr);
 hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream);
-hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream);
+hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream, hipEvent_t start = nullptr,
+                       hipEvent_t stop = nullptr);
 hipError_t tail_set_lds_limit(size_t bytes);
 hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream);
 

@@ -72,19 +72,82 @@ __device__ __forceinline__ double wave_scan_incl(double x) {
   return x;
 }
 
-// Sum over aligned groups of NW lanes (NW = 2, 4, 8 or 16); every lane of a
-// group gets its group's total.
-template <int NW>
-__device__ __forceinline__ double group_sum(double x) {
-  if (NW >= 2) x += dpp_swap<0xB1>(x);
-  if (NW >= 4) x += dpp_swap<0x4E>(x);
-  if (NW >= 8) x += dpp_swap<0x141>(x);
-  if (NW >= 16) x += dpp_swap<0x140>(x);
-  return x;
+// Value of lane l ^ (1 << S) within each 16-lane row (S = 0..3): quad
+// permutations for 1 and 2; for 4 and 8, a row shift left for the lanes whose
+// bit S is clear and a row shift right for the others (DPP bank masks select
+// the groups of four lanes each shift writes).
+template <int S>
+__device__ __forceinline__ int xor_lane_b32(int v) {
+  static_assert(S >= 0 && S < 4, "row-local partners only");
+  if constexpr (S == 0) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (S == 1) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (S == 2) {
+    const int t = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xf, 0x5, false);  // row_shl:4, lanes 0-3, 8-11
+    return __builtin_amdgcn_update_dpp(t, v, 0x114, 0xf, 0xA, false);         // row_shr:4, lanes 4-7, 12-15
+  } else {
+    const int t = __builtin_amdgcn_update_dpp(0, v, 0x108, 0xf, 0x3, false);  // row_shl:8, lanes 0-7
+    return __builtin_amdgcn_update_dpp(t, v, 0x118, 0xf, 0xC, false);         // row_shr:8, lanes 8-15
+  }
+}
+template <int S>
+__device__ __forceinline__ double xor_lane(double x) {
+  const int lo = xor_lane_b32<S>(__double2loint(x));
+  const int hi = xor_lane_b32<S>(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// One step of a row-local reduce-scatter of NV values (NV a power of two):
+// lane pairs l, l ^ (1 << S) exchange halves, the lane whose bit S is clear
+// keeps the lower half, the other the upper half, and each adds its partner's
+// copy of the half it keeps. With NV = 1 the pair simply adds.
+template <int S, int NV>
+__device__ __forceinline__ void rs_step(double* c, int lane) {
+  if constexpr (NV == 1) {
+    c[0] += xor_lane<S>(c[0]);
+  } else {
+    constexpr int H = NV / 2;
+    const bool up = (lane >> S) & 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = up ? c[i + H] : c[i];
+      const double send = up ? c[i] : c[i + H];
+      c[i] = keep + xor_lane<S>(send);
+    }
+  }
+}
+
+// Reduce-scatter of NP values (1, 2, 4, 8 or 16) over each 16-lane row in a
+// fixed order: log2(NP) halving steps, then plain pairwise steps. Returns, in
+// lane l, the row total of value j = bit-reverse of the low log2(NP) bits of
+// l (every lane with the same low bits holds the same total). 15 exchanges
+// for 16 values instead of 16 separate reductions.
+template <int NP>
+__device__ __forceinline__ double row_reduce_scatter(double* c, int lane) {
+  static_assert(NP == 1 || NP == 2 || NP == 4 || NP == 8 || NP == 16, "power of two up to 16");
+  rs_step<0, NP>(c, lane);
+  rs_step<1, (NP >= 2 ? NP / 2 : 1)>(c, lane);
+  rs_step<2, (NP >= 4 ? NP / 4 : 1)>(c, lane);
+  rs_step<3, (NP >= 8 ? NP / 8 : 1)>(c, lane);
+  return c[0];
 }
 
 // Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
 // linear combination of (W, M_1..M_NM). Returns false outside the domain.
+// The parameter domain of the oscillation formula: finite slot values and,
+// for Eq. 1, sin^2(2 theta13) < 1 (cos^2 theta13 from its square root).
+// Exactly the cases in which osc_coefficients returns false.
+__device__ inline bool osc_domain_ok(const OscPlan& o, const double* th) {
+  bool ok = true;
+  for (int j = 0; j < NSLOT; ++j) {
+    const double v = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];
+    ok = ok && isfinite(v);
+    if (j == 0 && o.formula == FORM_EQ1) ok = ok && v < 1.0;
+  }
+  return ok;
+}
+
 __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {
   double v[NSLOT];
   for (int j = 0; j < NSLOT; ++j) v[j] = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];

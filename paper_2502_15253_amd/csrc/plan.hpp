@@ -68,6 +68,9 @@ struct DsPlan {
   int blob, blob_n; // dpool offset and length of the static blob (layout: blob_layout)
 };
 
+static_assert(sizeof(DsPlan) % sizeof(double) == 0, "DsPlan is copied as doubles");
+constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
+
 constexpr int NLMAX = 8;  // norm parameters multiplying one source
 
 // Per-dataset static inputs of the bin stages, packed contiguously (integers

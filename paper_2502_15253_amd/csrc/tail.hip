@@ -30,6 +30,7 @@
 // order except where contributions can hit one shared parameter within a
 // phase (LDS atomics), which only affects the last bits.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "kernels.hpp"
 #include "osc.hpp"
@@ -42,6 +43,7 @@ struct Lds {
   double* th;     // P
   double* grad;   // P
   double* coef;   // 40
+  DsPlan* dsl;    // D dataset plans (copied from global memory once per launch)
   double* red;    // reduction scratch
   double* dyn;    // 6K + S*K + Nb: Hs, G0..G3, F1, Ss (per-source spectra), observed counts
   double* Hs;
@@ -73,7 +75,8 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.th = q; q += p.P;
   L.grad = q; q += p.P;
   L.coef = q; q += 40;
-  L.red = q; q += 16 * (NT / 64) + 16;
+  L.dsl = reinterpret_cast<DsPlan*>(q); q += p.D * DSPLAN_DOUBLES;
+  L.red = q; q += NT + 16;
   L.dyn = q; q += 6 * K + p.max_S * K + Nb;
   L.D = q; q += K + 1;
   L.C = q; q += K + 1;
@@ -94,30 +97,53 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   return L;
 }
 
-__device__ __forceinline__ double wave_sum(double v) { return wave_sum_fixed(v); }
+// Launch prologue: parameters into LDS, gradient cleared, and the dataset
+// plans copied to LDS so every later stage reads them without a global round
+// trip. The caller synchronises.
+template <int NT>
+__device__ __forceinline__ void load_params(const DevPlan& p, const double* th, Lds<NT>& L) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < p.P; i += NT) {
+    L.th[i] = th[i];
+    L.grad[i] = 0.0;
+  }
+  const double* src = reinterpret_cast<const double*>(p.ds);
+  double* dst = reinterpret_cast<double*>(L.dsl);
+  for (int i = tid; i < p.D * DSPLAN_DOUBLES; i += NT) dst[i] = src[i];
+}
 
-// Sum of N values over the workgroup; every thread gets the totals. Wave
-// partials go to red[j*NW + w]; groups of NW lanes finish them with shuffles.
+// Sum of N values (N <= 16) over the workgroup; every thread gets the
+// totals, summed in a fixed order. Each wavefront reduce-scatters the values
+// over its 16-lane rows (padded to a power of two), one lane per (value, row)
+// writes its row total to red[j * 4 NW + row], then thread j adds the 4 NW
+// row totals of value j in order. red holds NT + 16 doubles; the totals sit
+// at red[NT + j], past every partial, so back-to-back calls do not overlap.
 template <int NT, int N>
 __device__ __forceinline__ void block_sum(double* v, double* red) {
-  constexpr int NW = NT / 64;
-  static_assert(N <= 16, "reduction scratch too small");
+  constexpr int NW = NT / 64, R = 4 * NW;
+  static_assert(N >= 1 && N <= 16, "reduction scratch too small");
+  constexpr int NP = N <= 1 ? 1 : N <= 2 ? 2 : N <= 4 ? 4 : N <= 8 ? 8 : 16;
+  constexpr int LG = NP == 1 ? 0 : NP == 2 ? 1 : NP == 4 ? 2 : NP == 8 ? 3 : 4;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double c[NP];
 #pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
-  if (lane == 0) {
-#pragma unroll
-    for (int j = 0; j < N; ++j) red[j * NW + wid] = v[j];
+  for (int j = 0; j < NP; ++j) c[j] = j < N ? v[j] : 0.0;
+  const double x = row_reduce_scatter<NP>(c, lane);
+  if (((lane & 15) >> LG) == 0) {
+    int j = 0;
+    if constexpr (LG > 0) j = (int)(__builtin_bitreverse32((unsigned)lane) >> (32 - LG));
+    red[j * R + wid * 4 + (lane >> 4)] = x;
   }
   __syncthreads();
-  if (wid < (N * NW + 63) / 64) {  // whole wavefronts take part in the lane swaps
-    double x = tid < N * NW ? red[tid] : 0.0;
-    x = group_sum<NW>(x);
-    if (tid < N * NW && (tid % NW) == 0) red[16 * NW + tid / NW] = x;
+  if (tid < N) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < R; ++q) s += red[tid * R + q];
+    red[16 * R + tid] = s;
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = red[16 * NW + j];
+  for (int j = 0; j < N; ++j) v[j] = red[16 * R + j];
 }
 
 // out[i] = sum of x[j] for j < i (i = 0..n), or, with reverse, out[i] = sum of
@@ -216,7 +242,7 @@ __device__ __forceinline__ void prior_row(const DevPlan& p, const double* th, in
 template <int NT>
 __device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int d, int want_nll) {
   const int tid = threadIdx.x;
-  const DsPlan& ds = p.ds[d];
+  const DsPlan& ds = L.dsl[d];
   const int K = ds.K, Nb = ds.Nb, S = ds.S;
     {
       const int nbl = ds.blob_n;
@@ -271,11 +297,12 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   const int tid = threadIdx.x;
   for (int i = tid; i < p.P; i += NT)
     if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
+  if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
 
   double nll_total = 0.0;  // identical in every thread (block sums broadcast)
 
   for (int d = 0; d < p.D; ++d) {
-    const DsPlan& ds = p.ds[d];
+    const DsPlan& ds = L.dsl[d];
     const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
     const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
     const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
@@ -494,35 +521,12 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     }
     __syncthreads();
 
-    // ---- rescale adjoint: lambda_Hs -> LH, lambda_F -> Ld; oscillation parameters
-    double go[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = tid; k < K; k += NT) {
-      const double lh = L.C[k];
-      const double lhs = lh * L.F1[k];
-      L.LH[k] = lhs;
-      L.Ld[k] = lh * L.Hs[k];
-      for (int j = 0; j < 4; ++j) go[j] += lhs * L.Gs[j * K + k];
-    }
-    block_sum<NT, 4>(go, L.red);
-    if (tid == 0)
-      for (int j = 0; j < NSLOT; ++j)
-        if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += go[j];
-
-    // ---- flux modes (CSC gather per mode)
-    {
-      const double* mdcol = L.st + BL.mdcol;
-      const double* mdk = L.st + BL.mdk;
-      const double* mdc = L.st + BL.mdc;
-      const double* mdp = L.st + BL.mdp;
-      for (int m = tid; m < M; m += NT) {
-        double gm = 0.0;
-        const int e1 = (int)mdcol[m + 1];
-        for (int e = (int)mdcol[m]; e < e1; ++e) gm += L.Ld[(int)mdk[e]] * mdc[e];
-        atomicAdd(&L.grad[(int)mdp[m]], gm);
-      }
-    }
-    // ---- source norms: dNLL/dA_s = sum_k lambda_Hs[k] S[s][k], then the
-    // product rule over each source's norm list
+    // ---- rescale adjoint, oscillation parameters and source norms in one
+    // pass over the fine bins with one block reduction (in groups of up to
+    // 12 sources): lambda_Hs = lambda_H (1 + F), lambda_F -> Ld; the
+    // oscillation slots take sum_k lambda_Hs G_j, source s takes
+    // dNLL/dA_s = sum_k lambda_Hs S[s][k], then the product rule over its
+    // norm list
     {
       const double* nlp = L.st + BL.nlp;
       const double* nli = L.st + BL.nli;
@@ -535,14 +539,49 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
           atomicAdd(&L.grad[(int)nli[q]], gA * prod);
         }
       };
-      {  // one wavefront per source
-        const int lane = tid & 63, wid = tid >> 6;
-        for (int s = wid; s < S; s += NT / 64) {
-          double gA = 0.0;
-          for (int k = lane; k < K; k += 64) gA += L.LH[k] * L.Ss[s * K + k];
-          gA = wave_sum(gA);
-          if (lane == 0) apply(s, gA);
+      for (int s0 = 0; s0 == 0 || s0 < S; s0 += 12) {
+        const int ns = min(S - s0, 12);
+        double acc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+        for (int k = tid; k < K; k += NT) {
+          const double lh = L.C[k];
+          const double lhs = lh * L.F1[k];
+          if (s0 == 0) {
+            L.Ld[k] = lh * L.Hs[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] += lhs * L.Gs[j * K + k];
+          }
+#pragma unroll
+          for (int q = 0; q < 12; ++q)
+            if (q < ns) acc[4 + q] += lhs * L.Ss[(s0 + q) * K + k];
         }
+        if (ns <= 4) block_sum<NT, 8>(acc, L.red);
+        else block_sum<NT, 16>(acc, L.red);
+        if (s0 == 0 && tid == 0)
+          for (int j = 0; j < NSLOT; ++j)
+            if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += acc[j];
+        if (tid < ns) {
+          double gA = 0.0;  // acc[4 + tid] without a dynamically indexed register array
+#pragma unroll
+          for (int q = 0; q < 12; ++q)
+            if (q == tid) gA = acc[4 + q];
+          apply(s0 + tid, gA);
+        }
+      }
+    }
+    // ---- flux modes (CSC gather per mode; Ld was written before the block
+    // reduction's barriers)
+    {
+      const double* mdcol = L.st + BL.mdcol;
+      const double* mdk = L.st + BL.mdk;
+      const double* mdc = L.st + BL.mdc;
+      const double* mdp = L.st + BL.mdp;
+      for (int m = tid; m < M; m += NT) {
+        double gm = 0.0;
+        const int e1 = (int)mdcol[m + 1];
+        for (int e = (int)mdcol[m]; e < e1; ++e) gm += L.Ld[(int)mdk[e]] * mdc[e];
+        atomicAdd(&L.grad[(int)mdp[m]], gm);
       }
     }
     __syncthreads();
@@ -583,14 +622,10 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
 
   const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
                   const_cast<double*>(a.bin), 1};
-  for (int i = tid; i < p.P; i += NT) {
-    L.th[i] = a.theta[i];
-    L.grad[i] = 0.0;
-  }
-  if (tid == 0) {
-    L.flag[0] = 0;
-    if (!osc_coefficients(p.osc, a.theta, L.coef)) L.flag[0] |= ST_DOMAIN;
-  }
+  // the fold kernel has applied the oscillation coefficients; the domain of
+  // the oscillation parameters is checked from LDS in the serial stages
+  load_params<NT>(p, a.theta, L);
+  if (tid == 0) L.flag[0] = 0;
   __syncthreads();
   const double f = serial_stages<NT>(p, io, L, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
@@ -628,10 +663,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   const int P = p.P, G = p.G, KT = p.KT;
   const int NMOM = num_moments(p.osc.formula);
   const double* th = a.theta + (int64_t)f * P;
-  for (int i = tid; i < P; i += NT) {
-    L.th[i] = th[i];
-    L.grad[i] = 0.0;
-  }
+  load_params<NT>(p, th, L);
   if (tid == 0) {
     L.flag[0] = 0;
     if (!osc_coefficients(p.osc, th, L.coef)) L.flag[0] |= ST_DOMAIN;
@@ -718,18 +750,22 @@ hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream)
   return hipGetLastError();
 }
 
-hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream) {
+hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream, hipEvent_t start, hipEvent_t stop) {
   const size_t lds = tail_lds_bytes(a.plan, nt);
   const dim3 grid(1);
+  auto go = [&](auto kernel, int threads) {
+    if (start || stop) hipExtLaunchKernelGGL(kernel, grid, dim3(threads), (uint32_t)lds, stream, start, stop, 0, a);
+    else hipLaunchKernelGGL(kernel, grid, dim3(threads), lds, stream, a);
+  };
   switch (nt) {
     case 256:
-      hipLaunchKernelGGL(tail_kernel<256>, grid, dim3(256), lds, stream, a);
+      go(tail_kernel<256>, 256);
       break;
     case 512:
-      hipLaunchKernelGGL(tail_kernel<512>, grid, dim3(512), lds, stream, a);
+      go(tail_kernel<512>, 512);
       break;
     default:
-      hipLaunchKernelGGL(tail_kernel<1024>, grid, dim3(1024), lds, stream, a);
+      go(tail_kernel<1024>, 1024);
       break;
   }
   return hipGetLastError();

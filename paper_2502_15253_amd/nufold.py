@@ -16,6 +16,7 @@ import numpy as np
 NF_OK, NF_WDOMAIN, NF_WNOCONV = 0, 1, 2
 NF_EINVAL, NF_ESTATE, NF_ENOMEM, NF_EDEVICE, NF_EPARSE = -1, -2, -3, -4, -5
 NF_M64, NF_M32 = 0, 1
+NF_MAX_GRAPH_EVALS = 4096
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnufold.so")
 
@@ -40,6 +41,7 @@ SIGNATURES = {
     "nf_eval_nll": (C.c_int, [C.c_void_p, _dp, _dp]),
     "nf_eval_nll_grad": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "nf_eval_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "nf_eval_device_many": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "nf_expected": (C.c_int, [C.c_void_p, _dp, _dp]),
     "nf_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "nf_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp, _dp]),
@@ -220,6 +222,15 @@ class Engine:
         return _check(self.ctx, load().nf_eval_device(self.ctx, C.c_void_p(theta_ptr), C.c_void_p(out_ptr),
                                                       C.c_void_p(status_ptr) if status_ptr else None,
                                                       1 if want_grad else 0))
+
+    def eval_device_many(self, n, theta_ptr, out_ptr, status_ptr=None, want_grad=True):
+        """Enqueue n evaluations (theta rows of P doubles, out rows of 1 + P)
+        as one HIP graph launch; replays the cached graph when n, the
+        pointers and want_grad repeat. Returns immediately."""
+        return _check(self.ctx, load().nf_eval_device_many(self.ctx, int(n), C.c_void_p(theta_ptr),
+                                                           C.c_void_p(out_ptr),
+                                                           C.c_void_p(status_ptr) if status_ptr else None,
+                                                           1 if want_grad else 0))
 
     def fit(self, start, fixed=None, edm_tol=1e-7, max_iter=1000, want_cov=False):
         """Device L-BFGS fit from `start`; returns a dict (theta, nll, edm, status, iters,

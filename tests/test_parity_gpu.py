@@ -251,3 +251,40 @@ def test_device_pointer_entry_point_matches_host_path():
     f, g, _ = eng.eval_nll_grad(th)
     o = out_t.cpu().numpy()
     assert o[0] == f and np.array_equal(o[1:], g) and int(st.item()) == 0
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_graph_of_device_evaluations_matches_single_evaluations(mode):
+    """nf_eval_device_many: captured once, replayed on new parameter values,
+    captured again for another count; every row equals the host path."""
+    say("graph of device evaluations", mode)
+    import torch
+    desc, events = synth.model_and_events(1)
+    data = oracle_data(desc, events, 6)
+    stream = torch.cuda.Stream()
+    eng = nf.Engine(desc, mode, stream=stream.cuda_stream)
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+        eng.set_data(d, data[d])
+    P = eng.P
+    out_t = torch.zeros((5, 1 + P), dtype=torch.float64, device="cuda")
+    st = torch.full((5,), -7, dtype=torch.int32, device="cuda")
+    for rnd, (n, seed0) in enumerate(((5, 20), (5, 40), (3, 60))):
+        ths = np.stack([displaced(desc, seed0 + i) for i in range(5)])
+        theta_t = torch.tensor(ths, dtype=torch.float64, device="cuda") if rnd == 0 else theta_t
+        if rnd > 0:
+            theta_t.copy_(torch.tensor(ths, dtype=torch.float64))  # same buffer: the graph reads it anew
+        torch.cuda.synchronize()
+        eng.eval_device_many(n, theta_t.data_ptr(), out_t.data_ptr(), st.data_ptr(), True)
+        stream.synchronize()
+        o = out_t.cpu().numpy()
+        for i in range(n):
+            f, g, code = eng.eval_nll_grad(ths[i])
+            assert code == nf.NF_OK
+            # same kernels on the same inputs; LDS atomic order may move the last bits
+            assert abs(o[i, 0] - f) <= 1e-13 * max(1.0, abs(f)), (rnd, i)
+            assert np.max(np.abs(o[i, 1:] - g)) <= 1e-12 * max(1.0, np.max(np.abs(g))), (rnd, i)
+        assert np.all(st.cpu().numpy()[:n] == 0)
+    with pytest.raises(nf.NufoldError) as e:
+        eng.eval_device_many(0, theta_t.data_ptr(), out_t.data_ptr())
+    assert e.value.code == nf.NF_EINVAL
