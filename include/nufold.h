@@ -164,8 +164,13 @@ int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
  * "tail_threads" (bin-stage threads of the single evaluation: 256, 512 or
  * 1024), "batch_threads" (bin-stage threads per fit in batched launches: 256,
  * 512, 1024, or 0 = chosen from the model size). Changing "chunk" rebuilds
- * the work-item list. "timing" (0/1) turns per-kernel event timing on or off
- * (see nf_timing). Returns NF_EINVAL for unknown keys/values.
+ * the work-item list. "deterministic" (0/1, default 0): with 1 the fold
+ * kernel hands each fine bin's source rows to the last source to finish,
+ * which sums them in source order, so repeated evaluations agree bit for bit;
+ * with 0 each source adds its rows with device-scope atomic adds (no waiting
+ * at the end of the fold; the order of those additions, and so the last bits
+ * of the result, may vary between runs). "timing" (0/1) turns per-kernel event
+ * timing on or off (see nf_timing). Returns NF_EINVAL for unknown keys/values.
  */
 int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
 

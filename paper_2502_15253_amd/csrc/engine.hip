@@ -172,6 +172,7 @@ struct nf_ctx {
   int fold_block = 256;
   int tail_threads = 512;
   int timing = 0;
+  int deterministic = 0;  // fine-bin rows by ordered hand-off (1) or atomic adds (0)
   // minimiser buffers (allocated at the first fit) and the captured iteration graph
   int fit_m = 8;
   DevBuf<FitHeader> f_hdr;
@@ -880,6 +881,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fu.Sseg = c->d_Sseg.p;
   fu.bin = c->d_bin.p;
   fu.G = c->plan.G;
+  fu.atomic_rows = c->deterministic ? 0 : 1;
   TailArgs ta{};
   ta.plan = c->plan;
   ta.theta = theta_dev;
@@ -1679,6 +1681,10 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
       if (value != 0 && value != 256 && value != 512 && value != 1024)
         fail(NF_EINVAL, "batch_threads must be 0, 256, 512 or 1024");
       ctx->batch_threads_opt = (int)value;
+      drop_fit_graph(ctx);
+    } else if (k == "deterministic") {
+      if (value != 0 && value != 1) fail(NF_EINVAL, "deterministic must be 0 or 1");
+      ctx->deterministic = (int)value;
       drop_fit_graph(ctx);
     } else if (k == "timing") {
       ctx->timing = value ? 1 : 0;

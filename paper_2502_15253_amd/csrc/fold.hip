@@ -189,6 +189,31 @@ __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const dou
     }
   }
   const int kt = F.seg_kt[seg];
+  if (F.atomic_rows) {
+    // this segment's rows: lane r < 5 forms row r from the coefficients and
+    // adds A_s times it to the fine bin (fire-and-forget device-scope adds;
+    // the rows start at zero and the bin stages clear them after reading)
+    const int* info = F.kt_info + 5 * kt;
+    const int g0 = info[0], K = info[1], fs0 = info[3], kt0 = info[4];
+    const int s = (seg - g0) / K;
+    const int* nl = F.fs_nl + NLMAX * (fs0 + s);
+    double A = 1.0;
+#pragma unroll
+    for (int q = 0; q < NLMAX; ++q)
+      if (nl[q] >= 0) A *= a.theta[nl[q]];
+    if (lane < 5) {
+      int z = 0;  // opaque zero: keeps the coefficient loads here (see below)
+      asm volatile("" : "+v"(z));
+      const double* c0 = cf + 8 * lane + z;
+      double r = 0.0;
+#pragma unroll
+      for (int c = 0; c <= NM; ++c) r += c0[c] * M[c];
+      if (lane == 0) F.Sseg[seg] = r;
+      double* b = F.bin + 6 * (int64_t)kt0;
+      __hip_atomic_fetch_add(&b[lane * K + (kt - kt0)], A * r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   if (F.kt_need[kt] > 1) {
     if (lane == 0) {
 #pragma unroll

@@ -39,9 +39,13 @@ __host__ __device__ inline size_t fit_lds_doubles(int P, int m) {
 
 // Reduction of the single evaluation's fold results to fine bins, done by the
 // fold kernel itself: the last wavefront to finish a segment sums the
-// segment's item partials (fixed item order); the last segment of a fine bin
-// to finish applies the oscillation coefficients and the source norms and
-// writes that bin's rows (fixed source order). Counters return to zero.
+// segment's item partials (fixed item order) and applies the oscillation
+// coefficients. The segment's rows, scaled by its source norm, then reach the
+// fine bin either by device-scope atomic adds (atomic_rows = 1: no waiting,
+// the order of the additions of a bin's sources varies) or through the last
+// segment of the fine bin to finish, which sums them in source order and
+// stores the rows (atomic_rows = 0: reproducible bit for bit). Counters
+// return to zero.
 struct FoldFuse {
   const int* seg_item;  // [G+1] work-item range of each segment
   const double* Wseg;   // [G] summed weights of each segment
@@ -55,6 +59,9 @@ struct FoldFuse {
   double* Sseg;         // [G] oscillated fine spectrum S per segment (before the source norm)
   double* bin;          // per dataset at 6 kt0: rows Hs, dHs/dslot_0..3 over its K fine bins
   int G;
+  int atomic_rows;      // 1: every segment adds its rows with device-scope atomics (the bin
+                        // stages read and clear them); 0: the last segment of a fine bin
+                        // sums the segments in source order and stores the rows
 };
 
 struct FoldArgs {

@@ -286,6 +286,7 @@ __device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io
           if (i < nbl) L.st[i] = v[u];
           else if (j < n3 && (j < nb || j >= n1)) L.dyn[j] = v[u];
         }
+
       }
     }
 }
@@ -603,6 +604,15 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   __syncthreads();
 
   const bool bad = (L.flag[0] & ST_DOMAIN) || !isfinite(nll_total);
+  if (io.fused) {
+    // the fold kernel accumulates rows 0..4 into zeroed memory: clear them
+    // for the next launch (issued with the outputs, after every read)
+    for (int d = 0; d < p.D; ++d) {
+      double* b = io.bin + 6 * (int64_t)L.dsl[d].kt0;
+      const int n = 5 * L.dsl[d].K;
+      for (int j = tid; j < n; j += NT) b[j] = 0.0;
+    }
+  }
   if (io.out && want_nll && tid == 0) io.out[0] = bad ? INFINITY : nll_total;
   if (io.out && want_grad && want_nll)
     for (int i = tid; i < p.P; i += NT) io.out[1 + i] = bad ? 0.0 : L.grad[i];

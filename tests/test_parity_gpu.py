@@ -26,10 +26,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_engine(desc, events, data=None, mode="m64", chunk=None):
+def make_engine(desc, events, data=None, mode="m64", chunk=None, deterministic=None):
     eng = nf.Engine(desc, mode)
     if chunk:
         eng.set_option("chunk", chunk)
+    if deterministic is not None:
+        eng.set_option("deterministic", deterministic)
     for d, ev in enumerate(events):
         eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
     if data is not None:
@@ -61,7 +63,9 @@ def compare(eng, desc, events, data, theta, tol, what=""):
     err = np.max(np.abs(g_g - g_o))
     assert err <= tol * scale, f"{what}: grad err {err:.3e} (scale {scale:.3e}) at {np.argmax(np.abs(g_g - g_o))}"
     f_n, code = eng.eval_nll(theta)
-    assert f_n == f_g
+    # the same evaluation without the gradient; fine-bin sums by atomic adds may
+    # move the last bits of mu, which the deviance's cancellations amplify
+    assert abs(f_n - f_g) <= 1e-10 * max(1.0, abs(f_g))
     return f_g, g_g
 
 
@@ -78,12 +82,13 @@ def displaced(desc, seed, scale=0.3):
 @pytest.mark.parametrize("mode", ["m64", "m32"])
 @pytest.mark.parametrize("formula", ["eq1", "3nu"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_tiny_models(mode, formula, seed):
-    say("tiny", mode, formula, seed)
+@pytest.mark.parametrize("deterministic", [0, 1])
+def test_tiny_models(mode, formula, seed, deterministic):
+    say("tiny", mode, formula, seed, deterministic)
     desc = synth.tiny_model(10 + seed, formula=formula, n_datasets=2 + seed % 2, n_sources=1 + seed)
     events = synth.tiny_events(desc, 5000 + 1111 * seed, 50 + seed)
     data = oracle_data(desc, events, 60 + seed)
-    eng = make_engine(desc, events, data, mode)
+    eng = make_engine(desc, events, data, mode, deterministic=deterministic)
     for j in range(3):
         compare(eng, desc, events, data, displaced(desc, 70 + j), TOL[mode], f"tiny {formula} {seed} {j}")
 
@@ -100,12 +105,12 @@ def test_config1_full_size(mode):
         compare(eng, desc, events, data, displaced(desc, 100 + j), TOL[mode], f"c1 displaced {j}")
 
 
-@pytest.mark.parametrize("mode", ["m64", "m32"])
-def test_config2_full_size(mode):
-    say("config2", mode)
+@pytest.mark.parametrize("mode,deterministic", [("m64", 0), ("m32", 0), ("m64", 1)])
+def test_config2_full_size(mode, deterministic):
+    say("config2", mode, deterministic)
     desc, events = synth.model_and_events(2)
     data = oracle_data(desc, events, synth.data_seed(2))
-    eng = make_engine(desc, events, data, mode)
+    eng = make_engine(desc, events, data, mode, deterministic=deterministic)
     compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c2 start")
     compare(eng, desc, events, data, displaced(desc, 200), TOL[mode], "c2 displaced")
 
@@ -143,7 +148,7 @@ def test_repeated_evaluations_are_bitwise_identical():
     say("determinism")
     desc, events = synth.model_and_events(1)
     data = oracle_data(desc, events, 3)
-    eng = make_engine(desc, events, data)
+    eng = make_engine(desc, events, data, deterministic=1)
     th = displaced(desc, 8)
     f0, g0, _ = eng.eval_nll_grad(th)
     for _ in range(5):
@@ -250,7 +255,32 @@ def test_device_pointer_entry_point_matches_host_path():
     torch.cuda.synchronize()
     f, g, _ = eng.eval_nll_grad(th)
     o = out_t.cpu().numpy()
-    assert o[0] == f and np.array_equal(o[1:], g) and int(st.item()) == 0
+    # same kernels on the same inputs (fine-bin rows by atomic adds: last bits may move)
+    assert abs(o[0] - f) <= 1e-13 * max(1.0, abs(f)) and int(st.item()) == 0
+    assert np.max(np.abs(o[1:] - g)) <= 1e-12 * max(1.0, np.max(np.abs(g)))
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_deterministic_option_reproduces_bit_for_bit(mode):
+    """With deterministic = 1 every fine bin is summed in source order by one
+    wavefront: repeated evaluations (with other evaluations between them)
+    agree bit for bit, and agree with the atomic accumulation to rounding."""
+    say("deterministic option", mode)
+    desc, events = synth.model_and_events(3, 400_000)
+    m = Model(desc)
+    data = [mu.copy() for mu in LK.expected(m, events, synth.start_vector(desc))[0]]
+    eng = make_engine(desc, events, data, mode, deterministic=1)
+    th = [displaced(desc, 500 + j) for j in range(3)]
+    first = [eng.eval_nll_grad(t)[:2] for t in th]
+    for rep in range(3):
+        for t, (f0, g0) in zip(th, first):
+            f, g, _ = eng.eval_nll_grad(t)
+            assert f == f0 and np.array_equal(g, g0), rep
+    eng.set_option("deterministic", 0)
+    for t, (f0, g0) in zip(th, first):
+        f, g, _ = eng.eval_nll_grad(t)
+        assert abs(f - f0) <= 1e-12 * max(1.0, abs(f0))
+        assert np.max(np.abs(g - g0)) <= 1e-11 * max(1.0, np.max(np.abs(g0)))
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])
