@@ -504,6 +504,7 @@ void parse_model(nf_ctx* c, const char* text) {
         blob[B.fpar + e] = d.flux_param[ip[q.fx_mode + e]];
         blob[B.fcf + e] = dp[q.fx_coef + e];
       }
+      if (dp.size() % 2) dp.push_back(0.0);  // 16-byte aligned blobs (direct LDS copies in 16-byte units)
       q.blob = (int)dp.size();
       q.blob_n = B.total;
       dp.insert(dp.end(), blob.begin(), blob.end());
@@ -627,6 +628,7 @@ void upload_plan(nf_ctx* c) {
   if (b.empty()) b.push_back(BkgPlan{});
   c->d_bkg.upload(b, c->stream);
   c->plan.ds = c->d_ds.p;
+  c->plan.ds0 = c->dsplan.empty() ? DsPlan{} : c->dsplan[0];
   c->plan.bkg = c->d_bkg.p;
   c->plan.dpool = c->d_dpool.p;
   c->plan.ipool = c->d_ipool.p;

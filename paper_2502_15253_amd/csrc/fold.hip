@@ -104,7 +104,7 @@ __device__ __forceinline__ void accum64(double u, float wf, double a1, double a2
 __device__ __forceinline__ float phase_rev(float u, float bh, float bl) {
   const float p = bh * u;
   const float e = fmaf(bh, u, -p);           // exact low part of bh*u
-  const float fr = p - floorf(p);            // exact for |p| < 2^23
+  const float fr = __builtin_amdgcn_fractf(p);  // p - floor(p) in one instruction
   return fr + fmaf(bl, u, e);
 }
 

@@ -150,7 +150,7 @@ constexpr int MAX_BKG = 8;  // backgrounds per dataset
 // Dynamic LDS bytes used by the bin-stage kernel for a plan (matches carve()).
 __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
   const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
-  const size_t nd = 2 * (size_t)p.P + 40 + (size_t)p.D * DSPLAN_DOUBLES + (size_t)nt + 16 + 6 * K +
+  const size_t nd = 3 + 2 * (size_t)p.P + 40 + (size_t)p.D * DSPLAN_DOUBLES + (size_t)nt + 16 + 6 * K +
                     (size_t)p.max_S * K + Nb +
                     4 * (K + 1) + K + 3 * E + Nb + p.max_blob;
   const size_t ni = E + 2 + K + 3;

@@ -105,6 +105,7 @@ struct DevPlan {
   int max_K, max_Nb, max_S, max_B, max_M, max_nnz, max_nl;
   OscPlan osc;
   const DsPlan* ds;
+  DsPlan ds0;            // copy of ds[0] (read from the kernel arguments)
   const BkgPlan* bkg;
   const double* dpool;
   const int* ipool;

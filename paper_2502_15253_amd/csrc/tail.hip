@@ -71,12 +71,16 @@ template <int NT>
 __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   Lds<NT> L;
   const int K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
+  // regions filled by direct copies start at 16-byte boundaries (even offsets)
+  auto al = [](double* x) { return x + (reinterpret_cast<uintptr_t>(x) & 8 ? 1 : 0); };
   double* q = base;
   L.th = q; q += p.P;
   L.grad = q; q += p.P;
   L.coef = q; q += 40;
+  q = al(q);
   L.dsl = reinterpret_cast<DsPlan*>(q); q += p.D * DSPLAN_DOUBLES;
   L.red = q; q += NT + 16;
+  q = al(q);
   L.dyn = q; q += 6 * K + p.max_S * K + Nb;
   L.D = q; q += K + 1;
   L.C = q; q += K + 1;
@@ -87,6 +91,7 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.eY = q; q += E;
   L.eH = q; q += E;
   L.mu = q; q += Nb;
+  q = al(q);
   L.st = q; q += p.max_blob;
   L.fit = q; q += fit_lds_doubles(p.P, p.fit_m);
   int* r = reinterpret_cast<int*>(q);
@@ -233,62 +238,105 @@ __device__ __forceinline__ void prior_row(const DevPlan& p, const double* th, in
   }
 }
 
-// Stage dataset d's inputs in LDS in one pass (every load in flight before the
-// first LDS write): the static blob, the fine-bin rows, per-segment S and the
-// data. Fused (single evaluation): rows 0..4 and S were written by the fold
-// kernel (plain loads) and row 5 = 1 + F is formed later from the blob's flux
-// rows. Otherwise all six rows were written by this workgroup's phase A with
-// agent-scope stores. No barrier: the caller synchronises.
+// Asynchronous copies from global memory straight into LDS (global_load_lds:
+// no registers, every load in flight at once). dma_lds<NT, B> moves nbytes (a
+// multiple of B) in chunks of 64 B bytes, one per wavefront in turn, lane l
+// the B bytes at l B of its chunk; B = 16 needs 16-byte aligned source and
+// destination. The caller waits (s_waitcnt) and synchronises before reading.
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef __attribute__((address_space(1))) const void* global_cvoid_ptr;
+template <int NT, int B>
+__device__ __forceinline__ void dma_lds(char* dst, const char* src, int nbytes) {
+  static_assert(B == 4 || B == 16, "4- or 16-byte units");
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nunits = nbytes / B;
+  for (int c = wid; c * 64 < nunits; c += NW) {
+    const int idx = c * 64 + lane;
+    if (idx < nunits) {
+      const global_cvoid_ptr g = (global_cvoid_ptr)(src + (size_t)B * idx);
+      const lds_void_ptr l = (lds_void_ptr)(dst + (size_t)(64 * B) * c);
+      if constexpr (B == 16) __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+      else __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+    }
+  }
+}
+// n doubles: 16-byte units when source and destination share their
+// alignment modulo 16 (a leading or trailing double by 4-byte units), else
+// 4-byte units throughout.
+template <int NT>
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int n) {
+  char* d = reinterpret_cast<char*>(dst);
+  const char* s = reinterpret_cast<const char*>(src);
+  const unsigned da = (unsigned)(uintptr_t)(lds_void_ptr)d;
+  const unsigned sa = (unsigned)(uintptr_t)s;
+  if (((da ^ sa) & 15u) != 0 || n < 4) {
+    dma_lds<NT, 4>(d, s, 8 * n);
+    return;
+  }
+  const int head = (sa & 15u) ? 1 : 0;
+  const int body = (n - head) & ~1;
+  const int tail = n - head - body;
+  if (head) dma_lds<NT, 4>(d, s, 8);
+  dma_lds<NT, 16>(d + 8 * head, s + 8 * head, 8 * body);
+  if (tail) dma_lds<NT, 4>(d + 8 * (head + body), s + 8 * (head + body), 8);
+}
+
+// Stage dataset d's inputs in LDS: the static blob, the fine-bin rows,
+// per-segment S and the data. Fused (single evaluation): rows 0..4 and S were
+// written by the fold kernel in an earlier launch, so every array is copied
+// straight into LDS with direct global-to-LDS loads; row 5 = 1 + F is formed
+// later from the blob's flux rows. Otherwise all six rows were written by this
+// workgroup's phase A with agent-scope stores and are read back with coherent
+// loads, U per thread in flight before the LDS writes. No barrier: the caller
+// synchronises.
+template <int NT>
+__device__ __forceinline__ void stage_fused(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
+                                            int want_nll) {
+  const int K = ds.K;
+  const int n1 = 6 * K, n2 = n1 + ds.S * K;
+  copy_to_lds<NT>(L.st, p.dpool + ds.blob, ds.blob_n);
+  copy_to_lds<NT>(L.dyn, io.bin + 6 * (int64_t)ds.kt0, 5 * K);
+  copy_to_lds<NT>(L.dyn + n1, io.Sseg + ds.seg0, n2 - n1);
+  if (want_nll) copy_to_lds<NT>(L.dyn + n2, io.data + ds.data, ds.Nb);
+}
+
 template <int NT>
 __device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int d, int want_nll) {
   const int tid = threadIdx.x;
   const DsPlan& ds = L.dsl[d];
   const int K = ds.K, Nb = ds.Nb, S = ds.S;
-    {
-      const int nbl = ds.blob_n;
-      const int nb = io.fused ? 5 * K : 6 * K;
-      const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
-      const double* blob = p.dpool + ds.blob;
-      const double* b = io.bin + 6 * (int64_t)ds.kt0;
-      const double* sg = io.Sseg + ds.seg0;
-      const double* dt = io.data + ds.data;
-      const int total = nbl + n3;
-      constexpr int U = 16;
-      for (int base = 0; base < total; base += NT * U) {
-        double v[U];
-        if (io.fused) {
-          // one unconditional load per slot from a selected address (no
-          // branches, so all U loads are in flight together)
+  const int nbl = ds.blob_n;
+  const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
+  const double* blob = p.dpool + ds.blob;
+  const double* b = io.bin + 6 * (int64_t)ds.kt0;
+  const double* sg = io.Sseg + ds.seg0;
+  const double* dt = io.data + ds.data;
+  if (io.fused) {
+    // dataset 0 was staged with the parameters in the launch prologue
+    if (d > 0) stage_fused<NT>(p, io, L, ds, want_nll);
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
+  const int total = nbl + n3;
+  constexpr int U = 16;
+  for (int base = 0; base < total; base += NT * U) {
+    double v[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int i = base + u * NT + tid;
-            const int j = i - nbl;
-            const double* src = i < nbl ? blob + i
-                              : j < nb ? b + j
-                              : (j >= n1 && j < n2) ? sg + (j - n1)
-                              : (j >= n2 && j < n3) ? dt + (j - n2)
-                              : blob;
-            v[u] = *src;
-          }
-        } else {
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int i = base + u * NT + tid;
-            const int j = i - nbl;
-            v[u] = i < nbl ? blob[i]
-                 : j < n1 ? load_agent(b + j) : j < n2 ? load_agent(sg + (j - n1)) : j < n3 ? dt[j - n2] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = base + u * NT + tid;
-          const int j = i - nbl;
-          if (i < nbl) L.st[i] = v[u];
-          else if (j < n3 && (j < nb || j >= n1)) L.dyn[j] = v[u];
-        }
-
-      }
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + tid;
+      const int j = i - nbl;
+      v[u] = i < nbl ? blob[i]
+           : j < n1 ? load_agent(b + j) : j < n2 ? load_agent(sg + (j - n1)) : j < n3 ? dt[j - n2] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + tid;
+      const int j = i - nbl;
+      if (i < nbl) L.st[i] = v[u];
+      else if (j < n3) L.dyn[j] = v[u];
+    }
+  }
 }
 
 // Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
@@ -633,9 +681,15 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
                   const_cast<double*>(a.bin), 1};
   // the fold kernel has applied the oscillation coefficients; the domain of
-  // the oscillation parameters is checked from LDS in the serial stages
-  load_params<NT>(p, a.theta, L);
+  // the oscillation parameters is checked from LDS in the serial stages.
+  // Parameters, dataset plans and dataset 0's inputs go to LDS in one round
+  // of direct copies (dataset 0's plan comes with the kernel arguments).
+  copy_to_lds<NT>(L.th, a.theta, p.P);
+  copy_to_lds<NT>(reinterpret_cast<double*>(L.dsl), reinterpret_cast<const double*>(p.ds), p.D * DSPLAN_DOUBLES);
+  stage_fused<NT>(p, io, L, p.ds0, a.want_nll);
+  for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
   if (tid == 0) L.flag[0] = 0;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   const double f = serial_stages<NT>(p, io, L, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
