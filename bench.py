@@ -304,6 +304,48 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / dt / 1e9
 
 
+def event_sweep(args, nf, synth, torch, counts):
+    """Single-evaluation throughput and fold bandwidth of the medium-baseline
+    model at several event counts (the asymptote of the streaming fold): graph
+    replays for the rate, per-kernel dispatch events for the durations."""
+    stream = torch.cuda.Stream()
+    for n in counts:
+        log(f"sweep: generating {n:.0e} events")
+        desc, events = synth.model_and_events(3, n)
+        thetas = synth.osc_theta_list(desc, 64, seed=5)
+        for mode in ("m32", "m64"):
+            eng = nf.Engine(desc, mode, stream=stream.cuda_stream)
+            for d, ev in enumerate(events):
+                eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+            n_in = sum(len(ev["weight"]) for ev in events) - sum(eng.dropped(d) for d in range(eng.D))
+            for d, mu in enumerate(eng.expected(synth.start_vector(desc))[0]):
+                eng.set_data(d, mu)
+            th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
+            out_dev = torch.zeros((64, 1 + eng.P), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            n_graph = max(d for d in range(1, 65) if args.steps % d == 0)
+            eng.eval_device_many(n_graph, th_dev.data_ptr(), out_dev.data_ptr())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps // n_graph):
+                eng.eval_device_many(n_graph, th_dev.data_ptr(), out_dev.data_ptr())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            eng.set_option("timing", 1)
+            for k in range(args.steps):
+                eng.eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr())
+            cnt, fold_ms, tail_ms = eng.timing(reset=True)
+            eng.close()
+            bpe = 12 if mode == "m64" else 8
+            fold_us = fold_ms / cnt * 1e3
+            gbs = n_in * bpe / (fold_us * 1e-6) / 1e9
+            print(json.dumps(dict(events=n, events_in_range=n_in, mode=mode, evals_per_s=args.steps / (t1 - t0),
+                                  us_per_eval=(t1 - t0) / args.steps * 1e6, fold_us=fold_us,
+                                  tail_us=tail_ms / cnt * 1e3, fold_gbs=gbs, frac=gbs / HBM_PEAK_GBS)),
+                  flush=True)
+        del events
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +363,9 @@ def main():
                     help="training spectra for the warm-start section (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device copy of known size (counter calibration) and exit")
+    ap.add_argument("--event-sweep", default="",
+                    help="comma-separated event counts (e.g. 1e6,1e7,1e8): only time the single "
+                         "evaluation of the medium-baseline model at each count and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the event fold shards over "
@@ -335,6 +380,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.event_sweep:
+        event_sweep(args, nf, synth, torch, [int(float(x)) for x in args.event_sweep.split(",")])
         return
     # one explicit stream (default priority) that every engine enqueues on
     stream = torch.cuda.Stream()

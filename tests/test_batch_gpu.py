@@ -137,6 +137,39 @@ def test_fit_batch_scan_points_fold_once_and_match_single_fits():
         assert abs(rb["nll"][f] - r1["nll"]) < 1e-6
 
 
+def test_batched_profile_scan_matches_oracle_delta_chi2():
+    """Eq. 7 on a grid of fixed (sin^2 2theta13, dm2_ee): the batched nuisance
+    fits give the oracle's profile statistic Delta chi^2 = 2 [NLL(eta) - NLL_min]
+    to 1e-3 at every checked point (the oracle fits with scipy BFGS)."""
+    from oracle import fit as OFIT
+    say("batched profile scan vs oracle")
+    desc, events = synth.model_and_events(1, 30000)
+    m = Model(desc)
+    truth = synth.start_vector(desc)
+    data = synth.poisson_data(LK.expected(m, events, truth)[0], 7)
+    eng = engine(desc, events)
+    eng.set_data_batch(np.concatenate(data)[None, :])
+    for d, dat in enumerate(data):
+        eng.set_data(d, dat)
+    i13, iee = m.index["osc.sin2_2t13"], m.index["osc.dm2_ee"]
+    grid = [(s, d) for s in (0.03, 0.085, 0.14) for d in (2.2, 2.5, 2.8)]
+    start = np.tile(truth, (len(grid), 1))
+    start[:, i13] = [g[0] for g in grid]
+    start[:, iee] = [g[1] for g in grid]
+    fixed = m.fixed.copy()
+    fixed[[i13, iee]] = True
+    rb = eng.fit_batch(start, fixed=fixed, data_idx=np.zeros(len(grid), np.int32), edm_tol=1e-10)
+    assert rb["code"] == nf.NF_OK, rb["status"]
+    rg = eng.fit(truth, edm_tol=1e-10)
+    og = OFIT.fit(m, events, data, truth, gtol=1e-8)
+    assert abs(rg["nll"] - og["nll"]) < 1e-6
+    for f in (0, 4, 8, 5):
+        ro = OFIT.fit(m, events, data, start[f], fixed=fixed, gtol=1e-8)
+        dchi_gpu = 2.0 * (rb["nll"][f] - rg["nll"])
+        dchi_oracle = 2.0 * (ro["nll"] - og["nll"])
+        assert dchi_gpu > 0 and abs(dchi_gpu - dchi_oracle) < 1e-3, (grid[f], dchi_gpu, dchi_oracle)
+
+
 def test_fit_batch_config2_pseudo_experiments_converge():
     say("fit_batch c2")
     desc, events = synth.model_and_events(2, 300_000)
