@@ -161,6 +161,7 @@ struct nf_ctx {
   DevBuf<double> d_Sseg;
   DevBuf<double> d_bin;
   DevBuf<int> d_seg_cnt, d_kt_cnt, d_seg_kt, d_kt_need;  // fused fine-bin reduction in the fold
+  DevBuf<ItemEpi> d_epi;                                   // per work item epilogue records
   DevBuf<double> d_segm;
   double* h_stage = nullptr;  // pinned: theta, out, mu
   int32_t* h_status = nullptr;
@@ -206,6 +207,7 @@ struct nf_ctx {
     d_Wseg.release(); d_part.release(); d_theta.release(); d_out.release(); d_status.release();
     d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release();
     d_seg_cnt.release(); d_kt_cnt.release(); d_seg_kt.release(); d_kt_need.release(); d_segm.release();
+    d_epi.release();
     if (h_stage) (void)hipHostFree(h_stage);
     if (h_status) (void)hipHostFree(h_status);
     if (h_hdr) (void)hipHostFree(h_hdr);
@@ -743,6 +745,29 @@ void rebuild_events(nf_ctx* c) {
   c->d_w.upload(w, c->stream);
   c->d_items.upload(items, c->stream);
   c->d_seg_item.upload(seg_item, c->stream);
+  {
+    // per-item epilogue records (segment weight, fine-bin row, source, item range)
+    std::vector<int> seg_kt(std::max(1, c->plan.G), 0);
+    for (int kt = 0; kt < c->plan.KT; ++kt) {
+      const int* info = &c->ipool[c->plan.kt_info + 5 * kt];
+      for (int s2 = 0; s2 < info[2]; ++s2) seg_kt[info[0] + s2 * info[1]] = kt;
+    }
+    std::vector<ItemEpi> epi(std::max<size_t>(1, items.size()));
+    for (size_t i = 0; i < items.size(); ++i) {
+      const int g = items[i].seg, kt = seg_kt[g];
+      const int* info = &c->ipool[c->plan.kt_info + 5 * kt];
+      ItemEpi& e = epi[i];
+      e.W = Wseg[g];
+      e.row = 6 * info[4] + (kt - info[4]);
+      e.K = info[1];
+      e.first = seg_item[g];
+      e.nseg = seg_item[g + 1] - seg_item[g];
+      const int fs = info[3] + (g - info[0]) / info[1];
+      for (int q = 0; q < NLMAX; ++q) e.nl[q] = c->ipool[c->plan.fs_nl + NLMAX * fs + q];
+      e.pad_[0] = e.pad_[1] = 0;
+    }
+    c->d_epi.upload(epi, c->stream);
+  }
   c->d_Wseg.upload(Wseg, c->stream);
   c->d_part.alloc((size_t)MAX_MOM * std::max(1, c->nitems));
   {
@@ -871,6 +896,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.osc = c->osc;
   fa.part = c->d_part.p;
   FoldFuse& fu = fa.fuse;
+  fu.epi = c->d_epi.p;
   fu.seg_item = c->d_seg_item.p;
   fu.Wseg = c->d_Wseg.p;
   fu.seg_kt = c->d_seg_kt.p;

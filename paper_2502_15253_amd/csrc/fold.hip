@@ -22,12 +22,12 @@
 //
 // Single evaluation: the fold also finishes the reduction to fine bins. The
 // last wavefront to complete a segment sums the segment's partials (item
-// order); the last segment of a fine bin to complete applies the oscillation
-// coefficients (computed once per workgroup into LDS) and the source norms
-// and writes the bin's oscillated spectrum and its four slot derivatives
-// (source order). Hand-offs use write-through stores and device-scope
-// counters that the last arrival resets, so no extra launch or cache
-// write-back is needed and the results do not depend on arrival order.
+// order) and applies the oscillation coefficients (computed by each
+// wavefront into its own LDS rows) and the source norm; the segment's rows
+// reach the fine bin by device-scope atomic adds or, in the deterministic
+// mode, through the last segment of the fine bin to complete, which sums
+// them in source order. Hand-offs use write-through stores and device-scope
+// counters that the last arrival resets: no extra launch or cache write-back.
 // Batched evaluations keep the raw partials; their bin stages reduce them.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
@@ -157,13 +157,15 @@ __device__ __forceinline__ void wave_sum_store(double* m, double* part, int nite
 // sits under a branch.
 // Fine-bin reduction by the last arrivals (see FoldFuse). m: this item's NM
 // moment sums, identical in every lane; cf: the coefficient rows (LDS).
+// ep: the item's epilogue record; A: its source norm (both read before the
+// event loop).
 template <int NM>
 __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const double* m, int item, int seg,
-                                  int lane) {
+                                  int lane, const ItemEpi& ep, double A) {
   const FoldFuse& F = a.fuse;
-  const int ib = F.seg_item[seg], ie = F.seg_item[seg + 1];
+  const int ib = ep.first, ie = ep.first + ep.nseg;
   double M[NM + 1];
-  M[0] = F.Wseg[seg];
+  M[0] = ep.W;
   if (ie - ib == 1) {
 #pragma unroll
     for (int c = 0; c < NM; ++c) M[1 + c] = m[c];
@@ -188,19 +190,10 @@ __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const dou
       for (int c = 0; c < NM; ++c) M[1 + c] += load_agent(&a.part[(int64_t)c * a.nitems + it]);
     }
   }
-  const int kt = F.seg_kt[seg];
   if (F.atomic_rows) {
     // this segment's rows: lane r < 5 forms row r from the coefficients and
     // adds A_s times it to the fine bin (fire-and-forget device-scope adds;
     // the rows start at zero and the bin stages clear them after reading)
-    const int* info = F.kt_info + 5 * kt;
-    const int g0 = info[0], K = info[1], fs0 = info[3], kt0 = info[4];
-    const int s = (seg - g0) / K;
-    const int* nl = F.fs_nl + NLMAX * (fs0 + s);
-    double A = 1.0;
-#pragma unroll
-    for (int q = 0; q < NLMAX; ++q)
-      if (nl[q] >= 0) A *= a.theta[nl[q]];
     if (lane < 5) {
       int z = 0;  // opaque zero: keeps the coefficient loads here (see below)
       asm volatile("" : "+v"(z));
@@ -209,11 +202,12 @@ __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const dou
 #pragma unroll
       for (int c = 0; c <= NM; ++c) r += c0[c] * M[c];
       if (lane == 0) F.Sseg[seg] = r;
-      double* b = F.bin + 6 * (int64_t)kt0;
-      __hip_atomic_fetch_add(&b[lane * K + (kt - kt0)], A * r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(F.bin + ep.row + (int64_t)lane * ep.K, A * r, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
+  const int kt = F.seg_kt[seg];
   if (F.kt_need[kt] > 1) {
     if (lane == 0) {
 #pragma unroll
@@ -271,24 +265,42 @@ __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const dou
   }
 }
 
-// Oscillation coefficients of this launch's parameters into LDS (fused
-// launches only). Called by every thread before any early return.
-__device__ __forceinline__ void fold_coefficients(const FoldArgs& a, double* cf) {
-  if (a.fuse.seg_cnt) {
-    if (threadIdx.x == 0) (void)osc_coefficients(a.osc, a.theta, cf);
-    __syncthreads();
-  }
+// The item's epilogue record and the values of its source's norm parameters
+// (fused launches only), issued right after the first event loads: the loads
+// are independent of each other and are only waited for in the epilogue.
+__device__ __forceinline__ void item_prefetch(const FoldArgs& a, int item, ItemEpi& ep, double* thv) {
+  if (!a.fuse.seg_cnt) return;
+  ep = a.fuse.epi[item];
+#pragma unroll
+  for (int q = 0; q < NLMAX; ++q) thv[q] = a.theta[ep.nl[q] >= 0 ? ep.nl[q] : 0];
+}
+// Source norm A_s: the product of the source's norm parameters.
+__device__ __forceinline__ double item_norm(const ItemEpi& ep, const double* thv) {
+  double A = 1.0;
+#pragma unroll
+  for (int q = 0; q < NLMAX; ++q)
+    if (ep.nl[q] >= 0) A *= thv[q];
+  return A;
+}
+
+// Oscillation coefficients of this launch's parameters into the wavefront's
+// own LDS rows (fused launches only), by lane 0 with no barrier. Called after
+// the first event loads are issued, so its parameter loads and FP64 work
+// overlap their latency instead of delaying the stream.
+__device__ __forceinline__ void wave_coefficients(const FoldArgs& a, double* cf) {
+  if (a.fuse.seg_cnt && (threadIdx.x & 63) == 0) (void)osc_coefficients(a.osc, a.theta, cf);
 }
 
 template <int NM>
-__device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf, double* m, int item, int seg) {
+__device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf, double* m, int item, int seg,
+                                            const ItemEpi& ep, double A) {
   // the lane id is recomputed here rather than kept live across the event
   // loop (the register allocator would park it above the loop's registers)
   const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 #pragma unroll
   for (int c = 0; c < NM; ++c) m[c] = wave_sum_fixed(m[c]);
   if (a.fuse.seg_cnt) {
-    fold_bin_epilogue<NM>(a, cf, m, item, seg, lane);
+    fold_bin_epilogue<NM>(a, cf, m, item, seg, lane, ep, A);
   } else if (lane == 0) {
 #pragma unroll
     for (int c = 0; c < NM; ++c) a.part[(int64_t)c * a.nitems + item] = m[c];
@@ -298,12 +310,14 @@ __device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf,
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
-  __shared__ double cf[40];
+  __shared__ double cfw[4][40];  // coefficient rows per wavefront (blocks of at most 256 threads)
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
-  fold_coefficients(a, cf);
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;  // whole wavefronts leave together
+  double* cf = cfw[threadIdx.x >> 6];
+  ItemEpi ep{};
+  double thv[NLMAX];
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const WorkItem it = a.items[item];
@@ -319,6 +333,8 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   double2 pa = load_stream2(u + o);
   double2 qa = load_stream2(u + o + 2);
   float4 wa = load_stream4(w + o);
+  item_prefetch(a, item, ep, thv);
+  wave_coefficients(a, cf);
   for (int t = 0; t < niter; t += 2) {
     const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
     const double2 pb = load_stream2(u + ob);
@@ -338,19 +354,21 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
     accum64<FORM>(qb.y, wb.w, a1, a2, m);
     j += 512;
   }
-  fold_finish<NM>(a, cf, m, item, it.seg);
+  fold_finish<NM>(a, cf, m, item, it.seg, ep, a.fuse.seg_cnt ? item_norm(ep, thv) : 1.0);
 }
 
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
   constexpr double INV_2PI = 0.15915494309189533577;
-  __shared__ double cf[40];
+  __shared__ double cfw[4][40];  // coefficient rows per wavefront (blocks of at most 256 threads)
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
-  fold_coefficients(a, cf);
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;
+  double* cf = cfw[threadIdx.x >> 6];
+  ItemEpi ep{};
+  double thv[NLMAX];
   double a1, a2;
   fold_freqs<FORM>(a.osc, a.theta, a1, a2);
   const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
@@ -368,6 +386,8 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   int64_t o = j < cnt ? it.begin + j : a.zpad;
   float4 ua = load_stream4(u + o);
   float4 wa = load_stream4(w + o);
+  item_prefetch(a, item, ep, thv);
+  wave_coefficients(a, cf);
   for (int t = 0; t < niter; t += 2) {
     const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
     const float4 ub = load_stream4(u + ob);
@@ -388,7 +408,7 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   double m[NM];
 #pragma unroll
   for (int c = 0; c < NM; ++c) m[c] = (double)mf[c];
-  fold_finish<NM>(a, cf, m, item, it.seg);
+  fold_finish<NM>(a, cf, m, item, it.seg, ep, a.fuse.seg_cnt ? item_norm(ep, thv) : 1.0);
 }
 
 // ---------------------------------------------------------------- batched

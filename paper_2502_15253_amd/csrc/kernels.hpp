@@ -47,6 +47,7 @@ __host__ __device__ inline size_t fit_lds_doubles(int P, int m) {
 // stores the rows (atomic_rows = 0: reproducible bit for bit). Counters
 // return to zero.
 struct FoldFuse {
+  const ItemEpi* epi;   // [nitems] per-item epilogue record
   const int* seg_item;  // [G+1] work-item range of each segment
   const double* Wseg;   // [G] summed weights of each segment
   const int* seg_kt;    // [G] global fine bin of each segment

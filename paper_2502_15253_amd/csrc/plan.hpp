@@ -36,6 +36,20 @@ struct WorkItem {
   int32_t seg;
 };
 
+// What the single evaluation's fold epilogue needs about a work item, read at
+// the start of the wavefront so nothing is loaded after the event stream.
+constexpr int NLMAX = 8;  // norm parameters multiplying one source
+struct ItemEpi {
+  double W;           // summed weights of the item's segment
+  int32_t row;        // the segment's fine bin in the row block: 6 kt0 + (kt - kt0)
+  int32_t K;          // row stride (fine bins of the dataset)
+  int32_t first;      // first work item of the segment
+  int32_t nseg;       // work items of the segment
+  int32_t nl[NLMAX];  // the source's norm parameters (-1: none)
+  int32_t pad_[2];
+};
+static_assert(sizeof(ItemEpi) == 64, "ItemEpi is 64 bytes");
+
 struct BkgPlan {
   double scale;
   int rate;    // parameter index or -1 (rate fixed at 1)
@@ -70,8 +84,6 @@ struct DsPlan {
 
 static_assert(sizeof(DsPlan) % sizeof(double) == 0, "DsPlan is copied as doubles");
 constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
-
-constexpr int NLMAX = 8;  // norm parameters multiplying one source
 
 // Per-dataset static inputs of the bin stages, packed contiguously (integers
 // stored as exact doubles) so one batched copy stages them in LDS.
