@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -143,11 +144,23 @@ def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
     out = {}
     t_all = 0.0
     n_all = 0
+    from paper_2502_15253_amd import autotune as AT
+    tune_cache = os.path.join(tempfile.gettempdir(), "nufold_bench_autotune.json")
     for config, label in ((1, "single_detector"), (2, "three_detector")):
-        desc, _, eng = engine_for(nf, synth, config, stream)
+        desc, events, eng = engine_for(nf, synth, config, stream)
         data = pseudo_data(eng, desc, 2048)
         eng.set_data_batch(data)
         start = np.tile(synth.start_vector(desc), (2048, 1))
+        # batched launch choices (fold tile, bin-stage threads) from the
+        # library's autotuner, before the clock; the work-item size keeps its
+        # default, which suits batches (the single-evaluation choice favours
+        # small items)
+        nb0 = np.cumsum([0] + [len(ds["edges"]) - 1 for ds in desc["datasets"]])
+        for d in range(len(desc["datasets"])):
+            eng.set_data(d, data[0][nb0[d]:nb0[d + 1]])
+        tuned = AT.tune(eng, desc, [len(ev["weight"]) for ev in events], start[0], cache_path=tune_cache,
+                        evals=0, batch=2048, force=True)
+        log(f"autotuned {label}: {json.dumps(tuned)}")
         eng.fit_batch(start[:8], edm_tol=1e-7, max_iter=3000)  # graph capture and buffers
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -156,7 +169,8 @@ def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
         t_all += dt
         n_all += 2048
         ent = dict(fits=2048, seconds=dt, fits_per_s=2048 / dt, params=len(start[0]),
-                   converged=int(np.sum(r["status"] == 0)), mean_iters=float(r["iters"].mean()))
+                   converged=int(np.sum(r["status"] == 0)), mean_iters=float(r["iters"].mean()),
+                   launch_options=tuned["options"])
         log(f"batched {label}: {json.dumps(ent)}")
         if config == 1:
             # the plain per-fit GPU path on the first n_plain pseudo-experiments

@@ -163,7 +163,9 @@ int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
  * default 4096), "fold_block" (threads per fold workgroup: 64, 128 or 256),
  * "tail_threads" (bin-stage threads of the single evaluation: 256, 512 or
  * 1024), "batch_threads" (bin-stage threads per fit in batched launches: 256,
- * 512, 1024, or 0 = chosen from the model size). Changing "chunk" rebuilds
+ * 512, 1024, or 0 = chosen from the model size), "batch_fit_tile" (fits per
+ * wavefront tile of the batched fold, which reads each event once per tile:
+ * 1, 2, 4 or 8, default 4). Changing "chunk" rebuilds
  * the work-item list. "deterministic" (0/1, default 0): with 1 the fold
  * kernel hands each fine bin's source rows to the last source to finish,
  * which sums them in source order, so repeated evaluations agree bit for bit;
@@ -178,10 +180,12 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
  * Autotuner: times the launch choices above on this context's model, events
  * and data (evaluations at theta, P host values, `evals` timed evaluations
  * per candidate, device time from HIP events) and keeps the fastest:
- * tail_threads first, then chunk x fold_block; then, if batch > 0 and batch
- * data are set (nf_set_data_batch), batch_threads for batched launches of
- * `batch` fits. best (nullable): 4 values chunk, fold_block, tail_threads,
- * batch_threads. best_us (nullable): 2 values, the mean device time of one
+ * tail_threads first, then chunk x fold_block (skipped when evals = 0); then,
+ * if batch > 0 and batch
+ * data are set (nf_set_data_batch), batch_fit_tile x batch_threads for
+ * batched launches of `batch` fits. best (nullable): 5 values chunk,
+ * fold_block, tail_threads, batch_threads, batch_fit_tile. best_us
+ * (nullable): 2 values, the mean device time of one
  * evaluation and of one batched evaluation (0 if not tuned), microseconds.
  * Needs events and data. Replaces the options in place.
  */

@@ -1,7 +1,8 @@
 """Cached autotuning of the engine's launch choices.
 
 The search itself runs in the library (nf_autotune: device-timed sweeps of
-work-item size, fold workgroup size and bin-stage threads). This module keys
+work-item size, fold workgroup size, bin-stage threads, and for batched
+launches the fit tile of the batched fold and its bin-stage threads). This module keys
 its result by model, event counts, precision mode and device, stores it in a
 JSON file, and applies a stored choice to new engines without re-timing.
 """
@@ -11,7 +12,7 @@ import hashlib
 import json
 import os
 
-OPTIONS = ("chunk", "fold_block", "tail_threads", "batch_threads")
+OPTIONS = ("chunk", "fold_block", "tail_threads", "batch_threads", "batch_fit_tile")
 
 
 def default_cache_path():

@@ -174,6 +174,7 @@ struct nf_ctx {
   int tail_threads = 512;
   int timing = 0;
   int deterministic = 0;  // fine-bin rows by ordered hand-off (1) or atomic adds (0)
+  int batch_tile = FOLD_FT;  // fits per wavefront tile of the batched fold
   // minimiser buffers (allocated at the first fit) and the captured iteration graph
   int fit_m = 8;
   DevBuf<FitHeader> f_hdr;
@@ -1239,7 +1240,7 @@ double time_single(nf_ctx* c, int n) {
 double time_batch(nf_ctx* c, int B, int n) {
   EventPair ev;
   auto once = [&] {
-    hip_check(launch_fold_batch(c->mode, batch_fold_args(c, B, false), c->stream), "batch fold");
+    hip_check(launch_fold_batch(c->mode, batch_fold_args(c, B, false), c->stream, c->batch_tile), "batch fold");
     hip_check(launch_batch_tail(batch_tail_args(c, B, false, true, true), batch_threads(c), c->stream),
               "batch tail");
   };
@@ -1256,55 +1257,71 @@ double time_batch(nf_ctx* c, int B, int n) {
 // `batch` fits when batch data are set (batch > 0).
 int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t* best, double* best_us) {
   require_ready(c, true);
-  if (!theta || evals < 1 || batch < 0) fail(NF_EINVAL, "theta, evals >= 1 and batch >= 0 are required");
+  if (!theta || evals < 0 || batch < 0 || (evals == 0 && batch == 0))
+    fail(NF_EINVAL, "theta, evals >= 0, batch >= 0 and evals + batch > 0 are required");
   for (int i = 0; i < c->P; ++i)
     if (!std::isfinite(theta[i])) fail(NF_EINVAL, "theta contains a non-finite value");
   const int timing = c->timing;
   c->timing = 0;
   hip_check(hipMemcpy(c->d_theta.p, theta, sizeof(double) * c->P, hipMemcpyHostToDevice), "H2D");
-  double t_best = 1e300;
-  int nt_best = c->tail_threads;
-  for (int nt : {256, 512, 1024}) {
-    c->tail_threads = nt;
-    const double t = time_single(c, evals);
-    if (t < t_best) { t_best = t; nt_best = nt; }
-  }
-  c->tail_threads = nt_best;
-  t_best = 1e300;
-  int64_t ch_best = c->chunk;
-  int fb_best = c->fold_block;
-  for (int64_t ch : {1024, 2048, 4096, 8192}) {
-    if (ch != c->chunk) {
-      c->chunk = ch;
+  double t_best = 0.0;
+  if (evals > 0) {  // single-evaluation choices
+    t_best = 1e300;
+    int nt_best = c->tail_threads;
+    for (int nt : {256, 512, 1024}) {
+      c->tail_threads = nt;
+      const double t = time_single(c, evals);
+      if (t < t_best) { t_best = t; nt_best = nt; }
+    }
+    c->tail_threads = nt_best;
+    t_best = 1e300;
+    int64_t ch_best = c->chunk;
+    int fb_best = c->fold_block;
+    for (int64_t ch : {1024, 2048, 4096, 8192}) {
+      if (ch != c->chunk) {
+        c->chunk = ch;
+        rebuild_events(c);
+      }
+      for (int fb : {64, 128, 256}) {
+        c->fold_block = fb;
+        const double t = time_single(c, evals);
+        if (t < t_best) { t_best = t; ch_best = ch; fb_best = fb; }
+      }
+    }
+    if (ch_best != c->chunk) {
+      c->chunk = ch_best;
       rebuild_events(c);
     }
-    for (int fb : {64, 128, 256}) {
-      c->fold_block = fb;
-      const double t = time_single(c, evals);
-      if (t < t_best) { t_best = t; ch_best = ch; fb_best = fb; }
-    }
+    c->fold_block = fb_best;
   }
-  if (ch_best != c->chunk) {
-    c->chunk = ch_best;
-    rebuild_events(c);
-  }
-  c->fold_block = fb_best;
-  int bt_best = c->batch_threads_opt;
+  int bt_best = c->batch_threads_opt, ft_best = c->batch_tile;
   double tb_best = 0.0;
   if (batch > 0 && c->bt_nsets > 0) {
     ensure_batch(c, batch);
+    // every fit of the timed batch folds at its own oscillation point (as at
+    // the start of a batch of fits): the free oscillation slots of theta are
+    // spread by up to +-1% across the rows
     std::vector<double> th((size_t)batch * c->P);
-    for (int f = 0; f < batch; ++f) std::memcpy(&th[(size_t)f * c->P], theta, sizeof(double) * c->P);
+    for (int f = 0; f < batch; ++f) {
+      std::memcpy(&th[(size_t)f * c->P], theta, sizeof(double) * c->P);
+      for (int j = 0; j < NSLOT; ++j) {
+        const int q = c->osc.slot_param[j];
+        if (q >= 0) th[(size_t)f * c->P + q] *= 1.0 + 0.01 * ((double)((f * 7 + j * 13) % 21) / 10.0 - 1.0);
+      }
+    }
     std::vector<int> didx(batch, 0);
     hip_check(hipMemcpy(c->bt_theta.p, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice), "H2D");
     hip_check(hipMemcpy(c->bt_didx.p, didx.data(), sizeof(int) * batch, hipMemcpyHostToDevice), "H2D");
     tb_best = 1e300;
-    for (int nt : {256, 512, 1024}) {
-      c->batch_threads_opt = nt;
-      const double t = time_batch(c, batch, std::max(1, evals / 4));
-      if (t < tb_best) { tb_best = t; bt_best = nt; }
-    }
+    for (int ft : {1, 2, 4, 8})
+      for (int nt : {256, 512, 1024}) {
+        c->batch_tile = ft;
+        c->batch_threads_opt = nt;
+        const double t = time_batch(c, batch, std::max(1, evals / 4));
+        if (t < tb_best) { tb_best = t; bt_best = nt; ft_best = ft; }
+      }
     c->batch_threads_opt = bt_best;
+    c->batch_tile = ft_best;
   }
   drop_fit_graph(c);
   c->timing = timing;
@@ -1313,6 +1330,7 @@ int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t*
     best[1] = c->fold_block;
     best[2] = c->tail_threads;
     best[3] = c->batch_threads_opt;
+    best[4] = c->batch_tile;
   }
   if (best_us) {
     best_us[0] = t_best;
@@ -1354,7 +1372,7 @@ int expected_batch_impl(nf_ctx* c, int B, const double* theta, double* mu) {
   hip_check(hipMemcpyAsync(c->bt_pidx.p, pidx.data(), sizeof(int) * B, hipMemcpyHostToDevice, c->stream), "H2D");
   BatchFoldArgs fa = batch_fold_args(c, U, false);
   fa.theta = c->bt_fold_theta.p;
-  hip_check(launch_fold_batch(c->mode, fa, c->stream), "batch fold");
+  hip_check(launch_fold_batch(c->mode, fa, c->stream, c->batch_tile), "batch fold");
   BatchTailArgs ta = batch_tail_args(c, B, false, false, false);
   ta.part_idx = c->bt_pidx.p;
   ta.data = nullptr;
@@ -1384,7 +1402,7 @@ int eval_batch_impl(nf_ctx* c, int B, const double* theta, const int* didx, doub
   ensure_batch(c, B);
   hip_check(hipMemcpyAsync(c->bt_theta.p, theta, sizeof(double) * B * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
   if (didx) hip_check(hipMemcpyAsync(c->bt_didx.p, didx, sizeof(int) * B, hipMemcpyHostToDevice, c->stream), "H2D");
-  hip_check(launch_fold_batch(c->mode, batch_fold_args(c, B, false), c->stream), "batch fold");
+  hip_check(launch_fold_batch(c->mode, batch_fold_args(c, B, false), c->stream, c->batch_tile), "batch fold");
   hip_check(launch_batch_tail(batch_tail_args(c, B, false, grad != nullptr, didx != nullptr), batch_threads(c),
                               c->stream), "batch tail");
   std::vector<double> out((size_t)B * (1 + c->P));
@@ -1412,7 +1430,7 @@ void ensure_batch_fit_graph(nf_ctx* c, int B) {
   hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   hipError_t e = hipSuccess;
   for (int i = 0; i < FIT_CHUNK && e == hipSuccess; ++i) {
-    e = launch_fold_batch(c->mode, batch_fold_args(c, B, true), c->stream);
+    e = launch_fold_batch(c->mode, batch_fold_args(c, B, true), c->stream, c->batch_tile);
     if (e == hipSuccess)
       e = launch_batch_tail(batch_tail_args(c, B, true, true, true), batch_threads(c), c->stream);
   }
@@ -1709,6 +1727,10 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
       if (value != 0 && value != 256 && value != 512 && value != 1024)
         fail(NF_EINVAL, "batch_threads must be 0, 256, 512 or 1024");
       ctx->batch_threads_opt = (int)value;
+      drop_fit_graph(ctx);
+    } else if (k == "batch_fit_tile") {
+      if (value != 1 && value != 2 && value != 4 && value != 8) fail(NF_EINVAL, "batch_fit_tile must be 1, 2, 4 or 8");
+      ctx->batch_tile = (int)value;
       drop_fit_graph(ctx);
     } else if (k == "deterministic") {
       if (value != 0 && value != 1) fail(NF_EINVAL, "deterministic must be 0 or 1");

@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "fastmath.hpp"
 #include "kernels.hpp"
 #include "osc.hpp"
@@ -430,10 +432,9 @@ __device__ __forceinline__ bool batch_fit_active(const BatchFoldArgs& a, int f, 
   return true;
 }
 
-template <int FORM>
+template <int FORM, int FT>
 __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
-  constexpr int FT = FOLD_FT;
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   if (item >= a.nitems) return;
@@ -474,10 +475,9 @@ __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
     if (act[j]) wave_sum_store<NM>(m[j], a.part + (int64_t)(f0 + j) * NM * a.nitems, a.nitems, item, lane);
 }
 
-template <int FORM>
+template <int FORM, int FT>
 __global__ __launch_bounds__(256) void fold_batch_m32_kernel(BatchFoldArgs a) {
   constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
-  constexpr int FT = FOLD_FT;
   constexpr double INV_2PI = 0.15915494309189533577;
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
@@ -526,16 +526,26 @@ __global__ __launch_bounds__(256) void fold_batch_m32_kernel(BatchFoldArgs a) {
   }
 }
 
-hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream) {
+// ft: fits per wavefront tile (1, 2, 4 or 8); each tile reads the events once.
+hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream, int ft) {
   if (a.nitems <= 0 || a.B <= 0) return hipSuccess;
-  const dim3 grid((a.nitems + 3) / 4, (a.B + FOLD_FT - 1) / FOLD_FT);
+  const dim3 grid((a.nitems + 3) / 4, (a.B + ft - 1) / ft);
   const dim3 block(256);
-  if (mode == 0) {
-    if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL(fold_batch_m64_kernel<FORM_EQ1>, grid, block, 0, stream, a);
-    else hipLaunchKernelGGL(fold_batch_m64_kernel<FORM_3NU>, grid, block, 0, stream, a);
-  } else {
-    if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL(fold_batch_m32_kernel<FORM_EQ1>, grid, block, 0, stream, a);
-    else hipLaunchKernelGGL(fold_batch_m32_kernel<FORM_3NU>, grid, block, 0, stream, a);
+  auto go = [&](auto tile) {
+    constexpr int T = decltype(tile)::value;
+    if (mode == 0) {
+      if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_EQ1, T>), grid, block, 0, stream, a);
+      else hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
+    } else {
+      if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL((fold_batch_m32_kernel<FORM_EQ1, T>), grid, block, 0, stream, a);
+      else hipLaunchKernelGGL((fold_batch_m32_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
+    }
+  };
+  switch (ft) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    default: go(std::integral_constant<int, 4>{}); break;
   }
   return hipGetLastError();
 }

@@ -78,8 +78,9 @@ struct FoldArgs {
   FoldFuse fuse;        // used when fuse.seg_cnt != nullptr
 };
 
-// Batched fold: FT fits per wavefront, each event read once per tile.
-constexpr int FOLD_FT = 4;
+// Batched fold: a tile of FT fits per wavefront (FT = 1, 2, 4 or 8, a launch
+// choice), each event read once per tile.
+constexpr int FOLD_FT = 4;  // default tile
 struct BatchFoldArgs {
   const void* u;
   const float* w;
@@ -160,7 +161,7 @@ __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
 
 hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream, hipEvent_t start = nullptr,
                        hipEvent_t stop = nullptr);
-hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream);
+hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream, int ft = FOLD_FT);
 hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream, hipEvent_t start = nullptr,
                        hipEvent_t stop = nullptr);
 hipError_t tail_set_lds_limit(size_t bytes);

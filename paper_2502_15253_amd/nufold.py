@@ -293,11 +293,11 @@ class Engine:
     def autotune(self, theta, evals=50, batch=0):
         """Run the library's autotuner; returns ({option: value}, (us/eval, us/batched eval))."""
         th = np.ascontiguousarray(theta, dtype=np.float64)
-        best = np.zeros(4, dtype=np.int64)
+        best = np.zeros(5, dtype=np.int64)
         us = np.zeros(2)
         _check(self.ctx, load().nf_autotune(self.ctx, th.ctypes.data, evals, batch, best.ctypes.data,
                                             us.ctypes.data))
-        keys = ("chunk", "fold_block", "tail_threads", "batch_threads")
+        keys = ("chunk", "fold_block", "tail_threads", "batch_threads", "batch_fit_tile")
         return {k: int(v) for k, v in zip(keys, best)}, (float(us[0]), float(us[1]))
 
     def expected_batch(self, theta):

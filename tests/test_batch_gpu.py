@@ -137,6 +137,39 @@ def test_fit_batch_scan_points_fold_once_and_match_single_fits():
         assert abs(rb["nll"][f] - r1["nll"]) < 1e-6
 
 
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_batched_fold_tiles_give_the_same_results(mode):
+    """The batched fold's fit tile (fits per wavefront) only groups fits: every
+    tile size gives the oracle's results and the same values as the default."""
+    say("batched fold tiles", mode)
+    desc = synth.tiny_model(31, formula="3nu", n_datasets=2, n_sources=3)
+    events = synth.tiny_events(desc, 30000, 9)
+    m = Model(desc)
+    rng = np.random.default_rng(4)
+    B = 11
+    th = np.stack([displaced(desc, rng) for _ in range(B)])
+    data = pseudo_data(desc, events, 3)
+    eng = engine(desc, events, mode)
+    eng.set_data_batch(data)
+    didx = np.arange(B, dtype=np.int32) % 3
+    ref = None
+    for ft in (4, 1, 2, 8):
+        eng.set_option("batch_fit_tile", ft)
+        nll, g, code = eng.eval_batch(th, data_idx=didx)
+        assert code == nf.NF_OK
+        if ref is None:
+            ref = (nll, g)
+            for f in (0, 5, 10):
+                f_o, g_o = LK.nll_grad(m, events, split(desc, data[didx[f]]), th[f])
+                assert abs(nll[f] - f_o) <= TOL[mode] * max(1.0, abs(f_o))
+                assert np.max(np.abs(g[f] - g_o)) <= TOL[mode] * max(1.0, np.max(np.abs(g_o)))
+        else:
+            assert np.max(np.abs(nll - ref[0])) <= 1e-13 * max(1.0, np.max(np.abs(ref[0]))), ft
+            assert np.max(np.abs(g - ref[1])) <= 1e-12 * max(1.0, np.max(np.abs(ref[1]))), ft
+    with pytest.raises(nf.NufoldError):
+        eng.set_option("batch_fit_tile", 3)
+
+
 def test_batched_profile_scan_matches_oracle_delta_chi2():
     """Eq. 7 on a grid of fixed (sin^2 2theta13, dm2_ee): the batched nuisance
     fits give the oracle's profile statistic Delta chi^2 = 2 [NLL(eta) - NLL_min]
@@ -235,6 +268,7 @@ def test_autotuner_keeps_results_and_caches_its_choice(tmp_path):
     o = rec["options"]
     assert o["chunk"] in (1024, 2048, 4096, 8192) and o["fold_block"] in (64, 128, 256)
     assert o["tail_threads"] in (256, 512, 1024) and o["batch_threads"] in (256, 512, 1024)
+    assert o["batch_fit_tile"] in (1, 2, 4, 8)
     assert rec["us_per_eval"] > 0 and rec["us_per_batched_eval"] > 0
     # the tuned engine computes the same NLL and gradient (only summation order may change)
     f1, g1, _ = eng.eval_nll_grad(th)
@@ -249,4 +283,4 @@ def test_autotuner_keeps_results_and_caches_its_choice(tmp_path):
     for d, dat in enumerate(split(desc, data[0])):
         eng2.set_data(d, dat)
     f2, _, _ = eng2.eval_nll_grad(th)
-    assert f2 == f1
+    assert abs(f2 - f1) <= 1e-11 * max(1, abs(f1))
