@@ -414,6 +414,13 @@ def main():
         mus, _ = eng.expected(start)
         for d, mu in enumerate(mus):
             eng.set_data(d, mu)  # Asimov data at the start point
+        # launch choices (work-item size, fold workgroup, bin-stage threads)
+        # from the library's autotuner, before the clock
+        from paper_2502_15253_amd import autotune as AT
+        tuned = AT.tune(eng, desc, [len(ev["weight"]) for ev in events], thetas[0],
+                        cache_path=os.path.join(tempfile.gettempdir(), "nufold_bench_autotune.json"),
+                        evals=50, force=True)
+        log(f"{mode} autotuned: {json.dumps(tuned)}")
         th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
         out_dev = torch.zeros((len(thetas), 1 + eng.P), dtype=torch.float64, device="cuda")
         ptr_t = [th_dev[i].data_ptr() for i in range(len(thetas))]
@@ -457,23 +464,26 @@ def main():
         ev_over_us = eng.timing_overhead(200)
         assert bool(torch.isfinite(out_dev).all()), "non-finite NLL/gradient in the stream loops"
         # host C-ABI path, synchronous, including H2D of theta and D2H of NLL + gradient
+        # (median of 5 rounds of 100: host-side stalls hit single rounds)
         th_np = thetas
-        h0 = time.perf_counter()
-        nh = 50
-        for k in range(nh):
-            eng.eval_nll_grad(th_np[k % 64])
-        h1 = time.perf_counter()
+        host_rates = []
+        for _ in range(5):
+            h0 = time.perf_counter()
+            for k in range(100):
+                eng.eval_nll_grad(th_np[k % 64])
+            host_rates.append(100 / (time.perf_counter() - h0))
+        host_rate = float(np.median(host_rates))
         bpe = 12 if mode == "m64" else 8
         fold_us = fold_ms / cnt * 1e3
         achieved = n_in * bpe / (fold_us * 1e-6) / 1e9
         traffic = measured_traffic(mode, n_in * bpe)
         res = dict(
             evals_per_s=args.steps / (t1 - t0), ms_per_step=(t1 - t0) * 1e3 / args.steps,
-            graph_evals=n_graph,
+            graph_evals=n_graph, launch_options=tuned["options"],
             stream_loop_evals_per_s=args.steps / (s1 - s0),
             event_timed_evals_per_s=args.steps / (e1 - e0),
             fold_us=fold_us, tail_us=tail_ms / cnt * 1e3, event_pair_gap_us=ev_over_us,
-            host_path_evals_per_s=nh / (h1 - h0), events_in_range=n_in,
+            host_path_evals_per_s=host_rate, events_in_range=n_in,
             roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                           algorithmic_bytes_per_launch=n_in * bpe,
@@ -572,6 +582,7 @@ def main():
         },
         "timed_region": f"replays of one HIP graph of {main_res['graph_evals']} consecutive "
                         "evaluations (nf_eval_device_many), parameters and outputs resident in HBM",
+        "launch_options": main_res["launch_options"],
         "fold_us": main_res["fold_us"],
         "tail_us": main_res["tail_us"],
         "stream_loop_evals_per_s": main_res["stream_loop_evals_per_s"],
