@@ -175,6 +175,7 @@ struct nf_ctx {
   int timing = 0;
   int deterministic = 0;  // fine-bin rows by ordered hand-off (1) or atomic adds (0)
   int batch_tile = FOLD_FT;  // fits per wavefront tile of the batched fold
+  int max_lds = 65536;       // LDS bytes one workgroup may use on this device
   // minimiser buffers (allocated at the first fit) and the captured iteration graph
   int fit_m = 8;
   DevBuf<FitHeader> f_hdr;
@@ -1194,6 +1195,9 @@ BatchTailArgs batch_tail_args(nf_ctx* c, int B, bool fit, bool want_grad, bool u
   return a;
 }
 
+// whether a bin-stage workgroup of nt threads fits this model's LDS
+bool tail_fits(const nf_ctx* c, int nt) { return tail_lds_bytes(c->plan, nt) <= (size_t)c->max_lds; }
+
 int batch_threads(nf_ctx* c) {
   if (c->batch_threads_opt) return c->batch_threads_opt;
   return c->plan.G > 2048 ? 512 : 256;
@@ -1269,6 +1273,7 @@ int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t*
     t_best = 1e300;
     int nt_best = c->tail_threads;
     for (int nt : {256, 512, 1024}) {
+      if (!tail_fits(c, nt)) continue;
       c->tail_threads = nt;
       const double t = time_single(c, evals);
       if (t < t_best) { t_best = t; nt_best = nt; }
@@ -1315,6 +1320,7 @@ int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t*
     tb_best = 1e300;
     for (int ft : {1, 2, 4, 8})
       for (int nt : {256, 512, 1024}) {
+        if (!tail_fits(c, nt)) continue;
         c->batch_tile = ft;
         c->batch_threads_opt = nt;
         const double t = time_batch(c, batch, std::max(1, evals / 4));
@@ -1556,13 +1562,16 @@ int nf_create(nf_ctx** out, const char* model_json, int mode, void* hip_stream) 
     hip_check(hipGetDevice(&dev), "hipGetDevice");
     int maxlds = 0;
     hip_check(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
-    while (c->plan.fit_m > 4 && tail_lds_bytes(c->plan, 1024) > (size_t)maxlds) c->plan.fit_m -= 2;
+    c->max_lds = maxlds;
+    // budget for 512 bin-stage threads (the default); 1024 threads need a
+    // larger reduction scratch and are refused where they do not fit
+    while (c->plan.fit_m > 4 && tail_lds_bytes(c->plan, 512) > (size_t)maxlds) c->plan.fit_m -= 2;
     c->fit_m = c->plan.fit_m;
-    const size_t need = tail_lds_bytes(c->plan, 1024);
+    const size_t need = tail_lds_bytes(c->plan, 512);
     if (need > (size_t)maxlds)
       fail(NF_EINVAL, "model too large for one workgroup's LDS (" + std::to_string(need) + " > " +
                           std::to_string(maxlds) + " bytes)");
-    if (need > 65536) hip_check(tail_set_lds_limit(need), "hipFuncSetAttribute");
+    if (maxlds > 65536) hip_check(tail_set_lds_limit((size_t)maxlds), "hipFuncSetAttribute");
     upload_plan(c);
     hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     *out = c;
@@ -1721,11 +1730,13 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
       drop_fit_graph(ctx);
     } else if (k == "tail_threads") {
       if (value != 256 && value != 512 && value != 1024) fail(NF_EINVAL, "tail_threads must be 256, 512 or 1024");
+      if (!tail_fits(ctx, (int)value)) fail(NF_EINVAL, "not enough LDS for " + std::to_string(value) + " threads");
       ctx->tail_threads = (int)value;
       drop_fit_graph(ctx);
     } else if (k == "batch_threads") {
       if (value != 0 && value != 256 && value != 512 && value != 1024)
         fail(NF_EINVAL, "batch_threads must be 0, 256, 512 or 1024");
+      if (value && !tail_fits(ctx, (int)value)) fail(NF_EINVAL, "not enough LDS for " + std::to_string(value) + " threads");
       ctx->batch_threads_opt = (int)value;
       drop_fit_graph(ctx);
     } else if (k == "batch_fit_tile") {

@@ -93,6 +93,7 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.mu = q; q += Nb;
   q = al(q);
   L.st = q; q += p.max_blob;
+
   L.fit = q; q += fit_lds_doubles(p.P, p.fit_m);
   int* r = reinterpret_cast<int*>(q);
   L.kidx = r; r += E;
@@ -628,8 +629,21 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       const double* mdp = L.st + BL.mdp;
       for (int m = tid; m < M; m += NT) {
         double gm = 0.0;
-        const int e1 = (int)mdcol[m + 1];
-        for (int e = (int)mdcol[m]; e < e1; ++e) gm += L.Ld[(int)mdk[e]] * mdc[e];
+        const int e0 = (int)mdcol[m], e1 = (int)mdcol[m + 1];
+        // four entries per step: their index and coefficient reads, then
+        // their Ld reads, are independent (two LDS round trips per step)
+        for (int e = e0; e < e1; e += 4) {
+          int k[4];
+          double c[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool in = e + q < e1;
+            k[q] = in ? (int)mdk[e + q] : 0;
+            c[q] = in ? mdc[e + q] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) gm += L.Ld[k[q]] * c[q];
+        }
         atomicAdd(&L.grad[(int)mdp[m]], gm);
       }
     }
