@@ -485,27 +485,29 @@ void parse_model(nf_ctx* c, const char* text) {
       const HostDataset& d = c->ds[di];
       const BlobLayout B = blob_layout(q.Nb + 1, q.nbkg, q.Nb, q.nnz, q.M, q.S, q.nl, q.K);
       std::vector<double> blob(B.total, 0.0);
+      // 32-bit integer j of the int array at double offset off
+      auto put = [&](int off, int j, int v) { std::memcpy(reinterpret_cast<char*>(&blob[off]) + 4 * (size_t)j, &v, 4); };
       for (int i = 0; i <= q.Nb; ++i) blob[B.edges + i] = d.edges[i];
       for (int b = 0; b < q.nbkg; ++b) {
         const HostBkg& hb = d.bkgs[b];
         blob[B.bsc + b] = hb.scale;
-        blob[B.brt + b] = hb.rate;
+        put(B.brt, b, hb.rate);
         for (int i = 0; i < q.Nb; ++i) {
           blob[B.tmpl + b * q.Nb + i] = hb.tmpl[i];
-          blob[B.shp + b * q.Nb + i] = hb.shape.empty() ? -1.0 : (double)hb.shape[i];
+          put(B.shp, b * q.Nb + i, hb.shape.empty() ? -1 : hb.shape[i]);
         }
       }
       for (int e = 0; e < q.nnz; ++e) {
         blob[B.mdc + e] = dp[q.md_coef + e];
-        blob[B.mdk + e] = ip[q.md_k + e];
+        put(B.mdk, e, ip[q.md_k + e]);
       }
-      for (int m = 0; m <= q.M; ++m) blob[B.mdcol + m] = ip[q.md_col + m];
-      for (int m = 0; m < q.M; ++m) blob[B.mdp + m] = ip[q.md_param + m];
-      for (int s = 0; s <= q.S; ++s) blob[B.nlp + s] = ip[q.srcnorm_ptr + s] - q.nl0;
-      for (int j = 0; j < q.nl; ++j) blob[B.nli + j] = ip[q.nl0 + j];
-      for (int k = 0; k <= q.K; ++k) blob[B.frow + k] = ip[q.fx_row + k];
+      for (int m = 0; m <= q.M; ++m) put(B.mdcol, m, ip[q.md_col + m]);
+      for (int m = 0; m < q.M; ++m) put(B.mdp, m, ip[q.md_param + m]);
+      for (int s = 0; s <= q.S; ++s) put(B.nlp, s, ip[q.srcnorm_ptr + s] - q.nl0);
+      for (int j = 0; j < q.nl; ++j) put(B.nli, j, ip[q.nl0 + j]);
+      for (int k = 0; k <= q.K; ++k) put(B.frow, k, ip[q.fx_row + k]);
       for (int e = 0; e < q.nnz; ++e) {
-        blob[B.fpar + e] = d.flux_param[ip[q.fx_mode + e]];
+        put(B.fpar, e, d.flux_param[ip[q.fx_mode + e]]);
         blob[B.fcf + e] = dp[q.fx_coef + e];
       }
       if (dp.size() % 2) dp.push_back(0.0);  // 16-byte aligned blobs (direct LDS copies in 16-byte units)

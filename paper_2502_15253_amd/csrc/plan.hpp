@@ -85,28 +85,30 @@ struct DsPlan {
 static_assert(sizeof(DsPlan) % sizeof(double) == 0, "DsPlan is copied as doubles");
 constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
 
-// Per-dataset static inputs of the bin stages, packed contiguously (integers
-// stored as exact doubles) so one batched copy stages them in LDS.
+// Per-dataset static inputs of the bin stages, packed contiguously so one
+// batched copy stages them in LDS. Offsets count doubles; the integer arrays
+// (brt .. nli, frow, fpar) hold 32-bit integers, two per double slot.
 struct BlobLayout {
   int edges, tmpl, mdc, bsc, brt, shp, mdcol, mdk, mdp, nlp, nli, frow, fpar, fcf, total;
 };
 __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K) {
+  auto ints = [](int n) { return (n + 1) / 2; };  // double slots for n int32 values
   BlobLayout L;
   int o = 0;
   L.edges = o; o += E;
   L.tmpl = o; o += B * Nb;
   L.mdc = o; o += nnz;
   L.bsc = o; o += B;
-  L.brt = o; o += B;
-  L.shp = o; o += B * Nb;
-  L.mdcol = o; o += M + 1;
-  L.mdk = o; o += nnz;
-  L.mdp = o; o += M;
-  L.nlp = o; o += S + 1;
-  L.nli = o; o += nl;
-  L.frow = o; o += K + 1;   // flux basis by fine bin (CSR): row pointers,
-  L.fpar = o; o += nnz;     // parameter index and
-  L.fcf = o; o += nnz;      // coefficient of each entry
+  L.fcf = o; o += nnz;          // flux basis by fine bin (CSR): coefficient of each entry,
+  L.frow = o; o += ints(K + 1);  // row pointers and
+  L.fpar = o; o += ints(nnz);    // parameter index of each entry
+  L.brt = o; o += ints(B);
+  L.shp = o; o += ints(B * Nb);
+  L.mdcol = o; o += ints(M + 1);
+  L.mdk = o; o += ints(nnz);
+  L.mdp = o; o += ints(M);
+  L.nlp = o; o += ints(S + 1);
+  L.nli = o; o += ints(nl);
   L.total = o;
   return L;
 }

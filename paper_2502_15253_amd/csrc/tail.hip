@@ -358,9 +358,9 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
     double* X = L.st + BL.edges;  // edges, then X, then lambda_X
     const double* tmpl = L.st + BL.tmpl;
-    const double* shp = L.st + BL.shp;
+    const int* shp = reinterpret_cast<const int*>(L.st + BL.shp);
     const double* bsc = L.st + BL.bsc;
-    const double* brt = L.st + BL.brt;
+    const int* brt = reinterpret_cast<const int*>(L.st + BL.brt);
     L.Hs = L.dyn;
     L.Gs = L.dyn + K;
     L.F1 = L.dyn + 5 * K;
@@ -374,8 +374,8 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // thread forms 1 + F of its own and the previous fine bin from the blob's
     // flux rows (no extra barrier).
     {
-      const double* frow = L.st + BL.frow;
-      const double* fpar = L.st + BL.fpar;
+      const int* frow = reinterpret_cast<const int*>(L.st + BL.frow);
+      const int* fpar = reinterpret_cast<const int*>(L.st + BL.fpar);
       const double* fcf = L.st + BL.fcf;
       auto f1 = [&](int k) {
         if (!io.fused) return L.F1[k];
@@ -578,8 +578,8 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // dNLL/dA_s = sum_k lambda_Hs S[s][k], then the product rule over its
     // norm list
     {
-      const double* nlp = L.st + BL.nlp;
-      const double* nli = L.st + BL.nli;
+      const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
+      const int* nli = reinterpret_cast<const int*>(L.st + BL.nli);
       auto apply = [&](int s, double gA) {
         const int b = (int)nlp[s], e = (int)nlp[s + 1];
         for (int q = b; q < e; ++q) {
@@ -623,10 +623,10 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // ---- flux modes (CSC gather per mode; Ld was written before the block
     // reduction's barriers)
     {
-      const double* mdcol = L.st + BL.mdcol;
-      const double* mdk = L.st + BL.mdk;
+      const int* mdcol = reinterpret_cast<const int*>(L.st + BL.mdcol);
+      const int* mdk = reinterpret_cast<const int*>(L.st + BL.mdk);
       const double* mdc = L.st + BL.mdc;
-      const double* mdp = L.st + BL.mdp;
+      const int* mdp = reinterpret_cast<const int*>(L.st + BL.mdp);
       for (int m = tid; m < M; m += NT) {
         double gm = 0.0;
         const int e0 = (int)mdcol[m], e1 = (int)mdcol[m + 1];
