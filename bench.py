@@ -377,6 +377,9 @@ def main():
                     help="training spectra for the warm-start section (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device copy of known size (counter calibration) and exit")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch choices (for profiling runs: the kernel statistics then "
+                         "cover one configuration)")
     ap.add_argument("--event-sweep", default="",
                     help="comma-separated event counts (e.g. 1e6,1e7,1e8): only time the single "
                          "evaluation of the medium-baseline model at each count and exit")
@@ -417,10 +420,13 @@ def main():
         # launch choices (work-item size, fold workgroup, bin-stage threads)
         # from the library's autotuner, before the clock
         from paper_2502_15253_amd import autotune as AT
-        tuned = AT.tune(eng, desc, [len(ev["weight"]) for ev in events], thetas[0],
-                        cache_path=os.path.join(tempfile.gettempdir(), "nufold_bench_autotune.json"),
-                        evals=50, force=True)
-        log(f"{mode} autotuned: {json.dumps(tuned)}")
+        if args.no_autotune:
+            tuned = dict(options={k: eng.get_option(k) for k in AT.OPTIONS}, cached=None)
+        else:
+            tuned = AT.tune(eng, desc, [len(ev["weight"]) for ev in events], thetas[0],
+                            cache_path=os.path.join(tempfile.gettempdir(), "nufold_bench_autotune.json"),
+                            evals=50, force=True)
+        log(f"{mode} launch choices: {json.dumps(tuned)}")
         th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
         out_dev = torch.zeros((len(thetas), 1 + eng.P), dtype=torch.float64, device="cuda")
         ptr_t = [th_dev[i].data_ptr() for i in range(len(thetas))]

@@ -176,6 +176,10 @@ int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
  */
 int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
 
+/* Current value of an option of nf_set_option (same keys) into *value.
+ * NF_EINVAL for unknown keys or null pointers. */
+int nf_get_option(nf_ctx* ctx, const char* key, int64_t* value);
+
 /*
  * Autotuner: times the launch choices above on this context's model, events
  * and data (evaluations at theta, P host values, `evals` timed evaluations

@@ -1759,6 +1759,22 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
   });
 }
 
+int nf_get_option(nf_ctx* ctx, const char* key, int64_t* value) {
+  return guarded(ctx, [&] {
+    if (!key || !value) fail(NF_EINVAL, "key and value are required");
+    const std::string k = key;
+    if (k == "chunk") *value = ctx->chunk;
+    else if (k == "fold_block") *value = ctx->fold_block;
+    else if (k == "tail_threads") *value = ctx->tail_threads;
+    else if (k == "batch_threads") *value = ctx->batch_threads_opt;
+    else if (k == "batch_fit_tile") *value = ctx->batch_tile;
+    else if (k == "deterministic") *value = ctx->deterministic;
+    else if (k == "timing") *value = ctx->timing;
+    else fail(NF_EINVAL, "unknown option '" + k + "'");
+    return NF_OK;
+  });
+}
+
 int nf_set_data_batch(nf_ctx* ctx, int nsets, const double* counts, int on_device) {
   return guarded(ctx, [&] {
     if (nsets <= 0 || !counts) fail(NF_EINVAL, "nsets > 0 and counts are required");

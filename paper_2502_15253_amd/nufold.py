@@ -44,6 +44,7 @@ SIGNATURES = {
     "nf_eval_device_many": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "nf_expected": (C.c_int, [C.c_void_p, _dp, _dp]),
     "nf_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
+    "nf_get_option": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
     "nf_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp, _dp]),
 }
 
@@ -168,6 +169,11 @@ class Engine:
 
     def set_option(self, key, value):
         _check(self.ctx, load().nf_set_option(self.ctx, key.encode(), int(value)))
+
+    def get_option(self, key):
+        v = C.c_int64()
+        _check(self.ctx, load().nf_get_option(self.ctx, key.encode(), C.byref(v)))
+        return int(v.value)
 
     def set_events(self, d, e_true, e_reco, source=None, weight=None):
         if _is_cuda(e_true):

@@ -155,6 +155,7 @@ def test_batched_fold_tiles_give_the_same_results(mode):
     ref = None
     for ft in (4, 1, 2, 8):
         eng.set_option("batch_fit_tile", ft)
+        assert eng.get_option("batch_fit_tile") == ft
         nll, g, code = eng.eval_batch(th, data_idx=didx)
         assert code == nf.NF_OK
         if ref is None:

@@ -276,7 +276,9 @@ def test_deterministic_option_reproduces_bit_for_bit(mode):
         for t, (f0, g0) in zip(th, first):
             f, g, _ = eng.eval_nll_grad(t)
             assert f == f0 and np.array_equal(g, g0), rep
+    assert eng.get_option("deterministic") == 1
     eng.set_option("deterministic", 0)
+    assert eng.get_option("deterministic") == 0
     for t, (f0, g0) in zip(th, first):
         f, g, _ = eng.eval_nll_grad(t)
         assert abs(f - f0) <= 1e-12 * max(1.0, abs(f0))
