@@ -63,13 +63,23 @@ def cpu_baseline(desc, events, theta):
     m = Model(desc)
     mus, _ = LK.expected(m, events, theta)
     data = [mu.copy() for mu in mus]
-    t0 = time.perf_counter()
-    LK.nll_grad(m, events, data, theta)
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # numpy's library threads held to one
+        t0 = time.perf_counter()
+        LK.nll_grad(m, events, data, theta)
+        dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=1.0 / dt, unit="evals/s", cores=1, kind="oracle",
                 sample=f"1 full evaluation (NLL + complex-step gradient over {m.P} parameters) "
                        f"of the {sum(len(e['weight']) for e in events):.0e}-event workload, "
-                       f"numpy FP64, single thread, {dt:.1f} s")
+                       f"numpy FP64, single thread, {dt:.1f} s",
+                host=dict(cpu=model, logical_cpus=os.cpu_count(),
+                          usable_cpus=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None))
 
 
 COPY_BYTES = 512 << 20

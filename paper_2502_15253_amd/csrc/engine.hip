@@ -902,7 +902,6 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   FoldFuse& fu = fa.fuse;
   fu.epi = c->d_epi.p;
   fu.seg_item = c->d_seg_item.p;
-  fu.Wseg = c->d_Wseg.p;
   fu.seg_kt = c->d_seg_kt.p;
   fu.kt_need = c->d_kt_need.p;
   fu.kt_info = c->d_ipool.p + c->plan.kt_info;

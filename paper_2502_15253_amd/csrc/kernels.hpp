@@ -49,7 +49,6 @@ __host__ __device__ inline size_t fit_lds_doubles(int P, int m) {
 struct FoldFuse {
   const ItemEpi* epi;   // [nitems] per-item epilogue record
   const int* seg_item;  // [G+1] work-item range of each segment
-  const double* Wseg;   // [G] summed weights of each segment
   const int* seg_kt;    // [G] global fine bin of each segment
   const int* kt_need;   // [KT] segments with at least one work item, per fine bin
   const int* kt_info;   // [5 KT] g0, K, S, fs0, kt0 of each fine bin
