@@ -53,8 +53,8 @@ struct Lds {
   double* nD;
   double* D;      // K+1  edge densities
   double* C;      // K+1  cumulative, later lambda_C, then lambda_H
-  double* Ld;     // K+1  lambda_d, later lambda_F
-  double* Suf;    // K+1  suffix sums of lambda_C
+  double* Ld;     // K+1  lambda_d
+  double* Suf;    // K+1  suffix sums of lambda_C, later lambda_F
   double* LH;     // K    H (scan input), lambda_m (direct), later lambda_Hs
   double* eT;     // E    t, later e_m
   double* eY;     // E    y, later e_dlo
@@ -166,13 +166,10 @@ __device__ void block_scan(const double* x, double* out, int n, bool reverse, do
   const double v = wave_scan_incl(s);
   if (lane == 63) red[wid] = v;
   __syncthreads();
-  if (wid == 0) {  // exclusive scan of the wave totals
-    const double w = lane < NW ? red[lane] : 0.0;
-    const double incl = wave_scan_incl(w);
-    if (lane < NW) red[NW + lane] = incl - w;
-  }
-  __syncthreads();
-  double acc = red[NW + wid] + v - s;  // exclusive prefix of this thread's chunk
+  // the totals of the waves before this one, added in wave order
+  double pre = 0.0;
+  for (int w = 0; w < wid; ++w) pre += red[w];
+  double acc = pre + v - s;  // exclusive prefix of this thread's chunk
   if (!reverse) {
     for (int i = lo; i < hi; ++i) {
       out[i] = acc;
@@ -187,24 +184,6 @@ __device__ void block_scan(const double* x, double* out, int n, bool reverse, do
     }
   }
   __syncthreads();
-}
-
-// Cooperative copy global -> LDS with U independent loads in flight per thread.
-template <int NT, int U>
-__device__ __forceinline__ void stage(double* dst, const double* src, int n) {
-  for (int base = 0; base < n; base += NT * U) {
-    double v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * NT + (int)threadIdx.x;
-      v[u] = i < n ? src[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * NT + (int)threadIdx.x;
-      if (i < n) dst[i] = v[u];
-    }
-  }
 }
 
 __device__ __forceinline__ double pval(const double* th, int idx, double dflt) {
@@ -355,6 +334,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     const DsPlan& ds = L.dsl[d];
     const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
     const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
+    const double iwf = 1.0 / wf;  // densities m = H (1 + F) / w as products
     const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
     double* X = L.st + BL.edges;  // edges, then X, then lambda_X
     const double* tmpl = L.st + BL.tmpl;
@@ -388,10 +368,10 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         const double fa = k > 0 ? f1(k - 1) : 0.0;
         const double fb = k < K ? f1(k) : 0.0;
         double dk;
-        if (k == 0) dk = L.Hs[0] * fb / wf;
-        else if (k == K) dk = L.Hs[K - 1] * fa / wf;
+        if (k == 0) dk = L.Hs[0] * fb * iwf;
+        else if (k == K) dk = L.Hs[K - 1] * fa * iwf;
         else {
-          const double ma = L.Hs[k - 1] * fa / wf, mb = L.Hs[k] * fb / wf;
+          const double ma = L.Hs[k - 1] * fa * iwf, mb = L.Hs[k] * fb * iwf;
           dk = (ma * mb > 0.0) ? 2.0 * ma * mb / (ma + mb) : 0.0;
         }
         L.D[k] = dk;
@@ -401,7 +381,9 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         }
       }
     }
-    __syncthreads();
+    // the scan's first read is each thread's own element when K <= NT (one
+    // per thread, as written above); its own barrier then orders D
+    if (K > NT) __syncthreads();
     block_scan<NT>(L.LH, L.C, K, false, L.red);
 
     // ---- energy scale and analysis edges
@@ -428,10 +410,10 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       } else {
         k = (int)floor((y - y0) / wf);
         k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
-        t = (y - (y0 + k * wf)) / wf;
-        const double mk = L.Hs[k] * L.F1[k] / wf;
+        t = (y - (y0 + k * wf)) * iwf;
+        const double mk = L.Hs[k] * L.F1[k] * iwf;
         const double dl = L.D[k], dh = L.D[k + 1];
-        const double q = 0.5 * t * t - t * t * t / 3.0;
+        const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0);
         Xi = L.C[k] + wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + 6.0 * (mk - 0.5 * (dl + dh)) * q);
       }
       L.kidx[i] = k;
@@ -490,9 +472,9 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         gc[3] += lx;
       } else if (k >= 0) {
         const double t = L.eT[i], y = L.eY[i];
-        const double mk = L.Hs[k] * L.F1[k] / wf;
+        const double mk = L.Hs[k] * L.F1[k] * iwf;
         const double dl = L.D[k], dh = L.D[k + 1];
-        const double q = 0.5 * t * t - t * t * t / 3.0;
+        const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0);
         const double rho = dl * (1.0 - t) + dh * t + 6.0 * (mk - 0.5 * (dl + dh)) * t * (1.0 - t);
         const double fp = bb + 2.0 * c2 * y;
         const double ly = lx * rho / fp;
@@ -549,31 +531,32 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
 
     // ---- lambda_H per fine bin -> C
     for (int k = tid; k < K; k += NT) {
-      const double mk = L.Hs[k] * L.F1[k] / wf;
+      const double mk = L.Hs[k] * L.F1[k] * iwf;
       double lm = L.LH[k];
       if (k == 0) lm += L.Ld[0];
       if (k == K - 1) lm += L.Ld[K];
       if (k >= 1) {  // d_k = harmonic(m_{k-1}, m_k)
-        const double ma = L.Hs[k - 1] * L.F1[k - 1] / wf;
+        const double ma = L.Hs[k - 1] * L.F1[k - 1] * iwf;
         if (ma * mk > 0.0) {
           const double den = ma + mk;
           lm += L.Ld[k] * 2.0 * ma * ma / (den * den);
         }
       }
       if (k + 1 <= K - 1) {  // d_{k+1} = harmonic(m_k, m_{k+1})
-        const double mb = L.Hs[k + 1] * L.F1[k + 1] / wf;
+        const double mb = L.Hs[k + 1] * L.F1[k + 1] * iwf;
         if (mk * mb > 0.0) {
           const double den = mk + mb;
           lm += L.Ld[k + 1] * 2.0 * mb * mb / (den * den);
         }
       }
-      L.C[k] = L.Suf[k] + top + lm / wf;
+      L.C[k] = L.Suf[k] + top + lm * iwf;
     }
-    __syncthreads();
+    // no barrier: the next pass reads only its own fine bins' lambda_H and
+    // writes lambda_F over the suffix sums it has read (same thread mapping)
 
     // ---- rescale adjoint, oscillation parameters and source norms in one
     // pass over the fine bins with one block reduction (in groups of up to
-    // 12 sources): lambda_Hs = lambda_H (1 + F), lambda_F -> Ld; the
+    // 12 sources): lambda_Hs = lambda_H (1 + F), lambda_F -> Suf; the
     // oscillation slots take sum_k lambda_Hs G_j, source s takes
     // dNLL/dA_s = sum_k lambda_Hs S[s][k], then the product rule over its
     // norm list
@@ -598,7 +581,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
           const double lh = L.C[k];
           const double lhs = lh * L.F1[k];
           if (s0 == 0) {
-            L.Ld[k] = lh * L.Hs[k];
+            L.Suf[k] = lh * L.Hs[k];  // lambda_F
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[j] += lhs * L.Gs[j * K + k];
           }
@@ -620,8 +603,8 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         }
       }
     }
-    // ---- flux modes (CSC gather per mode; Ld was written before the block
-    // reduction's barriers)
+    // ---- flux modes (CSC gather per mode of lambda_F, written before the
+    // block reduction's barriers)
     {
       const int* mdcol = reinterpret_cast<const int*>(L.st + BL.mdcol);
       const int* mdk = reinterpret_cast<const int*>(L.st + BL.mdk);
@@ -642,7 +625,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
             c[q] = in ? mdc[e + q] : 0.0;
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) gm += L.Ld[k[q]] * c[q];
+          for (int q = 0; q < 4; ++q) gm += L.Suf[k[q]] * c[q];
         }
         atomicAdd(&L.grad[(int)mdp[m]], gm);
       }
