@@ -451,16 +451,16 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       }
       L.mu[i] = lam;
     }
-    if (NB <= 2) block_sum<NT, 3>(acc, L.red);
-    else block_sum<NT, 1 + MAX_BKG>(acc, L.red);
-    nll_total += acc[0];
     if (!want_grad) {
+      if (NB <= 2) block_sum<NT, 3>(acc, L.red);
+      else block_sum<NT, 1 + MAX_BKG>(acc, L.red);
+      nll_total += acc[0];
       __syncthreads();
       continue;
     }
-    if (tid == 0)
-      for (int b = 0; b < NB; ++b)
-        if ((int)brt[b] >= 0) L.grad[(int)brt[b]] += acc[1 + b];
+    // the deviance and background sums are reduced together with the edge
+    // pass's sums below; the edge pass only needs lambda_mu
+    __syncthreads();
 
     // ---- adjoint per edge: lambda_X, energy-scale coefficients, spline pieces
     double gc[4] = {0.0, 0.0, 0.0, 0.0};  // c0, c1, c2, out-of-range-above total
@@ -495,10 +495,27 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       if (i == E - 1)
         for (int q = k + 1; q <= K + 1; ++q) L.first[q + 1] = E;
     }
-    block_sum<NT, 4>(gc, L.red);
-    if (tid == 0)
+    {
+      // one block reduction: gc[0..3], then the deviance and background sums
+      double v[4 + 1 + MAX_BKG];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = gc[j];
+#pragma unroll
+      for (int j = 0; j <= MAX_BKG; ++j) v[4 + j] = acc[j];
+      if (NB <= 2) block_sum<NT, 7>(v, L.red);
+      else block_sum<NT, 5 + MAX_BKG>(v, L.red);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gc[j] = v[j];
+#pragma unroll
+      for (int j = 0; j <= MAX_BKG; ++j) acc[j] = v[4 + j];
+    }
+    nll_total += acc[0];
+    if (tid == 0) {
+      for (int b = 0; b < NB; ++b)
+        if ((int)brt[b] >= 0) L.grad[(int)brt[b]] += acc[1 + b];
       for (int j = 0; j < 3; ++j)
         if (ds.cidx[j] >= 0) L.grad[ds.cidx[j]] += gc[j];
+    }
     const double top = gc[3];
 
     // ---- gather per fine bin: lambda_C -> C, lambda_m (direct) -> LH, lambda_d -> Ld
