@@ -608,7 +608,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         }
         if (ns <= 4) block_sum<NT, 8>(acc, L.red);
         else block_sum<NT, 16>(acc, L.red);
-        if (s0 == 0 && tid == 0)
+        if (s0 == 0 && tid == NT - 1)  // a thread with no source to apply
           for (int j = 0; j < NSLOT; ++j)
             if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += acc[j];
         if (tid < ns) {
