@@ -435,7 +435,7 @@ def main():
         else:
             tuned = AT.tune(eng, desc, [len(ev["weight"]) for ev in events], thetas[0],
                             cache_path=os.path.join(tempfile.gettempdir(), "nufold_bench_autotune.json"),
-                            evals=50, force=True)
+                            evals=200, force=True)
         log(f"{mode} launch choices: {json.dumps(tuned)}")
         th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
         out_dev = torch.zeros((len(thetas), 1 + eng.P), dtype=torch.float64, device="cuda")
