@@ -151,9 +151,12 @@ __device__ __forceinline__ void wave_sum_store(double* m, double* part, int nite
 }
 
 // One wavefront folds one work item. Each lane takes 4 consecutive events
-// per step (16-byte loads) and the loop is software-pipelined two steps deep:
-// the loads of step t+1 are issued before step t is folded, so every wave
-// keeps its next loads in flight. Positions past the item's end load the 4
+// per step (16-byte loads) and the loop is software-pipelined: a step's loads
+// are issued three steps (M32) or one step (M64, whose registers and VALU are
+// the tighter budget) ahead of its folding, held there by scheduling barriers
+// (left alone, the compiler sinks them below the first arithmetic on the step
+// before, and a wave then has a single step in flight). With every wave of the
+// launch resident at once, the bytes a wave keeps in flight bound the stream. Positions past the item's end load the 4
 // zero-weight events at zpad, which add nothing (so the second half of the
 // last step may fold zeros); the loop is uniform over the wave and no load
 // sits under a branch.
@@ -342,6 +345,7 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
     const double2 pb = load_stream2(u + ob);
     const double2 qb = load_stream2(u + ob + 2);
     const float4 wb = load_stream4(w + ob);
+    __builtin_amdgcn_sched_barrier(0);  // the loads issue before the folding below
     accum64<FORM>(pa.x, wa.x, a1, a2, m);
     accum64<FORM>(pa.y, wa.y, a1, a2, m);
     accum64<FORM>(qa.x, wa.z, a1, a2, m);
@@ -350,6 +354,7 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
     pa = load_stream2(u + on);
     qa = load_stream2(u + on + 2);
     wa = load_stream4(w + on);
+    __builtin_amdgcn_sched_barrier(0);
     accum64<FORM>(pb.x, wb.x, a1, a2, m);
     accum64<FORM>(pb.y, wb.y, a1, a2, m);
     accum64<FORM>(qb.x, wb.z, a1, a2, m);
@@ -385,27 +390,49 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
 #pragma unroll
   for (int c = 0; c < NM; ++c) mf[c] = 0.0f;
   int j = lane * 4;
-  int64_t o = j < cnt ? it.begin + j : a.zpad;
+  auto at = [&](int off) { return j + off < cnt ? it.begin + j + off : a.zpad; };
+  int64_t o = at(0);
   float4 ua = load_stream4(u + o);
   float4 wa = load_stream4(w + o);
+  o = at(256);
+  float4 ub = load_stream4(u + o);
+  float4 wb = load_stream4(w + o);
+  o = at(512);
+  float4 uc = load_stream4(u + o);
+  float4 wc = load_stream4(w + o);
   item_prefetch(a, item, ep, thv);
   wave_coefficients(a, cf);
-  for (int t = 0; t < niter; t += 2) {
-    const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
-    const float4 ub = load_stream4(u + ob);
-    const float4 wb = load_stream4(w + ob);
-    accum32<FORM>(ua.x, wa.x, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(ua.y, wa.y, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(ua.z, wa.z, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(ua.w, wa.w, b1h, b1l, b2h, b2l, mf);
-    const int64_t on = j + 512 < cnt ? it.begin + j + 512 : a.zpad;
-    ua = load_stream4(u + on);
-    wa = load_stream4(w + on);
-    accum32<FORM>(ub.x, wb.x, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(ub.y, wb.y, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(ub.z, wb.z, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(ub.w, wb.w, b1h, b1l, b2h, b2l, mf);
-    j += 512;
+  auto fold4 = [&](const float4& uu, const float4& ww) {
+    accum32<FORM>(uu.x, ww.x, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(uu.y, ww.y, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(uu.z, ww.z, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(uu.w, ww.w, b1h, b1l, b2h, b2l, mf);
+  };
+  // four register sets rotate: each step's loads are issued three steps
+  // ahead of its folding (the scheduling barriers keep them ahead of the
+  // arithmetic)
+  for (int t = 0; t < niter; t += 4) {
+    o = at(768);
+    const float4 ud = load_stream4(u + o);
+    const float4 wd = load_stream4(w + o);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(ua, wa);
+    o = at(1024);
+    ua = load_stream4(u + o);
+    wa = load_stream4(w + o);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(ub, wb);
+    o = at(1280);
+    ub = load_stream4(u + o);
+    wb = load_stream4(w + o);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(uc, wc);
+    o = at(1536);
+    uc = load_stream4(u + o);
+    wc = load_stream4(w + o);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(ud, wd);
+    j += 1024;
   }
   double m[NM];
 #pragma unroll
