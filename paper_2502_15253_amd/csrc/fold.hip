@@ -421,17 +421,17 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
     ua = load_stream4(u + o);
     wa = load_stream4(w + o);
     __builtin_amdgcn_sched_barrier(0);
-    fold4(ub, wb);
+    if (t + 1 < niter) fold4(ub, wb);  // steps past the item's end are not folded
     o = at(1280);
     ub = load_stream4(u + o);
     wb = load_stream4(w + o);
     __builtin_amdgcn_sched_barrier(0);
-    fold4(uc, wc);
+    if (t + 2 < niter) fold4(uc, wc);
     o = at(1536);
     uc = load_stream4(u + o);
     wc = load_stream4(w + o);
     __builtin_amdgcn_sched_barrier(0);
-    fold4(ud, wd);
+    if (t + 3 < niter) fold4(ud, wd);
     j += 1024;
   }
   double m[NM];
