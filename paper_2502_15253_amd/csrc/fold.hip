@@ -152,11 +152,12 @@ __device__ __forceinline__ void wave_sum_store(double* m, double* part, int nite
 
 // One wavefront folds one work item. Each lane takes 4 consecutive events
 // per step (16-byte loads) and the loop is software-pipelined: a step's loads
-// are issued three steps (M32) or one step (M64, whose registers and VALU are
-// the tighter budget) ahead of its folding, held there by scheduling barriers
+// are issued three steps (M32) or two steps (M64, whose registers are the
+// tighter budget) ahead of its folding, held there by scheduling barriers
 // (left alone, the compiler sinks them below the first arithmetic on the step
 // before, and a wave then has a single step in flight). With every wave of the
-// launch resident at once, the bytes a wave keeps in flight bound the stream. Positions past the item's end load the 4
+// launch resident at once, the bytes a wave keeps in flight bound the stream.
+// Steps past the item's end are loaded (from zpad) but not folded. Positions past the item's end load the 4
 // zero-weight events at zpad, which add nothing (so the second half of the
 // last step may fold zeros); the loop is uniform over the wave and no load
 // sits under a branch.
@@ -334,32 +335,46 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
 #pragma unroll
   for (int c = 0; c < NM; ++c) m[c] = 0.0;
   int j = lane * 4;
-  int64_t o = j < cnt ? it.begin + j : a.zpad;
+  auto at = [&](int off) { return j + off < cnt ? it.begin + j + off : a.zpad; };
+  int64_t o = at(0);
   double2 pa = load_stream2(u + o);
   double2 qa = load_stream2(u + o + 2);
   float4 wa = load_stream4(w + o);
+  o = at(256);
+  double2 pb = load_stream2(u + o);
+  double2 qb = load_stream2(u + o + 2);
+  float4 wb = load_stream4(w + o);
   item_prefetch(a, item, ep, thv);
   wave_coefficients(a, cf);
-  for (int t = 0; t < niter; t += 2) {
-    const int64_t ob = j + 256 < cnt ? it.begin + j + 256 : a.zpad;
-    const double2 pb = load_stream2(u + ob);
-    const double2 qb = load_stream2(u + ob + 2);
-    const float4 wb = load_stream4(w + ob);
-    __builtin_amdgcn_sched_barrier(0);  // the loads issue before the folding below
-    accum64<FORM>(pa.x, wa.x, a1, a2, m);
-    accum64<FORM>(pa.y, wa.y, a1, a2, m);
-    accum64<FORM>(qa.x, wa.z, a1, a2, m);
-    accum64<FORM>(qa.y, wa.w, a1, a2, m);
-    const int64_t on = j + 512 < cnt ? it.begin + j + 512 : a.zpad;
-    pa = load_stream2(u + on);
-    qa = load_stream2(u + on + 2);
-    wa = load_stream4(w + on);
+  auto fold4 = [&](const double2& pp, const double2& qq, const float4& ww) {
+    accum64<FORM>(pp.x, ww.x, a1, a2, m);
+    accum64<FORM>(pp.y, ww.y, a1, a2, m);
+    accum64<FORM>(qq.x, ww.z, a1, a2, m);
+    accum64<FORM>(qq.y, ww.w, a1, a2, m);
+  };
+  // three register sets rotate: each step's loads are issued two steps ahead
+  // of its folding (the scheduling barriers keep them ahead of the
+  // arithmetic); steps past the item's end are loaded but not folded
+  for (int t = 0; t < niter; t += 3) {
+    o = at(512);
+    const double2 pc = load_stream2(u + o);
+    const double2 qc = load_stream2(u + o + 2);
+    const float4 wc = load_stream4(w + o);
     __builtin_amdgcn_sched_barrier(0);
-    accum64<FORM>(pb.x, wb.x, a1, a2, m);
-    accum64<FORM>(pb.y, wb.y, a1, a2, m);
-    accum64<FORM>(qb.x, wb.z, a1, a2, m);
-    accum64<FORM>(qb.y, wb.w, a1, a2, m);
-    j += 512;
+    fold4(pa, qa, wa);
+    o = at(768);
+    pa = load_stream2(u + o);
+    qa = load_stream2(u + o + 2);
+    wa = load_stream4(w + o);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 < niter) fold4(pb, qb, wb);
+    o = at(1024);
+    pb = load_stream2(u + o);
+    qb = load_stream2(u + o + 2);
+    wb = load_stream4(w + o);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 2 < niter) fold4(pc, qc, wc);
+    j += 768;
   }
   fold_finish<NM>(a, cf, m, item, it.seg, ep, a.fuse.seg_cnt ? item_norm(ep, thv) : 1.0);
 }
