@@ -184,13 +184,15 @@ int nf_get_option(nf_ctx* ctx, const char* key, int64_t* value);
  * Autotuner: times the launch choices above on this context's model, events
  * and data (evaluations at theta, P host values, `evals` timed evaluations
  * per candidate, device time from HIP events) and keeps the fastest:
- * tail_threads first, then chunk x fold_block (skipped when evals = 0); then,
- * if batch > 0 and batch
- * data are set (nf_set_data_batch), batch_fit_tile x batch_threads for
- * batched launches of `batch` fits. best (nullable): 5 values chunk,
- * fold_block, tail_threads, batch_threads, batch_fit_tile. best_us
- * (nullable): 2 values, the mean device time of one
- * evaluation and of one batched evaluation (0 if not tuned), microseconds.
+ * tail_threads first, then chunk x fold_block (both skipped when evals = 0);
+ * then, if batch > 0 and batch data are set (nf_set_data_batch),
+ * batch_fit_tile x batch_threads for batched launches of `batch` fits. In
+ * each sweep the current choice is timed first, and a candidate replaces the
+ * best so far only when it is more than 1% faster, so timing noise does not
+ * move the configuration between equivalent choices. best (nullable): 5
+ * values chunk, fold_block, tail_threads, batch_threads, batch_fit_tile.
+ * best_us (nullable): 2 values, the mean device time of one evaluation and
+ * of one batched evaluation (0 if not tuned), microseconds.
  * Needs events and data. Replaces the options in place.
  */
 int nf_autotune(nf_ctx* ctx, const double* theta, int evals, int batch, int64_t* best, double* best_us);

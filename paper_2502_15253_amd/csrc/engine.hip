@@ -1269,29 +1269,37 @@ int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t*
   const int timing = c->timing;
   c->timing = 0;
   hip_check(hipMemcpy(c->d_theta.p, theta, sizeof(double) * c->P, hipMemcpyHostToDevice), "H2D");
+  // the current choice is timed first and a candidate replaces the best so far
+  // only when it is faster by more than this margin, so that timing noise does
+  // not move the launch configuration between equivalent choices
+  constexpr double MARGIN = 0.01;
+  auto better = [](double t, double t_best) { return t < t_best * (1.0 - MARGIN); };
   double t_best = 0.0;
   if (evals > 0) {  // single-evaluation choices
-    t_best = 1e300;
     int nt_best = c->tail_threads;
+    t_best = time_single(c, evals);
     for (int nt : {256, 512, 1024}) {
-      if (!tail_fits(c, nt)) continue;
+      if (nt == nt_best || !tail_fits(c, nt)) continue;
       c->tail_threads = nt;
       const double t = time_single(c, evals);
-      if (t < t_best) { t_best = t; nt_best = nt; }
+      if (better(t, t_best)) { t_best = t; nt_best = nt; }
     }
     c->tail_threads = nt_best;
-    t_best = 1e300;
+    const int64_t ch_cur = c->chunk;
+    const int fb_cur = c->fold_block;
     int64_t ch_best = c->chunk;
     int fb_best = c->fold_block;
+    t_best = time_single(c, evals);
     for (int64_t ch : {1024, 2048, 4096, 8192}) {
       if (ch != c->chunk) {
         c->chunk = ch;
         rebuild_events(c);
       }
       for (int fb : {64, 128, 256}) {
+        if (ch == ch_cur && fb == fb_cur) continue;  // the current choice, timed above
         c->fold_block = fb;
         const double t = time_single(c, evals);
-        if (t < t_best) { t_best = t; ch_best = ch; fb_best = fb; }
+        if (better(t, t_best)) { t_best = t; ch_best = ch; fb_best = fb; }
       }
     }
     if (ch_best != c->chunk) {
@@ -1318,14 +1326,15 @@ int autotune_impl(nf_ctx* c, const double* theta, int evals, int batch, int64_t*
     std::vector<int> didx(batch, 0);
     hip_check(hipMemcpy(c->bt_theta.p, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice), "H2D");
     hip_check(hipMemcpy(c->bt_didx.p, didx.data(), sizeof(int) * batch, hipMemcpyHostToDevice), "H2D");
-    tb_best = 1e300;
+    tb_best = time_batch(c, batch, std::max(1, evals / 4));
+    const int bt_cur = bt_best, ft_cur = ft_best;
     for (int ft : {1, 2, 4, 8})
       for (int nt : {256, 512, 1024}) {
-        if (!tail_fits(c, nt)) continue;
+        if ((ft == ft_cur && nt == bt_cur) || !tail_fits(c, nt)) continue;
         c->batch_tile = ft;
         c->batch_threads_opt = nt;
         const double t = time_batch(c, batch, std::max(1, evals / 4));
-        if (t < tb_best) { tb_best = t; bt_best = nt; ft_best = ft; }
+        if (better(t, tb_best)) { tb_best = t; bt_best = nt; ft_best = ft; }
       }
     c->batch_threads_opt = bt_best;
     c->batch_tile = ft_best;
