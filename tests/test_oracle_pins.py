@@ -119,7 +119,7 @@ def test_eq1_differs_from_3nu_only_in_the_atmospheric_bracket():
     bracket = (np.sin(D(dee * 1e-3)) ** 2 - (1 - s12) * np.sin(D(d31 * 1e-3)) ** 2
                - s12 * np.sin(D(d31 * 1e-3 - d21 * 1e-5)) ** 2)
     assert np.max(np.abs((p3 - p1) - s2_2t13 * bracket)) < 1e-14
-    # and Eq. 1 is a good short-baseline approximation (survey of the paper's use)
+    # and Eq. 1 is a good short-baseline approximation (the regime the paper applies it in)
     assert np.max(np.abs(p3 - p1)) < 1e-4
 
 
