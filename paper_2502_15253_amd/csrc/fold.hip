@@ -100,14 +100,16 @@ __device__ __forceinline__ void accum64(double u, float wf, double a1, double a2
   }
 }
 
-// FP32 path: phases in revolutions t = x / 2pi, computed as a two-float
-// product so the fractional part keeps ~2^-24 relative accuracy of x even
-// when x reaches hundreds of radians; hardware sin/cos take revolutions.
+// FP32 path: phases in revolutions t = x / 2pi; hardware sin/cos take
+// revolutions. The frequency is split in two floats (bh + bl): bl holds what
+// an FP32 bh cannot, so no phase error common to all events builds up with
+// x. The product bh * u is rounded once; that error is at most half an ulp
+// of t, the same order as the FP32 rounding of u itself, and it varies from
+// event to event, so the segment sums average it out.
 __device__ __forceinline__ float phase_rev(float u, float bh, float bl) {
   const float p = bh * u;
-  const float e = fmaf(bh, u, -p);           // exact low part of bh*u
   const float fr = __builtin_amdgcn_fractf(p);  // p - floor(p) in one instruction
-  return fr + fmaf(bl, u, e);
+  return fmaf(bl, u, fr);
 }
 
 template <int FORM>
