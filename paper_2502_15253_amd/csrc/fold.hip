@@ -427,8 +427,34 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   };
   // four register sets rotate: each step's loads are issued three steps
   // ahead of its folding (the scheduling barriers keep them ahead of the
-  // arithmetic)
-  for (int t = 0; t < niter; t += 4) {
+  // arithmetic). While every load of an iteration lies inside the item, the
+  // addresses are plain pointer offsets; the last iterations go through at()
+  // (loads past the end read zpad, those steps are not folded).
+  int t = 0;
+  const float* pu = u + it.begin + j;
+  const float* pw = w + it.begin + j;
+  for (; (t << 8) + 1792 <= cnt; t += 4) {
+    const float4 ud = load_stream4(pu + 768);
+    const float4 wd = load_stream4(pw + 768);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(ua, wa);
+    ua = load_stream4(pu + 1024);
+    wa = load_stream4(pw + 1024);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(ub, wb);
+    ub = load_stream4(pu + 1280);
+    wb = load_stream4(pw + 1280);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(uc, wc);
+    uc = load_stream4(pu + 1536);
+    wc = load_stream4(pw + 1536);
+    __builtin_amdgcn_sched_barrier(0);
+    fold4(ud, wd);
+    pu += 1024;
+    pw += 1024;
+    j += 1024;
+  }
+  for (; t < niter; t += 4) {
     o = at(768);
     const float4 ud = load_stream4(u + o);
     const float4 wd = load_stream4(w + o);
