@@ -141,11 +141,16 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
     red[j * R + wid * 4 + (lane >> 4)] = x;
   }
   __syncthreads();
-  if (tid < N) {
+  // four lanes per value (4 N <= 64: all in wavefront 0), each summing a
+  // quarter of the R partials, then two quad exchanges; fixed order
+  if (tid < 4 * N) {
+    const int q = tid >> 2, part = tid & 3;
     double s = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < R; ++q) s += red[tid * R + q];
-    red[16 * R + tid] = s;
+#pragma unroll
+    for (int k = 0; k < R / 4; ++k) s += red[q * R + part * (R / 4) + k];
+    s += dpp_swap<0xB1>(s);  // quad_perm [1,0,3,2]
+    s += dpp_swap<0x4E>(s);  // quad_perm [2,3,0,1]
+    if (part == 0) red[16 * R + q] = s;
   }
   __syncthreads();
 #pragma unroll
