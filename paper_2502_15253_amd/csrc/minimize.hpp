@@ -93,6 +93,12 @@ __device__ double lbfgs_direction(const FitArgs& F, int P, int hn, int head, con
 
 // One minimiser step after an evaluation at theta_t (L.th): f_t, grad in Lg.
 // lds: scratch of fit_lds_doubles(P, m) doubles.
+//
+// Every thread copies the fit header into registers before the first barrier
+// and takes each decision from that copy, updating it identically; thread 0
+// stores it back after the last barrier. No thread reads a header field that
+// another thread of the same step may already have written, so all wavefronts
+// take the same branches and pass the same barriers.
 template <int NT>
 __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f_t, const double* Lg,
                            double* lds, double* red) {
@@ -112,11 +118,9 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
   double* rho = sm;
   double* gam = rho + m;
   double* alph = gam + m;
-  double* misc = alph + m;
 
-  // stage state (all threads read the header fields they need)
-  const int phase = H->phase;
-  int hn = H->hist_n, head = H->hist_head;
+  FitHeader h = *H;  // private snapshot; written back by thread 0 at the end
+  int hn = h.hist_n, head = h.hist_head;
   for (int i = tid; i < P; i += NT) {
     D[i] = F.d2[i];
     fr[i] = F.freem[i];
@@ -134,52 +138,51 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
       Yl[(int64_t)j * P + i] = F.Y[(int64_t)j * P + i];
     }
   __syncthreads();
-  if (tid == 0) H->nevals += 1;
+  h.nevals += 1;
 
   bool accept = false, new_trial = false, restart = false;
-  double alpha = H->alpha;
+  double alpha = h.alpha;
 
-  if (phase == PH_INIT) {
+  if (h.phase == PH_INIT) {
     if (!isfinite(f_t)) {
-      if (tid == 0) H->status = FIT_DOMAIN;
+      h.status = FIT_DOMAIN;
+      if (tid == 0) *H = h;
       return;
     }
     for (int i = tid; i < P; i += NT) {
       F.x[i] = th_t[i];
       gx[i] = gt[i];
     }
-    if (tid == 0) H->f = f_t;
+    h.f = f_t;
     restart = true;  // direction from -D g, first trial alpha = 1
   } else {
-    const double f0 = H->f, d0 = H->dphi0;
+    const double f0 = h.f, d0 = h.dphi0;
     const double dphi = isfinite(f_t) ? bdot<NT>(gt, pd, P, red) : NAN;
     const bool armijo = isfinite(f_t) && f_t <= f0 + LS_C1 * alpha * d0;
     const bool curv = isfinite(dphi) && fabs(dphi) <= -LS_C2 * d0;
-    double alo = H->a_lo, flo = H->f_lo, dlo = H->d_lo, ahi = H->a_hi, fhi = H->f_hi, dhi = H->d_hi;
-    int ph = phase;
+    double alo = h.a_lo, flo = h.f_lo, dlo = h.d_lo, ahi = h.a_hi, fhi = h.f_hi, dhi = h.d_hi;
+    int ph = h.phase;
     if (ph == PH_FORCE) {
       if (isfinite(f_t) && f_t < f0) accept = true;
       else {
         restart = true;
-        if (tid == 0) H->resets += 1;
+        h.resets += 1;
       }
     } else if (ph == PH_BRACKET) {
-      if (!armijo || (H->ls_steps > 0 && f_t >= H->f_prev)) {
-        alo = H->a_prev; flo = H->f_prev; dlo = H->d_prev;
+      if (!armijo || (h.ls_steps > 0 && f_t >= h.f_prev)) {
+        alo = h.a_prev; flo = h.f_prev; dlo = h.d_prev;
         ahi = alpha; fhi = isfinite(f_t) ? f_t : INFINITY; dhi = dphi;
         ph = PH_ZOOM;
       } else if (curv) {
         accept = true;
       } else if (dphi >= 0.0) {
         alo = alpha; flo = f_t; dlo = dphi;
-        ahi = H->a_prev; fhi = H->f_prev; dhi = H->d_prev;
+        ahi = h.a_prev; fhi = h.f_prev; dhi = h.d_prev;
         ph = PH_ZOOM;
       } else {
-        if (tid == 0) {
-          H->a_prev = alpha;
-          H->f_prev = f_t;
-          H->d_prev = dphi;
-        }
+        h.a_prev = alpha;
+        h.f_prev = f_t;
+        h.d_prev = dphi;
         alpha = fmin(2.0 * alpha, LS_AMAX);
         new_trial = true;
       }
@@ -196,7 +199,7 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
       }
     }
     if (!accept && ph == PH_ZOOM) {
-      const int steps = H->ls_steps + 1;
+      const int steps = h.ls_steps + 1;
       if (steps > LS_MAX_STEPS || fabs(ahi - alo) <= 1e-14 * fmax(1.0, fabs(alo))) {
         if (alo > 0.0 && flo < f0) {
           // accept the best sufficient-decrease point of the bracket: re-evaluate there
@@ -205,19 +208,17 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
           new_trial = true;
         } else {
           restart = true;
-          if (tid == 0) H->resets += 1;
+          h.resets += 1;
         }
       } else {
         alpha = cubic_step(alo, flo, dlo, ahi, fhi, dhi);
         new_trial = true;
       }
     }
-    if (tid == 0) {
-      H->phase = ph;
-      H->a_lo = alo; H->f_lo = flo; H->d_lo = dlo;
-      H->a_hi = ahi; H->f_hi = fhi; H->d_hi = dhi;
-      if (new_trial) H->ls_steps += 1;
-    }
+    h.phase = ph;
+    h.a_lo = alo; h.f_lo = flo; h.d_lo = dlo;
+    h.a_hi = ahi; h.f_hi = fhi; h.d_hi = dhi;
+    if (new_trial) h.ls_steps += 1;
     if (accept) {
       // s = theta_t - x, y = g_t - g_x; push when curvature is positive
       for (int i = tid; i < P; i += NT) {
@@ -253,13 +254,9 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
         F.x[i] = th_t[i];
         gx[i] = gt[i];
       }
-      if (tid == 0) {
-        H->df = H->f - f_t;
-        H->f = f_t;
-        H->iter += 1;
-        H->hist_n = hn;
-        H->hist_head = head;
-      }
+      h.df = h.f - f_t;
+      h.f = f_t;
+      h.iter += 1;
       __syncthreads();
     }
   }
@@ -267,10 +264,6 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
   if (accept || restart) {
     if (restart) {
       hn = 0;
-      if (tid == 0) {
-        H->hist_n = 0;
-        H->hist_head = 0;
-      }
       head = 0;
     }
     __syncthreads();
@@ -279,38 +272,35 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
       hn = 0;
       head = 0;
       d0 = lbfgs_direction<NT>(F, P, 0, 0, gx, q, r, pd, Sl, Yl, rho, gam, alph, D, fr, red);
-      if (tid == 0) {
-        H->hist_n = 0;
-        H->hist_head = 0;
-      }
     }
     const double edm = -0.5 * d0;
     int st = FIT_RUNNING;
-    const bool small_step = H->iter > 0 && H->df < fmax(H->edm_tol, 1e-15 * fabs(H->f));
-    if (!(d0 < 0.0) || (edm < H->edm_tol && small_step)) st = FIT_CONVERGED;
-    else if (H->iter >= H->max_iter) st = FIT_MAXITER;
-    else if (H->resets > 3) st = FIT_LSFAIL;
+    const bool small_step = h.iter > 0 && h.df < fmax(h.edm_tol, 1e-15 * fabs(h.f));
+    if (!(d0 < 0.0) || (edm < h.edm_tol && small_step)) st = FIT_CONVERGED;
+    else if (h.iter >= h.max_iter) st = FIT_MAXITER;
+    else if (h.resets > 3) st = FIT_LSFAIL;
     for (int i = tid; i < P; i += NT) {
       F.g[i] = gx[i];
       F.p[i] = pd[i];
       F.theta_next[i] = F.x[i] + pd[i];
     }
-    if (tid == 0) {
-      H->edm = edm;
-      H->dphi0 = d0;
-      H->alpha = 1.0;
-      H->phase = PH_BRACKET;
-      H->ls_steps = 0;
-      H->a_prev = 0.0;
-      H->f_prev = H->f;
-      H->d_prev = d0;
-      H->status = st;
-    }
+    h.edm = edm;
+    h.dphi0 = d0;
+    h.alpha = 1.0;
+    h.phase = PH_BRACKET;
+    h.ls_steps = 0;
+    h.a_prev = 0.0;
+    h.f_prev = h.f;
+    h.d_prev = d0;
+    h.status = st;
   } else if (new_trial) {
     for (int i = tid; i < P; i += NT) F.theta_next[i] = F.x[i] + alpha * pd[i];
-    if (tid == 0) H->alpha = alpha;
+    h.alpha = alpha;
   }
+  h.hist_n = hn;
+  h.hist_head = head;
   __syncthreads();
+  if (tid == 0) *H = h;
 }
 
 }  // namespace nufold
