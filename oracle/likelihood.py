@@ -82,15 +82,30 @@ def nll(model, events, data, theta, folds=None):
     return nll_from_mu(model, mus, ok, data, theta)
 
 
-def nll_grad(model, events, data, theta, folds=None):
-    """(NLL, gradient) with the complex-step gradient."""
+def prior_curvature(model):
+    """Diagonal of the priors' second derivatives: 1/sigma^2 and diag(V^-1)."""
+    c = np.zeros(model.P)
+    for i, mean, sigma in model.gauss:
+        c[i] += 1.0 / sigma ** 2
+    for idx, mean, cov in model.blocks:
+        c[np.asarray(idx)] += np.diag(np.linalg.inv(cov))
+    return c
+
+
+def nll_grad(model, events, data, theta, folds=None, fisher=False):
+    """(NLL, gradient) with the complex-step gradient. With fisher=True also
+    the diagonal of the Fisher information of the Poisson bins plus the prior
+    curvature, F_jj = sum_i (dmu_i/dtheta_j)^2 / mu_i + prior, whose
+    derivatives of mu come from the same complex steps (returned third)."""
     theta = np.asarray(theta, dtype=np.float64)
     if folds is None:
         folds = fold_all(model, events, theta)
-    f0 = nll(model, events, data, theta, folds)
+    mus0, ok0 = expected(model, events, theta, folds)
+    f0 = nll_from_mu(model, mus0, ok0, data, theta)
     g = np.zeros(model.P)
+    F = prior_curvature(model) if fisher else None
     if not np.isfinite(f0):
-        return f0, g
+        return (f0, g, F) if fisher else (f0, g)
     for j in range(model.P):
         th = theta.astype(np.complex128)
         th[j] += 1j * H_STEP
@@ -99,8 +114,13 @@ def nll_grad(model, events, data, theta, folds=None):
                   for ds, ev in zip(model.datasets, events)]
         else:
             fj = folds
-        g[j] = np.imag(nll(model, events, data, th, fj)) / H_STEP
-    return float(f0), g
+        mus, ok = expected(model, events, th, fj)
+        g[j] = np.imag(nll_from_mu(model, mus, ok, data, th)) / H_STEP
+        if fisher:
+            for mu0, mu in zip(mus0, mus):
+                dmu = np.imag(mu) / H_STEP
+                F[j] += np.sum(dmu ** 2 / np.real(mu0))
+    return (float(f0), g, F) if fisher else (float(f0), g)
 
 
 def saturated_statistic(nll_min):

@@ -9,6 +9,7 @@ import pytest
 from oracle.model import Model
 from oracle import likelihood as LK
 from paper_2502_15253_amd import synth
+import gradcheck
 
 pytestmark = pytest.mark.gpu
 
@@ -34,9 +35,10 @@ def test_backward_matches_oracle_gradient_and_finite_differences():
     y = f(x)
     (3.0 * y).backward()
     g = x.grad.cpu().numpy() / 3.0
-    f_o, g_o = LK.nll_grad(m, events, data, th)
+    f_o, g_o, F = LK.nll_grad(m, events, data, th, fisher=True)
     assert abs(y.item() - f_o) <= 1e-9 * max(1.0, abs(f_o))
     assert np.max(np.abs(g - g_o)) <= 1e-9 * max(1.0, np.max(np.abs(g_o)))
+    gradcheck.check(g, g_o, F, 1e-9, "autograd c3 m64", m.names)
     # central differences of the operation itself (h = 1e-6) on a few parameters
     for name in ("osc.dm2_31", "osc.sin2_t13", "norm", "escale.c1", "flux[40]"):
         i = m.index[name]

@@ -9,6 +9,8 @@ from oracle.model import Model
 from oracle import likelihood as LK
 from paper_2502_15253_amd import nufold as nf
 from paper_2502_15253_amd import synth
+import gradcheck
+from test_parity_gpu import GRAD_TOL
 
 pytestmark = pytest.mark.gpu
 TOL = {"m64": 1e-9, "m32": 1e-5}
@@ -70,9 +72,10 @@ def test_eval_batch_matches_oracle(mode, config, B, nev):
     folds = None
     for f in range(B):
         dat = split(desc, data[didx[f]])
-        f_o, g_o = LK.nll_grad(m, events, dat, thetas[f])
+        f_o, g_o, F = LK.nll_grad(m, events, dat, thetas[f], fisher=True)
         assert abs(nll[f] - f_o) <= tol * max(1.0, abs(f_o)), (f, nll[f], f_o)
         assert np.max(np.abs(grad[f] - g_o)) <= tol * max(1.0, np.max(np.abs(g_o))), f
+        gradcheck.check(grad[f], g_o, F, GRAD_TOL[mode], f"batch c{config} {mode} fit {f}", m.names)
         if config == 3 and f >= 1:
             break  # the oracle gradient at 1e6 events is slow; two fits suffice
 
@@ -161,9 +164,10 @@ def test_batched_fold_tiles_give_the_same_results(mode):
         if ref is None:
             ref = (nll, g)
             for f in (0, 5, 10):
-                f_o, g_o = LK.nll_grad(m, events, split(desc, data[didx[f]]), th[f])
+                f_o, g_o, F = LK.nll_grad(m, events, split(desc, data[didx[f]]), th[f], fisher=True)
                 assert abs(nll[f] - f_o) <= TOL[mode] * max(1.0, abs(f_o))
                 assert np.max(np.abs(g[f] - g_o)) <= TOL[mode] * max(1.0, np.max(np.abs(g_o)))
+                gradcheck.check(g[f], g_o, F, GRAD_TOL[mode], f"tile {ft} {mode} fit {f}", m.names)
         else:
             assert np.max(np.abs(nll - ref[0])) <= 1e-13 * max(1.0, np.max(np.abs(ref[0]))), ft
             assert np.max(np.abs(g - ref[1])) <= 1e-12 * max(1.0, np.max(np.abs(ref[1]))), ft
