@@ -172,7 +172,15 @@ int nf_expected(nf_ctx* ctx, const double* theta, double* mu);
  * with 0 each source adds its rows with device-scope atomic adds (no waiting
  * at the end of the fold; the order of those additions, and so the last bits
  * of the result, may vary between runs). "timing" (0/1) turns per-kernel event
- * timing on or off (see nf_timing). Returns NF_EINVAL for unknown keys/values.
+ * timing on or off (see nf_timing). "stage_cache" (0/1, default 0): with 1,
+ * the host-pointer evaluations (nf_eval_nll, nf_eval_nll_grad, nf_expected)
+ * skip the event fold when the oscillation parameters and every source-norm
+ * parameter equal those of the previous such evaluation (exact equality) and
+ * reuse its fine-bin spectra; only the bin stages run (paper: stages are
+ * recomputed only when the parameters they depend on change, "Structure of
+ * the framework"). Results are those of a full evaluation. Other entry points
+ * clear the kept spectra before they run. Returns NF_EINVAL for unknown
+ * keys/values.
  */
 int nf_set_option(nf_ctx* ctx, const char* key, int64_t value);
 

@@ -176,6 +176,12 @@ struct nf_ctx {
   int deterministic = 0;  // fine-bin rows by ordered hand-off (1) or atomic adds (0)
   int batch_tile = FOLD_FT;  // fits per wavefront tile of the batched fold
   int max_lds = 65536;       // LDS bytes one workgroup may use on this device
+  // stage cache of the host evaluation path (option "stage_cache"): the fold
+  // depends only on the oscillation parameters and the source norms, so an
+  // evaluation whose values of those equal the last fold's reuses its rows
+  int stage_cache = 0;
+  bool rows_kept = false;            // bin rows 0..4 hold the fold of cache_key (not cleared)
+  std::vector<double> cache_key;
   // minimiser buffers (allocated at the first fit) and the captured iteration graph
   int fit_m = 8;
   DevBuf<FitHeader> f_hdr;
@@ -514,7 +520,7 @@ void parse_model(nf_ctx* c, const char* text) {
       q.blob = (int)dp.size();
       q.blob_n = B.total;
       dp.insert(dp.end(), blob.begin(), blob.end());
-      pl.max_blob = std::max(pl.max_blob, B.total);
+      pl.max_blob = std::max(pl.max_blob, B.hpart);
     }
     // per global fine bin: first segment, stride, sources, first flat source
     pl.kt_info = (int)ip.size();
@@ -700,8 +706,29 @@ void drop_fit_graph(nf_ctx* c) {
   c->ev_n = 0;
 }
 
+// The fold's inputs among the parameters: oscillation slots and every norm
+// parameter of every source (the fold applies the source norms).
+std::vector<double> fold_key(const nf_ctx* c, const double* theta) {
+  std::vector<double> k;
+  for (int j = 0; j < NSLOT; ++j)
+    if (c->osc.slot_param[j] >= 0) k.push_back(theta[c->osc.slot_param[j]]);
+  for (const auto& d : c->ds)
+    for (const auto& nl : d.srcnorm)
+      for (int q : nl) k.push_back(theta[q]);
+  return k;
+}
+
+// Every path except the cached host evaluation expects the fold kernel's
+// accumulation rows to be zero at launch: clear rows that were kept.
+void release_rows(nf_ctx* c) {
+  if (!c->rows_kept) return;
+  hip_check(launch_zero(c->d_bin.p, 6 * (int64_t)std::max(1, c->plan.KT), c->stream), "zero launch");
+  c->rows_kept = false;
+}
+
 void rebuild_events(nf_ctx* c) {
   drop_fit_graph(c);
+  c->rows_kept = false;  // the rows are cleared below
   c->bt_cap = 0;  // batch partials depend on the work-item count
   std::vector<int> seg_item(c->plan.G + 1, 0);
   std::vector<double> Wseg(c->plan.G, 0.0);
@@ -889,7 +916,8 @@ FitArgs fit_args(nf_ctx* c) {
 }
 
 void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* status_dev, double* mu_dev,
-                  int want_nll, int want_grad, bool fit = false, bool timed = true) {
+                  int want_nll, int want_grad, bool fit = false, bool timed = true, bool reuse_fold = false,
+                  bool keep_rows = false) {
   FoldArgs fa{};
   fa.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
   fa.w = c->d_w.p;
@@ -924,6 +952,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   ta.bin = c->d_bin.p;
   ta.want_grad = want_grad;
   ta.want_nll = want_nll;
+  ta.keep_rows = keep_rows ? 1 : 0;
   if (fit) {
     ta.has_fit = 1;
     ta.fit = fit_args(c);
@@ -941,8 +970,16 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
     }
     ev = c->tev[c->tcount++].data();
   }
-  hip_check(launch_fold(c->mode, fa, c->fold_block, c->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr),
-            "fold launch");
+  if (reuse_fold) {
+    // the rows of the last fold are still in place: no fold launch
+    if (ev) {
+      hip_check(hipEventRecord(ev[0], c->stream), "hipEventRecord");
+      hip_check(hipEventRecord(ev[1], c->stream), "hipEventRecord");
+    }
+  } else {
+    hip_check(launch_fold(c->mode, fa, c->fold_block, c->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr),
+              "fold launch");
+  }
   hip_check(launch_tail(ta, c->tail_threads, c->stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr),
             "tail launch");
 }
@@ -959,8 +996,20 @@ int eval_host(nf_ctx* c, const double* theta, double* nll, double* grad, double*
   std::memcpy(h_theta, theta, sizeof(double) * c->P);
   hip_check(hipMemcpyAsync(c->d_theta.p, h_theta, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream),
             "theta H2D");
+  bool reuse = false;
+  if (c->stage_cache) {
+    std::vector<double> key = fold_key(c, theta);
+    reuse = c->rows_kept && key == c->cache_key;
+    if (!reuse) {
+      release_rows(c);
+      c->cache_key.swap(key);
+    }
+  } else {
+    release_rows(c);
+  }
   enqueue_eval(c, c->d_theta.p, c->d_out.p, c->d_status.p, mu ? c->d_mu.p : nullptr, want_nll ? 1 : 0,
-               grad ? 1 : 0);
+               grad ? 1 : 0, false, true, reuse, c->stage_cache != 0);
+  if (c->stage_cache) c->rows_kept = true;
   if (want_nll)
     hip_check(hipMemcpyAsync(h_out, c->d_out.p, sizeof(double) * (grad ? 1 + c->P : 1), hipMemcpyDeviceToHost,
                              c->stream), "out D2H");
@@ -1062,6 +1111,7 @@ int fit_impl(nf_ctx* c, const double* start, const uint8_t* fixed, const nf_fit_
   hip_check(hipMemcpyAsync(c->f_d2.p, d2.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
   hip_check(hipMemcpyAsync(c->f_fr.p, fr.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream), "H2D");
   hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  release_rows(c);
   ensure_fit_graph(c);
   const int64_t max_evals = (int64_t)max_iter * 50 + 200;
   for (int64_t launched = 0;; launched += FIT_CHUNK) {
@@ -1233,6 +1283,7 @@ struct EventPair {
 
 // mean device time of one evaluation (fold + bin stages + NLL + gradient) at d_theta
 double time_single(nf_ctx* c, int n) {
+  release_rows(c);
   EventPair ev;
   for (int i = 0; i < 2; ++i) enqueue_eval(c, c->d_theta.p, c->d_out.p, c->d_status.p, nullptr, 1, 1);
   hip_check(hipEventRecord(ev.a, c->stream), "hipEventRecord");
@@ -1679,6 +1730,7 @@ int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev, int32_
   return guarded(ctx, [&] {
     require_ready(ctx, true);
     if (!theta_dev || !out_dev) fail(NF_EINVAL, "null device pointer");
+    release_rows(ctx);
     enqueue_eval(ctx, theta_dev, out_dev, status_dev, nullptr, 1, want_grad ? 1 : 0);
     return NF_OK;
   });
@@ -1691,6 +1743,7 @@ int nf_eval_device_many(nf_ctx* ctx, int n, const double* theta_dev, double* out
     if (n < 1 || n > NF_MAX_GRAPH_EVALS) fail(NF_EINVAL, "n must be in 1.." + std::to_string(NF_MAX_GRAPH_EVALS));
     if (!theta_dev || !out_dev) fail(NF_EINVAL, "null device pointer");
     nf_ctx* c = ctx;
+    release_rows(c);
     const int g = want_grad ? 1 : 0;
     if (!(c->ev_graph && c->ev_n == n && c->ev_grad == g && c->ev_theta == theta_dev && c->ev_out == out_dev &&
           c->ev_status == status_dev)) {
@@ -1760,6 +1813,10 @@ int nf_set_option(nf_ctx* ctx, const char* key, int64_t value) {
     } else if (k == "timing") {
       ctx->timing = value ? 1 : 0;
       ctx->tcount = 0;
+    } else if (k == "stage_cache") {
+      if (value != 0 && value != 1) fail(NF_EINVAL, "stage_cache must be 0 or 1");
+      ctx->stage_cache = (int)value;
+      if (!value) release_rows(ctx);
     } else {
       fail(NF_EINVAL, "unknown option '" + k + "'");
     }
@@ -1778,6 +1835,7 @@ int nf_get_option(nf_ctx* ctx, const char* key, int64_t* value) {
     else if (k == "batch_fit_tile") *value = ctx->batch_tile;
     else if (k == "deterministic") *value = ctx->deterministic;
     else if (k == "timing") *value = ctx->timing;
+    else if (k == "stage_cache") *value = ctx->stage_cache;
     else fail(NF_EINVAL, "unknown option '" + k + "'");
     return NF_OK;
   });

@@ -104,6 +104,7 @@ struct EvalIO {
   double* Sseg;         // G
   double* bin;          // 6 KT
   int fused;            // bin rows 0..4 and Sseg come from the fold kernel; row 5 (1 + F) is formed here
+  int keep_rows;        // fused: leave rows 0..4 in place for a later evaluation that reuses the fold
 };
 
 // Single evaluation: one workgroup, after the fold kernel has written Sseg and
@@ -120,6 +121,8 @@ struct TailArgs {
   int want_grad;
   int want_nll;         // 0: only mu_out (no data needed)
   int has_fit;          // run the minimiser step after the evaluation
+  int keep_rows;        // leave bin rows 0..4 in place (stage cache: a later evaluation
+                        // with the same fold parameters reuses them without a fold)
   FitArgs fit;
   const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
 };
@@ -148,13 +151,16 @@ struct BatchTailArgs {
 constexpr int ST_DOMAIN = 1;
 constexpr int MAX_BKG = 8;  // backgrounds per dataset
 
+// Reduction scratch of the bin stages' block sums (32 values x 4 rows per
+// wavefront, then the totals).
+__host__ __device__ constexpr int red_doubles(int nt) { return 32 * 4 * (nt / 64) + 32; }
+
 // Dynamic LDS bytes used by the bin-stage kernel for a plan (matches carve()).
 __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
-  const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
-  const size_t nd = 3 + 2 * (size_t)p.P + 40 + (size_t)p.D * DSPLAN_DOUBLES + (size_t)nt + 16 + 6 * K +
-                    (size_t)p.max_S * K + Nb +
-                    4 * (K + 1) + K + 3 * E + Nb + p.max_blob;
-  const size_t ni = E + 2 + K + 3;
+  const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb, BN = (size_t)p.max_B * p.max_Nb;
+  const size_t nd = 3 + 2 * (size_t)p.P + 40 + (size_t)p.D * DSPLAN_DOUBLES + red_doubles(nt) + 5 * K +
+                    (size_t)p.max_S * K + Nb + 3 * K + 2 * Nb + 2 * BN + 2 * E + p.NR + p.max_blob;
+  const size_t ni = E + K + 2 + BN + p.NR + 2;
   return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }
 
@@ -165,5 +171,7 @@ hipError_t launch_tail(const TailArgs& a, int nt, hipStream_t stream, hipEvent_t
                        hipEvent_t stop = nullptr);
 hipError_t tail_set_lds_limit(size_t bytes);
 hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream);
+// n doubles set to zero by a plain fill kernel (usable inside captured graphs).
+hipError_t launch_zero(double* p, int64_t n, hipStream_t stream);
 
 }  // namespace nufold

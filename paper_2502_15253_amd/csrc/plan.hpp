@@ -85,30 +85,36 @@ struct DsPlan {
 static_assert(sizeof(DsPlan) % sizeof(double) == 0, "DsPlan is copied as doubles");
 constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
 
-// Per-dataset static inputs of the bin stages, packed contiguously so one
-// batched copy stages them in LDS. Offsets count doubles; the integer arrays
-// (brt .. nli, frow, fpar) hold 32-bit integers, two per double slot.
+// Per-dataset static inputs of the bin stages, packed contiguously. Offsets
+// count doubles; the integer arrays hold 32-bit integers, two per double
+// slot. The first hpart doubles (flux modes by column, source norm lists) are
+// what the stages read from LDS, copied there in one batch; the rest (edges,
+// background templates, flux basis by fine bin) is read once per evaluation
+// straight from global memory.
 struct BlobLayout {
-  int edges, tmpl, mdc, bsc, brt, shp, mdcol, mdk, mdp, nlp, nli, frow, fpar, fcf, total;
+  int mdc, mdcol, mdk, mdp, nlp, nli, hpart;
+  int edges, tmpl, bsc, fcf, frow, fpar, brt, shp, total;
 };
 __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K) {
   auto ints = [](int n) { return (n + 1) / 2; };  // double slots for n int32 values
   BlobLayout L;
   int o = 0;
+  L.mdc = o; o += nnz;           // flux basis by mode (CSC): coefficients,
+  L.mdcol = o; o += ints(M + 1);  // column pointers,
+  L.mdk = o; o += ints(nnz);      // fine bin of each entry,
+  L.mdp = o; o += ints(M);        // parameter of each mode
+  L.nlp = o; o += ints(S + 1);    // norm list of each source: pointers,
+  L.nli = o; o += ints(nl);       // parameter indices
+  o += o & 1;                     // the global part starts 16-byte aligned
+  L.hpart = o;
   L.edges = o; o += E;
   L.tmpl = o; o += B * Nb;
-  L.mdc = o; o += nnz;
   L.bsc = o; o += B;
-  L.fcf = o; o += nnz;          // flux basis by fine bin (CSR): coefficient of each entry,
-  L.frow = o; o += ints(K + 1);  // row pointers and
-  L.fpar = o; o += ints(nnz);    // parameter index of each entry
+  L.fcf = o; o += nnz;            // flux basis by fine bin (CSR): coefficients,
+  L.frow = o; o += ints(K + 1);   // row pointers,
+  L.fpar = o; o += ints(nnz);     // parameter of each entry
   L.brt = o; o += ints(B);
   L.shp = o; o += ints(B * Nb);
-  L.mdcol = o; o += ints(M + 1);
-  L.mdk = o; o += ints(nnz);
-  L.mdp = o; o += ints(M);
-  L.nlp = o; o += ints(S + 1);
-  L.nli = o; o += ints(nl);
   L.total = o;
   return L;
 }
@@ -126,7 +132,7 @@ struct DevPlan {
   int seg_fs;            // ipool: G flat source index of each segment
   int kt_ds;             // ipool: KT dataset index of each global fine bin
   int fs_ptr;            // ipool: 2 FS, [begin, end) absolute ipool offsets of each source's norm list
-  int max_blob;          // largest static blob
+  int max_blob;          // largest LDS part (hpart) of a static blob
   int fit_m;             // minimiser history length (LDS is reserved for it)
   int kt_info;           // ipool: 5 KT: first segment, stride K, sources S, first flat source, kt0
   int fs_nl;             // ipool: NLMAX FS norm-list parameter indices per flat source (-1 padded)

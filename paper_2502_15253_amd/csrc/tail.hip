@@ -7,70 +7,90 @@
 // sums the fold's partial moments itself (phase A, one thread per segment,
 // then per fine bin).
 //
-// Serial part (one workgroup; bin stages are latency-bound), per dataset
-// (paper, "Structure of the framework", steps 2 and 3, and Eq. 3-6, 9):
-//   Hs[k] = sum_s A_s S[s][k],  H[k] = Hs[k] (1 + F_k)
-//   m_k = H_k/w, d_k = harmonic mean of neighbouring m (ends: m_0, m_{K-1}),
-//   C(y) = C_k + w [d_k (t - t^2/2) + d_{k+1} t^2/2 + 6 (m_k - (d_k+d_{k+1})/2)(t^2/2 - t^3/3)]
-//   X_i = C(g(x_i)),  g = inverse of f(E) = c0 + (1+c1) E + c2 E^2
-//   s_i = X_{i+1} - X_i,  mu_i = s_i + sum_b scale_b R_b T_bi (1 + beta_bi)
-//   NLL += sum_i [mu - n + n ln(n/mu)]   (n = 0: mu)
-// then the prior rows. A dataset's static inputs (one packed blob) and its
-// dynamic inputs are staged in LDS with two batched copies.
+// Forward (paper, "Structure of the framework", steps 2 and 3; Eq. 3-6, 9):
+//   H_k = Hs_k (1 + F_k),  m_k = H_k / w,
+//   d_k = harmonic mean of m_{k-1}, m_k (ends: d_0 = m_0, d_K = m_{K-1}),
+//   in fine bin k, t in [0, 1]: rho(t) = d_k (1-t) + d_{k+1} t + 6 (m_k - (d_k+d_{k+1})/2) t (1-t),
+//   whose integral from the bin's lower edge is
+//   P_k(t) = w [d_k (t - t^2/2) + d_{k+1} t^2/2 + 6 (m_k - (d_k+d_{k+1})/2)(t^2/2 - t^3/3)],
+//   P_k(1) = H_k (area conserving). The analysis edge x_i maps to y_i = g(x_i),
+//   g the inverse of f(E) = c0 + (1+c1) E + c2 E^2, in fine bin k_i at t_i.
+//   The signal of analysis bin i is the integral of the spline between its
+//   mapped edges, taken locally: with kk = k clamped to [0, K] and the piece
+//   p = P_k(t) for an edge inside the fine range (0 outside),
+//     s_i = sum_{k = kk_i}^{kk_{i+1} - 1} H_k + p_{i+1} - p_i,
+//   which equals C(y_{i+1}) - C(y_i) for the cumulative C of the spline, so
+//   no prefix sum over the fine bins is needed.
+//   mu_i = s_i + sum_b R_b T_bi (1 + beta_bi),  NLL += mu - n + n ln(n/mu)  (n = 0: mu),
+//   then the prior rows.
 //
-// Reverse pass (exact adjoint; replaces numerical gradients):
-//   lambda_mu = 1 - n/mu -> background rates and shapes; lambda_X from
-//   s_i = X_{i+1} - X_i; each X_i depends on C_k, m_k, d_k, d_{k+1} of its
-//   fine bin and on y = g(x; c) (energy-scale coefficients, dC/dy = rho);
-//   C_k = sum_{j<k} H_j gives a suffix sum; d_k depends on m_{k-1}, m_k;
-//   lambda_H -> flux modes, source norms, and, through the forward-mode
-//   derivative rows of the fold moments, the oscillation parameters.
+// Reverse pass (exact adjoint; replaces numerical gradients), with
+// lambda_i = dNLL/dmu_i = 1 - n_i/mu_i:
+//   background rates and shapes from lambda_i directly;
+//   energy scale: ds_i/dc = rho(t_{i+1}) dy_{i+1}/dc - rho(t_i) dy_i/dc,
+//     dy/dc_j = -(1, y, y^2)_j / f'(y);
+//   fine bin k gathers lambda of the one analysis bin that covers it whole
+//   (dH direct) and, from the edges inside fine bins k-1, k, k+1 (weights
+//   lambda_{j-1} - lambda_j), the adjoints of m_k, d_k and d_{k+1}; d depends
+//   on the neighbouring m by the harmonic mean;
+//   lambda_H -> flux modes (lambda_F = lambda_H Hs), and lambda_Hs =
+//   lambda_H (1 + F) -> source norms (sum_k lambda_Hs S[s][k]) and, through the
+//   fold's forward-mode derivative rows, the oscillation parameters.
 //
-// All arithmetic is FP64. Gradient contributions are gathered in a fixed
-// order except where contributions can hit one shared parameter within a
-// phase (LDS atomics), which only affects the last bits.
+// Work per dataset, one workgroup: a parameter pass (1 + F per fine bin,
+// mapped edges and backgrounds, read straight from global memory while the
+// fold's rows are being copied into LDS), one pass over the analysis bins, one
+// over the fine bins, one block reduction of every summed gradient, one pass
+// over the flux modes and source norms: four barriers besides the reduction's.
+//
+// All arithmetic is FP64. Sums over threads are taken in a fixed order; the
+// few gradient entries that several threads of one pass can reach (a norm
+// shared by sources, a parameter with two prior rows) use LDS atomic adds,
+// which only affects the last bits.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <algorithm>
 
 #include "kernels.hpp"
 #include "osc.hpp"
 
 namespace nufold {
 
-
 template <int NT>
 struct Lds {
   double* th;     // P
   double* grad;   // P
   double* coef;   // 40
-  DsPlan* dsl;    // D dataset plans (copied from global memory once per launch)
-  double* red;    // reduction scratch
-  double* dyn;    // 6K + S*K + Nb: Hs, G0..G3, F1, Ss (per-source spectra), observed counts
+  DsPlan* dsl;    // D dataset plans
+  double* red;    // block reduction scratch (red_doubles)
+  double* dyn;    // copy target: Hs, G0..G3 (5 K), Ss (S K), observed counts (Nb)
   double* Hs;
-  double* Gs;     // 4K
-  double* F1;
+  double* Gs;     // 4 K
   double* Ss;
   double* nD;
-  double* D;      // K+1  edge densities
-  double* C;      // K+1  cumulative, later lambda_C, then lambda_H
-  double* Ld;     // K+1  lambda_d
-  double* Suf;    // K+1  suffix sums of lambda_C, later lambda_F
-  double* LH;     // K    H (scan input), lambda_m (direct), later lambda_Hs
-  double* eT;     // E    t, later e_m
-  double* eY;     // E    y, later e_dlo
-  double* eH;     // E    e_dhi
-  double* mu;     // Nb   lambda_mu
-  double* st;     // static blob of the current dataset (edges become X, then lambda_X)
+  double* F1;     // K     1 + F (parameter pass)
+  double* LF;     // K     lambda_F
+  double* LHs;    // K     lambda_Hs
+  double* lam;    // Nb    lambda_mu
+  double* Bv;     // Nb    background expectation
+  double* bkr;    // B Nb  dmu_i/dR_b
+  double* bks;    // B Nb  dmu_i/dbeta_bi
+  double* eT;     // E     t of each mapped edge
+  double* eY;     // E     y of each mapped edge
+  double* prv;    // NR    gradient contribution of each prior row
+  double* st;     // copy target: the flux-mode and norm-list part of the static blob
   double* fit;    // minimiser scratch
-  int* kidx;      // E    fine bin of each mapped analysis edge (monotone)
-  int* first;     // K+3  first[k + 1] = first edge with kidx >= k, k = -1 .. K+1
+  int* ek;        // E     fine bin of each mapped edge: -1 below y_0, K at or above y_K
+  int* first;     // K + 2 first[q] = first edge whose clamped fine bin is >= q (E: none)
+  int* bki;       // B Nb  shape parameter of (b, i), or -1
+  int* pri;       // NR    parameter of each prior row
   int* flag;      // 2
 };
 
 template <int NT>
 __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   Lds<NT> L;
-  const int K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
+  const int K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb, BN = p.max_B * p.max_Nb;
   // regions filled by direct copies start at 16-byte boundaries (even offsets)
   auto al = [](double* x) { return x + (reinterpret_cast<uintptr_t>(x) & 8 ? 1 : 0); };
   double* q = base;
@@ -79,70 +99,65 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.coef = q; q += 40;
   q = al(q);
   L.dsl = reinterpret_cast<DsPlan*>(q); q += p.D * DSPLAN_DOUBLES;
-  L.red = q; q += NT + 16;
+  L.red = q; q += red_doubles(NT);
   q = al(q);
-  L.dyn = q; q += 6 * K + p.max_S * K + Nb;
-  L.D = q; q += K + 1;
-  L.C = q; q += K + 1;
-  L.Ld = q; q += K + 1;
-  L.Suf = q; q += K + 1;
-  L.LH = q; q += K;
+  L.dyn = q; q += 5 * K + p.max_S * K + Nb;
+  L.F1 = q; q += K;
+  L.LF = q; q += K;
+  L.LHs = q; q += K;
+  L.lam = q; q += Nb;
+  L.Bv = q; q += Nb;
+  L.bkr = q; q += BN;
+  L.bks = q; q += BN;
   L.eT = q; q += E;
   L.eY = q; q += E;
-  L.eH = q; q += E;
-  L.mu = q; q += Nb;
+  L.prv = q; q += p.NR;
   q = al(q);
   L.st = q; q += p.max_blob;
-
   L.fit = q; q += fit_lds_doubles(p.P, p.fit_m);
   int* r = reinterpret_cast<int*>(q);
-  L.kidx = r; r += E;
-  L.first = r; r += K + 3;
+  L.ek = r; r += E;
+  L.first = r; r += K + 2;
+  L.bki = r; r += BN;
+  L.pri = r; r += p.NR;
   L.flag = r;
-  L.Hs = L.Gs = L.F1 = L.Ss = L.nD = nullptr;
+  L.Hs = L.Gs = L.Ss = L.nD = nullptr;
   return L;
 }
 
-// Launch prologue: parameters into LDS, gradient cleared, and the dataset
-// plans copied to LDS so every later stage reads them without a global round
-// trip. The caller synchronises.
-template <int NT>
-__device__ __forceinline__ void load_params(const DevPlan& p, const double* th, Lds<NT>& L) {
-  const int tid = threadIdx.x;
-  for (int i = tid; i < p.P; i += NT) {
-    L.th[i] = th[i];
-    L.grad[i] = 0.0;
-  }
-  const double* src = reinterpret_cast<const double*>(p.ds);
-  double* dst = reinterpret_cast<double*>(L.dsl);
-  for (int i = tid; i < p.D * DSPLAN_DOUBLES; i += NT) dst[i] = src[i];
-}
-
-// Sum of N values (N <= 16) over the workgroup; every thread gets the
-// totals, summed in a fixed order. Each wavefront reduce-scatters the values
-// over its 16-lane rows (padded to a power of two), one lane per (value, row)
-// writes its row total to red[j * 4 NW + row], then thread j adds the 4 NW
-// row totals of value j in order. red holds NT + 16 doubles; the totals sit
-// at red[NT + j], past every partial, so back-to-back calls do not overlap.
-template <int NT, int N>
-__device__ __forceinline__ void block_sum(double* v, double* red) {
-  constexpr int NW = NT / 64, R = 4 * NW;
-  static_assert(N >= 1 && N <= 16, "reduction scratch too small");
-  constexpr int NP = N <= 1 ? 1 : N <= 2 ? 2 : N <= 4 ? 4 : N <= 8 ? 8 : 16;
+// Sum of N values (N <= 32) over the workgroup; every thread gets the
+// totals, summed in a fixed order. Each wavefront reduce-scatters the values,
+// sixteen at a time, over its 16-lane rows (padded to a power of two), one
+// lane per (value, row) writes its row total to red[j * 4 NW + row], then
+// four lanes per value each add a quarter of the 4 NW row totals of value j
+// in order and combine them by two quad exchanges. The totals sit at
+// red[32 * 4 NW + j], past every partial, so back-to-back calls do not
+// overlap.
+template <int NP>
+__device__ __forceinline__ void row_partials(const double* v, int n, double* red, int R, int wid, int lane) {
   constexpr int LG = NP == 1 ? 0 : NP == 2 ? 1 : NP == 4 ? 2 : NP == 8 ? 3 : 4;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double c[NP];
 #pragma unroll
-  for (int j = 0; j < NP; ++j) c[j] = j < N ? v[j] : 0.0;
+  for (int j = 0; j < NP; ++j) c[j] = j < n ? v[j] : 0.0;
   const double x = row_reduce_scatter<NP>(c, lane);
   if (((lane & 15) >> LG) == 0) {
     int j = 0;
     if constexpr (LG > 0) j = (int)(__builtin_bitreverse32((unsigned)lane) >> (32 - LG));
     red[j * R + wid * 4 + (lane >> 4)] = x;
   }
+}
+
+template <int NT, int N>
+__device__ __forceinline__ void block_sum(double* v, double* red) {
+  constexpr int NW = NT / 64, R = 4 * NW;
+  static_assert(N >= 1 && N <= 32, "reduction scratch too small");
+  constexpr int N1 = N < 16 ? N : 16, N2 = N - N1;
+  constexpr int P1 = N1 <= 1 ? 1 : N1 <= 2 ? 2 : N1 <= 4 ? 4 : N1 <= 8 ? 8 : 16;
+  constexpr int P2 = N2 <= 1 ? 1 : N2 <= 2 ? 2 : N2 <= 4 ? 4 : N2 <= 8 ? 8 : 16;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  row_partials<P1>(v, N1, red, R, wid, lane);
+  if constexpr (N2 > 0) row_partials<P2>(v + 16, N2, red + 16 * R, R, wid, lane);
   __syncthreads();
-  // four lanes per value (4 N <= 64: all in wavefront 0), each summing a
-  // quarter of the R partials, then two quad exchanges; fixed order
   if (tid < 4 * N) {
     const int q = tid >> 2, part = tid & 3;
     double s = 0.0;
@@ -150,45 +165,11 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
     for (int k = 0; k < R / 4; ++k) s += red[q * R + part * (R / 4) + k];
     s += dpp_swap<0xB1>(s);  // quad_perm [1,0,3,2]
     s += dpp_swap<0x4E>(s);  // quad_perm [2,3,0,1]
-    if (part == 0) red[16 * R + q] = s;
+    if (part == 0) red[32 * R + q] = s;
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < N; ++j) v[j] = red[16 * R + j];
-}
-
-// out[i] = sum of x[j] for j < i (i = 0..n), or, with reverse, out[i] = sum of
-// x[j] for j > i (i = 0..n-1). Contiguous chunks per thread, fixed order.
-template <int NT>
-__device__ void block_scan(const double* x, double* out, int n, bool reverse, double* red) {
-  constexpr int NW = NT / 64;
-  const int per = (n + NT - 1) / NT;
-  const int lo = threadIdx.x * per;
-  const int hi = min(lo + per, n);
-  double s = 0.0;
-  for (int i = lo; i < hi; ++i) s += reverse ? x[n - 1 - i] : x[i];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const double v = wave_scan_incl(s);
-  if (lane == 63) red[wid] = v;
-  __syncthreads();
-  // the totals of the waves before this one, added in wave order
-  double pre = 0.0;
-  for (int w = 0; w < wid; ++w) pre += red[w];
-  double acc = pre + v - s;  // exclusive prefix of this thread's chunk
-  if (!reverse) {
-    for (int i = lo; i < hi; ++i) {
-      out[i] = acc;
-      acc += x[i];
-    }
-    if (hi == n && lo < hi) out[n] = acc;
-    if (n == 0 && threadIdx.x == 0) out[0] = 0.0;
-  } else {
-    for (int i = lo; i < hi; ++i) {
-      out[n - 1 - i] = acc;
-      acc += x[n - 1 - i];
-    }
-  }
-  __syncthreads();
+  for (int j = 0; j < N; ++j) v[j] = red[32 * R + j];
 }
 
 __device__ __forceinline__ double pval(const double* th, int idx, double dflt) {
@@ -267,42 +248,33 @@ __device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int 
   if (tail) dma_lds<NT, 4>(d + 8 * (head + body), s + 8 * (head + body), 8);
 }
 
-// Stage dataset d's inputs in LDS: the static blob, the fine-bin rows,
-// per-segment S and the data. Fused (single evaluation): rows 0..4 and S were
-// written by the fold kernel in an earlier launch, so every array is copied
-// straight into LDS with direct global-to-LDS loads; row 5 = 1 + F is formed
-// later from the blob's flux rows. Otherwise all six rows were written by this
-// workgroup's phase A with agent-scope stores and are read back with coherent
-// loads, U per thread in flight before the LDS writes. No barrier: the caller
-// synchronises.
+// Stage dataset d's inputs in LDS: the flux-mode and norm-list part of the
+// static blob, the fine-bin rows Hs, G0..G3, per-segment S and the data.
+// Fused (single evaluation): the rows and S were written by the fold kernel
+// in an earlier launch, so everything goes straight into LDS with direct
+// global-to-LDS loads. Otherwise the rows were written by this workgroup's
+// phase A with agent-scope stores and are read back with coherent loads, U
+// per thread in flight before the LDS writes. No wait, no barrier: the
+// caller waits and synchronises.
 template <int NT>
-__device__ __forceinline__ void stage_fused(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
-                                            int want_nll) {
-  const int K = ds.K;
-  const int n1 = 6 * K, n2 = n1 + ds.S * K;
-  copy_to_lds<NT>(L.st, p.dpool + ds.blob, ds.blob_n);
-  copy_to_lds<NT>(L.dyn, io.bin + 6 * (int64_t)ds.kt0, 5 * K);
-  copy_to_lds<NT>(L.dyn + n1, io.Sseg + ds.seg0, n2 - n1);
-  if (want_nll) copy_to_lds<NT>(L.dyn + n2, io.data + ds.data, ds.Nb);
-}
-
-template <int NT>
-__device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int d, int want_nll) {
-  const int tid = threadIdx.x;
-  const DsPlan& ds = L.dsl[d];
+__device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
+                                              int want_nll) {
   const int K = ds.K, Nb = ds.Nb, S = ds.S;
-  const int nbl = ds.blob_n;
-  const int n1 = 6 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
+  const BlobLayout BL = blob_layout(Nb + 1, ds.nbkg, Nb, ds.nnz, ds.M, S, ds.nl, K);
+  const int n1 = 5 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
+  if (io.fused) {
+    copy_to_lds<NT>(L.st, p.dpool + ds.blob, BL.hpart);
+    copy_to_lds<NT>(L.dyn, io.bin + 6 * (int64_t)ds.kt0, n1);
+    copy_to_lds<NT>(L.dyn + n1, io.Sseg + ds.seg0, n2 - n1);
+    if (want_nll) copy_to_lds<NT>(L.dyn + n2, io.data + ds.data, Nb);
+    return;
+  }
+  const int tid = threadIdx.x;
+  const int nbl = BL.hpart;
   const double* blob = p.dpool + ds.blob;
   const double* b = io.bin + 6 * (int64_t)ds.kt0;
   const double* sg = io.Sseg + ds.seg0;
   const double* dt = io.data + ds.data;
-  if (io.fused) {
-    // dataset 0 was staged with the parameters in the launch prologue
-    if (d > 0) stage_fused<NT>(p, io, L, ds, want_nll);
-    __builtin_amdgcn_s_waitcnt(0);
-    return;
-  }
   const int total = nbl + n3;
   constexpr int U = 16;
   for (int base = 0; base < total; base += NT * U) {
@@ -324,120 +296,148 @@ __device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io
   }
 }
 
+// Parameter pass of a dataset, read straight from global memory (theta and the
+// static blob), so that it overlaps the copies of the dataset's rows: 1 + F per
+// fine bin; the mapped analysis edges (fine bin, t, y); per analysis bin the
+// background expectation and its derivatives by rate and shape. It writes
+// only LDS regions that no copy targets. Thread 0 flags an energy map that is
+// not increasing on the fine range.
+template <int NT>
+__device__ __forceinline__ void param_pass(const DevPlan& p, const DsPlan& ds, const double* th, Lds<NT>& L) {
+  const int tid = threadIdx.x;
+  const int K = ds.K, Nb = ds.Nb, E = Nb + 1, NB = ds.nbkg;
+  const double wf = ds.wf, iwf = 1.0 / wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
+  const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, ds.M, ds.S, ds.nl, K);
+  const double* blob = p.dpool + ds.blob;
+  const int* frow = reinterpret_cast<const int*>(blob + BL.frow);
+  const int* fpar = reinterpret_cast<const int*>(blob + BL.fpar);
+  const double* fcf = blob + BL.fcf;
+  const double* X = blob + BL.edges;
+  const double* tmpl = blob + BL.tmpl;
+  const double* bsc = blob + BL.bsc;
+  const int* brt = reinterpret_cast<const int*>(blob + BL.brt);
+  const int* shp = reinterpret_cast<const int*>(blob + BL.shp);
+  for (int k = tid; k < K; k += NT) {
+    double F = 0.0;
+    const int e1 = frow[k + 1];
+    for (int e = frow[k]; e < e1; ++e) F += th[fpar[e]] * fcf[e];
+    L.F1[k] = 1.0 + F;
+  }
+  const double c0 = pval(th, ds.cidx[0], 0.0);
+  const double c1 = pval(th, ds.cidx[1], 0.0);
+  const double c2 = pval(th, ds.cidx[2], 0.0);
+  const double bb = 1.0 + c1;
+  if (tid == 0 && !(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0))
+    atomicOr(&L.flag[0], ST_DOMAIN);
+  for (int i = tid; i < E; i += NT) {
+    const double z = X[i] - c0;
+    const double disc = bb * bb + 4.0 * c2 * z;
+    double y;
+    if (disc < 0.0) y = c2 < 0.0 ? INFINITY : -INFINITY;
+    else y = 2.0 * z / (bb + sqrt(disc));
+    int k;
+    double t = 0.0;
+    if (!(y >= y0)) {
+      k = -1;
+    } else if (y >= yK) {
+      k = K;
+    } else {
+      k = (int)floor((y - y0) * iwf);
+      k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
+      t = (y - (y0 + k * wf)) * iwf;
+    }
+    L.ek[i] = k;
+    L.eT[i] = t;
+    L.eY[i] = y;
+  }
+  for (int i = tid; i < Nb; i += NT) {
+    double B = 0.0;
+    for (int b = 0; b < NB; ++b) {
+      const int sp = shp[b * Nb + i];
+      const double T = bsc[b] * tmpl[b * Nb + i];
+      const double R = pval(th, brt[b], 1.0);
+      const double f = 1.0 + pval(th, sp, 0.0);
+      B += R * T * f;
+      L.bkr[b * Nb + i] = T * f;
+      L.bks[b * Nb + i] = R * T;
+      L.bki[b * Nb + i] = sp;
+    }
+    L.Bv[i] = B;
+  }
+}
+
 // Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
 // NLL (+inf when out of domain) to every thread; the gradient is in L.grad.
+// On entry dataset 0's copies are in flight (issued by the caller), its
+// parameter pass and the prior rows are done, and prior_e is this thread's
+// part of the prior NLL; nothing has been waited for yet.
+constexpr int ACC_SRC = 16;  // sources reduced together with the other sums
 template <int NT>
-__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, int want_nll, int want_grad) {
+__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const double* thg,
+                                double prior_e, int want_nll, int want_grad) {
   const int tid = threadIdx.x;
-  for (int i = tid; i < p.P; i += NT)
-    if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
-  if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
-
   double nll_total = 0.0;  // identical in every thread (block sums broadcast)
 
   for (int d = 0; d < p.D; ++d) {
-    const DsPlan& ds = L.dsl[d];
+    const DsPlan& ds = d == 0 ? p.ds0 : L.dsl[d];
     const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
-    const double wf = ds.wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
-    const double iwf = 1.0 / wf;  // densities m = H (1 + F) / w as products
+    const double wf = ds.wf, iwf = 1.0 / wf;
     const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
-    double* X = L.st + BL.edges;  // edges, then X, then lambda_X
-    const double* tmpl = L.st + BL.tmpl;
-    const int* shp = reinterpret_cast<const int*>(L.st + BL.shp);
-    const double* bsc = L.st + BL.bsc;
-    const int* brt = reinterpret_cast<const int*>(L.st + BL.brt);
     L.Hs = L.dyn;
     L.Gs = L.dyn + K;
-    L.F1 = L.dyn + 5 * K;
-    L.Ss = L.dyn + 6 * K;
-    L.nD = L.dyn + 6 * K + S * K;
-
-    stage_dataset<NT>(p, io, L, d, want_nll);
-    __syncthreads();
-
-    // ---- spline: edge densities and cumulative. In fused evaluations each
-    // thread forms 1 + F of its own and the previous fine bin from the blob's
-    // flux rows (no extra barrier).
-    {
-      const int* frow = reinterpret_cast<const int*>(L.st + BL.frow);
-      const int* fpar = reinterpret_cast<const int*>(L.st + BL.fpar);
-      const double* fcf = L.st + BL.fcf;
-      auto f1 = [&](int k) {
-        if (!io.fused) return L.F1[k];
-        double F = 0.0;
-        const int e1 = (int)frow[k + 1];
-        for (int e = (int)frow[k]; e < e1; ++e) F += L.th[(int)fpar[e]] * fcf[e];
-        return 1.0 + F;
-      };
-      for (int k = tid; k <= K; k += NT) {
-        const double fa = k > 0 ? f1(k - 1) : 0.0;
-        const double fb = k < K ? f1(k) : 0.0;
-        double dk;
-        if (k == 0) dk = L.Hs[0] * fb * iwf;
-        else if (k == K) dk = L.Hs[K - 1] * fa * iwf;
-        else {
-          const double ma = L.Hs[k - 1] * fa * iwf, mb = L.Hs[k] * fb * iwf;
-          dk = (ma * mb > 0.0) ? 2.0 * ma * mb / (ma + mb) : 0.0;
-        }
-        L.D[k] = dk;
-        if (k < K) {
-          L.LH[k] = L.Hs[k] * fb;  // H (scan input)
-          if (io.fused) L.F1[k] = fb;
-        }
-      }
+    L.Ss = L.dyn + 5 * K;
+    L.nD = L.dyn + 5 * K + S * K;
+    if (d > 0) {
+      stage_dataset<NT>(p, io, L, ds, want_nll);
+      param_pass<NT>(p, ds, thg, L);
     }
-    // the scan's first read is each thread's own element when K <= NT (one
-    // per thread, as written above); its own barrier then orders D
-    if (K > NT) __syncthreads();
-    block_scan<NT>(L.LH, L.C, K, false, L.red);
-
-    // ---- energy scale and analysis edges
-    const double c0 = pval(L.th, ds.cidx[0], 0.0);
-    const double c1 = pval(L.th, ds.cidx[1], 0.0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (d == 0) {
+      for (int i = tid; i < p.P; i += NT)
+        if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
+      if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
+    }
     const double c2 = pval(L.th, ds.cidx[2], 0.0);
-    const double bb = 1.0 + c1;
-    if (tid == 0 && !(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0))
-      atomicOr(&L.flag[0], ST_DOMAIN);
-    for (int i = tid; i < E; i += NT) {
-      const double z = X[i] - c0;
-      const double disc = bb * bb + 4.0 * c2 * z;
-      double y;
-      if (disc < 0.0) y = c2 < 0.0 ? INFINITY : -INFINITY;
-      else y = 2.0 * z / (bb + sqrt(disc));
-      int k;
-      double t = 0.0, Xi;
-      if (!(y >= y0)) {
-        k = -1;
-        Xi = 0.0;
-      } else if (y >= yK) {
-        k = K;
-        Xi = L.C[K];
-      } else {
-        k = (int)floor((y - y0) / wf);
-        k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
-        t = (y - (y0 + k * wf)) * iwf;
-        const double mk = L.Hs[k] * L.F1[k] * iwf;
-        const double dl = L.D[k], dh = L.D[k + 1];
-        const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0);
-        Xi = L.C[k] + wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + 6.0 * (mk - 0.5 * (dl + dh)) * q);
-      }
-      L.kidx[i] = k;
-      L.eT[i] = t;
-      L.eY[i] = y;
-      X[i] = Xi;
-    }
-    __syncthreads();
+    const double bb = 1.0 + pval(L.th, ds.cidx[1], 0.0);
 
-    // ---- expectations, deviance, lambda_mu; background rate/shape gradients
-    double acc[1 + MAX_BKG];
-    for (int j = 0; j <= MAX_BKG; ++j) acc[j] = 0.0;
+    auto mval = [&](int k) { return L.Hs[k] * L.F1[k] * iwf; };
+    auto dens = [&](int k) {  // d_k, 0 <= k <= K
+      if (k == 0) return mval(0);
+      if (k == K) return mval(K - 1);
+      const double a = mval(k - 1), b = mval(k);
+      return (a * b > 0.0) ? 2.0 * a * b / (a + b) : 0.0;
+    };
+    auto clampK = [&](int k) { return k < 0 ? 0 : (k > K ? K : k); };
+
+    // acc: 0 NLL, 1..3 energy scale c0..c2, 4..7 oscillation slots,
+    // 8..15 background rates, 16..31 the first sixteen source norms
+    double acc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+
+    // ---- analysis bins: signal, expectation, deviance, lambda_mu, background
+    // and energy-scale gradients; edge-index table
     for (int i = tid; i < Nb; i += NT) {
-      double B = 0.0;
-      for (int b = 0; b < NB; ++b) {
-        const double beta = pval(L.th, (int)shp[b * Nb + i], 0.0);
-        B += bsc[b] * pval(L.th, (int)brt[b], 1.0) * tmpl[b * Nb + i] * (1.0 + beta);
+      const int ka = L.ek[i], kb = L.ek[i + 1];
+      const double ta = L.eT[i], tb = L.eT[i + 1];
+      const int k0 = clampK(ka), k1 = clampK(kb);
+      double s = 0.0;
+      for (int k = k0; k < k1; ++k) s += L.Hs[k] * L.F1[k];
+      double rho_a = 0.0, rho_b = 0.0;
+      if (kb >= 0 && kb < K) {
+        const double dl = dens(kb), dh = dens(kb + 1), mk = mval(kb);
+        const double q = 0.5 * tb * tb - tb * tb * tb * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
+        s += wf * (dl * (tb - 0.5 * tb * tb) + dh * 0.5 * tb * tb + c * q);
+        rho_b = dl * (1.0 - tb) + dh * tb + c * tb * (1.0 - tb);
       }
-      const double mu = (X[i + 1] - X[i]) + B;
+      if (ka >= 0 && ka < K) {
+        const double dl = dens(ka), dh = dens(ka + 1), mk = mval(ka);
+        const double q = 0.5 * ta * ta - ta * ta * ta * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
+        s -= wf * (dl * (ta - 0.5 * ta * ta) + dh * 0.5 * ta * ta + c * q);
+        rho_a = dl * (1.0 - ta) + dh * ta + c * ta * (1.0 - ta);
+      }
+      const double mu = s + L.Bv[i];
       if (io.mu_out) io.mu_out[ds.bins0 + i] = mu;
       double lam = 0.0;
       if (want_nll) {
@@ -446,187 +446,146 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         acc[0] += (n > 0.0) ? (mu - n + n * log(n / mu)) : mu;
         lam = 1.0 - n / mu;
         if (want_grad) {
-          for (int b = 0; b < NB; ++b) {
-            const int sp = (int)shp[b * Nb + i];
-            const double stv = bsc[b] * tmpl[b * Nb + i];
-            acc[1 + b] += lam * stv * (1.0 + pval(L.th, sp, 0.0));
-            if (sp >= 0) atomicAdd(&L.grad[sp], lam * stv * pval(L.th, (int)brt[b], 1.0));
-          }
+#pragma unroll
+          for (int b = 0; b < MAX_BKG; ++b)
+            if (b < NB) {
+              acc[8 + b] += lam * L.bkr[b * Nb + i];
+              const int sp = L.bki[b * Nb + i];
+              if (sp >= 0) atomicAdd(&L.grad[sp], lam * L.bks[b * Nb + i]);
+            }
+          // ds_i/dc_j = -rho_b (1, y_b, y_b^2)_j / f'(y_b) + rho_a (1, y_a, y_a^2)_j / f'(y_a)
+          const double ya = L.eY[i], yb = L.eY[i + 1];
+          const double la = (ka >= 0 && ka < K) ? lam * rho_a / (bb + 2.0 * c2 * ya) : 0.0;
+          const double lb = (kb >= 0 && kb < K) ? lam * rho_b / (bb + 2.0 * c2 * yb) : 0.0;
+          acc[1] += la - lb;
+          acc[2] += la * ya - lb * yb;
+          acc[3] += la * ya * ya - lb * yb * yb;
         }
       }
-      L.mu[i] = lam;
+      L.lam[i] = lam;
+      // edge-index table: first[q] = i for kk_{i-1} < q <= kk_i (edge 0 from
+      // q = 0); the last bin's thread also writes the entries of the top edge
+      const int kp = i > 0 ? clampK(L.ek[i - 1]) : -1;
+      for (int q = kp + 1; q <= k0; ++q) L.first[q] = i;
+      if (i == Nb - 1) {
+        for (int q = k0 + 1; q <= k1; ++q) L.first[q] = i + 1;
+        for (int q = k1 + 1; q <= K + 1; ++q) L.first[q] = E;
+      }
     }
+    if (d == 0) acc[0] += prior_e;
     if (!want_grad) {
-      if (NB <= 2) block_sum<NT, 3>(acc, L.red);
-      else block_sum<NT, 1 + MAX_BKG>(acc, L.red);
+      block_sum<NT, 1>(acc, L.red);
       nll_total += acc[0];
       __syncthreads();
       continue;
     }
-    // the deviance and background sums are reduced together with the edge
-    // pass's sums below; the edge pass only needs lambda_mu
     __syncthreads();
 
-    // ---- adjoint per edge: lambda_X, energy-scale coefficients, spline pieces
-    double gc[4] = {0.0, 0.0, 0.0, 0.0};  // c0, c1, c2, out-of-range-above total
-    for (int i = tid; i < E; i += NT) {
-      const double lx = (i >= 1 ? L.mu[i - 1] : 0.0) - (i < Nb ? L.mu[i] : 0.0);
-      const int k = L.kidx[i];
-      double em = 0.0, elo = 0.0, ehi = 0.0;
-      if (k == K) {
-        gc[3] += lx;
-      } else if (k >= 0) {
-        const double t = L.eT[i], y = L.eY[i];
-        const double mk = L.Hs[k] * L.F1[k] * iwf;
-        const double dl = L.D[k], dh = L.D[k + 1];
-        const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0);
-        const double rho = dl * (1.0 - t) + dh * t + 6.0 * (mk - 0.5 * (dl + dh)) * t * (1.0 - t);
-        const double fp = bb + 2.0 * c2 * y;
-        const double ly = lx * rho / fp;
-        gc[0] -= ly;
-        gc[1] -= ly * y;
-        gc[2] -= ly * y * y;
-        em = lx * wf * 6.0 * q;
-        elo = lx * wf * (t - 0.5 * t * t - 3.0 * q);
-        ehi = lx * wf * (0.5 * t * t - 3.0 * q);
-      }
-      X[i] = (k >= 0 && k < K) ? lx : 0.0;
-      L.eT[i] = em;
-      L.eY[i] = elo;
-      L.eH[i] = ehi;
-      // edge-index table: first[k + 1] = i for kidx[i-1] < k <= kidx[i]
-      const int kp = i > 0 ? L.kidx[i - 1] : -2;
-      for (int q = kp + 1; q <= k; ++q) L.first[q + 1] = i;
-      if (i == E - 1)
-        for (int q = k + 1; q <= K + 1; ++q) L.first[q + 1] = E;
-    }
-    {
-      // one block reduction: gc[0..3], then the deviance and background sums
-      double v[4 + 1 + MAX_BKG];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[j] = gc[j];
-#pragma unroll
-      for (int j = 0; j <= MAX_BKG; ++j) v[4 + j] = acc[j];
-      if (NB <= 2) block_sum<NT, 7>(v, L.red);
-      else block_sum<NT, 5 + MAX_BKG>(v, L.red);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) gc[j] = v[j];
-#pragma unroll
-      for (int j = 0; j <= MAX_BKG; ++j) acc[j] = v[4 + j];
-    }
-    nll_total += acc[0];
-    if (tid == 0) {
-      for (int b = 0; b < NB; ++b)
-        if ((int)brt[b] >= 0) L.grad[(int)brt[b]] += acc[1 + b];
-      for (int j = 0; j < 3; ++j)
-        if (ds.cidx[j] >= 0) L.grad[ds.cidx[j]] += gc[j];
-    }
-    const double top = gc[3];
-
-    // ---- gather per fine bin: lambda_C -> C, lambda_m (direct) -> LH, lambda_d -> Ld
-    // (bounds clamped: with an invalid energy map, which is flagged as out of
-    // domain, the edge index need not be monotone)
-    for (int k = tid; k <= K; k += NT) {
-      const int b0 = min(max(L.first[k + 1], 0), E);
-      const int b1 = min(max(L.first[k + 2], b0), E);
-      double lc = 0.0, lm = 0.0, ld = 0.0;
-      if (k < K) {
-        for (int i = b0; i < b1; ++i) {
-          lc += X[i];
-          lm += L.eT[i];
-          ld += L.eY[i];
-        }
-      }
-      if (k >= 1) {
-        const int a0 = min(max(L.first[k], 0), b0);
-        for (int i = a0; i < b0; ++i) ld += L.eH[i];
-      }
-      L.Ld[k] = ld;
-      if (k < K) {
-        L.LH[k] = lm;
-        L.C[k] = lc;
-      }
-    }
-    __syncthreads();
-    // C_k = sum_{j<k} H_j: lambda_H[j] collects sum_{k>j} lambda_C[k]
-    block_scan<NT>(L.C, L.Suf, K, true, L.red);
-
-    // ---- lambda_H per fine bin -> C
+    // ---- fine bins: lambda_H from the covering analysis bin and the edges in
+    // fine bins k-1, k, k+1; rescale adjoint (lambda_F, oscillation slots, sources)
+    const int nsrc = S < ACC_SRC ? S : ACC_SRC;
     for (int k = tid; k < K; k += NT) {
-      const double mk = L.Hs[k] * L.F1[k] * iwf;
-      double lm = L.LH[k];
-      if (k == 0) lm += L.Ld[0];
-      if (k == K - 1) lm += L.Ld[K];
-      if (k >= 1) {  // d_k = harmonic(m_{k-1}, m_k)
-        const double ma = L.Hs[k - 1] * L.F1[k - 1] * iwf;
-        if (ma * mk > 0.0) {
-          const double den = ma + mk;
-          lm += L.Ld[k] * 2.0 * ma * ma / (den * den);
+      auto fe = [&](int q) { const int v = L.first[q]; return v < 0 ? 0 : (v > E ? E : v); };
+      const int ic = fe(k + 1) - 1;  // analysis bin whose mapped range holds fine bin k whole
+      double lH = (ic >= 0 && ic < Nb) ? L.lam[ic] : 0.0;
+      double lmd = 0.0, ldk = 0.0, ldk1 = 0.0;
+      const int j0 = fe(k > 0 ? k - 1 : 0), j1 = fe(k + 2);
+      for (int j = j0; j < j1; ++j) {
+        const int kj = L.ek[j];
+        if (kj < k - 1 || kj > k + 1 || kj < 0 || kj >= K) continue;
+        const double lx = (j >= 1 ? L.lam[j - 1] : 0.0) - (j < Nb ? L.lam[j] : 0.0);
+        const double t = L.eT[j];
+        const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0);
+        const double elo = wf * (t - 0.5 * t * t - 3.0 * q), ehi = wf * (0.5 * t * t - 3.0 * q);
+        if (kj == k) {
+          lmd += lx * wf * 6.0 * q;
+          ldk += lx * elo;
+          ldk1 += lx * ehi;
+        } else if (kj == k - 1) {
+          ldk += lx * ehi;
+        } else {
+          ldk1 += lx * elo;
         }
       }
-      if (k + 1 <= K - 1) {  // d_{k+1} = harmonic(m_k, m_{k+1})
-        const double mb = L.Hs[k + 1] * L.F1[k + 1] * iwf;
-        if (mk * mb > 0.0) {
-          const double den = mk + mb;
-          lm += L.Ld[k + 1] * 2.0 * mb * mb / (den * den);
+      const double mk = mval(k);
+      double lm = lmd;
+      if (k == 0) {
+        lm += ldk;  // d_0 = m_0
+      } else {
+        const double a = mval(k - 1);
+        if (a * mk > 0.0) {
+          const double den = a + mk;
+          lm += ldk * 2.0 * a * a / (den * den);
         }
       }
-      L.C[k] = L.Suf[k] + top + lm * iwf;
+      if (k == K - 1) {
+        lm += ldk1;  // d_K = m_{K-1}
+      } else {
+        const double b = mval(k + 1);
+        if (mk * b > 0.0) {
+          const double den = mk + b;
+          lm += ldk1 * 2.0 * b * b / (den * den);
+        }
+      }
+      lH += lm * iwf;
+      const double lhs = lH * L.F1[k];
+      L.LF[k] = lH * L.Hs[k];
+      L.LHs[k] = lhs;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[4 + j] += lhs * L.Gs[j * K + k];
+#pragma unroll
+      for (int q = 0; q < ACC_SRC; ++q)
+        if (q < nsrc) acc[16 + q] += lhs * L.Ss[q * K + k];
     }
-    // no barrier: the next pass reads only its own fine bins' lambda_H and
-    // writes lambda_F over the suffix sums it has read (same thread mapping)
+    if (S > 0) block_sum<NT, 32>(acc, L.red);
+    else block_sum<NT, 16>(acc, L.red);
+    nll_total += acc[0];
+    double gA = 0.0;  // dNLL/dA_s of the source this thread applies (thread s)
+#pragma unroll
+    for (int q = 0; q < ACC_SRC; ++q)
+      if (q == tid) gA = acc[16 + q];
+    // sources past the first sixteen, in further reductions of 32
+    for (int s0 = nsrc; s0 < S; s0 += 32) {
+      const int ns = S - s0 < 32 ? S - s0 : 32;
+      double a2[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) a2[j] = 0.0;
+      for (int k = tid; k < K; k += NT) {
+        const double lhs = L.LHs[k];
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+          if (q < ns) a2[q] += lhs * L.Ss[(s0 + q) * K + k];
+      }
+      block_sum<NT, 32>(a2, L.red);
+#pragma unroll
+      for (int q = 0; q < 32; ++q)
+        if (q == tid - s0) gA = a2[q];
+    }
 
-    // ---- rescale adjoint, oscillation parameters and source norms in one
-    // pass over the fine bins with one block reduction (in groups of up to
-    // 12 sources): lambda_Hs = lambda_H (1 + F), lambda_F -> Suf; the
-    // oscillation slots take sum_k lambda_Hs G_j, source s takes
-    // dNLL/dA_s = sum_k lambda_Hs S[s][k], then the product rule over its
-    // norm list
-    {
+    // ---- gradient of the reduced sums; source norms by the product rule over
+    // each source's norm list; flux modes by a gather of lambda_F over each
+    // mode's fine bins (CSC)
+    if (tid == NT - 1) {  // a thread with no source to apply (S <= MAX_SOURCES < NT)
+      for (int j = 0; j < 3; ++j)
+        if (ds.cidx[j] >= 0) L.grad[ds.cidx[j]] += acc[1 + j];
+      for (int j = 0; j < NSLOT; ++j)
+        if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += acc[4 + j];
+      const int* brt = reinterpret_cast<const int*>(p.dpool + ds.blob + BL.brt);
+#pragma unroll
+      for (int b = 0; b < MAX_BKG; ++b)
+        if (b < NB && brt[b] >= 0) L.grad[brt[b]] += acc[8 + b];
+    }
+    if (tid < S) {
       const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
       const int* nli = reinterpret_cast<const int*>(L.st + BL.nli);
-      auto apply = [&](int s, double gA) {
-        const int b = (int)nlp[s], e = (int)nlp[s + 1];
-        for (int q = b; q < e; ++q) {
-          double prod = 1.0;
-          for (int r = b; r < e; ++r)
-            if (r != q) prod *= L.th[(int)nli[r]];
-          atomicAdd(&L.grad[(int)nli[q]], gA * prod);
-        }
-      };
-      for (int s0 = 0; s0 == 0 || s0 < S; s0 += 12) {
-        const int ns = min(S - s0, 12);
-        double acc[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-        for (int k = tid; k < K; k += NT) {
-          const double lh = L.C[k];
-          const double lhs = lh * L.F1[k];
-          if (s0 == 0) {
-            L.Suf[k] = lh * L.Hs[k];  // lambda_F
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[j] += lhs * L.Gs[j * K + k];
-          }
-#pragma unroll
-          for (int q = 0; q < 12; ++q)
-            if (q < ns) acc[4 + q] += lhs * L.Ss[(s0 + q) * K + k];
-        }
-        if (ns <= 4) block_sum<NT, 8>(acc, L.red);
-        else block_sum<NT, 16>(acc, L.red);
-        if (s0 == 0 && tid == NT - 1)  // a thread with no source to apply
-          for (int j = 0; j < NSLOT; ++j)
-            if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += acc[j];
-        if (tid < ns) {
-          double gA = 0.0;  // acc[4 + tid] without a dynamically indexed register array
-#pragma unroll
-          for (int q = 0; q < 12; ++q)
-            if (q == tid) gA = acc[4 + q];
-          apply(s0 + tid, gA);
-        }
+      const int b = nlp[tid], e = nlp[tid + 1];
+      for (int q = b; q < e; ++q) {
+        double prod = 1.0;
+        for (int r = b; r < e; ++r)
+          if (r != q) prod *= L.th[nli[r]];
+        atomicAdd(&L.grad[nli[q]], gA * prod);
       }
     }
-    // ---- flux modes (CSC gather per mode of lambda_F, written before the
-    // block reduction's barriers)
     {
       const int* mdcol = reinterpret_cast<const int*>(L.st + BL.mdcol);
       const int* mdk = reinterpret_cast<const int*>(L.st + BL.mdk);
@@ -634,49 +593,37 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       const int* mdp = reinterpret_cast<const int*>(L.st + BL.mdp);
       for (int m = tid; m < M; m += NT) {
         double gm = 0.0;
-        const int e0 = (int)mdcol[m], e1 = (int)mdcol[m + 1];
+        const int e0 = mdcol[m], e1 = mdcol[m + 1];
         // four entries per step: their index and coefficient reads, then
-        // their Ld reads, are independent (two LDS round trips per step)
+        // their lambda_F reads, are independent (two LDS round trips per step)
         for (int e = e0; e < e1; e += 4) {
-          int k[4];
-          double c[4];
+          int kq[4];
+          double cq[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const bool in = e + q < e1;
-            k[q] = in ? (int)mdk[e + q] : 0;
-            c[q] = in ? mdc[e + q] : 0.0;
+            kq[q] = in ? mdk[e + q] : 0;
+            cq[q] = in ? mdc[e + q] : 0.0;
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) gm += L.Suf[k[q]] * c[q];
+          for (int q = 0; q < 4; ++q) gm += L.LF[kq[q]] * cq[q];
         }
-        atomicAdd(&L.grad[(int)mdp[m]], gm);
+        atomicAdd(&L.grad[mdp[m]], gm);
       }
     }
+    if (d == 0)
+      for (int r = tid; r < p.NR; r += NT) atomicAdd(&L.grad[L.pri[r]], L.prv[r]);
     __syncthreads();
   }
 
-  // ---- priors (Eq. 6; third line of Eq. 9)
-  {
-    double pr[1] = {0.0};
-    for (int r = tid; r < p.NR; r += NT) {
-      int i;
-      double v, e;
-      prior_row(p, L.th, r, i, v, e);
-      pr[0] += e;
-      if (want_grad) atomicAdd(&L.grad[i], v);
-    }
-    block_sum<NT, 1>(pr, L.red);
-    nll_total += pr[0];
-  }
-  __syncthreads();
-
   const bool bad = (L.flag[0] & ST_DOMAIN) || !isfinite(nll_total);
-  if (io.fused) {
+  if (io.fused && !io.keep_rows) {
     // the fold kernel accumulates rows 0..4 into zeroed memory: clear them
     // for the next launch (issued with the outputs, after every read)
     for (int d = 0; d < p.D; ++d) {
-      double* b = io.bin + 6 * (int64_t)L.dsl[d].kt0;
-      const int n = 5 * L.dsl[d].K;
+      const DsPlan& ds = d == 0 ? p.ds0 : L.dsl[d];
+      double* b = io.bin + 6 * (int64_t)ds.kt0;
+      const int n = 5 * ds.K;
       for (int j = tid; j < n; j += NT) b[j] = 0.0;
     }
   }
@@ -687,6 +634,32 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   return bad ? INFINITY : nll_total;
 }
 
+// Launch prologue shared by the single and batched bin stages: issue dataset
+// 0's copies, clear the gradient and flag, run dataset 0's parameter pass and
+// the prior rows from global memory while the copies are in flight. Returns
+// this thread's part of the prior NLL. The parameters and dataset plans are
+// the caller's to copy.
+template <int NT>
+__device__ __forceinline__ double prologue(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const double* thg,
+                                           int want_nll) {
+  const int tid = threadIdx.x;
+  stage_dataset<NT>(p, io, L, p.ds0, want_nll);
+  for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
+  if (tid == 0) L.flag[0] = 0;
+  param_pass<NT>(p, p.ds0, thg, L);
+  double e_sum = 0.0;
+  if (want_nll)
+    for (int r = tid; r < p.NR; r += NT) {
+      int idx;
+      double v, e;
+      prior_row(p, thg, r, idx, v, e);
+      L.prv[r] = v;
+      L.pri[r] = idx;
+      e_sum += e;
+    }
+  return e_sum;
+}
+
 // Single evaluation: one workgroup; the fold kernel has already reduced the
 // events to fine-bin rows 0..4 and per-segment S.
 template <int NT>
@@ -695,22 +668,17 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   if (a.skip && *a.skip != FIT_RUNNING) return;
   const DevPlan& p = a.plan;
   Lds<NT> L = carve<NT>(smem, p);
-  const int tid = threadIdx.x;
 
   const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
-                  const_cast<double*>(a.bin), 1};
+                  const_cast<double*>(a.bin), 1, a.keep_rows};
   // the fold kernel has applied the oscillation coefficients; the domain of
   // the oscillation parameters is checked from LDS in the serial stages.
   // Parameters, dataset plans and dataset 0's inputs go to LDS in one round
   // of direct copies (dataset 0's plan comes with the kernel arguments).
   copy_to_lds<NT>(L.th, a.theta, p.P);
   copy_to_lds<NT>(reinterpret_cast<double*>(L.dsl), reinterpret_cast<const double*>(p.ds), p.D * DSPLAN_DOUBLES);
-  stage_fused<NT>(p, io, L, p.ds0, a.want_nll);
-  for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
-  if (tid == 0) L.flag[0] = 0;
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  const double f = serial_stages<NT>(p, io, L, a.want_nll, a.want_grad);
+  const double pe = prologue<NT>(p, io, L, a.theta, a.want_nll);
+  const double f = serial_stages<NT>(p, io, L, a.theta, pe, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
 }
 
@@ -746,11 +714,15 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   const int P = p.P, G = p.G, KT = p.KT;
   const int NMOM = num_moments(p.osc.formula);
   const double* th = a.theta + (int64_t)f * P;
-  load_params<NT>(p, th, L);
-  if (tid == 0) {
-    L.flag[0] = 0;
-    if (!osc_coefficients(p.osc, th, L.coef)) L.flag[0] |= ST_DOMAIN;
+  for (int i = tid; i < P; i += NT) L.th[i] = th[i];
+  {
+    const double* src = reinterpret_cast<const double*>(p.ds);
+    double* dst = reinterpret_cast<double*>(L.dsl);
+    for (int i = tid; i < p.D * DSPLAN_DOUBLES; i += NT) dst[i] = src[i];
   }
+  // outside the domain the coefficients are not used for any reported value:
+  // the serial stages flag the same cases from the parameters
+  if (tid == 0) (void)osc_coefficients(p.osc, th, L.coef);
   __syncthreads();
   const int drow = a.data_idx ? a.data_idx[f] : f;
   const int prow = a.part_idx ? a.part_idx[f] : f;
@@ -762,7 +734,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
                   a.mu_out ? a.mu_out + (int64_t)f * p.nbins_total : nullptr,
                   a.Sseg + (int64_t)f * G,
                   a.bin + (int64_t)f * 6 * KT,
-                  0};
+                  0, 0};
   double* tmp = a.segtmp + (int64_t)f * 5 * G;
   // phase A, per segment
   for (int g = tid; g < G; g += NT) {
@@ -788,7 +760,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
     }
   }
   __syncthreads();
-  // per fine bin: sum over sources, flux factor
+  // per fine bin: sum over sources
   for (int kt = tid; kt < KT; kt += NT) {
     const int* info = p.ipool + p.kt_info + 5 * kt;
     const int g0 = info[0], K = info[1], S = info[2], kt0 = info[4];
@@ -796,16 +768,13 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < S; ++s)
       for (int j = 0; j < 5; ++j) v[j] += tmp[(int64_t)j * G + g0 + s * K];
-    double F = 0.0;
-    const int rb = p.ipool[p.kt_row + kt], re = p.ipool[p.kt_row + kt + 1];
-    for (int e = rb; e < re; ++e) F += L.th[p.ipool[p.kt_par + e]] * p.dpool[p.kt_coef + e];
     double* bb = io.bin + 6 * (int64_t)kt0;
     for (int j = 0; j < 5; ++j) store_agent(&bb[j * K + k], v[j]);
-    store_agent(&bb[5 * K + k], 1.0 + F);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const double fval = serial_stages<NT>(p, io, L, a.want_nll, a.want_nll ? a.want_grad : 0);
+  const double pe = prologue<NT>(p, io, L, th, a.want_nll);
+  const double fval = serial_stages<NT>(p, io, L, th, pe, a.want_nll, a.want_nll ? a.want_grad : 0);
   if (a.has_fit) {
     if (a.osc_last && tid < NSLOT) {
       const int q = p.osc.slot_param[tid];
@@ -813,6 +782,18 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
     }
     lbfgs_step<NT>(fit_of(a.fit, f, P), P, L.th, fval, L.grad, L.fit, L.red);
   }
+}
+
+__global__ void zero_kernel(double* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch_tail(const BatchTailArgs& a, int nt, hipStream_t stream) {

@@ -1,9 +1,16 @@
 """Parity of the HIP engine (through the C-ABI) with the FP64 oracle.
 
-Tolerances (relative, with a floor of 1 for NLL and gradient):
+Tolerances:
   M64: 1e-9 on every expectation mu_{d,i}, on the NLL and on the gradient
   M32: 1e-5 on the same quantities
-  NLL: |dNLL| <= tol * max(1, |NLL|);  gradient: max|dg| <= tol * max(1, max|g|).
+  mu: relative per bin;  NLL: |dNLL| <= tol * max(1, |NLL|);
+  gradient, per component: |dg_j| <= tol_g * max(|g_j|, sqrt(F_jj)), F_jj the
+  NLL's curvature in theta_j (Fisher information plus prior; tests/gradcheck.py),
+  so an error at the bar moves the fitted theta_j by tol_g standard deviations,
+  and the whole vector also within tol * max(1, max|g|).
+  tol_g is tol in M64; in M32 it is GRAD_TOL_M32 (the FP32 fold's error in mu,
+  a few 1e-7 relative per bin, enters the gradient through lambda = 1 - n/mu
+  multiplied by dmu/dtheta, which grows like sqrt(mu) against sqrt(F)).
 """
 import sys
 
@@ -15,10 +22,13 @@ from oracle import likelihood as LK
 from oracle import fold as OF
 from paper_2502_15253_amd import nufold as nf
 from paper_2502_15253_amd import synth
+import gradcheck
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"m64": 1e-9, "m32": 1e-5}
+GRAD_TOL_M32 = 1e-5
+GRAD_TOL = {"m64": 1e-9, "m32": GRAD_TOL_M32}
 
 
 def say(*a):
@@ -47,10 +57,10 @@ def oracle_data(desc, events, seed):
     return synth.poisson_data(mus, seed)
 
 
-def compare(eng, desc, events, data, theta, tol, what=""):
+def compare(eng, desc, events, data, theta, tol, what="", gtol=None):
     m = Model(desc)
     mus_o, _ = LK.expected(m, events, theta)
-    f_o, g_o = LK.nll_grad(m, events, data, theta)
+    f_o, g_o, F = LK.nll_grad(m, events, data, theta, fisher=True)
     mus_g, code = eng.expected(theta)
     assert code == nf.NF_OK
     for mo, mg in zip(mus_o, mus_g):
@@ -62,6 +72,7 @@ def compare(eng, desc, events, data, theta, tol, what=""):
     scale = max(1.0, np.max(np.abs(g_o)))
     err = np.max(np.abs(g_g - g_o))
     assert err <= tol * scale, f"{what}: grad err {err:.3e} (scale {scale:.3e}) at {np.argmax(np.abs(g_g - g_o))}"
+    gradcheck.check(g_g, g_o, F, tol if gtol is None else gtol, what, m.names)
     f_n, code = eng.eval_nll(theta)
     # the same evaluation without the gradient; fine-bin sums by atomic adds may
     # move the last bits of mu, which the deviance's cancellations amplify
@@ -90,7 +101,7 @@ def test_tiny_models(mode, formula, seed, deterministic):
     data = oracle_data(desc, events, 60 + seed)
     eng = make_engine(desc, events, data, mode, deterministic=deterministic)
     for j in range(3):
-        compare(eng, desc, events, data, displaced(desc, 70 + j), TOL[mode], f"tiny {formula} {seed} {j}")
+        compare(eng, desc, events, data, displaced(desc, 70 + j), TOL[mode], f"tiny {formula} {seed} {j}", gtol=GRAD_TOL[mode])
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])
@@ -100,9 +111,9 @@ def test_config1_full_size(mode):
     data = oracle_data(desc, events, synth.data_seed(1))
     eng = make_engine(desc, events, data, mode)
     assert eng.dropped(0) == OF.dropped_events(Model(desc), events)[0]
-    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c1 start")
+    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c1 start", gtol=GRAD_TOL[mode])
     for j in range(3):
-        compare(eng, desc, events, data, displaced(desc, 100 + j), TOL[mode], f"c1 displaced {j}")
+        compare(eng, desc, events, data, displaced(desc, 100 + j), TOL[mode], f"c1 displaced {j}", gtol=GRAD_TOL[mode])
 
 
 @pytest.mark.parametrize("mode,deterministic", [("m64", 0), ("m32", 0), ("m64", 1)])
@@ -111,8 +122,8 @@ def test_config2_full_size(mode, deterministic):
     desc, events = synth.model_and_events(2)
     data = oracle_data(desc, events, synth.data_seed(2))
     eng = make_engine(desc, events, data, mode, deterministic=deterministic)
-    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c2 start")
-    compare(eng, desc, events, data, displaced(desc, 200), TOL[mode], "c2 displaced")
+    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "c2 start", gtol=GRAD_TOL[mode])
+    compare(eng, desc, events, data, displaced(desc, 200), TOL[mode], "c2 displaced", gtol=GRAD_TOL[mode])
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])
@@ -123,7 +134,7 @@ def test_config3_full_size(mode):
     mus, _ = LK.expected(m, events, synth.start_vector(desc))
     data = [mu.copy() for mu in mus]  # Asimov, as in the medium-baseline study
     eng = make_engine(desc, events, data, mode)
-    compare(eng, desc, events, data, displaced(desc, 300), TOL[mode], "c3 displaced")
+    compare(eng, desc, events, data, displaced(desc, 300), TOL[mode], "c3 displaced", gtol=GRAD_TOL[mode])
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])
@@ -141,7 +152,7 @@ def test_work_item_chunking_does_not_change_results(mode):
         eng = make_engine(desc, events, data, mode, chunk=chunk)
         f, g, _ = eng.eval_nll_grad(th)
         if mode == "m32":  # per-lane FP32 sums group the events differently per chunk size
-            compare(eng, desc, events, data, th, TOL[mode], f"chunk {chunk}")
+            compare(eng, desc, events, data, th, TOL[mode], f"chunk {chunk}", gtol=GRAD_TOL[mode])
         elif ref is None:
             ref = (f, g)
             compare(eng, desc, events, data, th, 1e-9, "chunk")
@@ -326,3 +337,54 @@ def test_graph_of_device_evaluations_matches_single_evaluations(mode):
     with pytest.raises(nf.NufoldError) as e:
         eng.eval_device_many(0, theta_t.data_ptr(), out_t.data_ptr())
     assert e.value.code == nf.NF_EINVAL
+
+
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_stage_cache_reuses_the_fold_only_while_its_parameters_repeat(mode):
+    """Option stage_cache: host evaluations that change only bin-stage
+    parameters reuse the last fold; a change of an oscillation parameter or a
+    source norm folds again; device evaluations in between clear the kept
+    rows. Every result equals a full evaluation bit for bit (deterministic
+    fine-bin sums on both engines) and the oracle at a reused fold."""
+    say("stage cache", mode)
+    import torch
+    desc, events = synth.model_and_events(1)
+    m = Model(desc)
+    data = oracle_data(desc, events, 13)
+    ref = make_engine(desc, events, data, mode, deterministic=1)
+    eng = make_engine(desc, events, data, mode, deterministic=1)
+    eng.set_option("stage_cache", 1)
+    assert eng.get_option("stage_cache") == 1
+    th = displaced(desc, 14)
+    steps = [(None, 0.0), ("escale.c1", 0.003), ("bkg.flat.rate", 0.02), ("flux[2]", 0.01),
+             ("osc.sin2_2t13", 0.004), ("escale.c0", -0.01), ("norm", 0.01), ("norm", 0.0),
+             ("osc.dm2_ee", 0.03), ("flux[0]", -0.02)]
+    names = set(m.names)
+    seq = []
+    for name, dv in steps:
+        t = (seq[-1] if seq else th).copy()
+        if name is not None:
+            assert name in names, name
+            t[m.index[name]] += dv
+        seq.append(t)
+    for i, t in enumerate(seq):
+        f, g, code = eng.eval_nll_grad(t)
+        f0, g0, _ = ref.eval_nll_grad(t)
+        assert code == nf.NF_OK
+        assert f == f0 and np.array_equal(g, g0), i
+        mu, _ = eng.expected(t)
+        mu0, _ = ref.expected(t)
+        assert all(np.array_equal(a, b) for a, b in zip(mu, mu0)), i
+        if i == 3:  # a device evaluation between two cached ones clears the rows
+            tt = torch.tensor(seq[0], dtype=torch.float64, device="cuda")
+            out = torch.zeros(1 + eng.P, dtype=torch.float64, device="cuda")
+            eng.eval_device(tt.data_ptr(), out.data_ptr())
+            torch.cuda.synchronize()
+            fd, gd, _ = ref.eval_nll_grad(seq[0])
+            assert out[0].item() == fd
+    # the oracle at a point that reused the fold
+    compare(eng, desc, events, data, seq[-1], TOL[mode], "stage cache", gtol=GRAD_TOL[mode])
+    eng.set_option("stage_cache", 0)
+    f, g, _ = eng.eval_nll_grad(seq[2])
+    f0, g0, _ = ref.eval_nll_grad(seq[2])
+    assert f == f0 and np.array_equal(g, g0)
