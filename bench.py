@@ -7,13 +7,15 @@ One step = one full model evaluation at a new parameter vector: the event fold
 Inputs (events, data, 64 parameter vectors whose oscillation parameters all
 differ) are resident in device memory before the timed region.
 
-Prints one JSON line. Per-kernel durations come from HIP events recorded on
-the engine's stream around every fold and bin-stage launch of the timed
-region; the roofline entry prices the fold (the dominant kernel) against
-MI355X's 8 TB/s HBM peak with the algorithmic bytes it must read
-(u = L/E and w per event: 12 B in FP64 mode, 8 B in FP32 mode).
-The CPU baseline is the FP64 oracle (NLL plus complex-step gradient) timed on
-the host for one evaluation of the same workload.
+Prints one JSON line. Per-kernel durations come from HIP start/stop events
+carried by the fold and bin-stage dispatches on the engine's stream; the
+roofline entry prices the fold (the dominant kernel) against MI355X's 8 TB/s
+HBM peak with the algorithmic bytes it must read (u = L/E and w per event:
+12 B in FP64 mode, 8 B in FP32 mode), from evaluations cycled over engine
+replicas whose event sets together exceed the 256 MB Infinity Cache (the
+single-engine, cache-resident figure is reported beside it). Both precision
+modes are measured. The CPU baseline is the FP64 oracle (NLL plus
+complex-step gradient) timed on the host, on one core and on every core.
 """
 import argparse
 import hashlib
@@ -29,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COLD_STEPS = 240  # evaluations of the replica-rotated loop (at least)
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fold_juno_like_1e7_traffic.json")
 
 
@@ -87,6 +90,50 @@ def cpu_baseline(desc, events, theta):
                           usable_cpus=len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None))
 
 
+def _oracle_worker(args):
+    """One worker of the all-cores CPU leg: builds the same workload from its
+    seeds (spawned process, numpy only) and times whole oracle evaluations
+    for about `seconds` seconds of work. Returns (evaluations, seconds)."""
+    n_events, theta_seed, k, seconds = args
+    from threadpoolctl import threadpool_limits
+    from paper_2502_15253_amd import synth
+    from oracle.model import Model
+    from oracle import likelihood as LK
+    desc, events = synth.model_and_events(3, n_events)
+    m = Model(desc)
+    thetas = synth.osc_theta_list(desc, 64, seed=theta_seed)
+    data = [mu.copy() for mu in LK.expected(m, events, synth.start_vector(desc))[0]]
+    n = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while True:
+            LK.nll_grad(m, events, data, thetas[(k + n) % 64])
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+    return n, dt
+
+
+def cpu_baseline_all_cores(n_events, seconds=15.0):
+    """The oracle as it stands on every usable host core: one spawned process
+    per core, each timing whole evaluations of the same workload (numpy FP64,
+    one library thread each); the rate is the sum of the per-process rates."""
+    import multiprocessing as mp
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    ncpu = max(1, min(ncpu, 16))
+    ctx = mp.get_context("spawn")  # fresh interpreters: no device state inherited
+    t0 = time.perf_counter()
+    with ctx.Pool(ncpu) as pool:
+        res = pool.map(_oracle_worker, [(n_events, 5, k, seconds) for k in range(ncpu)])
+    wall = time.perf_counter() - t0
+    rate = sum(n / dt for n, dt in res)
+    return dict(value=rate, unit="evals/s", cores=ncpu, kind="oracle",
+                sample=f"{sum(n for n, _ in res)} full evaluations over {ncpu} processes (one per core), "
+                       f"about {seconds:.0f} s of work each, {wall:.0f} s wall including each process "
+                       f"building the workload")
+
+
 COPY_BYTES = 512 << 20
 
 
@@ -143,7 +190,10 @@ def engine_for(nf, synth, config, stream, n_events=None):
 def plain_fit(eng, desc, start, h=1e-6):
     """The paper's method on the GPU: one fit at a time, BFGS on the host with
     central finite-difference gradients, every function value one GPU
-    evaluation (fold + bin stages + NLL). Like Minuit's internal parameters,
+    evaluation (fold + bin stages + NLL) with stage caching (the fold is
+    re-run only when an oscillation parameter or a source norm changed, as the
+    paper's caches recompute a stage only when its parameters change; option
+    stage_cache of the library). Like Minuit's internal parameters,
     the minimiser works in scaled variables z = (theta - start) / s, with s the
     prior width (else 5% of the start value), so that its initial metric is
     sensible; fixed parameters stay at their start. Returns (NLL, evaluations)."""
@@ -171,11 +221,15 @@ def plain_fit(eng, desc, start, h=1e-6):
             out[j] = (f(z + e) - f(z - e)) / (2 * h)
         return out
 
-    r = minimize(f, np.zeros(len(idx)), jac=g, method="BFGS", options=dict(gtol=1e-6, maxiter=5000))
+    eng.set_option("stage_cache", 1)
+    try:
+        r = minimize(f, np.zeros(len(idx)), jac=g, method="BFGS", options=dict(gtol=1e-6, maxiter=5000))
+    finally:
+        eng.set_option("stage_cache", 0)
     return r.fun, n[0]
 
 
-def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
+def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples, n_plain_c2=3, n_plain_c3=16):
     """Pseudo-experiment fits/s: batched adjoint fits (2048 + 2048 pseudo-experiments
     of the 1050 m single-detector and three-detector models, and a 200 x 200
     profile scan) against the plain per-fit GPU path; and the learned warm start
@@ -255,15 +309,33 @@ def fits_section(nf, synth, torch, stream, n_plain, surrogate_samples):
                                        best=[float(grid[k, 0]), float(grid[k, 1])],
                                        delta_chi2_max=float(2 * (nll.max() - nll.min())))
             log(f"scan: {json.dumps(out['scan_200x200'])}")
+        if config == 2 and n_plain_c2 > 0:
+            # agreement of the batched 302-parameter fits with the plain path on
+            # the first pseudo-experiments (a different minimiser: host BFGS on
+            # finite differences)
+            nb = np.cumsum([0] + [len(ds["edges"]) - 1 for ds in desc["datasets"]])
+            t0 = time.perf_counter()
+            dmax, nev = 0.0, 0
+            for j in range(n_plain_c2):
+                for d in range(len(desc["datasets"])):
+                    eng.set_data(d, data[j][nb[d]:nb[d + 1]])
+                fmin, ne = plain_fit(eng, desc, start[j])
+                nev += ne
+                dmax = max(dmax, 2.0 * (fmin - r["nll"][j]))
+            tp = time.perf_counter() - t0
+            ent["plain"] = dict(fits=n_plain_c2, seconds=tp, fits_per_s=n_plain_c2 / tp,
+                                evals_per_fit=nev / n_plain_c2, max_delta_chi2_plain_minus_batched=dmax)
+            ent["batched_over_plain"] = ent["fits_per_s"] / ent["plain"]["fits_per_s"]
+            log(f"plain three_detector: {json.dumps(ent['plain'])}")
         out[label] = ent
         eng.close()
     out["ensemble_fits_per_s"] = n_all / t_all
     if surrogate_samples > 0:
-        out["warm_start"] = warm_start_section(nf, synth, torch, stream, surrogate_samples)
+        out["warm_start"] = warm_start_section(nf, synth, torch, stream, surrogate_samples, n_plain=n_plain_c3)
     return out
 
 
-def warm_start_section(nf, synth, torch, stream, n_samples, E=256, n_plain=2):
+def warm_start_section(nf, synth, torch, stream, n_samples, E=256, n_plain=16):
     """Medium-baseline pseudo-experiments at random points of the training box:
     exact batched fits from the box centre (cold) and from the surrogate's
     proposal (warm). A third fit from the generating point gives the reference
@@ -329,13 +401,17 @@ def warm_start_section(nf, synth, torch, stream, n_samples, E=256, n_plain=2):
                train_tflops=6.0 * sur.net.nparam * 1024 * steps / t_train / 1e12,
                heldout_rms_dlogmu=float(np.sqrt(np.mean(err ** 2))),
                cold=dict(seconds=tc, fits_per_s=E / tc, found_global_min=float(np.mean(rc["nll"] - best < 5e-4)),
+                         correct_fits_per_s=float(np.sum(rc["nll"] - best < 5e-4)) / tc,
                          mean_iters=float(rc["iters"].mean())),
                warm=dict(seconds=tsur + tw, surrogate_s=tsur, fits_per_s=E / (tsur + tw),
                          found_global_min=float(np.mean(rw["nll"] - best < 5e-4)),
+                         correct_fits_per_s=float(np.sum(rw["nll"] - best < 5e-4)) / (tsur + tw),
                          mean_iters=float(rw["iters"].mean())),
                plain=dict(fits=n_plain, seconds=tp, fits_per_s=n_plain / tp, evals_per_fit=nev / max(1, n_plain),
                           max_delta_chi2_vs_batched=dmax))
     res["warm_over_plain"] = res["warm"]["fits_per_s"] / res["plain"]["fits_per_s"]
+    res["warm_over_cold_correct_fits"] = res["warm"]["correct_fits_per_s"] / max(res["cold"]["correct_fits_per_s"],
+                                                                                 1e-300)
     eng.close()
     log(f"warm start: {json.dumps(res)}")
     return res
@@ -406,7 +482,11 @@ def main():
     ap.add_argument("--mode", default="m32", choices=["m32", "m64"])
     ap.add_argument("--events", type=float, default=1e7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--both-modes", action="store_true", help="also measure the other precision mode")
+    ap.add_argument("--one-mode", action="store_true", help="skip the other precision mode")
+    ap.add_argument("--cold-only", action="store_true",
+                    help="only the replica-rotated (cold) evaluation loop with the default launch choices "
+                         "(for profiled runs) and exit")
+    ap.add_argument("--no-cpu-all-cores", action="store_true", help="skip the all-cores oracle leg")
     ap.add_argument("--replicas", type=int, default=6,
                     help="event-set replicas cycled for the cold (HBM) figure; 0 skips it")
     ap.add_argument("--no-fits", action="store_true", help="skip the pseudo-experiment fits/s section")
@@ -534,13 +614,15 @@ def main():
         log(f"{mode}: {json.dumps(res)}")
         return res
 
-    def run_cold(mode, R, steps):
+    def run_cold(mode, R, steps, options=None):
         """The same evaluations cycled over R engines that each hold their own
         copy of the event set, so that consecutive folds read different
         buffers whose total exceeds the 256 MB Infinity Cache."""
         engs = []
         for r in range(R):
             e = nf.Engine(desc, mode, stream=stream.cuda_stream)
+            for k, v in (options or {}).items():
+                e.set_option(k, v)
             for d, ev in enumerate(events):
                 e.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
             for d, mu in enumerate(e.expected(start)[0]):
@@ -573,25 +655,56 @@ def main():
         bpe = 12 if mode == "m64" else 8
         fold_us = fold_ms / cnt * 1e3
         achieved = n_in * bpe / (fold_us * 1e-6) / 1e9
-        res = dict(replicas=R, resident_bytes=R * n_in * bpe, evals_per_s=steps / (t1 - t0),
+        res = dict(replicas=R, steps=steps, resident_bytes=R * n_in * bpe, evals_per_s=steps / (t1 - t0),
                    fold_us=fold_us, tail_us=tail_ms / cnt * 1e3,
                    achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS)
         log(f"{mode} cold: {json.dumps(res)}")
         return res
 
+    if args.cold_only:
+        # profiling run: only the replica-rotated loop, default launch choices
+        res = run_cold(args.mode, max(args.replicas, 4), max(args.steps, COLD_STEPS))
+        print(json.dumps(dict(mode=args.mode, cold=res)), flush=True)
+        return
+
+    def roofline(res, cold, copy_gbs):
+        """The fold's roofline entry: HBM-bound, priced with the replica-rotated
+        (cold) fold durations, whose event set does not fit the Infinity Cache;
+        the single-engine (MALL-resident) figure is kept beside it."""
+        warm = res["roofline"]
+        rf = dict(warm)
+        rf["frac_mall_warm"] = warm["frac"]
+        rf["achieved_mall_warm"] = warm["achieved"]
+        rf["fold_us_mall_warm"] = res["fold_us"]
+        if cold is not None:
+            rf["achieved"] = cold["achieved_gbs"]
+            rf["frac"] = cold["frac"]
+            rf["fold_us"] = cold["fold_us"]
+            rf["duration"] = (f"mean fold duration from HIP start/stop events carried by every fold dispatch "
+                              f"(hipExtLaunchKernel) of {cold['steps']} evaluations cycled over "
+                              f"{cold['replicas']} engines holding their own copies of the event set "
+                              f"({cold['resident_bytes'] / 1e6:.0f} MB, more than the 256 MB Infinity Cache), "
+                              "on the engine stream")
+        rf["frac_of_copy_bandwidth"] = rf["achieved"] / copy_gbs
+        rf["copy_bandwidth_gbs"] = copy_gbs
+        rf["frac_whole_evaluation"] = (rf["algorithmic_bytes_per_launch"] / (res["ms_per_step"] * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS)
+        return rf
+
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
+    cold_steps = max(args.steps, COLD_STEPS)
     main_res = run(args.mode)
-    main_res["roofline"]["frac_of_copy_bandwidth"] = main_res["roofline"]["achieved"] / copy_gbs
-    main_res["roofline"]["copy_bandwidth_gbs"] = copy_gbs
-    main_res["roofline"]["frac_whole_evaluation"] = (main_res["roofline"]["algorithmic_bytes_per_launch"]
-                                                     / (main_res["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
-    cold = None
-    if args.replicas > 0:
-        cold = run_cold(args.mode, args.replicas, max(args.steps, 4 * args.replicas))
+    cold = (run_cold(args.mode, args.replicas, cold_steps, main_res["launch_options"]) if args.replicas > 0
+            else None)
+    main_res["roofline"] = roofline(main_res, cold, copy_gbs)
     other = None
-    if args.both_modes:
-        other = run("m64" if args.mode == "m32" else "m32")
+    if not args.one_mode:
+        om = "m64" if args.mode == "m32" else "m32"
+        other = run(om)
+        ocold = run_cold(om, args.replicas, cold_steps, other["launch_options"]) if args.replicas > 0 else None
+        other["roofline"] = roofline(other, ocold, copy_gbs)
+        other["cold"] = ocold
     fits = None
     if not args.no_fits:
         fits = fits_section(nf, synth, torch, stream, args.plain_fits, args.surrogate_samples)
@@ -599,6 +712,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (whole evaluations, about ten seconds)")
         cpu = cpu_baseline(desc, events, thetas[0])
+        if not args.no_cpu_all_cores:
+            log("timing the CPU oracle on every host core (one process per core)")
+            cpu["all_cores"] = cpu_baseline_all_cores(n_events)
 
     line = {
         "metric": "fold+NLL+grad evals/s (1e7-event JUNO-like); pseudo-exp fits/s vs plain",

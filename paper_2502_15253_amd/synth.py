@@ -320,6 +320,129 @@ def config3_events(n=10_000_000):
     return [make_events(n, 1.8, 12.0, 10, 1.0e5, event_seed(3, 0), "c3")]
 
 
+# Conditional splitting of datasets (paper, "Conditional splitting of
+# datasets"): the three Double Chooz histograms FD-I, FD-II and ND split by
+# the reactors in operation (both, reactor 1 only, reactor 2 only: a single
+# source has a unique baseline) and by the neutron-capture type (Gd, H: other
+# binning and other backgrounds), 3 x 3 x 2 = 18 histograms of uneven sizes,
+# plus the reactor-off phases of FD-I and FD-II as one-bin rate terms (second
+# line of Eq. 9: the Poisson probability of the total reactor-off rate; their
+# small residual antineutrino signal is folded like the others).
+SPLIT_PHASES = ("FD-I", "FD-II", "ND")
+SPLIT_REACTORS = ("both", "R1", "R2")
+SPLIT_CAPTURES = ("Gd", "H")
+SPLIT_BASE = {"FD-I": (997.5, 1102.5), "FD-II": (997.5, 1102.5), "ND": (380.0, 420.0)}
+SPLIT_EDGES = {"Gd": uniform_edges(1.0, 7.65, 38), "H": uniform_edges(1.35, 5.9, 26)}
+SPLIT_OFF_EDGES = [1.0, 8.0]
+
+
+def _split_rate(phase, reactors, capture):
+    base = {"FD-I": 4.0e4, "FD-II": 1.0e5, "ND": 2.0e5}[phase]
+    frac = {"both": 0.7, "R1": 0.16, "R2": 0.14}[reactors]
+    return base * frac * (1.0 if capture == "Gd" else 0.45)
+
+
+def split_model():
+    """18 uneven histograms plus two one-bin reactor-off rate terms."""
+    T = TRUTH
+    params = [param("osc.sin2_2t13", T["sin2_2t13"]),
+              param("osc.dm2_ee", T["dm2_ee"], (2.50, 0.10)),
+              param("reactor0.norm", 1.0, (1.0, 0.015)),
+              param("reactor1.norm", 1.0, (1.0, 0.015)),
+              param("residual.norm", 1.0, (1.0, 0.3))]
+    cov_priors = []
+    for cap in SPLIT_CAPTURES:
+        eff = [f"{ph}.{cap}.eff" for ph in SPLIT_PHASES]
+        params += [param(n, 1.0) for n in eff]
+        cov_priors.append(dict(params=eff, mean=[1.0] * 3,
+                               cov=(1e-4 * np.array([[1.0, 0.5, 0.5], [0.5, 1.0, 0.5],
+                                                     [0.5, 0.5, 1.0]])).tolist()))
+    fine = C1_FINE
+    cen = fine_centres(fine["y0"], fine["width"], fine["n"])
+    for cap in SPLIT_CAPTURES:
+        nb = len(SPLIT_EDGES[cap]) - 1
+        params += [param(f"{cap}.flux[{m}]", 0.0, (0.0, 0.03)) for m in range(6)]
+        params += [param(f"{cap}.li9.shape[{i}]", 0.0, (0.0, 0.10)) for i in range(nb)]
+        for ph in SPLIT_PHASES:
+            params += escale_params(f"{ph}.{cap}.escale.")
+    for ph in SPLIT_PHASES:
+        params += [param(f"{ph}.li9.rate", 1.0), param(f"{ph}.fn.rate", 1.0, (1.0, 0.1))]
+        for r in SPLIT_REACTORS:
+            for cap in SPLIT_CAPTURES:
+                params.append(param(f"{ph}.{r}.{cap}.acc.rate", 1.0, (1.0, 0.05)))
+    trng = rng_for(4200)
+    tmpl = {(cap, kind): template_seeded(SPLIT_EDGES[cap], trng)
+            for cap in SPLIT_CAPTURES for kind in ("li9", "fn", "acc")}
+    datasets = []
+    for ph in SPLIT_PHASES:
+        for r in SPLIT_REACTORS:
+            for cap in SPLIT_CAPTURES:
+                edges = SPLIT_EDGES[cap]
+                nb = len(edges) - 1
+                rate = _split_rate(ph, r, cap)
+                b0, b1 = SPLIT_BASE[ph]
+                srcs = {"both": [dict(baseline_m=b0, norm=["reactor0.norm"]),
+                                 dict(baseline_m=b1, norm=["reactor1.norm"])],
+                        "R1": [dict(baseline_m=b0, norm=["reactor0.norm"])],
+                        "R2": [dict(baseline_m=b1, norm=["reactor1.norm"])]}[r]
+                nodes = list(np.linspace(edges[0], edges[-1], 6))
+                bk = 0.05 if cap == "Gd" else 0.25  # H capture: larger accidental background
+                datasets.append(dict(
+                    name=f"{ph}.{r}.{cap}", fine=dict(fine), edges=edges, sources=srcs,
+                    norm=[f"{ph}.{cap}.eff"],
+                    flux=dict(params=[f"{cap}.flux[{m}]" for m in range(6)],
+                              basis=hat_basis(cen, nodes)),
+                    escale=dict(c0=f"{ph}.{cap}.escale.c0", c1=f"{ph}.{cap}.escale.c1",
+                                c2=f"{ph}.{cap}.escale.c2"),
+                    backgrounds=[
+                        dict(name="li9", rate=f"{ph}.li9.rate", scale=0.02 * rate,
+                             template=tmpl[(cap, "li9")],
+                             shape=[f"{cap}.li9.shape[{i}]" for i in range(nb)]),
+                        dict(name="fn", rate=f"{ph}.fn.rate", scale=0.01 * rate,
+                             template=tmpl[(cap, "fn")], shape=None),
+                        dict(name="acc", rate=f"{ph}.{r}.{cap}.acc.rate", scale=bk * rate,
+                             template=tmpl[(cap, "acc")], shape=None),
+                    ]))
+    for ph in ("FD-I", "FD-II"):
+        b0, b1 = SPLIT_BASE[ph]
+        datasets.append(dict(
+            name=f"{ph}.off", fine=dict(fine), edges=list(SPLIT_OFF_EDGES),
+            sources=[dict(baseline_m=b0, norm=["residual.norm"]),
+                     dict(baseline_m=b1, norm=["residual.norm"])],
+            norm=[], flux=None, escale=dict(c0=None, c1=None, c2=None),
+            backgrounds=[
+                dict(name="li9", rate=f"{ph}.li9.rate", scale=60.0, template=[1.0], shape=None),
+                dict(name="fn", rate=f"{ph}.fn.rate", scale=25.0, template=[1.0], shape=None)]))
+    return dict(
+        version=1,
+        osc=dict(formula="eq1", sin2_2t13=dict(param="osc.sin2_2t13"),
+                 dm2_ee=dict(param="osc.dm2_ee"),
+                 sin2_t12=dict(value=T["sin2_t12"]), dm2_21=dict(value=T["dm2_21"])),
+        params=params, cov_priors=cov_priors, datasets=datasets)
+
+
+def split_events(scale=1.0):
+    """Events of the split workload: 1e5 per reactor-on histogram at scale 1
+    (uneven: the single-reactor and H-capture histograms get fewer), 2e4 per
+    reactor-off term with a residual rate of 2 events."""
+    out = []
+    j = 0
+    for ph in SPLIT_PHASES:
+        for r in SPLIT_REACTORS:
+            for cap in SPLIT_CAPTURES:
+                ns = 1 if r != "both" else 2
+                n = int(scale * 1.0e5 * (1.0 if r == "both" else 0.4) * (1.0 if cap == "Gd" else 0.6))
+                out.append(make_events(max(n, 8), 1.8, 10.0, ns, _split_rate(ph, r, cap),
+                                       event_seed(6, j), "c1",
+                                       source_fracs=None if ns == 1 else [0.5, 0.5]))
+                j += 1
+    for _ in ("FD-I", "FD-II"):
+        out.append(make_events(max(int(scale * 2.0e4), 8), 1.8, 10.0, 2, 2.0, event_seed(6, j), "c1",
+                               source_fracs=[0.5, 0.5]))
+        j += 1
+    return out
+
+
 def model_and_events(config, n_events=None):
     if config == 1:
         return config1_model(), config1_events(*(() if n_events is None else (n_events,)))
@@ -327,6 +450,8 @@ def model_and_events(config, n_events=None):
         return config2_model(), config2_events(*(() if n_events is None else (n_events,)))
     if config == 3:
         return config3_model(), config3_events(*(() if n_events is None else (n_events,)))
+    if config == "split":
+        return split_model(), split_events(*(() if n_events is None else (n_events,)))
     raise ValueError(config)
 
 

@@ -481,3 +481,35 @@ def test_asimov_fit_recovers_truth():
     assert r["edm"] < 1e-7
     assert abs(r["theta"][m.index["osc.sin2_2t13"]] - 0.085) < 1e-4
     assert abs(r["theta"][m.index["osc.dm2_ee"]] - 2.5) < 1e-3
+
+
+# ---------------------------------------------------------------- dataset splitting
+
+def test_split_workload_structure_and_rate_terms():
+    """The split workload has 18 reactor-on histograms of uneven sizes and two
+    one-bin reactor-off datasets; the NLL term of a one-bin dataset is the
+    Poisson probability of the total observed rate (second line of Eq. 9),
+    checked against scipy's Poisson log-probability."""
+    desc, events = synth.model_and_events("split", 0.05)
+    m = Model(desc)
+    nbs = [ds.Nb for ds in m.datasets]
+    assert len(nbs) == 20 and nbs[18:] == [1, 1]
+    assert len(set(nbs[:18])) == 2 and len({len(e["weight"]) for e in events[:18]}) >= 4
+    assert [ds.S for ds in m.datasets[:3]] == [2, 2, 1]
+    th = synth.start_vector(desc)
+    mus, ok = LK.expected(m, events, th)
+    assert ok
+    data = [np.round(mu) for mu in mus]
+    # only the off-term differs between the two data sets
+    d2 = [x.copy() for x in data]
+    d2[18] = d2[18] + 7.0
+    f1, f2 = LK.nll(m, events, data, th), LK.nll(m, events, d2, th)
+    mu, n1, n2 = mus[18][0], data[18][0], d2[18][0]
+
+    def dev(n):  # -log P(n; mu) + log P(n; n)
+        return -stats.poisson.logpmf(n, mu) + stats.poisson.logpmf(n, n)
+
+    assert f2 - f1 == pytest.approx(dev(n2) - dev(n1), rel=1e-10, abs=1e-10)
+    # the off-term's expectation: backgrounds plus the folded residual signal
+    bk = [b["scale"] * th[m.index[b["rate"]]] for b in desc["datasets"][18]["backgrounds"]]
+    assert mus[18][0] > sum(bk)
