@@ -11,7 +11,7 @@ on an edge belongs to the upper bin; events outside [y_0, y_K) are dropped.
 """
 import numpy as np
 
-from .oscillation import prob_eq1, prob_3nu
+from .oscillation import prob_eq1, prob_3nu, prob_4nu
 
 
 def fine_edges(ds):
@@ -47,6 +47,10 @@ def baseline_over_energy(ds, events):
 def survival(model, u, osc):
     if model.formula == "eq1":
         return prob_eq1(u, *osc)
+    if model.formula == "4nu":
+        s13, m31, s14, m41 = osc
+        s12, m21 = model.osc_constants
+        return prob_4nu(u, s12, s13, m21, m31, s14, m41)
     return prob_3nu(u, *osc)
 
 

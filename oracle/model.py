@@ -3,9 +3,11 @@
 The model description is a plain dict (JSON-compatible):
   params      list of {name, start, prior: [mean, sigma] | None, fixed}
   cov_priors  list of {params: [names], mean: [...], cov: [[...]]}   (Eq. 6, Eq. 9 third line)
-  osc         {formula: "eq1" | "3nu", <slot>: {param: name} | {value: v}}
+  osc         {formula: "eq1" | "3nu" | "4nu", <slot>: {param: name} | {value: v}}
               eq1 slots: sin2_2t13, dm2_ee, sin2_t12, dm2_21   (Eq. 1)
               3nu slots: sin2_t12, sin2_t13, dm2_21, dm2_31    (exact vacuum form of Eq. 10)
+              4nu slots: sin2_t13, dm2_31, sin2_2t14, dm2_41   (vacuum 3+1, sterile searches)
+                  plus fixed values sin2_t12, dm2_21: {value: v}
   datasets    list of {name, fine: {y0, width, n}, edges, sources: [{baseline_m, norm}],
               norm, flux: {params, basis (M x K)}, escale: {c0, c1, c2},
               backgrounds: [{rate, scale, template, shape}]}
@@ -15,6 +17,9 @@ import numpy as np
 
 EQ1_SLOTS = ("sin2_2t13", "dm2_ee", "sin2_t12", "dm2_21")
 NU3_SLOTS = ("sin2_t12", "sin2_t13", "dm2_21", "dm2_31")
+# 3+1: four slots that may be parameters, and the solar pair, which is fixed
+NU4_SLOTS = ("sin2_t13", "dm2_31", "sin2_2t14", "dm2_41")
+NU4_CONSTANTS = ("sin2_t12", "dm2_21")
 
 
 class Dataset:
@@ -67,9 +72,11 @@ class Model:
                                 np.asarray(c["cov"], dtype=np.float64)))
         osc = desc["osc"]
         self.formula = osc["formula"]
-        slots = EQ1_SLOTS if self.formula == "eq1" else NU3_SLOTS
-        if self.formula not in ("eq1", "3nu"):
+        if self.formula not in ("eq1", "3nu", "4nu"):
             raise ValueError(self.formula)
+        slots = {"eq1": EQ1_SLOTS, "3nu": NU3_SLOTS, "4nu": NU4_SLOTS}[self.formula]
+        self.osc_constants = ([float(osc[c]["value"]) for c in NU4_CONSTANTS]
+                              if self.formula == "4nu" else [])
         self.osc_slots = []
         for s in slots:
             v = osc[s]

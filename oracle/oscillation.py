@@ -14,6 +14,7 @@ PHASE_K = 1.266932679039099
 DM2_EE_UNIT = 1e-3
 DM2_31_UNIT = 1e-3
 DM2_21_UNIT = 1e-5
+DM2_41_UNIT = 1e-3
 
 
 def sin2_t13_from_sin2_2t13(s2_2t13):
@@ -93,3 +94,30 @@ def prob_eq10(u, s2_t12, s2_t13, dm2_21, dm2_31):
 def prob_two_flavour(u, s2_2t, dm2_ev2):
     """Textbook two-flavour survival probability 1 - sin^2(2th) sin^2(dm2 L/4E), dm2 in eV^2."""
     return 1.0 - s2_2t * np.sin(PHASE_K * dm2_ev2 * u) ** 2
+
+
+def sin2_t14_from_sin2_2t14(s2_2t14):
+    """sin^2(theta14) from sin^2(2 theta14), branch theta14 <= pi/4."""
+    return 0.5 * (1.0 - np.sqrt(1.0 - s2_2t14))
+
+
+def prob_4nu(u, s2_t12, s2_t13, dm2_21, dm2_31, s2_2t14, dm2_41):
+    """Vacuum 3+1 electron-antineutrino survival probability (the model of the
+    paper's sterile-neutrino searches, "Extensions of the framework"; the
+    paper does not print it).
+
+    P = 1 - 4 sum_{i<j} |Ue_i|^2 |Ue_j|^2 sin^2(dm2_ji L / 4E), i, j = 1..4, with
+    the first row of U = R34 R24 R14 R23 R13 R12 (no CP phases):
+    |Ue1|^2 = c12^2 c13^2 c14^2, |Ue2|^2 = s12^2 c13^2 c14^2, |Ue3|^2 = s13^2 c14^2,
+    |Ue4|^2 = s14^2; dm2_41 in 1e-3 eV^2 (fit units), dm2_4j = dm2_41 - dm2_j1.
+    """
+    s2_t14 = sin2_t14_from_sin2_2t14(s2_2t14)
+    c2_12, c2_13, c2_14 = 1.0 - s2_t12, 1.0 - s2_t13, 1.0 - s2_t14
+    ue = [c2_12 * c2_13 * c2_14, s2_t12 * c2_13 * c2_14, s2_t13 * c2_14, s2_t14]
+    m2 = [0.0, dm2_21 * DM2_21_UNIT, dm2_31 * DM2_31_UNIT, dm2_41 * DM2_41_UNIT]
+    p = 1.0
+    for i in range(4):
+        for j in range(i + 1, 4):
+            d = PHASE_K * (m2[j] - m2[i]) * u
+            p = p - 4.0 * ue[i] * ue[j] * np.sin(d) ** 2
+    return p

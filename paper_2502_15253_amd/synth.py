@@ -443,6 +443,58 @@ def split_events(scale=1.0):
     return out
 
 
+# Sterile-neutrino search (paper, "Extensions of the framework"): the
+# near/far short-baseline layout with the 3+1 survival probability; the
+# tested parameters are sin^2(2 theta14) and dm2_41 (1e-3 eV^2 units), the
+# conventional oscillation parameters are nuisances (sin^2 theta13 free,
+# dm2_31 with a prior; theta12 and dm2_21 fixed at their world averages).
+STERILE_DM2_41 = 50.0  # 0.05 eV^2 start value
+
+
+def sterile_model():
+    """Near (400 m) and far (1050 m) detector, two reactors each, 40 bins each, 3+1."""
+    T = TRUTH
+    params = [param("osc.sin2_t13", T["sin2_t13"]),
+              param("osc.dm2_31", T["dm2_31"], (2.53, 0.05)),
+              param("osc.sin2_2t14", 0.0),
+              param("osc.dm2_41", STERILE_DM2_41, fixed=True),
+              param("reactor0.norm", 1.0, (1.0, 0.015)),
+              param("reactor1.norm", 1.0, (1.0, 0.015))]
+    params += [param(f"flux[{m}]", 0.0, (0.0, 0.05)) for m in range(4)]
+    names, base, rates = ["FD", "ND"], [(997.5, 1102.5), (380.0, 420.0)], [1.0e5, 2.0e5]
+    fine = C1_FINE
+    cen = fine_centres(fine["y0"], fine["width"], fine["n"])
+    datasets = []
+    for d, nm in enumerate(names):
+        params += [param(f"{nm}.eff", 1.0, (1.0, 0.01)), *escale_params(f"{nm}.escale."),
+                   param(f"{nm}.bkg.flat.rate", 1.0, (1.0, 0.10)), param(f"{nm}.bkg.exp.rate", 1.0)]
+        datasets.append(dict(
+            name=nm, fine=dict(fine), edges=C1_EDGES,
+            sources=[dict(baseline_m=base[d][0], norm=["reactor0.norm"]),
+                     dict(baseline_m=base[d][1], norm=["reactor1.norm"])],
+            norm=[f"{nm}.eff"],
+            flux=dict(params=[f"flux[{m}]" for m in range(4)],
+                      basis=hat_basis(cen, [1.0, 10.0 / 3.0, 17.0 / 3.0, 8.0])),
+            escale=dict(c0=f"{nm}.escale.c0", c1=f"{nm}.escale.c1", c2=f"{nm}.escale.c2"),
+            backgrounds=[
+                dict(name="flat", rate=f"{nm}.bkg.flat.rate", scale=0.015 * rates[d],
+                     template=template_flat(C1_EDGES), shape=None),
+                dict(name="exp", rate=f"{nm}.bkg.exp.rate", scale=0.02 * rates[d],
+                     template=template_exp(C1_EDGES, 2.0), shape=None)]))
+    return dict(
+        version=1,
+        osc=dict(formula="4nu", sin2_t13=dict(param="osc.sin2_t13"), dm2_31=dict(param="osc.dm2_31"),
+                 sin2_2t14=dict(param="osc.sin2_2t14"), dm2_41=dict(param="osc.dm2_41"),
+                 sin2_t12=dict(value=T["sin2_t12"]), dm2_21=dict(value=T["dm2_21"])),
+        params=params, cov_priors=[], datasets=datasets)
+
+
+def sterile_events(n=100_000):
+    rates = [1.0e5, 2.0e5]
+    return [make_events(n, 1.8, 10.0, 2, rates[d], event_seed(7, d), "c1", source_fracs=[0.5, 0.5])
+            for d in range(2)]
+
+
 def model_and_events(config, n_events=None):
     if config == 1:
         return config1_model(), config1_events(*(() if n_events is None else (n_events,)))
@@ -450,6 +502,8 @@ def model_and_events(config, n_events=None):
         return config2_model(), config2_events(*(() if n_events is None else (n_events,)))
     if config == 3:
         return config3_model(), config3_events(*(() if n_events is None else (n_events,)))
+    if config == "sterile":
+        return sterile_model(), sterile_events(*(() if n_events is None else (n_events,)))
     if config == "split":
         return split_model(), split_events(*(() if n_events is None else (n_events,)))
     raise ValueError(config)

@@ -513,3 +513,84 @@ def test_split_workload_structure_and_rate_terms():
     # the off-term's expectation: backgrounds plus the folded residual signal
     bk = [b["scale"] * th[m.index[b["rate"]]] for b in desc["datasets"][18]["backgrounds"]]
     assert mus[18][0] > sum(bk)
+
+
+# ---------------------------------------------------------------- 3+1 (sterile)
+
+def _ue_row_4(s2_t12, s2_t13, s2_t14):
+    """|U_ej|^2, j = 1..4, from the product of 4 x 4 rotations R34 R24 R14 R23 R13 R12."""
+    t12, t13, t14 = (np.arcsin(np.sqrt(x)) for x in (s2_t12, s2_t13, s2_t14))
+
+    def rot(i, j, t):
+        R = np.eye(4)
+        R[i, i] = R[j, j] = np.cos(t)
+        R[i, j] = np.sin(t)
+        R[j, i] = -np.sin(t)
+        return R
+
+    U = rot(2, 3, 0.6) @ rot(1, 3, 0.2) @ rot(0, 3, t14) @ rot(1, 2, 0.7) @ rot(0, 2, t13) @ rot(0, 1, t12)
+    return U[0] ** 2
+
+
+@pytest.mark.parametrize("dm2_41", [0.5, 30.0, 400.0])
+def test_4nu_equals_quantum_amplitude_with_four_mass_states(dm2_41):
+    rng = np.random.default_rng(71)
+    u = rng.uniform(100.0, 2.0e4, 3000)
+    s12, s13, s2_2t14, m21, m31 = 0.307, 0.0218, 0.08, 7.53, 2.53
+    s14 = osc.sin2_t14_from_sin2_2t14(s2_2t14)
+    row = _ue_row_4(s12, s13, s14)
+    m2 = np.array([0.0, m21 * 1e-5, m31 * 1e-3, dm2_41 * 1e-3])
+    amp = (row[None, :] * np.exp(-1j * 2.0 * osc.PHASE_K * np.outer(u, m2))).sum(axis=1)
+    ref = np.abs(amp) ** 2
+    p = osc.prob_4nu(u, s12, s13, m21, m31, s2_2t14, dm2_41)
+    # both routes round phases of up to x_max rad: allow a few ulp of x_max
+    x_max = 2.0 * osc.PHASE_K * m2.max() * u.max()
+    assert np.max(np.abs(p - ref)) < 1e-14 + 4e-16 * x_max
+    assert np.all(p <= 1.0 + 1e-15) and np.all(p >= -1e-15)
+
+
+def test_4nu_reduces_to_3nu_without_sterile_mixing():
+    rng = np.random.default_rng(72)
+    u = rng.uniform(50.0, 3.0e4, 5000)
+    for m31 in (2.53, -2.45):
+        p4 = osc.prob_4nu(u, 0.307, 0.0218, 7.53, m31, 0.0, 17.0)
+        p3 = osc.prob_3nu(u, 0.307, 0.0218, 7.53, m31)
+        assert np.max(np.abs(p4 - p3)) < 1e-15
+
+
+def test_4nu_two_flavour_limit():
+    u = np.linspace(10.0, 2000.0, 777)
+    p = osc.prob_4nu(u, 0.0, 0.0, 7.53, 2.53, 0.1, 250.0)
+    assert np.max(np.abs(p - osc.prob_two_flavour(u, 0.1, 0.25))) < 1e-15
+
+
+def test_4nu_fast_sterile_oscillation_averages_to_half():
+    """With dm2_41 large the sterile terms average to 1/2 over a narrow L/E
+    window in which the three-flavour phases barely move: the mean equals
+    c14^4 times the three-flavour oscillation plus the constant 1 - sin^2(2th14)/2
+    (since |Ue1|^2 + |Ue2|^2 + |Ue3|^2 = c14^2)."""
+    s12, s13, m21, m31, s2_2t14, m41 = 0.307, 0.0218, 7.53, 2.53, 0.1, 2.0e5  # 200 eV^2
+    u0 = 350.0
+    period = np.pi / (osc.PHASE_K * m41 * 1e-3)     # of sin^2 in u
+    n = 400
+    u = u0 + period * (np.arange(200 * n) + 0.5) / n   # 200 whole periods, midpoint rule
+    pbar = osc.prob_4nu(u, s12, s13, m21, m31, s2_2t14, m41).mean()
+    s14 = osc.sin2_t14_from_sin2_2t14(s2_2t14)
+    c14_4 = (1.0 - s14) ** 2
+    osc3 = 1.0 - osc.prob_3nu(u, s12, s13, m21, m31).mean()
+    assert pbar == pytest.approx(1.0 - c14_4 * osc3 - 0.5 * s2_2t14, abs=2e-6)
+
+
+def test_sterile_workload_at_zero_mixing_is_the_three_flavour_model():
+    """The 3+1 model with sin^2(2 theta14) = 0 folds exactly the spectra of the
+    same layout with the exact three-flavour probability."""
+    desc, events = synth.model_and_events("sterile", 20000)
+    d3 = json.loads(json.dumps(desc))
+    T = synth.TRUTH
+    d3["osc"] = dict(formula="3nu", sin2_t12=dict(value=T["sin2_t12"]), sin2_t13=dict(param="osc.sin2_t13"),
+                     dm2_21=dict(value=T["dm2_21"]), dm2_31=dict(param="osc.dm2_31"))
+    th = synth.start_vector(desc)
+    m4, m3 = Model(desc), Model(d3)
+    assert th[m4.index["osc.sin2_2t14"]] == 0.0
+    for a, b in zip(LK.expected(m4, events, th)[0], LK.expected(m3, events, th)[0]):
+        assert np.max(np.abs(a - b) / b) < 1e-14
