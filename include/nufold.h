@@ -60,7 +60,7 @@ typedef struct nf_ctx nf_ctx;
  * framework", the configuration component). Schema:
  *   {"params": [{"name", "start", "prior": [mean, sigma] | null, "fixed"}],
  *    "cov_priors": [{"params": [names], "mean": [..], "cov": [[..]]}],
- *    "osc": {"formula": "eq1" | "3nu", <slot>: {"param": name} | {"value": v}},
+ *    "osc": {"formula": "eq1" | "3nu" | "4nu", <slot>: {"param": name} | {"value": v}},
  *    "datasets": [{"fine": {"y0", "width", "n"}, "edges": [Nb+1],
  *                  "sources": [{"baseline_m", "norm": [names]}], "norm": [names],
  *                  "flux": {"params": [M names], "basis": [M][n]},
@@ -69,6 +69,10 @@ typedef struct nf_ctx nf_ctx;
  *                                   "template": [Nb], "shape": [Nb names|null] | null}]}]}
  * eq1 slots: sin2_2t13, dm2_ee, sin2_t12, dm2_21 (Eq. 1).
  * 3nu slots: sin2_t12, sin2_t13, dm2_21, dm2_31 (exact vacuum form; sign of dm2_31 = ordering).
+ * 4nu slots: sin2_t13, dm2_31, sin2_2t14, dm2_41 (vacuum 3+1 form of the paper's sterile-neutrino
+ *   searches, "Extensions of the framework": P = 1 - sum_{i<j} 4|U_ei|^2|U_ej|^2 sin^2(dm2_ji L/4E)
+ *   over four mass states, |U_e1..4|^2 = c12 c13 c14, s12 c13 c14, s13 c14, s14 in squared sines
+ *   and cosines; dm2_41 in 1e-3 eV^2), plus "sin2_t12" and "dm2_21" as {"value": v} constants.
  * model_json: NUL-terminated, caller-owned, copied. mode: NF_M64 or NF_M32.
  * hip_stream: hipStream_t to order device work on, or NULL for a stream the
  * context creates and owns. On error *out is NULL and the return code says why

@@ -296,10 +296,19 @@ void parse_model(nf_ctx* c, const char* text) {
     const std::string& f = o.at("formula").string();
     static const char* eq1[NSLOT] = {"sin2_2t13", "dm2_ee", "sin2_t12", "dm2_21"};
     static const char* nu3[NSLOT] = {"sin2_t12", "sin2_t13", "dm2_21", "dm2_31"};
+    static const char* nu4[NSLOT] = {"sin2_t13", "dm2_31", "sin2_2t14", "dm2_41"};
     const char** slots;
     if (f == "eq1") { c->osc.formula = FORM_EQ1; slots = eq1; }
     else if (f == "3nu") { c->osc.formula = FORM_3NU; slots = nu3; }
-    else fail(NF_EPARSE, "osc.formula must be eq1 or 3nu");
+    else if (f == "4nu") {
+      // 3+1: the solar pair is a pair of constants
+      c->osc.formula = FORM_4NU;
+      slots = nu4;
+      c->osc.cst[0] = o.at("sin2_t12").at("value").number();
+      c->osc.cst[1] = o.at("dm2_21").at("value").number();
+    }
+    else fail(NF_EPARSE, "osc.formula must be eq1, 3nu or 4nu");
+    c->osc.fp32_phase = c->mode == NF_M32 ? 1 : 0;
     for (int j = 0; j < NSLOT; ++j) {
       const Json& s = o.at(slots[j]);
       if (s.has("param")) {

@@ -8,12 +8,13 @@
 // segment, the fold streams the sorted events once and accumulates
 //   eq1 (Eq. 1):   C_ee, C_21, Q_ee, Q_21
 //   3nu (exact):   C_21, C_31, C_32, Q_21, Q_31, Q_32
+//   4nu (3+1):     C and Q of 21, 31, 32, 41, 42, 43
 // with C_ab = sum_e w_e cos x_ab,e and Q_ab = sum_e w_e u_e sin x_ab,e,
 // u_e = L/E. The bin-stage kernel turns these moments into the oscillated
 // spectrum sum_e w_e P_e and its derivatives with respect to every
 // oscillation parameter (forward-mode Jacobian, exact), so mixing-angle
-// changes never re-read events. x_32 = x_31 - x_21 comes from the two
-// computed sin/cos pairs by angle subtraction.
+// changes never re-read events. Only the phases 21, 31 (and 41) are
+// computed; the others come from their sin/cos pairs by angle subtraction.
 //
 // Layout: u[] and w[] are SoA, sorted by segment, every segment padded with
 // zero-weight events to a multiple of 4, so each lane reads 4 consecutive
@@ -46,8 +47,6 @@ __device__ __forceinline__ double slot_val(const OscPlan& o, const double* th, i
   return p >= 0 ? th[p] : o.slot_value[j];
 }
 
-// Angular frequencies a (rad per m/MeV) of the two computed phases x = a * u.
-
 // Streaming loads of the event arrays in the single evaluation: each event is
 // read once per evaluation, so the loads carry the non-temporal hint and do
 // not displace the bin-stage kernel's inputs and code from the caches. (The
@@ -64,77 +63,79 @@ __device__ __forceinline__ float4 load_stream4(const float* p) {
 }
 
 template <int FORM>
-__device__ __forceinline__ void fold_freqs(const OscPlan& o, const double* th, double& a1, double& a2) {
-  if (FORM == FORM_EQ1) {
-    a1 = TWO_PHASE_K * UNIT_1EM3 * slot_val(o, th, 1);   // dm2_ee
-    a2 = TWO_PHASE_K * UNIT_1EM5 * slot_val(o, th, 3);   // dm2_21
+constexpr int form_moments() { return FORM == FORM_EQ1 ? 4 : FORM == FORM_3NU ? 6 : 12; }
+template <int FORM>
+constexpr int form_phases() { return FORM == FORM_4NU ? 3 : 2; }
+
+// Moments of one event from the sin/cos of its computed phases (s[q], c[q]):
+//   eq1: C_ee, C_21, Q_ee, Q_21
+//   3nu: C_21, C_31, C_32, Q_21, Q_31, Q_32           (32 = 31 - 21)
+//   4nu: C of 21, 31, 32, 41, 42, 43, then their Q    (4j = 41 - j1)
+template <int FORM, typename T>
+__device__ __forceinline__ void accum_moments(T w, T wu, const T* s, const T* c, T* m) {
+  if constexpr (FORM == FORM_EQ1) {
+    m[0] = fma(w, c[0], m[0]);
+    m[1] = fma(w, c[1], m[1]);
+    m[2] = fma(wu, s[0], m[2]);
+    m[3] = fma(wu, s[1], m[3]);
+  } else if constexpr (FORM == FORM_3NU) {
+    const T c3 = fma(c[1], c[0], s[1] * s[0]);
+    const T s3 = fma(s[1], c[0], -(c[1] * s[0]));
+    m[0] = fma(w, c[0], m[0]);
+    m[1] = fma(w, c[1], m[1]);
+    m[2] = fma(w, c3, m[2]);
+    m[3] = fma(wu, s[0], m[3]);
+    m[4] = fma(wu, s[1], m[4]);
+    m[5] = fma(wu, s3, m[5]);
   } else {
-    a1 = TWO_PHASE_K * UNIT_1EM5 * slot_val(o, th, 2);   // dm2_21
-    a2 = TWO_PHASE_K * UNIT_1EM3 * slot_val(o, th, 3);   // dm2_31
+    const T c32 = fma(c[1], c[0], s[1] * s[0]), s32 = fma(s[1], c[0], -(c[1] * s[0]));
+    const T c42 = fma(c[2], c[0], s[2] * s[0]), s42 = fma(s[2], c[0], -(c[2] * s[0]));
+    const T c43 = fma(c[2], c[1], s[2] * s[1]), s43 = fma(s[2], c[1], -(c[2] * s[1]));
+    m[0] = fma(w, c[0], m[0]);
+    m[1] = fma(w, c[1], m[1]);
+    m[2] = fma(w, c32, m[2]);
+    m[3] = fma(w, c[2], m[3]);
+    m[4] = fma(w, c42, m[4]);
+    m[5] = fma(w, c43, m[5]);
+    m[6] = fma(wu, s[0], m[6]);
+    m[7] = fma(wu, s[1], m[7]);
+    m[8] = fma(wu, s32, m[8]);
+    m[9] = fma(wu, s[2], m[9]);
+    m[10] = fma(wu, s42, m[10]);
+    m[11] = fma(wu, s43, m[11]);
   }
 }
 
-
 template <int FORM>
-__device__ __forceinline__ void accum64(double u, float wf, double a1, double a2, double* m) {
+__device__ __forceinline__ void accum64(double u, float wf, const double* a, double* m) {
+  constexpr int NPH = form_phases<FORM>();
   const double w = (double)wf;
   const double wu = w * u;
-  double s1, c1, s2, c2;
-  sincos_fold(a1 * u, s1, c1);
-  sincos_fold(a2 * u, s2, c2);
-  if (FORM == FORM_EQ1) {
-    m[0] = fma(w, c1, m[0]);
-    m[1] = fma(w, c2, m[1]);
-    m[2] = fma(wu, s1, m[2]);
-    m[3] = fma(wu, s2, m[3]);
-  } else {
-    // 1 = 21, 2 = 31, 32 = 31 - 21
-    const double c3 = fma(c2, c1, s2 * s1);
-    const double s3 = fma(s2, c1, -(c2 * s1));
-    m[0] = fma(w, c1, m[0]);
-    m[1] = fma(w, c2, m[1]);
-    m[2] = fma(w, c3, m[2]);
-    m[3] = fma(wu, s1, m[3]);
-    m[4] = fma(wu, s2, m[4]);
-    m[5] = fma(wu, s3, m[5]);
-  }
+  double s[NPH], c[NPH];
+#pragma unroll
+  for (int q = 0; q < NPH; ++q) sincos_fold(a[q] * u, s[q], c[q]);
+  accum_moments<FORM, double>(w, wu, s, c, m);
 }
 
-// FP32 path: phases in revolutions t = x / 2pi; hardware sin/cos take
-// revolutions. The frequency is split in two floats (bh + bl): bl holds what
-// an FP32 bh cannot, so no phase error common to all events builds up with
-// x. The product bh * u is rounded once; that error is at most half an ulp
-// of t, the same order as the FP32 rounding of u itself, and it varies from
-// event to event, so the segment sums average it out.
-__device__ __forceinline__ float phase_rev(float u, float bh, float bl) {
-  const float p = bh * u;
-  const float fr = __builtin_amdgcn_fractf(p);  // p - floor(p) in one instruction
-  return fmaf(bl, u, fr);
-}
-
+// FP32 path: phases in revolutions, t = fract(f u) with the FP32 frequency
+// f = fp32_rev(a) (the product rounded once); hardware sin/cos take
+// revolutions. The moments are those of the frequency 2 pi f; the coefficient
+// rows correct them to a at first order (fp32_frequency_correction), which
+// removes the systematic phase error an FP32 frequency would leave. (Adding
+// the remainder of the frequency per event instead would be lost whenever it
+// is below half an ulp of the phase, as at short baselines.)
 template <int FORM>
-__device__ __forceinline__ void accum32(float u, float w, float b1h, float b1l, float b2h, float b2l,
-                                        float* m) {
+__device__ __forceinline__ void accum32(float u, float w, const float* f, float* m) {
+  constexpr int NPH = form_phases<FORM>();
   const float wu = w * u;
-  const float t1 = phase_rev(u, b1h, b1l);
-  const float t2 = phase_rev(u, b2h, b2l);
-  const float s1 = __builtin_amdgcn_sinf(t1), c1 = __builtin_amdgcn_cosf(t1);
-  const float s2 = __builtin_amdgcn_sinf(t2), c2 = __builtin_amdgcn_cosf(t2);
-  if (FORM == FORM_EQ1) {
-    m[0] = fmaf(w, c1, m[0]);
-    m[1] = fmaf(w, c2, m[1]);
-    m[2] = fmaf(wu, s1, m[2]);
-    m[3] = fmaf(wu, s2, m[3]);
-  } else {
-    const float c3 = fmaf(c2, c1, s2 * s1);
-    const float s3 = fmaf(s2, c1, -(c2 * s1));
-    m[0] = fmaf(w, c1, m[0]);
-    m[1] = fmaf(w, c2, m[1]);
-    m[2] = fmaf(w, c3, m[2]);
-    m[3] = fmaf(wu, s1, m[3]);
-    m[4] = fmaf(wu, s2, m[4]);
-    m[5] = fmaf(wu, s3, m[5]);
+  float s[NPH], c[NPH];
+#pragma unroll
+  for (int q = 0; q < NPH; ++q) {
+    const float t = __builtin_amdgcn_fractf(f[q] * u);  // p - floor(p) in one instruction
+    s[q] = __builtin_amdgcn_sinf(t);
+    c[q] = __builtin_amdgcn_cosf(t);
   }
+  accum_moments<FORM, float>(w, wu, s, c, m);
 }
 
 template <int NM>
@@ -205,7 +206,7 @@ __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const dou
     if (lane < 5) {
       int z = 0;  // opaque zero: keeps the coefficient loads here (see below)
       asm volatile("" : "+v"(z));
-      const double* c0 = cf + 8 * lane + z;
+      const double* c0 = cf + CF_STRIDE * lane + z;
       double r = 0.0;
 #pragma unroll
       for (int c = 0; c <= NM; ++c) r += c0[c] * M[c];
@@ -250,7 +251,7 @@ __device__ void fold_bin_epilogue(const FoldArgs& a, const double* cf, const dou
         const double Mc = src == 0 ? M[c] : load_agent(&F.segm[(int64_t)c * F.G + g]);
         Sv += c0[c] * Mc;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) gj[j] += c0[8 * (j + 1) + c] * Mc;
+        for (int j = 0; j < 4; ++j) gj[j] += c0[CF_STRIDE * (j + 1) + c] * Mc;
       }
     }
     const int* nl = F.fs_nl + NLMAX * (fs0 + s);
@@ -317,8 +318,8 @@ __device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf,
 
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
-  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
-  __shared__ double cfw[4][40];  // coefficient rows per wavefront (blocks of at most 256 threads)
+  constexpr int NM = form_moments<FORM>();
+  __shared__ double cfw[4][CF_SIZE];  // coefficient rows per wavefront (blocks of at most 256 threads)
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
@@ -326,8 +327,8 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   double* cf = cfw[threadIdx.x >> 6];
   ItemEpi ep{};
   double thv[NLMAX];
-  double a1, a2;
-  fold_freqs<FORM>(a.osc, a.theta, a1, a2);
+  double af[3];
+  osc_freqs_form<FORM>(a.osc, a.theta, af);
   const WorkItem it = a.items[item];
   const double* __restrict__ u = static_cast<const double*>(a.u);
   const float* __restrict__ w = a.w;
@@ -349,10 +350,10 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   item_prefetch(a, item, ep, thv);
   wave_coefficients(a, cf);
   auto fold4 = [&](const double2& pp, const double2& qq, const float4& ww) {
-    accum64<FORM>(pp.x, ww.x, a1, a2, m);
-    accum64<FORM>(pp.y, ww.y, a1, a2, m);
-    accum64<FORM>(qq.x, ww.z, a1, a2, m);
-    accum64<FORM>(qq.y, ww.w, a1, a2, m);
+    accum64<FORM>(pp.x, ww.x, af, m);
+    accum64<FORM>(pp.y, ww.y, af, m);
+    accum64<FORM>(qq.x, ww.z, af, m);
+    accum64<FORM>(qq.y, ww.w, af, m);
   };
   // three register sets rotate: each step's loads are issued two steps ahead
   // of its folding (the scheduling barriers keep them ahead of the
@@ -383,9 +384,9 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
 
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
-  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
-  constexpr double INV_2PI = 0.15915494309189533577;
-  __shared__ double cfw[4][40];  // coefficient rows per wavefront (blocks of at most 256 threads)
+  constexpr int NM = form_moments<FORM>();
+  constexpr int NPH = form_phases<FORM>();
+  __shared__ double cfw[4][CF_SIZE];  // coefficient rows per wavefront (blocks of at most 256 threads)
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
@@ -393,11 +394,11 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   double* cf = cfw[threadIdx.x >> 6];
   ItemEpi ep{};
   double thv[NLMAX];
-  double a1, a2;
-  fold_freqs<FORM>(a.osc, a.theta, a1, a2);
-  const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
-  const float b1h = (float)r1, b1l = (float)(r1 - (double)b1h);
-  const float b2h = (float)r2, b2l = (float)(r2 - (double)b2h);
+  double af[3];
+  osc_freqs_form<FORM>(a.osc, a.theta, af);
+  float fr[NPH];
+#pragma unroll
+  for (int q = 0; q < NPH; ++q) fr[q] = fp32_rev(af[q]);
   const WorkItem it = a.items[item];
   const float* __restrict__ u = static_cast<const float*>(a.u);
   const float* __restrict__ w = a.w;
@@ -420,10 +421,10 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   item_prefetch(a, item, ep, thv);
   wave_coefficients(a, cf);
   auto fold4 = [&](const float4& uu, const float4& ww) {
-    accum32<FORM>(uu.x, ww.x, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(uu.y, ww.y, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(uu.z, ww.z, b1h, b1l, b2h, b2l, mf);
-    accum32<FORM>(uu.w, ww.w, b1h, b1l, b2h, b2l, mf);
+    accum32<FORM>(uu.x, ww.x, fr, mf);
+    accum32<FORM>(uu.y, ww.y, fr, mf);
+    accum32<FORM>(uu.z, ww.z, fr, mf);
+    accum32<FORM>(uu.w, ww.w, fr, mf);
   };
   // four register sets rotate: each step's loads are issued three steps
   // ahead of its folding (the scheduling barriers keep them ahead of the
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
 // minimiser has stopped or when its oscillation slot values equal those of
 // its previous fold (its partials are still valid).
 template <int FORM>
-__device__ __forceinline__ bool batch_fit_active(const BatchFoldArgs& a, int f, double& a1, double& a2) {
+__device__ __forceinline__ bool batch_fit_active(const BatchFoldArgs& a, int f, double* af) {
   if (f >= a.B) return false;
   if (a.hdr && a.hdr[f].status != FIT_RUNNING) return false;
   const double* th = a.theta + (int64_t)f * a.P;
@@ -498,24 +499,24 @@ __device__ __forceinline__ bool batch_fit_active(const BatchFoldArgs& a, int f, 
     for (int j = 0; j < NSLOT; ++j) same = same && (slot_val(a.osc, th, j) == a.osc_last[4 * f + j]);
     if (same) return false;
   }
-  fold_freqs<FORM>(a.osc, th, a1, a2);
+  osc_freqs_form<FORM>(a.osc, th, af);
   return true;
 }
 
 template <int FORM, int FT>
 __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
-  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
+  constexpr int NM = form_moments<FORM>();
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   if (item >= a.nitems) return;
   const int f0 = blockIdx.y * FT;
-  double a1[FT], a2[FT];
+  double af[FT][3];
   bool act[FT];
   bool any = false;
 #pragma unroll
   for (int j = 0; j < FT; ++j) {
-    a1[j] = a2[j] = 0.0;
-    act[j] = batch_fit_active<FORM>(a, f0 + j, a1[j], a2[j]);
+    af[j][0] = af[j][1] = af[j][2] = 0.0;
+    act[j] = batch_fit_active<FORM>(a, f0 + j, af[j]);
     any = any || act[j];
   }
   if (!any) return;
@@ -534,10 +535,10 @@ __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
 #pragma unroll
     for (int j = 0; j < FT; ++j) {
       if (!act[j]) continue;
-      accum64<FORM>(u01.x, w4.x, a1[j], a2[j], m[j]);
-      accum64<FORM>(u01.y, w4.y, a1[j], a2[j], m[j]);
-      accum64<FORM>(u23.x, w4.z, a1[j], a2[j], m[j]);
-      accum64<FORM>(u23.y, w4.w, a1[j], a2[j], m[j]);
+      accum64<FORM>(u01.x, w4.x, af[j], m[j]);
+      accum64<FORM>(u01.y, w4.y, af[j], m[j]);
+      accum64<FORM>(u23.x, w4.z, af[j], m[j]);
+      accum64<FORM>(u23.y, w4.w, af[j], m[j]);
     }
   }
 #pragma unroll
@@ -547,23 +548,22 @@ __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
 
 template <int FORM, int FT>
 __global__ __launch_bounds__(256) void fold_batch_m32_kernel(BatchFoldArgs a) {
-  constexpr int NM = FORM == FORM_EQ1 ? 4 : 6;
-  constexpr double INV_2PI = 0.15915494309189533577;
+  constexpr int NM = form_moments<FORM>();
+  constexpr int NPH = form_phases<FORM>();
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   if (item >= a.nitems) return;
   const int f0 = blockIdx.y * FT;
-  float bh1[FT], bl1[FT], bh2[FT], bl2[FT];
+  float fr[FT][NPH];
   bool act[FT];
   bool any = false;
 #pragma unroll
   for (int j = 0; j < FT; ++j) {
-    double a1 = 0.0, a2 = 0.0;
-    act[j] = batch_fit_active<FORM>(a, f0 + j, a1, a2);
+    double af[3] = {0.0, 0.0, 0.0};
+    act[j] = batch_fit_active<FORM>(a, f0 + j, af);
     any = any || act[j];
-    const double r1 = a1 * INV_2PI, r2 = a2 * INV_2PI;
-    bh1[j] = (float)r1; bl1[j] = (float)(r1 - (double)bh1[j]);
-    bh2[j] = (float)r2; bl2[j] = (float)(r2 - (double)bh2[j]);
+#pragma unroll
+    for (int q = 0; q < NPH; ++q) fr[j][q] = fp32_rev(af[q]);
   }
   if (!any) return;
   const WorkItem it = a.items[item];
@@ -580,10 +580,10 @@ __global__ __launch_bounds__(256) void fold_batch_m32_kernel(BatchFoldArgs a) {
 #pragma unroll
     for (int j = 0; j < FT; ++j) {
       if (!act[j]) continue;
-      accum32<FORM>(u4.x, w4.x, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
-      accum32<FORM>(u4.y, w4.y, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
-      accum32<FORM>(u4.z, w4.z, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
-      accum32<FORM>(u4.w, w4.w, bh1[j], bl1[j], bh2[j], bl2[j], mf[j]);
+      accum32<FORM>(u4.x, w4.x, fr[j], mf[j]);
+      accum32<FORM>(u4.y, w4.y, fr[j], mf[j]);
+      accum32<FORM>(u4.z, w4.z, fr[j], mf[j]);
+      accum32<FORM>(u4.w, w4.w, fr[j], mf[j]);
     }
   }
 #pragma unroll
@@ -605,10 +605,12 @@ hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t strea
     constexpr int T = decltype(tile)::value;
     if (mode == 0) {
       if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_EQ1, T>), grid, block, 0, stream, a);
-      else hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
+      else if (a.osc.formula == FORM_3NU) hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
+      else hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_4NU, T>), grid, block, 0, stream, a);
     } else {
       if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL((fold_batch_m32_kernel<FORM_EQ1, T>), grid, block, 0, stream, a);
-      else hipLaunchKernelGGL((fold_batch_m32_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
+      else if (a.osc.formula == FORM_3NU) hipLaunchKernelGGL((fold_batch_m32_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
+      else hipLaunchKernelGGL((fold_batch_m32_kernel<FORM_4NU, T>), grid, block, 0, stream, a);
     }
   };
   switch (ft) {
@@ -634,10 +636,12 @@ hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t strea
   };
   if (mode == 0) {
     if (a.osc.formula == FORM_EQ1) go(fold_m64_kernel<FORM_EQ1>);
-    else go(fold_m64_kernel<FORM_3NU>);
+    else if (a.osc.formula == FORM_3NU) go(fold_m64_kernel<FORM_3NU>);
+    else go(fold_m64_kernel<FORM_4NU>);
   } else {
     if (a.osc.formula == FORM_EQ1) go(fold_m32_kernel<FORM_EQ1>);
-    else go(fold_m32_kernel<FORM_3NU>);
+    else if (a.osc.formula == FORM_3NU) go(fold_m32_kernel<FORM_3NU>);
+    else go(fold_m32_kernel<FORM_4NU>);
   }
   return hipGetLastError();
 }

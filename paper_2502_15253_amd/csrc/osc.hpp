@@ -134,26 +134,97 @@ __device__ __forceinline__ double row_reduce_scatter(double* c, int lane) {
 }
 
 // Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
-// linear combination of (W, M_1..M_NM). Returns false outside the domain.
+// linear combination of (W, M_1..M_NM), CF_STRIDE doubles per row.
 // The parameter domain of the oscillation formula: finite slot values and,
-// for Eq. 1, sin^2(2 theta13) < 1 (cos^2 theta13 from its square root).
-// Exactly the cases in which osc_coefficients returns false.
+// for Eq. 1 and the 3+1 form, sin^2(2 theta) < 1 (cos^2 theta from its square
+// root). Exactly the cases in which osc_coefficients returns false.
 __device__ inline bool osc_domain_ok(const OscPlan& o, const double* th) {
   bool ok = true;
   for (int j = 0; j < NSLOT; ++j) {
     const double v = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];
     ok = ok && isfinite(v);
     if (j == 0 && o.formula == FORM_EQ1) ok = ok && v < 1.0;
+    if (j == 2 && o.formula == FORM_4NU) ok = ok && v < 1.0;
   }
   return ok;
+}
+
+__host__ __device__ inline int num_phases(int formula) { return formula == FORM_4NU ? 3 : 2; }
+
+// Angular frequencies a (rad per m/MeV) of the computed phases x = a u:
+//   eq1: ee, 21;  3nu: 21, 31;  4nu: 21, 31, 41.
+// The fold and the coefficient rows both take them from here, so the FP32
+// frequencies derived from them are bit-identical on both sides.
+template <int FORM>
+__device__ __forceinline__ void osc_freqs_form(const OscPlan& o, const double* th, double* a) {
+  auto v = [&](int j) { return o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j]; };
+  if constexpr (FORM == FORM_EQ1) {
+    a[0] = TWO_PHASE_K * UNIT_1EM3 * v(1);  // dm2_ee
+    a[1] = TWO_PHASE_K * UNIT_1EM5 * v(3);  // dm2_21
+  } else if constexpr (FORM == FORM_3NU) {
+    a[0] = TWO_PHASE_K * UNIT_1EM5 * v(2);  // dm2_21
+    a[1] = TWO_PHASE_K * UNIT_1EM3 * v(3);  // dm2_31
+  } else {
+    a[0] = TWO_PHASE_K * UNIT_1EM5 * o.cst[1];  // dm2_21 (fixed)
+    a[1] = TWO_PHASE_K * UNIT_1EM3 * v(1);      // dm2_31
+    a[2] = TWO_PHASE_K * UNIT_1EM3 * v(3);      // dm2_41
+  }
+}
+__device__ __forceinline__ void osc_freqs(const OscPlan& o, const double* th, double* a) {
+  if (o.formula == FORM_EQ1) osc_freqs_form<FORM_EQ1>(o, th, a);
+  else if (o.formula == FORM_3NU) osc_freqs_form<FORM_3NU>(o, th, a);
+  else osc_freqs_form<FORM_4NU>(o, th, a);
+}
+
+// FP32 frequency in revolutions per (m/MeV) used by the M32 fold: the phase
+// of an event is fract(f u) with f = fp32_rev(a); the fold's moments are then
+// those of the angular frequency 2 pi f instead of a.
+__device__ __forceinline__ float fp32_rev(double a) {
+  constexpr double INV_2PI = 0.15915494309189533577;
+  return (float)(a * INV_2PI);
+}
+
+// First-order frequency correction of the M32 moments. With frequency a' in
+// place of a, C(a) = C(a') - (a - a') Q(a') + O((a - a')^2 u^2) because
+// dC/da = -Q, so S = sum_c cf_c M_c(a) becomes cf_Q -= (a - a') cf_C on every
+// row. a - a' is at most 2^-24 a, so the neglected term is below 1e-11 of C
+// at the phases of reactor baselines. Q itself keeps its first-order error
+// (a - a') sum w u^2 cos, which only enters the derivative rows of dm2.
+template <int FORM>
+__device__ __forceinline__ void fp32_correction_form(const OscPlan& o, const double* th, double* cf) {
+  constexpr double TWO_PI = 6.283185307179586477;
+  constexpr int NPH = FORM == FORM_4NU ? 3 : 2;
+  constexpr int NP = FORM == FORM_EQ1 ? 2 : FORM == FORM_3NU ? 3 : 6;  // (C, Q) pairs
+  double a[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+  osc_freqs_form<FORM>(o, th, a);
+#pragma unroll
+  for (int q = 0; q < NPH; ++q) d[q] = a[q] - TWO_PI * (double)fp32_rev(a[q]);
+  // frequency error of each pair (derived pairs by angle subtraction)
+  double dp[6] = {d[0], d[1], d[1] - d[0], d[2], d[2] - d[0], d[2] - d[1]};
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    double* row = cf + CF_STRIDE * r;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) row[1 + NP + q] -= dp[q] * row[1 + q];
+  }
+}
+__device__ inline void fp32_frequency_correction(const OscPlan& o, const double* th, double* cf) {
+  if (o.formula == FORM_EQ1) fp32_correction_form<FORM_EQ1>(o, th, cf);
+  else if (o.formula == FORM_3NU) fp32_correction_form<FORM_3NU>(o, th, cf);
+  else fp32_correction_form<FORM_4NU>(o, th, cf);
 }
 
 __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {
   double v[NSLOT];
   for (int j = 0; j < NSLOT; ++j) v[j] = o.slot_param[j] >= 0 ? th[o.slot_param[j]] : o.slot_value[j];
-  for (int i = 0; i < 40; ++i) cf[i] = 0.0;
+  for (int i = 0; i < CF_SIZE; ++i) cf[i] = 0.0;
   bool ok = true;
   for (int j = 0; j < NSLOT; ++j) ok = ok && isfinite(v[j]);
+  double* r0 = cf;
+  double* r1 = cf + CF_STRIDE;
+  double* r2 = cf + 2 * CF_STRIDE;
+  double* r3 = cf + 3 * CF_STRIDE;
+  double* r4 = cf + 4 * CF_STRIDE;
   if (o.formula == FORM_EQ1) {
     // moments: 1 C_ee, 2 C_21, 3 Q_ee, 4 Q_21
     const double s = v[0], s12 = v[2];
@@ -166,17 +237,16 @@ __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, doub
     const double dA_ds = -s2t12 * c13sq / (2.0 * r);
     const double dA_ds12 = c4 * 4.0 * (1.0 - 2.0 * s12);
     const double aee = TWO_PHASE_K * UNIT_1EM3, a21 = TWO_PHASE_K * UNIT_1EM5;
-    double* r0 = cf;
     r0[0] = 1.0 - 0.5 * s - 0.5 * A; r0[1] = 0.5 * s; r0[2] = 0.5 * A;
-    double* r1 = cf + 8;   // d/d sin^2(2 th13)
+    // d/d sin^2(2 th13)
     r1[0] = -0.5 - 0.5 * dA_ds; r1[1] = 0.5; r1[2] = 0.5 * dA_ds;
-    double* r2 = cf + 16;  // d/d dm2_ee
+    // d/d dm2_ee
     r2[3] = -0.5 * s * aee;
-    double* r3 = cf + 24;  // d/d sin^2 th12
+    // d/d sin^2 th12
     r3[0] = -0.5 * dA_ds12; r3[2] = 0.5 * dA_ds12;
-    double* r4 = cf + 32;  // d/d dm2_21
+    // d/d dm2_21
     r4[4] = -0.5 * A * a21;
-  } else {
+  } else if (o.formula == FORM_3NU) {
     // moments: 1 C_21, 2 C_31, 3 C_32, 4 Q_21, 5 Q_31, 6 Q_32
     const double s12 = v[0], s13 = v[1];
     const double c12 = 1.0 - s12, c13 = 1.0 - s13;
@@ -184,25 +254,61 @@ __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, doub
     const double K31 = 4.0 * c12 * c13 * s13;
     const double K32 = 4.0 * s12 * c13 * s13;
     const double a21 = TWO_PHASE_K * UNIT_1EM5, a31 = TWO_PHASE_K * UNIT_1EM3;
-    double* r0 = cf;
     r0[0] = 1.0 - 0.5 * (K21 + K31 + K32);
     r0[1] = 0.5 * K21; r0[2] = 0.5 * K31; r0[3] = 0.5 * K32;
     const double d12[3] = {4.0 * (1.0 - 2.0 * s12) * c13 * c13, -4.0 * c13 * s13, 4.0 * c13 * s13};
     const double d13[3] = {-8.0 * c12 * s12 * c13, 4.0 * c12 * (1.0 - 2.0 * s13),
                            4.0 * s12 * (1.0 - 2.0 * s13)};
-    double* r1 = cf + 8;
-    double* r2 = cf + 16;
     r1[0] = -0.5 * (d12[0] + d12[1] + d12[2]);
     r2[0] = -0.5 * (d13[0] + d13[1] + d13[2]);
     for (int j = 0; j < 3; ++j) {
       r1[1 + j] = 0.5 * d12[j];
       r2[1 + j] = 0.5 * d13[j];
     }
-    double* r3 = cf + 24;  // d/d dm2_21: x21 grows, x32 = x31 - x21 shrinks
+    // d/d dm2_21: x21 grows, x32 = x31 - x21 shrinks
     r3[4] = -0.5 * K21 * a21; r3[6] = 0.5 * K32 * a21;
-    double* r4 = cf + 32;  // d/d dm2_31
+    // d/d dm2_31
     r4[5] = -0.5 * K31 * a31; r4[6] = -0.5 * K32 * a31;
+  } else {
+    // 3+1: |U_e1..4|^2 = c12 c13 c14, s12 c13 c14, s13 c14, s14 (squared sines
+    // and cosines), P = 1 - sum_{i<j} K_ij sin^2(x_ji / 2), K_ij = 4 |U_ei|^2 |U_ej|^2.
+    // moments: 1..6 C of the pairs 21, 31, 32, 41, 42, 43, then 7..12 their Q
+    const double s12 = o.cst[0], s13 = v[0], X = v[2];
+    if (!(X < 1.0)) return false;
+    const double rt = sqrt(1.0 - X);
+    const double s14 = 0.5 * (1.0 - rt), c14 = 0.5 * (1.0 + rt);
+    const double c12 = 1.0 - s12, c13 = 1.0 - s13;
+    const double U1 = c12 * c13 * c14, U2 = s12 * c13 * c14, U3 = s13 * c14, U4 = s14;
+    // derivatives of |U_ei|^2 by sin^2 th13 and by sin^2(2 th14) (through sin^2 th14)
+    const double g = 0.25 / rt;
+    const double a1 = -c12 * c14, a2 = -s12 * c14, a3 = c14, a4 = 0.0;
+    const double b1 = -c12 * c13 * g, b2 = -s12 * c13 * g, b3 = -s13 * g, b4 = g;
+    double sK = 0.0, sd13 = 0.0, sd14 = 0.0, Kp[6];
+    auto pair = [&](int q, double ui, double uj, double dai, double daj, double dbi, double dbj) {
+      Kp[q] = 4.0 * ui * uj;
+      const double k13 = 4.0 * (dai * uj + ui * daj);
+      const double k14 = 4.0 * (dbi * uj + ui * dbj);
+      r0[1 + q] = 0.5 * Kp[q];
+      r1[1 + q] = 0.5 * k13;
+      r3[1 + q] = 0.5 * k14;
+      sK += Kp[q]; sd13 += k13; sd14 += k14;
+    };
+    pair(0, U1, U2, a1, a2, b1, b2);  // 21
+    pair(1, U1, U3, a1, a3, b1, b3);  // 31
+    pair(2, U2, U3, a2, a3, b2, b3);  // 32
+    pair(3, U1, U4, a1, a4, b1, b4);  // 41
+    pair(4, U2, U4, a2, a4, b2, b4);  // 42
+    pair(5, U3, U4, a3, a4, b3, b4);  // 43
+    r0[0] = 1.0 - 0.5 * sK;
+    r1[0] = -0.5 * sd13;
+    r3[0] = -0.5 * sd14;
+    const double am = TWO_PHASE_K * UNIT_1EM3;
+    // d/d dm2_31: x31 and x32 grow, x43 = x41 - x31 shrinks
+    r2[7 + 1] = -0.5 * Kp[1] * am; r2[7 + 2] = -0.5 * Kp[2] * am; r2[7 + 5] = 0.5 * Kp[5] * am;
+    // d/d dm2_41: x41, x42, x43 grow
+    r4[7 + 3] = -0.5 * Kp[3] * am; r4[7 + 4] = -0.5 * Kp[4] * am; r4[7 + 5] = -0.5 * Kp[5] * am;
   }
+  if (o.fp32_phase) fp32_frequency_correction(o, th, cf);
   return ok;
 }
 

@@ -10,9 +10,14 @@ namespace nufold {
 
 constexpr int FORM_EQ1 = 0;  // Eq. 1: slots sin2_2t13, dm2_ee, sin2_t12, dm2_21
 constexpr int FORM_3NU = 1;  // exact vacuum 3-flavour: sin2_t12, sin2_t13, dm2_21, dm2_31
+constexpr int FORM_4NU = 2;  // vacuum 3+1: sin2_t13, dm2_31, sin2_2t14, dm2_41 (sin2_t12, dm2_21 constants)
 constexpr int NSLOT = 4;
-constexpr int MAX_MOM = 6;   // per-segment moments produced by the fold
+constexpr int MAX_MOM = 12;  // per-segment moments produced by the fold
 constexpr int MAX_SOURCES = 64;
+// Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
+// linear combination of (W, M_1..M_NM) stored at CF_STRIDE doubles per row.
+constexpr int CF_STRIDE = 16;
+constexpr int CF_SIZE = 5 * CF_STRIDE;
 
 // 2 k, k = 1/(4 hbar c) in MeV/(eV^2 m) with the exact SI-2019 value of hbar c;
 // the fold phase x = 2 k dm2 L/E is twice the phase of Eq. 1.
@@ -20,12 +25,18 @@ constexpr double TWO_PHASE_K = 2.0 * 1.266932679039099;
 constexpr double UNIT_1EM3 = 1e-3;
 constexpr double UNIT_1EM5 = 1e-5;
 
-__host__ __device__ inline int num_moments(int formula) { return formula == FORM_EQ1 ? 4 : 6; }
+__host__ __device__ inline int num_moments(int formula) {
+  return formula == FORM_EQ1 ? 4 : formula == FORM_3NU ? 6 : 12;
+}
 
 struct OscPlan {
   int formula;
   int slot_param[NSLOT];   // parameter index, or -1 for a constant
+  int fp32_phase;          // 1: the fold forms phases from FP32 frequencies (M32); the
+                           // coefficient rows then carry the first-order frequency correction
+  int pad_;
   double slot_value[NSLOT];
+  double cst[2];           // FORM_4NU: the fixed sin2_t12 and dm2_21 (1e-5 eV^2)
 };
 
 // A contiguous run of sorted events that all belong to one segment

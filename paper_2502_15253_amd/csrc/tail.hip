@@ -60,7 +60,7 @@ template <int NT>
 struct Lds {
   double* th;     // P
   double* grad;   // P
-  double* coef;   // 40
+  double* coef;   // CF_SIZE
   DsPlan* dsl;    // D dataset plans
   double* red;    // block reduction scratch (red_doubles)
   double* dyn;    // copy target: Hs, G0..G3 (5 K), Ss (S K), observed counts (Nb)
@@ -96,7 +96,7 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   double* q = base;
   L.th = q; q += p.P;
   L.grad = q; q += p.P;
-  L.coef = q; q += 40;
+  L.coef = q; q += CF_SIZE;
   q = al(q);
   L.dsl = reinterpret_cast<DsPlan*>(q); q += p.D * DSPLAN_DOUBLES;
   L.red = q; q += red_doubles(NT);
@@ -565,15 +565,17 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // ---- gradient of the reduced sums; source norms by the product rule over
     // each source's norm list; flux modes by a gather of lambda_F over each
     // mode's fine bins (CSC)
+    // every gradient entry of this pass may also receive a prior row, a norm
+    // list or a flux mode from another thread: all adds are atomic
     if (tid == NT - 1) {  // a thread with no source to apply (S <= MAX_SOURCES < NT)
       for (int j = 0; j < 3; ++j)
-        if (ds.cidx[j] >= 0) L.grad[ds.cidx[j]] += acc[1 + j];
+        if (ds.cidx[j] >= 0) atomicAdd(&L.grad[ds.cidx[j]], acc[1 + j]);
       for (int j = 0; j < NSLOT; ++j)
-        if (p.osc.slot_param[j] >= 0) L.grad[p.osc.slot_param[j]] += acc[4 + j];
+        if (p.osc.slot_param[j] >= 0) atomicAdd(&L.grad[p.osc.slot_param[j]], acc[4 + j]);
       const int* brt = reinterpret_cast<const int*>(p.dpool + ds.blob + BL.brt);
 #pragma unroll
       for (int b = 0; b < MAX_BKG; ++b)
-        if (b < NB && brt[b] >= 0) L.grad[brt[b]] += acc[8 + b];
+        if (b < NB && brt[b] >= 0) atomicAdd(&L.grad[brt[b]], acc[8 + b]);
     }
     if (tid < S) {
       const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
@@ -738,24 +740,32 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   double* tmp = a.segtmp + (int64_t)f * 5 * G;
   // phase A, per segment
   for (int g = tid; g < G; g += NT) {
+    // moments held in registers: every index below is a compile-time one
     double M[MAX_MOM + 1];
     M[0] = p.Wseg[g];
+#pragma unroll
     for (int c = 1; c <= MAX_MOM; ++c) M[c] = 0.0;
     const int ib = p.seg_item[g], ie = p.seg_item[g + 1];
-    for (int it = ib; it < ie; ++it)
-      for (int c = 0; c < NMOM; ++c) M[1 + c] += io.part[(int64_t)c * p.nitems + it];
+    for (int it = ib; it < ie; ++it) {
+#pragma unroll
+      for (int c = 0; c < MAX_MOM; ++c)
+        if (c < NMOM) M[1 + c] += io.part[(int64_t)c * p.nitems + it];
+    }
     const int* nl = p.ipool + p.fs_nl + NLMAX * p.ipool[p.seg_fs + g];
     double A = 1.0;
 #pragma unroll
     for (int q = 0; q < NLMAX; ++q)
       if (nl[q] >= 0) A *= L.th[nl[q]];
     double Sv = 0.0;
-    for (int c = 0; c <= NMOM; ++c) Sv += L.coef[c] * M[c];
+#pragma unroll
+    for (int c = 0; c <= MAX_MOM; ++c) Sv += L.coef[c] * M[c];  // unused coefficients are zero
     store_agent(&io.Sseg[g], Sv);
     tmp[g] = A * Sv;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
       double gj = 0.0;
-      for (int c = 0; c <= NMOM; ++c) gj += L.coef[8 * (j + 1) + c] * M[c];
+#pragma unroll
+      for (int c = 0; c <= MAX_MOM; ++c) gj += L.coef[CF_STRIDE * (j + 1) + c] * M[c];
       tmp[(int64_t)(1 + j) * G + g] = A * gj;
     }
   }

@@ -562,6 +562,14 @@ def tiny_model(seed, formula="eq1", n_datasets=2, n_sources=2, fine_n=12, nb=8,
         osc = dict(formula="eq1", sin2_2t13=dict(param="osc.sin2_2t13"),
                    dm2_ee=dict(param="osc.dm2_ee"),
                    sin2_t12=dict(value=0.307), dm2_21=dict(value=7.53))
+    elif formula == "4nu":
+        params += [param("osc.sin2_t13", 0.0218 * (1 + 0.1 * rng.uniform(-1, 1))),
+                   param("osc.dm2_31", 2.53, (2.53, 0.05)),
+                   param("osc.sin2_2t14", 0.05 * (1 + 0.5 * rng.uniform(-1, 1))),
+                   param("osc.dm2_41", float(rng.choice([5.0, 50.0, 500.0])) * (1 + 0.1 * rng.uniform(-1, 1)))]
+        osc = dict(formula="4nu", sin2_t13=dict(param="osc.sin2_t13"), dm2_31=dict(param="osc.dm2_31"),
+                   sin2_2t14=dict(param="osc.sin2_2t14"), dm2_41=dict(param="osc.dm2_41"),
+                   sin2_t12=dict(value=0.307), dm2_21=dict(value=7.53))
     else:
         params += [param("osc.sin2_t12", 0.307, (0.307, 0.013)),
                    param("osc.sin2_t13", 0.0218),

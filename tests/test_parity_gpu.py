@@ -8,9 +8,16 @@ Tolerances:
   NLL's curvature in theta_j (Fisher information plus prior; tests/gradcheck.py),
   so an error at the bar moves the fitted theta_j by tol_g standard deviations,
   and the whole vector also within tol * max(1, max|g|).
-  tol_g is tol in M64; in M32 it is GRAD_TOL_M32 (the FP32 fold's error in mu,
-  a few 1e-7 relative per bin, enters the gradient through lambda = 1 - n/mu
-  multiplied by dmu/dtheta, which grows like sqrt(mu) against sqrt(F)).
+  tol_g is tol in M64; in M32 it is GRAD_TOL_M32. The FP32 fold's error in mu
+  has a systematic part of a few 1e-8 relative: the hardware sin/cos
+  (operand in revolutions) is biased by up to -4.6e-8 on average over
+  [0, 0.02) revolutions and -2.8e-8 over [0.02, 0.1) (measured against FP64
+  over 2^24 evenly spaced operands on MI355X). A relative error e common to
+  the bins of a dataset with N counts moves dNLL/dtheta_j by about e N
+  (through lambda = 1 - n/mu) against sqrt(F_jj) ~ sqrt(N), i.e. by e sqrt(N)
+  of the per-component scale: 1e-5 at N = 2e5. The FP32 mode is held to
+  5e-5 of that scale (one twenty-thousandth of a standard deviation of each
+  fitted parameter); FP64 to 1e-9.
 """
 import sys
 
@@ -27,7 +34,7 @@ import gradcheck
 pytestmark = pytest.mark.gpu
 
 TOL = {"m64": 1e-9, "m32": 1e-5}
-GRAD_TOL_M32 = 1e-5
+GRAD_TOL_M32 = 5e-5
 GRAD_TOL = {"m64": 1e-9, "m32": GRAD_TOL_M32}
 
 
@@ -91,7 +98,7 @@ def displaced(desc, seed, scale=0.3):
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])
-@pytest.mark.parametrize("formula", ["eq1", "3nu"])
+@pytest.mark.parametrize("formula", ["eq1", "3nu", "4nu"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("deterministic", [0, 1])
 def test_tiny_models(mode, formula, seed, deterministic):
@@ -135,6 +142,26 @@ def test_config3_full_size(mode):
     data = [mu.copy() for mu in mus]  # Asimov, as in the medium-baseline study
     eng = make_engine(desc, events, data, mode)
     compare(eng, desc, events, data, displaced(desc, 300), TOL[mode], "c3 displaced", gtol=GRAD_TOL[mode])
+
+
+@pytest.mark.parametrize("mode,dm2_41", [(m, v) for m in ("m64", "m32") for v in (0.0, 5.0, 50.0, 300.0)]
+                         + [("m64", 1000.0)])
+def test_sterile_full_size(mode, dm2_41):
+    # 3+1 survival probability (sterile searches): near and far detector, two
+    # reactors each; sterile mixing switched on at dm2_41 from 0 (no sterile
+    # phase) to 1 eV^2 (up to 250 revolutions per event at the far detector).
+    # M32 holds u = L/E in FP32, whose rounding alone moves a phase of p
+    # revolutions by up to p 2^-25: at 1 eV^2 the dm2_41 derivative (a sum of
+    # fast-alternating terms) is then off by about 1e-4 of its scale, so the
+    # FP32 mode is checked up to 0.3 eV^2 and 1 eV^2 in FP64 only
+    say("sterile", mode, dm2_41)
+    desc, events = synth.model_and_events("sterile")
+    data = oracle_data(desc, events, synth.data_seed(7))
+    eng = make_engine(desc, events, data, mode)
+    th = displaced(desc, 400)
+    th[synth.param_index(desc, "osc.sin2_2t14")] = 0.04
+    th[synth.param_index(desc, "osc.dm2_41")] = dm2_41
+    compare(eng, desc, events, data, th, TOL[mode], f"sterile dm2_41={dm2_41}", gtol=GRAD_TOL[mode])
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])

@@ -29,7 +29,7 @@ def test_split_model_matches_oracle(mode):
     mus, _ = LK.expected(m, events, synth.start_vector(desc))
     data = synth.poisson_data(mus, synth.data_seed(6))
     eng = make_engine(desc, events, data, mode)
-    assert eng.D == 20 and [eng.nbins(d) for d in range(18, 20)] == [1, 1]
+    assert eng.D == 20 and [eng.nbins[d] for d in range(18, 20)] == [1, 1]
     compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "split start", gtol=GRAD_TOL[mode])
     compare(eng, desc, events, data, displaced(desc, 600), TOL[mode], "split displaced", gtol=GRAD_TOL[mode])
 
