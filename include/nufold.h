@@ -143,6 +143,30 @@ int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev,
                    int32_t* status_dev, int want_grad);
 
 /*
+ * Allocation-free device evaluation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Arguments, outputs and result are those of
+ * nf_eval_device (same kernels); the evaluation's scratch (fold partials,
+ * per-segment moments and spectra, fine-bin rows, arrival counters) lives in
+ * one static device array per GPU of NF_NOALLOC_SCRATCH_BYTES bytes, part of
+ * the library's code object and held until the process ends, instead of the
+ * context's own buffers. The call enqueues a fill kernel that clears the
+ * part of the array that must start at zero, then the fold and the bin
+ * stages, on the context's stream; it calls no hipMalloc, hipFree or other
+ * allocating routine (the context itself was set up by nf_create and
+ * nf_set_events beforehand). The array keeps the last call's contents, and
+ * every call on one GPU uses the same array: calls that can overlap on one
+ * GPU (other streams or contexts, without ordering between them) race and
+ * give wrong results. Needs 8 (6 KT + G) + 4 (G + KT) + 8 NM nitems +
+ * 8 13 G bytes (each part rounded up to 256; KT fine bins, G segments,
+ * nitems work items, NM fold moments); a context that needs more gets
+ * NF_EINVAL and an error message with its need.
+ */
+#define NF_NOALLOC_SCRATCH_BYTES (16u << 20)
+int nf_eval_device_noalloc(nf_ctx* ctx, const double* theta_dev, double* out_dev,
+                           int32_t* status_dev, int want_grad);
+
+/*
  * n device evaluations in order, launched as one HIP graph on the context's
  * stream: evaluation i reads theta_dev + i*P and writes NLL and gradient to
  * out_dev + i*(1+P) (and its status to status_dev[i] when status_dev is not

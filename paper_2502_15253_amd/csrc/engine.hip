@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -19,7 +20,29 @@
 
 using namespace nufold;
 
+// Scratch of the allocation-free evaluation (nf_eval_device_noalloc): one
+// array per GPU, part of the loaded code object, held until the process
+// ends. Host code never uses the array's name as an address: each device's
+// address comes from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[NF_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept; nullptr if the lookup fails.
+void* scratch_address() {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) ptr = nullptr;
+  addr[dev] = ptr;
+  return ptr;
+}
 
 struct ApiError : std::runtime_error {
   int code;
@@ -206,6 +229,7 @@ struct nf_ctx {
   const double* ev_theta = nullptr;
   double* ev_out = nullptr;
   int32_t* ev_status = nullptr;
+  void* scratch_dev = nullptr;  // this device's `scratch` array (nf_eval_device_noalloc)
   std::vector<std::array<hipEvent_t, 4>> tev;  // per-evaluation kernel start/stop events (fold, bin stages)
   size_t tcount = 0;
 
@@ -924,9 +948,23 @@ FitArgs fit_args(nf_ctx* c) {
   return f;
 }
 
+// Scratch of one single evaluation: fold partials, per-segment moments and
+// spectra, fine-bin rows and arrival counters (the context's own buffers, or
+// the static array of the allocation-free entry point).
+struct EvalScratch {
+  double* part;
+  double* segm;
+  double* Sseg;
+  double* bin;
+  int* seg_cnt;
+  int* kt_cnt;
+};
+
 void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* status_dev, double* mu_dev,
                   int want_nll, int want_grad, bool fit = false, bool timed = true, bool reuse_fold = false,
-                  bool keep_rows = false) {
+                  bool keep_rows = false, const EvalScratch* scr = nullptr) {
+  const EvalScratch own{c->d_part.p, c->d_segm.p, c->d_Sseg.p, c->d_bin.p, c->d_seg_cnt.p, c->d_kt_cnt.p};
+  const EvalScratch& sc = scr ? *scr : own;
   FoldArgs fa{};
   fa.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
   fa.w = c->d_w.p;
@@ -935,7 +973,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.zpad = c->zpad;
   fa.theta = theta_dev;
   fa.osc = c->osc;
-  fa.part = c->d_part.p;
+  fa.part = sc.part;
   FoldFuse& fu = fa.fuse;
   fu.epi = c->d_epi.p;
   fu.seg_item = c->d_seg_item.p;
@@ -943,11 +981,11 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fu.kt_need = c->d_kt_need.p;
   fu.kt_info = c->d_ipool.p + c->plan.kt_info;
   fu.fs_nl = c->d_ipool.p + c->plan.fs_nl;
-  fu.seg_cnt = c->d_seg_cnt.p;
-  fu.kt_cnt = c->d_kt_cnt.p;
-  fu.segm = c->d_segm.p;
-  fu.Sseg = c->d_Sseg.p;
-  fu.bin = c->d_bin.p;
+  fu.seg_cnt = sc.seg_cnt;
+  fu.kt_cnt = sc.kt_cnt;
+  fu.segm = sc.segm;
+  fu.Sseg = sc.Sseg;
+  fu.bin = sc.bin;
   fu.G = c->plan.G;
   fu.atomic_rows = c->deterministic ? 0 : 1;
   TailArgs ta{};
@@ -957,8 +995,8 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   ta.out = out_dev;
   ta.status = status_dev;
   ta.mu_out = mu_dev;
-  ta.Sseg = c->d_Sseg.p;
-  ta.bin = c->d_bin.p;
+  ta.Sseg = sc.Sseg;
+  ta.bin = sc.bin;
   ta.want_grad = want_grad;
   ta.want_nll = want_nll;
   ta.keep_rows = keep_rows ? 1 : 0;
@@ -1630,6 +1668,8 @@ int nf_create(nf_ctx** out, const char* model_json, int mode, void* hip_stream) 
     }
     int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
+    c->scratch_dev = scratch_address();
+    if (!c->scratch_dev) fail(NF_EDEVICE, "hipGetSymbolAddress of the static scratch array failed");
     int maxlds = 0;
     hip_check(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
     c->max_lds = maxlds;
@@ -1741,6 +1781,43 @@ int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev, int32_
     if (!theta_dev || !out_dev) fail(NF_EINVAL, "null device pointer");
     release_rows(ctx);
     enqueue_eval(ctx, theta_dev, out_dev, status_dev, nullptr, 1, want_grad ? 1 : 0);
+    return NF_OK;
+  });
+}
+
+int nf_eval_device_noalloc(nf_ctx* ctx, const double* theta_dev, double* out_dev, int32_t* status_dev,
+                           int want_grad) {
+  return guarded(ctx, [&] {
+    require_ready(ctx, true);
+    if (!theta_dev || !out_dev) fail(NF_EINVAL, "null device pointer");
+    nf_ctx* c = ctx;
+    if (!c->scratch_dev) fail(NF_EDEVICE, "no static scratch array on this device");
+    // layout: the part that must start at zero (fine-bin rows, per-segment
+    // spectra of segments without events, arrival counters) first, cleared by
+    // a fill kernel on every call; then fold partials and segment moments,
+    // which every call writes before it reads them
+    const size_t G = (size_t)std::max(1, c->plan.G), KT = (size_t)std::max(1, c->plan.KT);
+    const size_t NI = (size_t)std::max(1, c->nitems);
+    const size_t NM = (size_t)num_moments(c->osc.formula);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_bin = 0;
+    const size_t o_Sseg = o_bin + up(sizeof(double) * 6 * KT);
+    const size_t o_seg_cnt = o_Sseg + up(sizeof(double) * G);
+    const size_t o_kt_cnt = o_seg_cnt + up(sizeof(int) * G);
+    const size_t zero_end = o_kt_cnt + up(sizeof(int) * KT);
+    const size_t o_part = zero_end;
+    const size_t o_segm = o_part + up(sizeof(double) * NM * NI);
+    const size_t total = o_segm + up(sizeof(double) * (MAX_MOM + 1) * G);
+    if (total > (size_t)NF_NOALLOC_SCRATCH_BYTES)
+      fail(NF_EINVAL, "this context needs " + std::to_string(total) + " bytes of evaluation scratch, more than "
+                      "the " + std::to_string((size_t)NF_NOALLOC_SCRATCH_BYTES) + " of the static array; use nf_eval_device");
+    unsigned char* base = static_cast<unsigned char*>(c->scratch_dev);
+    const EvalScratch sc{reinterpret_cast<double*>(base + o_part), reinterpret_cast<double*>(base + o_segm),
+                         reinterpret_cast<double*>(base + o_Sseg), reinterpret_cast<double*>(base + o_bin),
+                         reinterpret_cast<int*>(base + o_seg_cnt), reinterpret_cast<int*>(base + o_kt_cnt)};
+    hip_check(launch_zero(reinterpret_cast<double*>(base), (int64_t)(zero_end / sizeof(double)), c->stream),
+              "zero launch");
+    enqueue_eval(c, theta_dev, out_dev, status_dev, nullptr, 1, want_grad ? 1 : 0, false, false, false, false, &sc);
     return NF_OK;
   });
 }

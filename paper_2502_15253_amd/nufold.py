@@ -42,6 +42,7 @@ SIGNATURES = {
     "nf_eval_nll_grad": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "nf_eval_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "nf_eval_device_many": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "nf_eval_device_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "nf_expected": (C.c_int, [C.c_void_p, _dp, _dp]),
     "nf_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "nf_get_option": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
@@ -228,6 +229,14 @@ class Engine:
         return _check(self.ctx, load().nf_eval_device(self.ctx, C.c_void_p(theta_ptr), C.c_void_p(out_ptr),
                                                       C.c_void_p(status_ptr) if status_ptr else None,
                                                       1 if want_grad else 0))
+
+    def eval_device_noalloc(self, theta_ptr, out_ptr, status_ptr=None, want_grad=True):
+        """As eval_device, with the evaluation's scratch in the library's static
+        per-GPU array (no device allocation); returns immediately."""
+        return _check(self.ctx, load().nf_eval_device_noalloc(self.ctx, C.c_void_p(theta_ptr),
+                                                              C.c_void_p(out_ptr),
+                                                              C.c_void_p(status_ptr) if status_ptr else None,
+                                                              1 if want_grad else 0))
 
     def eval_device_many(self, n, theta_ptr, out_ptr, status_ptr=None, want_grad=True):
         """Enqueue n evaluations (theta rows of P doubles, out rows of 1 + P)
