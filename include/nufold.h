@@ -54,6 +54,7 @@ extern "C" {
                           per-wave and later sums, bin stages, NLL and gradient in FP64     */
 
 typedef struct nf_ctx nf_ctx;
+typedef struct nf_mlp nf_mlp;  /* surrogate network (see nf_mlp_create) */
 
 /*
  * Create a context from a JSON model description (paper: "Structure of the
@@ -237,12 +238,21 @@ int nf_autotune(nf_ctx* ctx, const double* theta, int evals, int batch, int64_t*
  * Fit options and result (paper: "Structure of the framework" -- minimise
  * -ln L until the estimated distance to the minimum is below a threshold).
  */
+#define NF_SURROGATE 1  /* nf_fit_opts.warm_start: starts proposed by the attached surrogate */
 typedef struct {
   double edm_tol;   /* stop when EDM = 1/2 g^T H g < edm_tol; <= 0 selects 1e-7     */
   int max_iter;     /* accepted iterations; <= 0 selects 1000                        */
   int want_cov;     /* 1: covariance = inverse of the central-difference Hessian of
                        the adjoint gradient at the minimum (2 evaluations per free
                        parameter), written to result->cov                           */
+  int warm_start;   /* 0: every fit starts at its start vector; NF_SURROGATE: the
+                       surrogate's input parameters of each start vector are first
+                       replaced by the best of its start grid fitted to that fit's
+                       observed counts on the surrogate (nf_set_surrogate), and the
+                       exact NLL judges: the proposal replaces the start only where
+                       it is lower there; the exact fit then runs from the chosen
+                       start. NF_ESTATE if no surrogate is attached.                 */
+  int pad_;
 } nf_fit_opts;
 
 typedef struct {
@@ -271,6 +281,25 @@ typedef struct {
  */
 int nf_fit(nf_ctx* ctx, const double* start, const uint8_t* fixed, const nf_fit_opts* opts,
            nf_fit_result* result);
+
+/*
+ * Attach a surrogate network to a context for warm starts (not in the paper:
+ * the learned part proposes start points only; every reported NLL comes from
+ * the exact fold). net (caller-owned, must stay alive while attached; NULL
+ * detaches) maps x (n_in values) to the standardised log expectations of all
+ * analysis bins, concatenated in dataset order (its n_out must equal their
+ * total): log mu_j = y_j out_std_j + out_mean_j. Input i is parameter
+ * param_index[i] through x_i = (theta_i - center_i) / half_i. A warm start
+ * of one fit runs nf_mlp_fit_inputs (surrogate Poisson deviance plus the
+ * input prior x_prior, x_weight; `iters` Adam steps of size lr) from each of
+ * the n_starts rows of `starts` (n_starts x n_in, in x units) on that fit's
+ * observed counts, keeps the row of lowest surrogate deviance, clips it to
+ * [-1, 1] and writes center + half x into the fit's start vector. All arrays
+ * are copied. NF_EINVAL for bad sizes or indices.
+ */
+int nf_set_surrogate(nf_ctx* ctx, nf_mlp* net, int n_in, const int* param_index, const double* center,
+                     const double* half, const float* out_mean, const float* out_std, const float* x_prior,
+                     const float* x_weight, int n_starts, const float* starts, int iters, float lr);
 
 /*
  * Batched pseudo-experiments and scans (paper: parallel fits with individual
@@ -306,6 +335,38 @@ int nf_eval_batch(nf_ctx* ctx, int B, const double* theta, const int* data_idx, 
 int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, const int* data_idx,
                  const nf_fit_opts* opts, double* theta_out, double* nll_out, double* edm_out,
                  int* status_out, int* iters_out, int* evals_out);
+
+/*
+ * Mixed ensembles (paper: parallel fits of pseudo-experiment ensembles; here
+ * ensembles drawn from several models at once, e.g. a single-detector and a
+ * three-detector model of uneven bin and parameter counts): the batched fits
+ * of n contexts advanced together. Each member is one context with its own
+ * batch data (nf_set_data_batch) and the arguments of nf_fit_batch; contexts
+ * must be distinct and on one device. Every iteration is one HIP graph that
+ * holds every member's batched fold and bin-stage + L-BFGS launches on
+ * branches of their own (forked from and joined to the first member's
+ * stream, so the members' kernels run side by side), replayed until every fit
+ * of every member has stopped; opts (nullable) applies to all members.
+ * Results per member as in nf_fit_batch. Returns NF_OK when every fit
+ * converged, NF_WNOCONV when some did not (first member's nf_last_error), or
+ * the error of the first member whose arguments are invalid (on that
+ * member's context).
+ */
+typedef struct {
+  nf_ctx* ctx;
+  int B;                    /* fits of this member                                      */
+  int pad_;
+  const double* start;      /* B x P (P of this member's model), host                   */
+  const uint8_t* fixed;     /* NULL or P bytes                                          */
+  const int* data_idx;      /* NULL (fit f uses batch row f) or B rows                  */
+  double* theta_out;        /* outputs, host, each nullable: B x P, then B values each  */
+  double* nll_out;
+  double* edm_out;
+  int* status_out;
+  int* iters_out;
+  int* evals_out;
+} nf_batch_member;
+int nf_fit_batch_group(int n, const nf_batch_member* members, const nf_fit_opts* opts);
 
 /*
  * Expected counts mu (Eq. 3-5: signal from the fold and bin stages plus
@@ -351,7 +412,6 @@ int nf_timing_overhead(nf_ctx* ctx, int n, double* us);
  * Each handle owns its device memory and is used by one host thread at a time.
  * Host-pointer calls are synchronous. Return codes as above.
  */
-typedef struct nf_mlp nf_mlp;
 
 /* Create a network; parameters start at zero (set them with nf_mlp_set_params).
  * max_batch bounds B in every call. hip_stream as in nf_create. */

@@ -20,6 +20,10 @@
 
 using namespace nufold;
 
+namespace nufold {
+int mlp_shape(const nf_mlp* n, int* n_in, int* n_out, int* max_batch);  // mlp.hip
+}
+
 // Scratch of the allocation-free evaluation (nf_eval_device_noalloc): one
 // array per GPU, part of the loaded code object, held until the process
 // ends. Host code never uses the array's name as an address: each device's
@@ -229,6 +233,15 @@ struct nf_ctx {
   const double* ev_theta = nullptr;
   double* ev_out = nullptr;
   int32_t* ev_status = nullptr;
+  // surrogate for warm starts (nf_set_surrogate; the network is the caller's)
+  struct Surrogate {
+    nf_mlp* net = nullptr;
+    int n_in = 0, n_out = 0, max_batch = 0, n_starts = 0, iters = 0;
+    float lr = 0.f;
+    std::vector<int> idx;
+    std::vector<double> center, half;
+    std::vector<float> out_mean, out_std, x_prior, x_weight, starts;
+  } sur;
   void* scratch_dev = nullptr;  // this device's `scratch` array (nf_eval_device_noalloc)
   std::vector<std::array<hipEvent_t, 4>> tev;  // per-evaluation kernel start/stop events (fold, bin stages)
   size_t tcount = 0;
@@ -1133,12 +1146,68 @@ std::vector<double> preconditioner(nf_ctx* c, const double* start) {
   return d2;
 }
 
+// Warm starts (nf_fit_opts.warm_start): B start vectors (B x P, host) and the
+// observed counts of each fit (B x all bins); writes the B start vectors with
+// the surrogate's inputs replaced by the best of the start grid fitted on the
+// surrogate to each fit's counts.
+std::vector<double> surrogate_starts(nf_ctx* c, int B, const double* start, const std::vector<double>& obs) {
+  auto& s = c->sur;
+  if (!s.net) fail(NF_ESTATE, "warm start requested but no surrogate is attached (nf_set_surrogate)");
+  const int S = s.n_starts, Ni = s.n_in, No = s.n_out;
+  const int64_t N = (int64_t)B * S;
+  std::vector<float> X((size_t)N * Ni), Nobs((size_t)N * No), F((size_t)N);
+  for (int f = 0; f < B; ++f)
+    for (int k = 0; k < S; ++k) {
+      const int64_t r = (int64_t)f * S + k;
+      std::memcpy(&X[(size_t)r * Ni], &s.starts[(size_t)k * Ni], sizeof(float) * Ni);
+      for (int j = 0; j < No; ++j) Nobs[(size_t)r * No + j] = (float)obs[(size_t)f * No + j];
+    }
+  for (int64_t o = 0; o < N; o += s.max_batch) {
+    const int n = (int)std::min<int64_t>(s.max_batch, N - o);
+    const int code = nf_mlp_fit_inputs(s.net, n, &X[(size_t)o * Ni], &Nobs[(size_t)o * No], s.out_mean.data(),
+                                       s.out_std.data(), s.x_prior.data(), s.x_weight.data(), s.iters, s.lr,
+                                       &F[(size_t)o]);
+    if (code < 0) fail(code, std::string("surrogate warm start: ") + nf_mlp_last_error(s.net));
+  }
+  const size_t P = c->P;
+  std::vector<double> out(start, start + (size_t)B * P);
+  for (int f = 0; f < B; ++f) {
+    int best = -1;
+    for (int k = 0; k < S; ++k) {
+      const float v = F[(size_t)f * S + k];
+      if (std::isfinite(v) && (best < 0 || v < F[(size_t)f * S + best])) best = k;
+    }
+    if (best < 0) continue;  // no finite surrogate fit: keep the given start
+    const float* x = &X[((size_t)f * S + best) * Ni];
+    for (int i = 0; i < Ni; ++i) {
+      const double xi = std::min(1.0, std::max(-1.0, (double)x[i]));
+      out[(size_t)f * P + s.idx[i]] = s.center[i] + s.half[i] * xi;
+    }
+  }
+  return out;
+}
+
+bool want_warm(const nf_fit_opts* opts) { return opts && opts->warm_start == NF_SURROGATE; }
+
 int fit_impl(nf_ctx* c, const double* start, const uint8_t* fixed, const nf_fit_opts* opts,
              nf_fit_result* res) {
   require_ready(c, true);
   if (!start || !res) fail(NF_EINVAL, "start and result are required");
   for (int i = 0; i < c->P; ++i)
     if (!std::isfinite(start[i])) fail(NF_EINVAL, "start[" + std::to_string(i) + "] is not finite");
+  std::vector<double> warm;
+  if (want_warm(opts)) {
+    std::vector<double> obs(std::max(1, c->nbins_total));
+    hip_check(hipMemcpy(obs.data(), c->d_data.p, sizeof(double) * c->nbins_total, hipMemcpyDeviceToHost), "D2H");
+    warm = surrogate_starts(c, 1, start, obs);
+    // the exact fold judges the proposal: it replaces the start only if its
+    // NLL is lower
+    double f0 = INFINITY, f1 = INFINITY;
+    (void)eval_host(c, start, &f0, nullptr, nullptr);
+    (void)eval_host(c, warm.data(), &f1, nullptr, nullptr);
+    if (!(f1 < f0)) warm.assign(start, start + c->P);
+    start = warm.data();
+  }
   const double tol = (opts && opts->edm_tol > 0) ? opts->edm_tol : 1e-7;
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 1000;
   ensure_fit_buffers(c);
@@ -1537,19 +1606,44 @@ int eval_batch_impl(nf_ctx* c, int B, const double* theta, const int* didx, doub
   return NF_OK;
 }
 
+template <typename F>
+int guarded(nf_ctx* c, F&& f) {
+  if (!c) return NF_EINVAL;
+  try {
+    c->err.clear();
+    return f();
+  } catch (const ApiError& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return NF_ENOMEM;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return NF_EINVAL;
+  }
+}
+
+// FIT_CHUNK iterations of the batched fits of c on stream s: per iteration
+// the batched fold, then the bin stages, adjoint and L-BFGS step of every fit.
+hipError_t batch_fit_iterations(nf_ctx* c, int B, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < FIT_CHUNK && e == hipSuccess; ++i) {
+    e = launch_fold_batch(c->mode, batch_fold_args(c, B, true), s, c->batch_tile);
+    if (e == hipSuccess) e = launch_batch_tail(batch_tail_args(c, B, true, true, true), batch_threads(c), s);
+  }
+  return e;
+}
+
 void ensure_batch_fit_graph(nf_ctx* c, int B) {
   if (c->bf_graph && c->bf_graph_B == B) return;
   if (c->bf_graph) (void)hipGraphExecDestroy(c->bf_graph);
   c->bf_graph = nullptr;
   hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < FIT_CHUNK && e == hipSuccess; ++i) {
-    e = launch_fold_batch(c->mode, batch_fold_args(c, B, true), c->stream, c->batch_tile);
-    if (e == hipSuccess)
-      e = launch_batch_tail(batch_tail_args(c, B, true, true, true), batch_threads(c), c->stream);
-  }
+  const hipError_t e = batch_fit_iterations(c, B, c->stream);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  if (e != hipSuccess && g) (void)hipGraphDestroy(g);
   hip_check(e, "batch capture launch");
   hip_check(e2, "hipStreamEndCapture");
   const hipError_t e3 = hipGraphInstantiate(&c->bf_graph, g, nullptr, nullptr, 0);
@@ -1558,14 +1652,34 @@ void ensure_batch_fit_graph(nf_ctx* c, int B) {
   c->bf_graph_B = B;
 }
 
-int fit_batch_impl(nf_ctx* c, int B, const double* start, const uint8_t* fixed, const int* didx,
-                   const nf_fit_opts* opts, double* theta_out, double* nll_out, double* edm_out, int* status_out,
-                   int* iters_out, int* evals_out) {
+// Host side of a batched fit before its first iteration: argument checks,
+// start points, preconditioners, free-parameter masks, data rows and fresh
+// fit headers, uploaded on the context's stream (synchronised on return).
+// Returns the iteration limit in graph iterations.
+int64_t batch_fit_prepare(nf_ctx* c, int B, const double* start, const uint8_t* fixed, const int* didx,
+                          const nf_fit_opts* opts) {
   require_ready(c, false);
   if (B <= 0 || !start) fail(NF_EINVAL, "B > 0 and start are required");
   check_didx(c, B, didx);
   for (int64_t i = 0; i < (int64_t)B * c->P; ++i)
     if (!std::isfinite(start[i])) fail(NF_EINVAL, "start contains a non-finite value");
+  std::vector<double> warm;
+  if (want_warm(opts)) {
+    const size_t nb = (size_t)c->nbins_total;
+    std::vector<double> all((size_t)c->bt_nsets * nb), obs((size_t)B * nb);
+    hip_check(hipMemcpy(all.data(), c->bt_data.p, sizeof(double) * all.size(), hipMemcpyDeviceToHost), "D2H");
+    for (int f = 0; f < B; ++f)
+      std::memcpy(&obs[f * nb], &all[(size_t)(didx ? didx[f] : f) * nb], sizeof(double) * nb);
+    warm = surrogate_starts(c, B, start, obs);
+    // the exact fold judges every proposal: it replaces its fit's start only
+    // if its NLL is lower
+    std::vector<double> n0(B), n1(B);
+    (void)eval_batch_impl(c, B, start, didx, n0.data(), nullptr);
+    (void)eval_batch_impl(c, B, warm.data(), didx, n1.data(), nullptr);
+    for (int f = 0; f < B; ++f)
+      if (!(n1[f] < n0[f])) std::memcpy(&warm[(size_t)f * c->P], start + (size_t)f * c->P, sizeof(double) * c->P);
+    start = warm.data();
+  }
   const double tol = (opts && opts->edm_tol > 0) ? opts->edm_tol : 1e-7;
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 1000;
   ensure_batch(c, B);
@@ -1592,23 +1706,32 @@ int fit_batch_impl(nf_ctx* c, int B, const double* start, const uint8_t* fixed, 
   hip_check(hipMemcpyAsync(c->bt_osc_last.p, nanv.data(), sizeof(double) * B * 4, hipMemcpyHostToDevice, c->stream), "H2D");
   hip_check(hipMemcpyAsync(c->bt_didx.p, rows.data(), sizeof(int) * B, hipMemcpyHostToDevice, c->stream), "H2D");
   hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  ensure_batch_fit_graph(c, B);
-  const int64_t max_evals = (int64_t)max_iter * 50 + 200;
-  for (int64_t launched = 0;; launched += FIT_CHUNK) {
-    hip_check(hipGraphLaunch(c->bf_graph, c->stream), "hipGraphLaunch");
-    hip_check(hipMemcpyAsync(c->bh_hdr.data(), c->bf_hdr.p, sizeof(FitHeader) * B, hipMemcpyDeviceToHost, c->stream), "D2H");
-    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-    int running = 0;
-    for (int f = 0; f < B; ++f) running += c->bh_hdr[f].status == FIT_RUNNING;
-    if (!running) break;
-    if (launched + FIT_CHUNK >= max_evals) {
-      for (int f = 0; f < B; ++f)
-        if (c->bh_hdr[f].status == FIT_RUNNING) c->bh_hdr[f].status = FIT_MAXITER;
-      break;
-    }
-  }
+  return (int64_t)max_iter * 50 + 200;
+}
+
+// Enqueue the copy of the fit headers to the host on stream s (the caller
+// synchronises s before reading them).
+void batch_fit_headers_d2h(nf_ctx* c, int B, hipStream_t s) {
+  hip_check(hipMemcpyAsync(c->bh_hdr.data(), c->bf_hdr.p, sizeof(FitHeader) * B, hipMemcpyDeviceToHost, s), "D2H");
+}
+
+int batch_fit_running(const nf_ctx* c, int B) {
+  int running = 0;
+  for (int f = 0; f < B; ++f) running += c->bh_hdr[f].status == FIT_RUNNING;
+  return running;
+}
+
+void batch_fit_stop(nf_ctx* c, int B) {
+  for (int f = 0; f < B; ++f)
+    if (c->bh_hdr[f].status == FIT_RUNNING) c->bh_hdr[f].status = FIT_MAXITER;
+}
+
+// Outputs of a finished batched fit (each pointer nullable); NF_WNOCONV when
+// some fit did not converge.
+int batch_fit_collect(nf_ctx* c, int B, double* theta_out, double* nll_out, double* edm_out, int* status_out,
+                      int* iters_out, int* evals_out) {
   if (theta_out)
-    hip_check(hipMemcpy(theta_out, c->bf_x.p, sizeof(double) * B * P, hipMemcpyDeviceToHost), "D2H");
+    hip_check(hipMemcpy(theta_out, c->bf_x.p, sizeof(double) * B * c->P, hipMemcpyDeviceToHost), "D2H");
   bool all_ok = true;
   for (int f = 0; f < B; ++f) {
     const FitHeader& fh = c->bh_hdr[f];
@@ -1626,23 +1749,120 @@ int fit_batch_impl(nf_ctx* c, int B, const double* start, const uint8_t* fixed, 
   return NF_OK;
 }
 
-template <typename F>
-int guarded(nf_ctx* c, F&& f) {
-  if (!c) return NF_EINVAL;
-  try {
-    c->err.clear();
-    return f();
-  } catch (const ApiError& e) {
-    c->err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    c->err = "host allocation failed";
-    return NF_ENOMEM;
-  } catch (const std::exception& e) {
-    c->err = e.what();
-    return NF_EINVAL;
+int fit_batch_impl(nf_ctx* c, int B, const double* start, const uint8_t* fixed, const int* didx,
+                   const nf_fit_opts* opts, double* theta_out, double* nll_out, double* edm_out, int* status_out,
+                   int* iters_out, int* evals_out) {
+  const int64_t max_evals = batch_fit_prepare(c, B, start, fixed, didx, opts);
+  ensure_batch_fit_graph(c, B);
+  for (int64_t launched = 0;; launched += FIT_CHUNK) {
+    hip_check(hipGraphLaunch(c->bf_graph, c->stream), "hipGraphLaunch");
+    batch_fit_headers_d2h(c, B, c->stream);
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (!batch_fit_running(c, B)) break;
+    if (launched + FIT_CHUNK >= max_evals) {
+      batch_fit_stop(c, B);
+      break;
+    }
   }
+  return batch_fit_collect(c, B, theta_out, nll_out, edm_out, status_out, iters_out, evals_out);
 }
+
+// Batched fits of several contexts advanced together: one HIP graph holds
+// FIT_CHUNK iterations of every member, each member's launches on a branch of
+// its own (forked from and joined to the first member's stream), so the
+// members' kernels run side by side; the graph is replayed, and every
+// member's headers are polled after each replay, until all fits of all
+// members have stopped.
+int fit_batch_group_impl(int n, const nf_batch_member* mem, const nf_fit_opts* opts) {
+  if (n < 1 || !mem) return NF_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    if (!mem[k].ctx) return NF_EINVAL;
+    for (int j = 0; j < k; ++j)
+      if (mem[j].ctx == mem[k].ctx) {
+        mem[k].ctx->err = "a context appears twice in the group";
+        return NF_EINVAL;
+      }
+  }
+  std::vector<int64_t> limit(n);
+  for (int k = 0; k < n; ++k) {
+    nf_ctx* c = mem[k].ctx;
+    const int code = guarded(c, [&] {
+      limit[k] = batch_fit_prepare(c, mem[k].B, mem[k].start, mem[k].fixed, mem[k].data_idx, opts);
+      return NF_OK;
+    });
+    if (code != NF_OK) return code;
+  }
+  nf_ctx* c0 = mem[0].ctx;
+  return guarded(c0, [&] {
+    hipStream_t s0 = c0->stream;
+    std::vector<hipStream_t> side(n, nullptr);
+    std::vector<hipEvent_t> ev(n, nullptr);
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&] {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      for (auto& x : side)
+        if (x) (void)hipStreamDestroy(x);
+      for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    };
+    try {
+      for (int k = 0; k < n; ++k) {
+        hip_check(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming), "hipEventCreate");
+        if (k > 0) hip_check(hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking), "hipStreamCreate");
+      }
+      hip_check(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      hipError_t e = hipEventRecord(ev[0], s0);
+      for (int k = 1; k < n && e == hipSuccess; ++k) e = hipStreamWaitEvent(side[k], ev[0], 0);
+      for (int k = 0; k < n && e == hipSuccess; ++k)
+        e = batch_fit_iterations(mem[k].ctx, mem[k].B, k == 0 ? s0 : side[k]);
+      for (int k = 1; k < n && e == hipSuccess; ++k) {
+        e = hipEventRecord(ev[k], side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s0, ev[k], 0);
+      }
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(s0, &g);
+      if (e != hipSuccess && g) (void)hipGraphDestroy(g);
+      hip_check(e, "group capture");
+      hip_check(e2, "hipStreamEndCapture");
+      const hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      hip_check(e3, "hipGraphInstantiate");
+      std::vector<bool> done(n, false);
+      for (int64_t launched = 0;; launched += FIT_CHUNK) {
+        hip_check(hipGraphLaunch(exec, s0), "hipGraphLaunch");
+        for (int k = 0; k < n; ++k) batch_fit_headers_d2h(mem[k].ctx, mem[k].B, s0);
+        hip_check(hipStreamSynchronize(s0), "hipStreamSynchronize");
+        bool any = false;
+        for (int k = 0; k < n; ++k) {
+          if (done[k]) continue;
+          if (!batch_fit_running(mem[k].ctx, mem[k].B)) {
+            done[k] = true;
+          } else if (launched + FIT_CHUNK >= limit[k]) {
+            batch_fit_stop(mem[k].ctx, mem[k].B);
+            done[k] = true;
+          } else {
+            any = true;
+          }
+        }
+        if (!any) break;
+      }
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
+    int worst = NF_OK;
+    for (int k = 0; k < n; ++k) {
+      const nf_batch_member& m = mem[k];
+      const int code = batch_fit_collect(m.ctx, m.B, m.theta_out, m.nll_out, m.edm_out, m.status_out, m.iters_out,
+                                         m.evals_out);
+      if (code != NF_OK) worst = code;
+    }
+    if (worst != NF_OK) c0->err = "some fits did not converge (see each member's status)";
+    return worst;
+  });
+}
+
 
 }  // namespace
 
@@ -1979,6 +2199,51 @@ int nf_fit_batch(nf_ctx* ctx, int B, const double* start, const uint8_t* fixed, 
     return fit_batch_impl(ctx, B, start, fixed, data_idx, opts, theta_out, nll_out, edm_out, status_out, iters_out,
                           evals_out);
   });
+}
+
+int nf_set_surrogate(nf_ctx* ctx, nf_mlp* net, int n_in, const int* param_index, const double* center,
+                     const double* half, const float* out_mean, const float* out_std, const float* x_prior,
+                     const float* x_weight, int n_starts, const float* starts, int iters, float lr) {
+  return guarded(ctx, [&] {
+    auto& s = ctx->sur;
+    if (!net) {
+      s = nf_ctx::Surrogate{};
+      return NF_OK;
+    }
+    int ni = 0, no = 0, mb = 0;
+    if (mlp_shape(net, &ni, &no, &mb) != NF_OK) fail(NF_EINVAL, "bad network handle");
+    if (n_in != ni) fail(NF_EINVAL, "n_in differs from the network's input width");
+    if (no != ctx->nbins_total) fail(NF_EINVAL, "the network's outputs must cover every analysis bin");
+    if (n_starts < 1 || iters < 1 || !(lr > 0.f)) fail(NF_EINVAL, "n_starts, iters and lr must be positive");
+    if (!param_index || !center || !half || !out_mean || !out_std || !x_prior || !x_weight || !starts)
+      fail(NF_EINVAL, "null array");
+    for (int i = 0; i < n_in; ++i) {
+      if (param_index[i] < 0 || param_index[i] >= ctx->P) fail(NF_EINVAL, "parameter index out of range");
+      if (!std::isfinite(center[i]) || !(half[i] > 0.0)) fail(NF_EINVAL, "center must be finite and half > 0");
+    }
+    nf_ctx::Surrogate t;
+    t.net = net;
+    t.n_in = n_in;
+    t.n_out = no;
+    t.max_batch = mb;
+    t.n_starts = n_starts;
+    t.iters = iters;
+    t.lr = lr;
+    t.idx.assign(param_index, param_index + n_in);
+    t.center.assign(center, center + n_in);
+    t.half.assign(half, half + n_in);
+    t.out_mean.assign(out_mean, out_mean + no);
+    t.out_std.assign(out_std, out_std + no);
+    t.x_prior.assign(x_prior, x_prior + n_in);
+    t.x_weight.assign(x_weight, x_weight + n_in);
+    t.starts.assign(starts, starts + (size_t)n_starts * n_in);
+    s = std::move(t);
+    return NF_OK;
+  });
+}
+
+int nf_fit_batch_group(int n, const nf_batch_member* members, const nf_fit_opts* opts) {
+  return fit_batch_group_impl(n, members, opts);
 }
 
 int nf_fit(nf_ctx* ctx, const double* start, const uint8_t* fixed, const nf_fit_opts* opts,

@@ -772,3 +772,14 @@ int nf_mlp_fit_inputs(nf_mlp* n, int B, float* x, const float* nobs, const float
 }
 
 }  // extern "C"
+
+namespace nufold {
+// Shape of a network, for the engine's warm starts.
+int mlp_shape(const nf_mlp* n, int* n_in, int* n_out, int* max_batch) {
+  if (!n) return NF_EINVAL;
+  *n_in = n->n_in;
+  *n_out = n->n_out;
+  *max_batch = n->max_batch;
+  return NF_OK;
+}
+}  // namespace nufold

@@ -49,8 +49,12 @@ SIGNATURES = {
     "nf_timing": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), _dp, _dp]),
 }
 
+NF_SURROGATE = 1
+
+
 class FitOpts(C.Structure):
-    _fields_ = [("edm_tol", C.c_double), ("max_iter", C.c_int), ("want_cov", C.c_int)]
+    _fields_ = [("edm_tol", C.c_double), ("max_iter", C.c_int), ("want_cov", C.c_int),
+                ("warm_start", C.c_int), ("pad_", C.c_int)]
 
 
 class FitResult(C.Structure):
@@ -65,6 +69,17 @@ SIGNATURES["nf_fit_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_voi
                                         C.POINTER(FitOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p])
 
+class BatchMember(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("B", C.c_int), ("pad_", C.c_int), ("start", C.c_void_p),
+                ("fixed", C.c_void_p), ("data_idx", C.c_void_p), ("theta_out", C.c_void_p),
+                ("nll_out", C.c_void_p), ("edm_out", C.c_void_p), ("status_out", C.c_void_p),
+                ("iters_out", C.c_void_p), ("evals_out", C.c_void_p)]
+
+
+SIGNATURES["nf_fit_batch_group"] = (C.c_int, [C.c_int, C.POINTER(BatchMember), C.POINTER(FitOpts)])
+SIGNATURES["nf_set_surrogate"] = (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                            C.c_int, C.c_float])
 SIGNATURES["nf_timing_overhead"] = (C.c_int, [C.c_void_p, C.c_int, _dp])
 SIGNATURES["nf_autotune"] = (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p])
 SIGNATURES["nf_expected_batch"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
@@ -247,7 +262,7 @@ class Engine:
                                                            C.c_void_p(status_ptr) if status_ptr else None,
                                                            1 if want_grad else 0))
 
-    def fit(self, start, fixed=None, edm_tol=1e-7, max_iter=1000, want_cov=False):
+    def fit(self, start, fixed=None, edm_tol=1e-7, max_iter=1000, want_cov=False, warm_start=False):
         """Device L-BFGS fit from `start`; returns a dict (theta, nll, edm, status, iters,
         evals, cov, code)."""
         st = np.ascontiguousarray(start, dtype=np.float64)
@@ -256,7 +271,7 @@ class Engine:
         fx = None
         if fixed is not None:
             fx = np.ascontiguousarray(np.asarray(fixed, dtype=bool).astype(np.uint8))
-        opts = FitOpts(edm_tol, max_iter, 1 if want_cov else 0)
+        opts = FitOpts(edm_tol, max_iter, 1 if want_cov else 0, NF_SURROGATE if warm_start else 0, 0)
         res = FitResult()
         res.theta = th.ctypes.data
         res.cov = cov.ctypes.data if cov is not None else None
@@ -284,7 +299,7 @@ class Engine:
                                                      nll.ctypes.data, g.ctypes.data if g is not None else None))
         return nll, g, code
 
-    def fit_batch(self, start, fixed=None, data_idx=None, edm_tol=1e-7, max_iter=1000):
+    def fit_batch(self, start, fixed=None, data_idx=None, edm_tol=1e-7, max_iter=1000, warm_start=False):
         st = np.ascontiguousarray(start, dtype=np.float64)
         B = st.shape[0]
         th = np.zeros((B, self.P))
@@ -292,12 +307,27 @@ class Engine:
         status, iters, evals = (np.zeros(B, dtype=np.int32) for _ in range(3))
         fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=bool).astype(np.uint8))
         di = None if data_idx is None else np.ascontiguousarray(data_idx, dtype=np.int32)
-        opts = FitOpts(edm_tol, max_iter, 0)
+        opts = FitOpts(edm_tol, max_iter, 0, NF_SURROGATE if warm_start else 0, 0)
         code = _check(self.ctx, load().nf_fit_batch(
             self.ctx, B, st.ctypes.data, fx.ctypes.data if fx is not None else None,
             di.ctypes.data if di is not None else None, C.byref(opts), th.ctypes.data, nll.ctypes.data,
             edm.ctypes.data, status.ctypes.data, iters.ctypes.data, evals.ctypes.data))
         return dict(theta=th, nll=nll, edm=edm, status=status, iters=iters, evals=evals, code=code)
+
+    def set_surrogate(self, net, param_index, center, half, out_mean, out_std, x_prior, x_weight, starts,
+                      iters=200, lr=0.02):
+        """Attach a surrogate network (Mlp) for warm starts (nf_set_surrogate);
+        net=None detaches."""
+        if net is None:
+            return _check(self.ctx, load().nf_set_surrogate(self.ctx, None, 0, None, None, None, None, None, None,
+                                                            None, 0, None, 0, 0.0))
+        self._sur = [np.ascontiguousarray(param_index, np.int32), np.ascontiguousarray(center, np.float64),
+                     np.ascontiguousarray(half, np.float64), np.ascontiguousarray(out_mean, np.float32),
+                     np.ascontiguousarray(out_std, np.float32), np.ascontiguousarray(x_prior, np.float32),
+                     np.ascontiguousarray(x_weight, np.float32), np.ascontiguousarray(starts, np.float32), net]
+        a = self._sur
+        return _check(self.ctx, load().nf_set_surrogate(self.ctx, net.h, len(a[0]), *[x.ctypes.data for x in a[:7]],
+                                                        a[7].shape[0], a[7].ctypes.data, int(iters), float(lr)))
 
     def timing_overhead(self, n=200):
         """Mean gap (us) between two back-to-back timing events on the stream."""
@@ -327,6 +357,38 @@ class Engine:
         n, f, t = C.c_int64(), C.c_double(), C.c_double()
         _check(self.ctx, load().nf_timing(self.ctx, 1 if reset else 0, C.byref(n), C.byref(f), C.byref(t)))
         return n.value, f.value, t.value
+
+
+def fit_batch_group(members, edm_tol=1e-7, max_iter=1000, warm_start=False):
+    """Batched fits of several engines advanced together (nf_fit_batch_group).
+    members: list of (engine, start B x P, fixed or None, data_idx or None).
+    Returns one result dict per member (as Engine.fit_batch) and the code."""
+    keep, arr, outs = [], (BatchMember * len(members))(), []
+    for k, (eng, start, fixed, didx) in enumerate(members):
+        st = np.ascontiguousarray(start, dtype=np.float64)
+        B = st.shape[0]
+        fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=bool).astype(np.uint8))
+        di = None if didx is None else np.ascontiguousarray(didx, dtype=np.int32)
+        o = dict(theta=np.zeros((B, eng.P)), nll=np.zeros(B), edm=np.zeros(B),
+                 status=np.zeros(B, np.int32), iters=np.zeros(B, np.int32), evals=np.zeros(B, np.int32))
+        keep += [st, fx, di]
+        m = arr[k]
+        m.ctx, m.B = eng.ctx, B
+        m.start = st.ctypes.data
+        m.fixed = fx.ctypes.data if fx is not None else None
+        m.data_idx = di.ctypes.data if di is not None else None
+        m.theta_out, m.nll_out, m.edm_out = o["theta"].ctypes.data, o["nll"].ctypes.data, o["edm"].ctypes.data
+        m.status_out, m.iters_out, m.evals_out = (o["status"].ctypes.data, o["iters"].ctypes.data,
+                                                  o["evals"].ctypes.data)
+        outs.append(o)
+    opts = FitOpts(edm_tol, max_iter, 0, NF_SURROGATE if warm_start else 0, 0)
+    code = load().nf_fit_batch_group(len(members), arr, C.byref(opts))
+    if code < 0:
+        msgs = [m for m in (_err(e.ctx) for e, *_ in members) if m]
+        raise NufoldError(code, "; ".join(msgs))
+    for o in outs:
+        o["code"] = code
+    return outs, code
 
 
 def _mlp_err(h):

@@ -178,21 +178,37 @@ class Surrogate:
         y = self.net.forward(self.space.to_x(theta))
         return y * self.out_std + self.out_mean
 
-    def warm_start(self, nobs, grid=(4, 16), iters=200, lr=0.02, base=None):
-        """Start points for fits of each row of observed counts (E x bins).
-        Surrogate fits from a grid over the inputs without a prior (others at
-        their prior means), run together; the best per row wins."""
+    def start_grid(self, grid=(4, 16)):
+        """Start rows (x units) of the surrogate fits: a grid over the inputs
+        without a prior, every other input at its prior mean."""
         sp = self.space
-        E = nobs.shape[0]
         free = np.where(sp.free)[0]
         axes = []
         for j, f in enumerate(free):
             n = grid[j] if j < len(grid) else 1
             axes.append((np.arange(n) + 0.5) / n * 2.0 - 1.0)
         mesh = np.array(np.meshgrid(*axes, indexing="ij")).reshape(len(free), -1).T
-        S = mesh.shape[0]
-        x0 = np.tile(sp.x_prior, (S, 1))
+        x0 = np.tile(sp.x_prior, (mesh.shape[0], 1))
         x0[:, free] = mesh
+        return x0.astype(np.float32)
+
+    def attach(self, eng, grid=(4, 16), iters=200, lr=0.02):
+        """Attach this network to an engine for warm starts inside the library's
+        fits (nf_set_surrogate; fits then take warm_start=True): the same start
+        grid, surrogate fits and choice as warm_start below."""
+        sp = self.space
+        return eng.set_surrogate(self.net, sp.inputs, sp.center, sp.half, self.out_mean, self.out_std,
+                                 sp.x_prior.astype(np.float32), sp.x_weight.astype(np.float32),
+                                 self.start_grid(grid), iters=iters, lr=lr)
+
+    def warm_start(self, nobs, grid=(4, 16), iters=200, lr=0.02, base=None):
+        """Start points for fits of each row of observed counts (E x bins).
+        Surrogate fits from a grid over the inputs without a prior (others at
+        their prior means), run together; the best per row wins."""
+        sp = self.space
+        E = nobs.shape[0]
+        x0 = self.start_grid(grid)
+        S = x0.shape[0]
         X0 = np.tile(x0, (E, 1)).astype(np.float32)
         N = np.repeat(np.asarray(nobs, np.float32), S, axis=0)
         out_x = np.empty_like(X0)

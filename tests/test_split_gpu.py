@@ -11,7 +11,7 @@ from oracle.model import Model
 from oracle import likelihood as LK
 from paper_2502_15253_amd import nufold as nf
 from paper_2502_15253_amd import synth
-from test_parity_gpu import compare, displaced, make_engine, TOL, GRAD_TOL
+from test_parity_gpu import compare, displaced, make_engine, TOL, GRAD_TOL, GRAD_MAX_TOL
 
 pytestmark = pytest.mark.gpu
 
@@ -30,8 +30,8 @@ def test_split_model_matches_oracle(mode):
     data = synth.poisson_data(mus, synth.data_seed(6))
     eng = make_engine(desc, events, data, mode)
     assert eng.D == 20 and [eng.nbins[d] for d in range(18, 20)] == [1, 1]
-    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "split start", gtol=GRAD_TOL[mode])
-    compare(eng, desc, events, data, displaced(desc, 600), TOL[mode], "split displaced", gtol=GRAD_TOL[mode])
+    compare(eng, desc, events, data, synth.start_vector(desc), TOL[mode], "split start", gtol=GRAD_TOL[mode], gmax=GRAD_MAX_TOL[mode])
+    compare(eng, desc, events, data, displaced(desc, 600), TOL[mode], "split displaced", gtol=GRAD_TOL[mode], gmax=GRAD_MAX_TOL[mode])
 
 
 def test_split_batched_fits_match_single_fits():

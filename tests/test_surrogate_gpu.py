@@ -77,3 +77,21 @@ def test_surrogate_warm_start_finds_the_global_minimum_more_often():
         f"iterations cold {rc['iters'].mean():.1f} warm {rw['iters'].mean():.1f}")
     assert ok_warm >= 0.8
     assert ok_warm >= ok_cold + 0.2
+    # the same warm start requested through the C-ABI (nf_fit_opts.warm_start
+    # with the network attached by nf_set_surrogate): the same proposals,
+    # judged by the exact NLL at the start (a proposal replaces the cold start
+    # only where it is lower there), so every fit that takes the proposal ends
+    # at the host warm start's minimum and every other one at the cold fit's
+    sur.attach(eng)
+    ra = eng.fit_batch(cold, edm_tol=1e-6, max_iter=2000, warm_start=True)
+    n_cold, _, _ = eng.eval_batch(cold, want_grad=False)
+    n_warm, _, _ = eng.eval_batch(warm, want_grad=False)
+    took = n_warm < n_cold
+    ref = np.where(took, rw["nll"], rc["nll"])
+    say("ABI warm start: proposals taken", int(took.sum()), "of", E, "; max |dNLL|",
+        float(np.max(np.abs(ra["nll"] - ref))))
+    assert np.max(np.abs(ra["nll"] - ref)) < 1e-6
+    assert np.mean(ra["nll"] - best < 5e-4) >= ok_warm - 0.02
+    eng.set_surrogate(None, None, None, None, None, None, None, None, None)
+    with pytest.raises(nf.NufoldError):
+        eng.fit_batch(cold[:2], warm_start=True)
