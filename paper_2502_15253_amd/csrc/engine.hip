@@ -535,7 +535,12 @@ void parse_model(nf_ctx* c, const char* text) {
     for (size_t di = 0; di < c->dsplan.size(); ++di) {
       DsPlan& q = c->dsplan[di];
       const HostDataset& d = c->ds[di];
-      const BlobLayout B = blob_layout(q.Nb + 1, q.nbkg, q.Nb, q.nnz, q.M, q.S, q.nl, q.K);
+      int fw = 1;
+      for (int k = 0; k < q.K; ++k) fw = std::max(fw, ip[q.fx_row + k + 1] - ip[q.fx_row + k]);
+      if (fw > FLUX_FW_MAX)
+        fail(NF_EPARSE, "at most " + std::to_string(FLUX_FW_MAX) + " flux modes may be non-zero in one fine bin");
+      q.fw = fw;
+      const BlobLayout B = blob_layout(q.Nb + 1, q.nbkg, q.Nb, q.nnz, q.M, q.S, q.nl, q.K, fw);
       std::vector<double> blob(B.total, 0.0);
       // 32-bit integer j of the int array at double offset off
       auto put = [&](int off, int j, int v) { std::memcpy(reinterpret_cast<char*>(&blob[off]) + 4 * (size_t)j, &v, 4); };
@@ -557,10 +562,13 @@ void parse_model(nf_ctx* c, const char* text) {
       for (int m = 0; m < q.M; ++m) put(B.mdp, m, ip[q.md_param + m]);
       for (int s = 0; s <= q.S; ++s) put(B.nlp, s, ip[q.srcnorm_ptr + s] - q.nl0);
       for (int j = 0; j < q.nl; ++j) put(B.nli, j, ip[q.nl0 + j]);
-      for (int k = 0; k <= q.K; ++k) put(B.frow, k, ip[q.fx_row + k]);
-      for (int e = 0; e < q.nnz; ++e) {
-        put(B.fpar, e, d.flux_param[ip[q.fx_mode + e]]);
-        blob[B.fcf + e] = dp[q.fx_coef + e];
+      for (int k = 0; k < q.K; ++k) {
+        const int e0 = ip[q.fx_row + k], e1 = ip[q.fx_row + k + 1];
+        for (int j = 0; j < fw; ++j) {
+          const int e = e0 + j;
+          put(B.fpar, k * fw + j, e < e1 ? d.flux_param[ip[q.fx_mode + e]] : -1);
+          blob[B.fcf + k * fw + j] = e < e1 ? dp[q.fx_coef + e] : 0.0;
+        }
       }
       if (dp.size() % 2) dp.push_back(0.0);  // 16-byte aligned blobs (direct LDS copies in 16-byte units)
       q.blob = (int)dp.size();

@@ -14,6 +14,7 @@ constexpr int FORM_4NU = 2;  // vacuum 3+1: sin2_t13, dm2_31, sin2_2t14, dm2_41 
 constexpr int NSLOT = 4;
 constexpr int MAX_MOM = 12;  // per-segment moments produced by the fold
 constexpr int MAX_SOURCES = 64;
+constexpr int FLUX_FW_MAX = 8;  // flux modes non-zero in one fine bin (fixed-width rows)
 // Oscillation coefficient rows: row 0 gives S, rows 1..4 dS/d(slot j), each a
 // linear combination of (W, M_1..M_NM) stored at CF_STRIDE doubles per row.
 constexpr int CF_STRIDE = 16;
@@ -91,6 +92,8 @@ struct DsPlan {
   int cidx[3];      // energy-scale parameters c0, c1, c2 (-1: fixed at 0)
   int bkg0;         // index of the first BkgPlan
   int blob, blob_n; // dpool offset and length of the static blob (layout: blob_layout)
+  int fw;           // flux basis entries per fine bin in the blob's fixed-width rows (>= 1)
+  int pad_;
 };
 
 static_assert(sizeof(DsPlan) % sizeof(double) == 0, "DsPlan is copied as doubles");
@@ -100,13 +103,15 @@ constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
 // count doubles; the integer arrays hold 32-bit integers, two per double
 // slot. The first hpart doubles (flux modes by column, source norm lists) are
 // what the stages read from LDS, copied there in one batch; the rest (edges,
-// background templates, flux basis by fine bin) is read once per evaluation
-// straight from global memory.
+// background templates, the flux basis by fine bin in rows of fixed width fw,
+// unused entries with parameter -1) is read by each thread into registers,
+// every load independent of the others.
 struct BlobLayout {
   int mdc, mdcol, mdk, mdp, nlp, nli, hpart;
-  int edges, tmpl, bsc, fcf, frow, fpar, brt, shp, total;
+  int edges, tmpl, bsc, fcf, fpar, brt, shp, total;
 };
-__host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K) {
+__host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K,
+                                                  int fw) {
   auto ints = [](int n) { return (n + 1) / 2; };  // double slots for n int32 values
   BlobLayout L;
   int o = 0;
@@ -121,9 +126,8 @@ __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz,
   L.edges = o; o += E;
   L.tmpl = o; o += B * Nb;
   L.bsc = o; o += B;
-  L.fcf = o; o += nnz;            // flux basis by fine bin (CSR): coefficients,
-  L.frow = o; o += ints(K + 1);   // row pointers,
-  L.fpar = o; o += ints(nnz);     // parameter of each entry
+  L.fcf = o; o += K * fw;         // flux basis by fine bin, fw entries per bin: coefficients,
+  L.fpar = o; o += ints(K * fw);  // parameter of each entry (-1: unused)
   L.brt = o; o += ints(B);
   L.shp = o; o += ints(B * Nb);
   L.total = o;

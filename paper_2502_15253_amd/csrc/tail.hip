@@ -63,27 +63,28 @@ struct Lds {
   double* coef;   // CF_SIZE
   DsPlan* dsl;    // D dataset plans
   double* red;    // block reduction scratch (red_doubles)
-  double* dyn;    // copy target: Hs, G0..G3 (5 K), Ss (S K), observed counts (Nb)
-  double* Hs;
-  double* Gs;     // 4 K
-  double* Ss;
-  double* nD;
-  double* F1;     // K     1 + F (parameter pass)
+  double* Hk;     // K     H_k = Hs_k (1 + F_k)
+  double* mk;     // K     m_k = H_k / w
+  double* F1;     // K     1 + F_k
   double* LF;     // K     lambda_F
-  double* LHs;    // K     lambda_Hs
+  double* LHs;    // K     lambda_Hs (read back only for sources past the first sixteen)
+  double* Hs;     // K     the oscillated spectrum with source norms (fold row 0)
+  double* Ss;     // S K   per-source spectra (copy target)
   double* lam;    // Nb    lambda_mu
   double* Bv;     // Nb    background expectation
   double* bkr;    // B Nb  dmu_i/dR_b
   double* bks;    // B Nb  dmu_i/dbeta_bi
   double* eT;     // E     t of each mapped edge
   double* eY;     // E     y of each mapped edge
+  double* eP;     // E     spline integral from its fine bin's lower edge to the mapped edge (0 outside)
+  double* eR;     // E     spline density at the mapped edge over f'(y) (0 outside)
   double* prv;    // NR    gradient contribution of each prior row
   double* st;     // copy target: the flux-mode and norm-list part of the static blob
   double* fit;    // minimiser scratch
   int* ek;        // E     fine bin of each mapped edge: -1 below y_0, K at or above y_K
   int* first;     // K + 2 first[q] = first edge whose clamped fine bin is >= q (E: none)
-  int* bki;       // B Nb  shape parameter of (b, i), or -1
   int* pri;       // NR    parameter of each prior row
+  int* bki;       // B Nb  shape parameter of (b, i), or -1
   int* flag;      // 2
 };
 
@@ -100,17 +101,22 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   q = al(q);
   L.dsl = reinterpret_cast<DsPlan*>(q); q += p.D * DSPLAN_DOUBLES;
   L.red = q; q += red_doubles(NT);
-  q = al(q);
-  L.dyn = q; q += 5 * K + p.max_S * K + Nb;
+  L.Hk = q; q += K;
+  L.mk = q; q += K;
   L.F1 = q; q += K;
   L.LF = q; q += K;
   L.LHs = q; q += K;
+  L.Hs = q; q += K;
+  q = al(q);
+  L.Ss = q; q += p.max_S * K;
   L.lam = q; q += Nb;
   L.Bv = q; q += Nb;
   L.bkr = q; q += BN;
   L.bks = q; q += BN;
   L.eT = q; q += E;
   L.eY = q; q += E;
+  L.eP = q; q += E;
+  L.eR = q; q += E;
   L.prv = q; q += p.NR;
   q = al(q);
   L.st = q; q += p.max_blob;
@@ -118,10 +124,9 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   int* r = reinterpret_cast<int*>(q);
   L.ek = r; r += E;
   L.first = r; r += K + 2;
-  L.bki = r; r += BN;
   L.pri = r; r += p.NR;
+  L.bki = r; r += BN;
   L.flag = r;
-  L.Hs = L.Gs = L.Ss = L.nD = nullptr;
   return L;
 }
 
@@ -248,167 +253,212 @@ __device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int 
   if (tail) dma_lds<NT, 4>(d + 8 * (head + body), s + 8 * (head + body), 8);
 }
 
-// Stage dataset d's inputs in LDS: the flux-mode and norm-list part of the
-// static blob, the fine-bin rows Hs, G0..G3, per-segment S and the data.
-// Fused (single evaluation): the rows and S were written by the fold kernel
-// in an earlier launch, so everything goes straight into LDS with direct
-// global-to-LDS loads. Otherwise the rows were written by this workgroup's
-// phase A with agent-scope stores and are read back with coherent loads, U
-// per thread in flight before the LDS writes. No wait, no barrier: the
-// caller waits and synchronises.
-template <int NT>
-__device__ __forceinline__ void stage_dataset(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
-                                              int want_nll) {
-  const int K = ds.K, Nb = ds.Nb, S = ds.S;
-  const BlobLayout BL = blob_layout(Nb + 1, ds.nbkg, Nb, ds.nnz, ds.M, S, ds.nl, K);
-  const int n1 = 5 * K, n2 = n1 + S * K, n3 = n2 + (want_nll ? Nb : 0);
-  if (io.fused) {
-    copy_to_lds<NT>(L.st, p.dpool + ds.blob, BL.hpart);
-    copy_to_lds<NT>(L.dyn, io.bin + 6 * (int64_t)ds.kt0, n1);
-    copy_to_lds<NT>(L.dyn + n1, io.Sseg + ds.seg0, n2 - n1);
-    if (want_nll) copy_to_lds<NT>(L.dyn + n2, io.data + ds.data, Nb);
-    return;
-  }
-  const int tid = threadIdx.x;
-  const int nbl = BL.hpart;
-  const double* blob = p.dpool + ds.blob;
+// ---------------------------------------------------------------- inputs
+// What one thread reads for one fine bin, one analysis bin and one mapped
+// edge of a dataset, straight into registers: every load is independent of
+// the others (fixed offsets from the dataset plan), so a thread issues all of
+// them at once when the dataset starts. The fold's rows were written by the
+// fold kernel (single evaluation: plain loads) or by this workgroup's phase A
+// (batched: coherent agent-scope loads).
+struct FineIn {   // parameter pass: the oscillated spectrum and the flux row
+  double hs, fc[FLUX_FW_MAX];
+  int fp[FLUX_FW_MAX];
+};
+struct FineRows { // adjoint: the oscillation-slot derivative rows
+  double g[4];
+};
+struct BinIn {
+  double n, T[MAX_BKG];
+  int sp[MAX_BKG];
+};
+
+__device__ __forceinline__ double ld(const double* p, int coherent) { return coherent ? load_agent(p) : *p; }
+
+__device__ __forceinline__ void load_fine(const DevPlan& p, const EvalIO& io, const DsPlan& ds,
+                                          const BlobLayout& BL, int k, FineIn& r) {
+  const int fw = ds.fw, co = io.fused ? 0 : 1;
   const double* b = io.bin + 6 * (int64_t)ds.kt0;
-  const double* sg = io.Sseg + ds.seg0;
-  const double* dt = io.data + ds.data;
-  const int total = nbl + n3;
-  constexpr int U = 16;
-  for (int base = 0; base < total; base += NT * U) {
-    double v[U];
+  const double* blob = p.dpool + ds.blob;
+  const int* fpar = reinterpret_cast<const int*>(blob + BL.fpar);
+  r.hs = ld(b + k, co);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * NT + tid;
-      const int j = i - nbl;
-      v[u] = i < nbl ? blob[i]
-           : j < n1 ? load_agent(b + j) : j < n2 ? load_agent(sg + (j - n1)) : j < n3 ? dt[j - n2] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * NT + tid;
-      const int j = i - nbl;
-      if (i < nbl) L.st[i] = v[u];
-      else if (j < n3) L.dyn[j] = v[u];
-    }
+  for (int j = 0; j < FLUX_FW_MAX; ++j) {
+    r.fc[j] = j < fw ? blob[BL.fcf + k * fw + j] : 0.0;
+    r.fp[j] = j < fw ? fpar[k * fw + j] : -1;
   }
 }
 
-// Parameter pass of a dataset, read straight from global memory (theta and the
-// static blob), so that it overlaps the copies of the dataset's rows: 1 + F per
-// fine bin; the mapped analysis edges (fine bin, t, y); per analysis bin the
-// background expectation and its derivatives by rate and shape. It writes
-// only LDS regions that no copy targets. Thread 0 flags an energy map that is
-// not increasing on the fine range.
-template <int NT>
-__device__ __forceinline__ void param_pass(const DevPlan& p, const DsPlan& ds, const double* th, Lds<NT>& L) {
-  const int tid = threadIdx.x;
-  const int K = ds.K, Nb = ds.Nb, E = Nb + 1, NB = ds.nbkg;
-  const double wf = ds.wf, iwf = 1.0 / wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
-  const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, ds.M, ds.S, ds.nl, K);
+__device__ __forceinline__ void load_rows(const EvalIO& io, const DsPlan& ds, int k, FineRows& r) {
+  const int K = ds.K, co = io.fused ? 0 : 1;
+  const double* b = io.bin + 6 * (int64_t)ds.kt0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r.g[j] = ld(b + (j + 1) * K + k, co);
+}
+
+__device__ __forceinline__ void load_bin(const DevPlan& p, const EvalIO& io, const DsPlan& ds,
+                                         const BlobLayout& BL, int i, int want_nll, BinIn& r) {
+  const int Nb = ds.Nb, NB = ds.nbkg;
   const double* blob = p.dpool + ds.blob;
-  const int* frow = reinterpret_cast<const int*>(blob + BL.frow);
-  const int* fpar = reinterpret_cast<const int*>(blob + BL.fpar);
-  const double* fcf = blob + BL.fcf;
-  const double* X = blob + BL.edges;
-  const double* tmpl = blob + BL.tmpl;
-  const double* bsc = blob + BL.bsc;
-  const int* brt = reinterpret_cast<const int*>(blob + BL.brt);
   const int* shp = reinterpret_cast<const int*>(blob + BL.shp);
-  for (int k = tid; k < K; k += NT) {
-    double F = 0.0;
-    const int e1 = frow[k + 1];
-    for (int e = frow[k]; e < e1; ++e) F += th[fpar[e]] * fcf[e];
-    L.F1[k] = 1.0 + F;
-  }
-  const double c0 = pval(th, ds.cidx[0], 0.0);
-  const double c1 = pval(th, ds.cidx[1], 0.0);
-  const double c2 = pval(th, ds.cidx[2], 0.0);
-  const double bb = 1.0 + c1;
-  if (tid == 0 && !(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0))
-    atomicOr(&L.flag[0], ST_DOMAIN);
-  for (int i = tid; i < E; i += NT) {
-    const double z = X[i] - c0;
-    const double disc = bb * bb + 4.0 * c2 * z;
-    double y;
-    if (disc < 0.0) y = c2 < 0.0 ? INFINITY : -INFINITY;
-    else y = 2.0 * z / (bb + sqrt(disc));
-    int k;
-    double t = 0.0;
-    if (!(y >= y0)) {
-      k = -1;
-    } else if (y >= yK) {
-      k = K;
-    } else {
-      k = (int)floor((y - y0) * iwf);
-      k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
-      t = (y - (y0 + k * wf)) * iwf;
-    }
-    L.ek[i] = k;
-    L.eT[i] = t;
-    L.eY[i] = y;
-  }
-  for (int i = tid; i < Nb; i += NT) {
-    double B = 0.0;
-    for (int b = 0; b < NB; ++b) {
-      const int sp = shp[b * Nb + i];
-      const double T = bsc[b] * tmpl[b * Nb + i];
-      const double R = pval(th, brt[b], 1.0);
-      const double f = 1.0 + pval(th, sp, 0.0);
-      B += R * T * f;
-      L.bkr[b * Nb + i] = T * f;
-      L.bks[b * Nb + i] = R * T;
-      L.bki[b * Nb + i] = sp;
-    }
-    L.Bv[i] = B;
+  r.n = want_nll ? io.data[ds.data + i] : 0.0;
+#pragma unroll
+  for (int b = 0; b < MAX_BKG; ++b) {
+    r.T[b] = b < NB ? blob[BL.bsc + b] * blob[BL.tmpl + b * Nb + i] : 0.0;
+    r.sp[b] = b < NB ? shp[b * Nb + i] : -1;
   }
 }
 
 // Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
 // NLL (+inf when out of domain) to every thread; the gradient is in L.grad.
-// On entry dataset 0's copies are in flight (issued by the caller), its
-// parameter pass and the prior rows are done, and prior_e is this thread's
-// part of the prior NLL; nothing has been waited for yet.
+// On entry the parameters are in LDS (waited for and synchronised), the
+// gradient and flag are clear, the prior rows are in L.prv / L.pri, and
+// prior_e is this thread's part of the prior NLL.
+//
+// Per dataset: (a) the flux-mode and norm-list tables and the per-source
+// spectra go to LDS by asynchronous direct copies; (b) parameter pass, each
+// thread loading its own fine bin, analysis bin and edge into registers (all
+// loads independent): 1 + F, H and m per fine bin, the background
+// expectation and its factors per analysis bin, the mapped edges; (c) per
+// mapped edge the densities, the
+// spline integral up to the edge and its density, and the edge-index table;
+// (d) per analysis bin the signal, expectation, deviance, lambda and the
+// background and energy-scale sums; (e) per fine bin the adjoint; one block
+// reduction of every summed gradient; (f) source norms, flux modes, priors.
 constexpr int ACC_SRC = 16;  // sources reduced together with the other sums
 template <int NT>
-__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const double* thg,
-                                double prior_e, int want_nll, int want_grad) {
+__device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, double prior_e, int want_nll,
+                                int want_grad) {
   const int tid = threadIdx.x;
   double nll_total = 0.0;  // identical in every thread (block sums broadcast)
 
-  for (int d = 0; d < p.D; ++d) {
+#pragma unroll 1
+  for (int dloop = 0; dloop < p.D; ++dloop) {
+    // an opaque copy of the dataset index: nothing derived from the dataset
+    // is hoisted out of the loop (where it would hold registers throughout)
+    int d = dloop;
+    asm volatile("" : "+s"(d));
     const DsPlan& ds = d == 0 ? p.ds0 : L.dsl[d];
     const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
-    const double wf = ds.wf, iwf = 1.0 / wf;
-    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K);
-    L.Hs = L.dyn;
-    L.Gs = L.dyn + K;
-    L.Ss = L.dyn + 5 * K;
-    L.nD = L.dyn + 5 * K + S * K;
-    if (d > 0) {
-      stage_dataset<NT>(p, io, L, ds, want_nll);
-      param_pass<NT>(p, ds, thg, L);
+    const double wf = ds.wf, iwf = 1.0 / wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
+    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K, ds.fw);
+    const double* blob = p.dpool + ds.blob;
+    const int* brt = reinterpret_cast<const int*>(blob + BL.brt);
+
+    // ---- (a) inputs
+    copy_to_lds<NT>(L.st, blob, BL.hpart);
+    if (io.fused) {
+      copy_to_lds<NT>(L.Ss, io.Sseg + ds.seg0, S * K);
+    } else {
+      // written by this workgroup's phase A: coherent loads, then LDS stores
+      for (int j = tid; j < S * K; j += NT) L.Ss[j] = load_agent(io.Sseg + ds.seg0 + j);
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    int brt_b[MAX_BKG];
+#pragma unroll
+    for (int b = 0; b < MAX_BKG; ++b) brt_b[b] = b < NB ? brt[b] : -1;
+
+    // ---- (b) parameter pass
+    const double c0 = pval(L.th, ds.cidx[0], 0.0);
+    const double c1 = pval(L.th, ds.cidx[1], 0.0);
+    const double c2 = pval(L.th, ds.cidx[2], 0.0);
+    const double bb = 1.0 + c1;
+    if (tid == 0 && !(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0))
+      atomicOr(&L.flag[0], ST_DOMAIN);
     if (d == 0) {
       for (int i = tid; i < p.P; i += NT)
         if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
       if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
     }
-    const double c2 = pval(L.th, ds.cidx[2], 0.0);
-    const double bb = 1.0 + pval(L.th, ds.cidx[1], 0.0);
+    for (int k = tid; k < K; k += NT) {
+      FineIn x;
+      load_fine(p, io, ds, BL, k, x);
+      double F = 0.0;
+#pragma unroll
+      for (int j = 0; j < FLUX_FW_MAX; ++j)
+        if (x.fp[j] >= 0) F += L.th[x.fp[j]] * x.fc[j];
+      const double f1 = 1.0 + F;
+      const double H = x.hs * f1;
+      L.F1[k] = f1;
+      L.Hs[k] = x.hs;
+      L.Hk[k] = H;
+      L.mk[k] = H * iwf;
+    }
+    for (int i = tid; i < Nb; i += NT) {
+      BinIn x;
+      load_bin(p, io, ds, BL, i, want_nll, x);
+      double B = 0.0;
+#pragma unroll
+      for (int b = 0; b < MAX_BKG; ++b)
+        if (b < NB) {
+          const double R = pval(L.th, brt_b[b], 1.0);
+          const double f = 1.0 + pval(L.th, x.sp[b], 0.0);
+          B += R * x.T[b] * f;
+          L.bkr[b * Nb + i] = x.T[b] * f;
+          L.bks[b * Nb + i] = R * x.T[b];
+          L.bki[b * Nb + i] = x.sp[b];
+        }
+      L.Bv[i] = B;
+      if (want_nll) L.lam[i] = x.n;  // the observed count, replaced by lambda in (d)
+    }
+    for (int e = tid; e < E; e += NT) {
+      const double X = blob[BL.edges + e];
+      const double z = X - c0;
+      const double disc = bb * bb + 4.0 * c2 * z;
+      double y;
+      if (disc < 0.0) y = c2 < 0.0 ? INFINITY : -INFINITY;
+      else y = 2.0 * z / (bb + sqrt(disc));
+      int k;
+      double t = 0.0;
+      if (!(y >= y0)) {
+        k = -1;
+      } else if (y >= yK) {
+        k = K;
+      } else {
+        k = (int)floor((y - y0) * iwf);
+        k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
+        t = (y - (y0 + k * wf)) * iwf;
+      }
+      L.ek[e] = k;
+      L.eT[e] = t;
+      L.eY[e] = y;
+    }
+    __syncthreads();
 
-    auto mval = [&](int k) { return L.Hs[k] * L.F1[k] * iwf; };
     auto dens = [&](int k) {  // d_k, 0 <= k <= K
-      if (k == 0) return mval(0);
-      if (k == K) return mval(K - 1);
-      const double a = mval(k - 1), b = mval(k);
+      if (k == 0) return L.mk[0];
+      if (k == K) return L.mk[K - 1];
+      const double a = L.mk[k - 1], b = L.mk[k];
       return (a * b > 0.0) ? 2.0 * a * b / (a + b) : 0.0;
     };
     auto clampK = [&](int k) { return k < 0 ? 0 : (k > K ? K : k); };
+
+    // ---- (c) per mapped edge: the spline integral from its fine bin's lower
+    // edge, P_k(t), and the density there over f'(y); edge-index table
+    for (int e = tid; e < E; e += NT) {
+      const int k = L.ek[e];
+      double piece = 0.0, rr = 0.0;
+      if (k >= 0 && k < K) {
+        const double t = L.eT[e], y = L.eY[e];
+        const double dl = dens(k), dh = dens(k + 1), mk = L.mk[k];
+        const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
+        piece = wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + c * q);
+        const double rho = dl * (1.0 - t) + dh * t + c * t * (1.0 - t);
+        rr = rho / (bb + 2.0 * c2 * y);
+      }
+      L.eP[e] = piece;
+      L.eR[e] = rr;
+      // first[q] = e for kk_{e-1} < q <= kk_e (edge 0 from q = 0); the top
+      // edge's thread also writes the entries past it
+      const int kk = clampK(k);
+      const int kp = e > 0 ? clampK(L.ek[e - 1]) : -1;
+      for (int q = kp + 1; q <= kk; ++q) L.first[q] = e;
+      if (e == E - 1)
+        for (int q = kk + 1; q <= K + 1; ++q) L.first[q] = E;
+    }
+    __syncthreads();
+
+    // the adjoint's inputs of this thread's fine bin, in flight during (d)
+    FineRows rows;
+    if (tid < K && want_grad) load_rows(io, ds, tid, rows);
 
     // acc: 0 NLL, 1..3 energy scale c0..c2, 4..7 oscillation slots,
     // 8..15 background rates, 16..31 the first sixteen source norms
@@ -416,32 +466,19 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
 #pragma unroll
     for (int j = 0; j < 32; ++j) acc[j] = 0.0;
 
-    // ---- analysis bins: signal, expectation, deviance, lambda_mu, background
-    // and energy-scale gradients; edge-index table
+    // ---- (d) analysis bins: signal, expectation, deviance, lambda_mu,
+    // background and energy-scale gradients
     for (int i = tid; i < Nb; i += NT) {
-      const int ka = L.ek[i], kb = L.ek[i + 1];
-      const double ta = L.eT[i], tb = L.eT[i + 1];
-      const int k0 = clampK(ka), k1 = clampK(kb);
+      const int k0 = clampK(L.ek[i]), k1 = clampK(L.ek[i + 1]);
       double s = 0.0;
-      for (int k = k0; k < k1; ++k) s += L.Hs[k] * L.F1[k];
-      double rho_a = 0.0, rho_b = 0.0;
-      if (kb >= 0 && kb < K) {
-        const double dl = dens(kb), dh = dens(kb + 1), mk = mval(kb);
-        const double q = 0.5 * tb * tb - tb * tb * tb * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
-        s += wf * (dl * (tb - 0.5 * tb * tb) + dh * 0.5 * tb * tb + c * q);
-        rho_b = dl * (1.0 - tb) + dh * tb + c * tb * (1.0 - tb);
-      }
-      if (ka >= 0 && ka < K) {
-        const double dl = dens(ka), dh = dens(ka + 1), mk = mval(ka);
-        const double q = 0.5 * ta * ta - ta * ta * ta * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
-        s -= wf * (dl * (ta - 0.5 * ta * ta) + dh * 0.5 * ta * ta + c * q);
-        rho_a = dl * (1.0 - ta) + dh * ta + c * ta * (1.0 - ta);
-      }
+      for (int k = k0; k < k1; ++k) s += L.Hk[k];
+      s += L.eP[i + 1];
+      s -= L.eP[i];
       const double mu = s + L.Bv[i];
       if (io.mu_out) io.mu_out[ds.bins0 + i] = mu;
       double lam = 0.0;
       if (want_nll) {
-        const double n = L.nD[i];
+        const double n = L.lam[i];
         if (!(mu > 0.0)) atomicOr(&L.flag[0], ST_DOMAIN);
         acc[0] += (n > 0.0) ? (mu - n + n * log(n / mu)) : mu;
         lam = 1.0 - n / mu;
@@ -455,24 +492,18 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
             }
           // ds_i/dc_j = -rho_b (1, y_b, y_b^2)_j / f'(y_b) + rho_a (1, y_a, y_a^2)_j / f'(y_a)
           const double ya = L.eY[i], yb = L.eY[i + 1];
-          const double la = (ka >= 0 && ka < K) ? lam * rho_a / (bb + 2.0 * c2 * ya) : 0.0;
-          const double lb = (kb >= 0 && kb < K) ? lam * rho_b / (bb + 2.0 * c2 * yb) : 0.0;
+          const double la = lam * L.eR[i], lb = lam * L.eR[i + 1];
           acc[1] += la - lb;
           acc[2] += la * ya - lb * yb;
           acc[3] += la * ya * ya - lb * yb * yb;
         }
       }
       L.lam[i] = lam;
-      // edge-index table: first[q] = i for kk_{i-1} < q <= kk_i (edge 0 from
-      // q = 0); the last bin's thread also writes the entries of the top edge
-      const int kp = i > 0 ? clampK(L.ek[i - 1]) : -1;
-      for (int q = kp + 1; q <= k0; ++q) L.first[q] = i;
-      if (i == Nb - 1) {
-        for (int q = k0 + 1; q <= k1; ++q) L.first[q] = i + 1;
-        for (int q = k1 + 1; q <= K + 1; ++q) L.first[q] = E;
-      }
     }
     if (d == 0) acc[0] += prior_e;
+    // the flux-mode and norm-list copies of (a) have landed once every wave
+    // has waited for its own and passed the next barrier
+    __builtin_amdgcn_s_waitcnt(0);
     if (!want_grad) {
       block_sum<NT, 1>(acc, L.red);
       nll_total += acc[0];
@@ -481,10 +512,13 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     }
     __syncthreads();
 
-    // ---- fine bins: lambda_H from the covering analysis bin and the edges in
-    // fine bins k-1, k, k+1; rescale adjoint (lambda_F, oscillation slots, sources)
+    // ---- (e) fine bins: lambda_H from the covering analysis bin and the edges
+    // in fine bins k-1, k, k+1; rescale adjoint (lambda_F, oscillation slots, sources)
     const int nsrc = S < ACC_SRC ? S : ACC_SRC;
     for (int k = tid; k < K; k += NT) {
+      FineRows x;
+      if (k == tid) x = rows;
+      else load_rows(io, ds, k, x);
       auto fe = [&](int q) { const int v = L.first[q]; return v < 0 ? 0 : (v > E ? E : v); };
       const int ic = fe(k + 1) - 1;  // analysis bin whose mapped range holds fine bin k whole
       double lH = (ic >= 0 && ic < Nb) ? L.lam[ic] : 0.0;
@@ -507,12 +541,12 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
           ldk1 += lx * elo;
         }
       }
-      const double mk = mval(k);
+      const double mk = L.mk[k];
       double lm = lmd;
       if (k == 0) {
         lm += ldk;  // d_0 = m_0
       } else {
-        const double a = mval(k - 1);
+        const double a = L.mk[k - 1];
         if (a * mk > 0.0) {
           const double den = a + mk;
           lm += ldk * 2.0 * a * a / (den * den);
@@ -521,7 +555,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       if (k == K - 1) {
         lm += ldk1;  // d_K = m_{K-1}
       } else {
-        const double b = mval(k + 1);
+        const double b = L.mk[k + 1];
         if (mk * b > 0.0) {
           const double den = mk + b;
           lm += ldk1 * 2.0 * b * b / (den * den);
@@ -532,7 +566,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       L.LF[k] = lH * L.Hs[k];
       L.LHs[k] = lhs;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[4 + j] += lhs * L.Gs[j * K + k];
+      for (int j = 0; j < 4; ++j) acc[4 + j] += lhs * x.g[j];
 #pragma unroll
       for (int q = 0; q < ACC_SRC; ++q)
         if (q < nsrc) acc[16 + q] += lhs * L.Ss[q * K + k];
@@ -544,38 +578,37 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
 #pragma unroll
     for (int q = 0; q < ACC_SRC; ++q)
       if (q == tid) gA = acc[16 + q];
-    // sources past the first sixteen, in further reductions of 32
-    for (int s0 = nsrc; s0 < S; s0 += 32) {
-      const int ns = S - s0 < 32 ? S - s0 : 32;
-      double a2[32];
+    // sources past the first sixteen, in further reductions of 16
+#pragma unroll 1
+    for (int s0 = nsrc; s0 < S; s0 += 16) {
+      const int ns = S - s0 < 16 ? S - s0 : 16;
+      double a2[16];
 #pragma unroll
-      for (int j = 0; j < 32; ++j) a2[j] = 0.0;
+      for (int j = 0; j < 16; ++j) a2[j] = 0.0;
       for (int k = tid; k < K; k += NT) {
         const double lhs = L.LHs[k];
 #pragma unroll
-        for (int q = 0; q < 32; ++q)
+        for (int q = 0; q < 16; ++q)
           if (q < ns) a2[q] += lhs * L.Ss[(s0 + q) * K + k];
       }
-      block_sum<NT, 32>(a2, L.red);
+      block_sum<NT, 16>(a2, L.red);
 #pragma unroll
-      for (int q = 0; q < 32; ++q)
+      for (int q = 0; q < 16; ++q)
         if (q == tid - s0) gA = a2[q];
     }
 
-    // ---- gradient of the reduced sums; source norms by the product rule over
-    // each source's norm list; flux modes by a gather of lambda_F over each
-    // mode's fine bins (CSC)
-    // every gradient entry of this pass may also receive a prior row, a norm
-    // list or a flux mode from another thread: all adds are atomic
+    // ---- (f) gradient of the reduced sums; source norms by the product rule
+    // over each source's norm list; flux modes by a gather of lambda_F over
+    // each mode's fine bins (CSC); priors. Every gradient entry of this pass
+    // may receive several contributions: all adds are atomic.
     if (tid == NT - 1) {  // a thread with no source to apply (S <= MAX_SOURCES < NT)
       for (int j = 0; j < 3; ++j)
         if (ds.cidx[j] >= 0) atomicAdd(&L.grad[ds.cidx[j]], acc[1 + j]);
       for (int j = 0; j < NSLOT; ++j)
         if (p.osc.slot_param[j] >= 0) atomicAdd(&L.grad[p.osc.slot_param[j]], acc[4 + j]);
-      const int* brt = reinterpret_cast<const int*>(p.dpool + ds.blob + BL.brt);
 #pragma unroll
       for (int b = 0; b < MAX_BKG; ++b)
-        if (b < NB && brt[b] >= 0) atomicAdd(&L.grad[brt[b]], acc[8 + b]);
+        if (b < NB && brt_b[b] >= 0) atomicAdd(&L.grad[brt_b[b]], acc[8 + b]);
     }
     if (tid < S) {
       const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
@@ -636,25 +669,22 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   return bad ? INFINITY : nll_total;
 }
 
-// Launch prologue shared by the single and batched bin stages: issue dataset
-// 0's copies, clear the gradient and flag, run dataset 0's parameter pass and
-// the prior rows from global memory while the copies are in flight. Returns
-// this thread's part of the prior NLL. The parameters and dataset plans are
-// the caller's to copy.
+// Launch prologue shared by the single and batched bin stages, after the
+// parameters and dataset plans have reached LDS (waited for and
+// synchronised): clears the gradient and flag and evaluates the prior rows
+// into LDS. Returns this thread's part of the prior NLL. The caller
+// synchronises before the serial stages read the rows.
 template <int NT>
-__device__ __forceinline__ double prologue(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const double* thg,
-                                           int want_nll) {
+__device__ __forceinline__ double prologue(const DevPlan& p, Lds<NT>& L, int want_nll) {
   const int tid = threadIdx.x;
-  stage_dataset<NT>(p, io, L, p.ds0, want_nll);
   for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
   if (tid == 0) L.flag[0] = 0;
-  param_pass<NT>(p, p.ds0, thg, L);
   double e_sum = 0.0;
   if (want_nll)
     for (int r = tid; r < p.NR; r += NT) {
       int idx;
       double v, e;
-      prior_row(p, thg, r, idx, v, e);
+      prior_row(p, L.th, r, idx, v, e);
       L.prv[r] = v;
       L.pri[r] = idx;
       e_sum += e;
@@ -675,12 +705,15 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
                   const_cast<double*>(a.bin), 1, a.keep_rows};
   // the fold kernel has applied the oscillation coefficients; the domain of
   // the oscillation parameters is checked from LDS in the serial stages.
-  // Parameters, dataset plans and dataset 0's inputs go to LDS in one round
-  // of direct copies (dataset 0's plan comes with the kernel arguments).
+  // Parameters and dataset plans go to LDS by direct copies (dataset 0's plan
+  // comes with the kernel arguments).
   copy_to_lds<NT>(L.th, a.theta, p.P);
   copy_to_lds<NT>(reinterpret_cast<double*>(L.dsl), reinterpret_cast<const double*>(p.ds), p.D * DSPLAN_DOUBLES);
-  const double pe = prologue<NT>(p, io, L, a.theta, a.want_nll);
-  const double f = serial_stages<NT>(p, io, L, a.theta, pe, a.want_nll, a.want_grad);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const double pe = prologue<NT>(p, L, a.want_nll);
+  __syncthreads();
+  const double f = serial_stages<NT>(p, io, L, pe, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
 }
 
@@ -783,8 +816,9 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const double pe = prologue<NT>(p, io, L, th, a.want_nll);
-  const double fval = serial_stages<NT>(p, io, L, th, pe, a.want_nll, a.want_nll ? a.want_grad : 0);
+  const double pe = prologue<NT>(p, L, a.want_nll);
+  __syncthreads();
+  const double fval = serial_stages<NT>(p, io, L, pe, a.want_nll, a.want_nll ? a.want_grad : 0);
   if (a.has_fit) {
     if (a.osc_last && tid < NSLOT) {
       const int q = p.osc.slot_param[tid];
