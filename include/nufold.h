@@ -159,9 +159,10 @@ int nf_eval_device(nf_ctx* ctx, const double* theta_dev, double* out_dev,
  * every call on one GPU uses the same array: calls that can overlap on one
  * GPU (other streams or contexts, without ordering between them) race and
  * give wrong results. Needs 8 (6 KT + G) + 4 (G + KT) + 8 NM nitems +
- * 8 13 G bytes (each part rounded up to 256; KT fine bins, G segments,
- * nitems work items, NM fold moments); a context that needs more gets
- * NF_EINVAL and an error message with its need.
+ * 8 13 G + 8 R bytes (each part rounded up to 256; KT fine bins, G segments,
+ * nitems work items, NM fold moments, R the parameter-pass values: about
+ * KT + 5 analysis bins + 2 background terms + prior rows); a context that
+ * needs more gets NF_EINVAL and an error message with its need.
  */
 #define NF_NOALLOC_SCRATCH_BYTES (16u << 20)
 int nf_eval_device_noalloc(nf_ctx* ctx, const double* theta_dev, double* out_dev,

@@ -190,6 +190,7 @@ struct nf_ctx {
   DevBuf<int> d_seg_cnt, d_kt_cnt, d_seg_kt, d_kt_need;  // fused fine-bin reduction in the fold
   DevBuf<ItemEpi> d_epi;                                   // per work item epilogue records
   DevBuf<double> d_segm;
+  DevBuf<double> d_pre;  // parameter-pass buffer of the single evaluation
   double* h_stage = nullptr;  // pinned: theta, out, mu
   int32_t* h_status = nullptr;
   int nitems = 0;
@@ -253,6 +254,7 @@ struct nf_ctx {
     d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release();
     d_seg_cnt.release(); d_kt_cnt.release(); d_seg_kt.release(); d_kt_need.release(); d_segm.release();
     d_epi.release();
+    d_pre.release();
     if (h_stage) (void)hipHostFree(h_stage);
     if (h_status) (void)hipHostFree(h_status);
     if (h_hdr) (void)hipHostFree(h_hdr);
@@ -528,6 +530,27 @@ void parse_model(nf_ctx* c, const char* text) {
     }
     pl.KT = kt;
     pl.FS = fs;
+    // parameter-pass buffer of the single evaluation
+    {
+      int bk = 0;
+      for (size_t di = 0; di < c->dsplan.size(); ++di) {
+        c->dsplan[di].e0 = c->dsplan[di].bins0 + (int)di;
+        c->dsplan[di].bk0 = bk;
+        bk += c->dsplan[di].nbkg * c->dsplan[di].Nb;
+      }
+      const int ET = bins0 + pl.D;
+      int o = 0;
+      pl.pre_F1 = o; o += std::max(1, kt);
+      pl.pre_ek = o; o += ET;
+      pl.pre_et = o; o += ET;
+      pl.pre_ey = o; o += ET;
+      pl.pre_eq = o; o += ET;
+      pl.pre_B = o; o += std::max(1, bins0);
+      pl.pre_bkr = o; o += std::max(1, bk);
+      pl.pre_bks = o; o += std::max(1, bk);
+      pl.pre_prv = o;  // NR is known after the priors below
+      pl.pre_total = o;
+    }
     c->fit_m = std::min(std::max(c->P, 8), 24);  // L-BFGS history; reduced below if LDS is short
     pl.fit_m = c->fit_m;
     // static blobs (one per dataset) for the serial bin stages
@@ -681,6 +704,8 @@ void parse_model(nf_ctx* c, const char* text) {
     pl.prow_blk = (int)ip.size();
     for (int b = 0; b < pl.nblk; ++b)
       for (int r = bptr[b]; r < bptr[b + 1]; ++r) ip.push_back(b);
+    pl.pre_misc = pl.pre_prv + std::max(1, pl.NR);
+    pl.pre_total = pl.pre_misc + 2 + pl.D;
   } catch (const JsonError& e) {
     fail(NF_EPARSE, e.what());
   }
@@ -705,6 +730,7 @@ void upload_plan(nf_ctx* c) {
   c->d_mu.alloc(std::max(1, c->nbins_total));
   c->d_Sseg.alloc((size_t)std::max(1, c->plan.G));
   c->d_bin.alloc((size_t)6 * std::max(1, c->plan.KT));
+  c->d_pre.alloc((size_t)c->plan.pre_total);
   {
     // fine bin of every segment (static), arrival counters and segment moments
     const int G = std::max(1, c->plan.G), KT = std::max(1, c->plan.KT);
@@ -979,12 +1005,14 @@ struct EvalScratch {
   double* bin;
   int* seg_cnt;
   int* kt_cnt;
+  double* pre;
 };
 
 void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* status_dev, double* mu_dev,
                   int want_nll, int want_grad, bool fit = false, bool timed = true, bool reuse_fold = false,
                   bool keep_rows = false, const EvalScratch* scr = nullptr) {
-  const EvalScratch own{c->d_part.p, c->d_segm.p, c->d_Sseg.p, c->d_bin.p, c->d_seg_cnt.p, c->d_kt_cnt.p};
+  const EvalScratch own{c->d_part.p, c->d_segm.p, c->d_Sseg.p, c->d_bin.p, c->d_seg_cnt.p, c->d_kt_cnt.p,
+                        c->d_pre.p};
   const EvalScratch& sc = scr ? *scr : own;
   FoldArgs fa{};
   fa.u = c->mode == NF_M64 ? (const void*)c->d_u64.p : (const void*)c->d_u32.p;
@@ -995,6 +1023,9 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.theta = theta_dev;
   fa.osc = c->osc;
   fa.part = sc.part;
+  fa.plan = c->plan;
+  fa.pre = sc.pre;
+  fa.npre = c->plan.D + 1;
   FoldFuse& fu = fa.fuse;
   fu.epi = c->d_epi.p;
   fu.seg_item = c->d_seg_item.p;
@@ -1018,6 +1049,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   ta.mu_out = mu_dev;
   ta.Sseg = sc.Sseg;
   ta.bin = sc.bin;
+  ta.pre = sc.pre;
   ta.want_grad = want_grad;
   ta.want_nll = want_nll;
   ta.keep_rows = keep_rows ? 1 : 0;
@@ -1039,11 +1071,12 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
     ev = c->tev[c->tcount++].data();
   }
   if (reuse_fold) {
-    // the rows of the last fold are still in place: no fold launch
-    if (ev) {
-      hip_check(hipEventRecord(ev[0], c->stream), "hipEventRecord");
-      hip_check(hipEventRecord(ev[1], c->stream), "hipEventRecord");
-    }
+    // the rows of the last fold are still in place: the launch runs only its
+    // parameter-pass workgroups
+    FoldArgs pa = fa;
+    pa.nitems = 0;
+    hip_check(launch_fold(c->mode, pa, c->fold_block, c->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr),
+              "parameter pass launch");
   } else {
     hip_check(launch_fold(c->mode, fa, c->fold_block, c->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr),
               "fold launch");
@@ -2035,14 +2068,16 @@ int nf_eval_device_noalloc(nf_ctx* ctx, const double* theta_dev, double* out_dev
     const size_t zero_end = o_kt_cnt + up(sizeof(int) * KT);
     const size_t o_part = zero_end;
     const size_t o_segm = o_part + up(sizeof(double) * NM * NI);
-    const size_t total = o_segm + up(sizeof(double) * (MAX_MOM + 1) * G);
+    const size_t o_pre = o_segm + up(sizeof(double) * (MAX_MOM + 1) * G);
+    const size_t total = o_pre + up(sizeof(double) * (size_t)c->plan.pre_total);
     if (total > (size_t)NF_NOALLOC_SCRATCH_BYTES)
       fail(NF_EINVAL, "this context needs " + std::to_string(total) + " bytes of evaluation scratch, more than "
                       "the " + std::to_string((size_t)NF_NOALLOC_SCRATCH_BYTES) + " of the static array; use nf_eval_device");
     unsigned char* base = static_cast<unsigned char*>(c->scratch_dev);
     const EvalScratch sc{reinterpret_cast<double*>(base + o_part), reinterpret_cast<double*>(base + o_segm),
                          reinterpret_cast<double*>(base + o_Sseg), reinterpret_cast<double*>(base + o_bin),
-                         reinterpret_cast<int*>(base + o_seg_cnt), reinterpret_cast<int*>(base + o_kt_cnt)};
+                         reinterpret_cast<int*>(base + o_seg_cnt), reinterpret_cast<int*>(base + o_kt_cnt),
+                         reinterpret_cast<double*>(base + o_pre)};
     hip_check(launch_zero(reinterpret_cast<double*>(base), (int64_t)(zero_end / sizeof(double)), c->stream),
               "zero launch");
     enqueue_eval(c, theta_dev, out_dev, status_dev, nullptr, 1, want_grad ? 1 : 0, false, false, false, false, &sc);

@@ -38,6 +38,7 @@
 #include "fastmath.hpp"
 #include "kernels.hpp"
 #include "osc.hpp"
+#include "stages.hpp"
 
 namespace nufold {
 
@@ -316,13 +317,83 @@ __device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf,
   }
 }
 
+// Parameter pass of the single evaluation, in the first npre workgroups of
+// the fold launch (they run alongside the event stream): workgroup b < D
+// forms dataset b's flux factors, mapped edges and background terms;
+// workgroup D evaluates the prior rows, sums their NLL in a fixed order and
+// checks the parameters' domain. The parameters are read from global memory
+// (a few hundred values, cached). red: this workgroup's LDS rows (at least
+// 2 x (blockDim / 64) doubles).
+__device__ void parameter_pass(const FoldArgs& a, int b, double* red) {
+  const DevPlan& p = a.plan;
+  const double* th = a.theta;
+  double* pre = a.pre;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (b < p.D) {
+    const DsPlan& ds = b == 0 ? p.ds0 : p.ds[b];
+    const int K = ds.K, Nb = ds.Nb, E = Nb + 1, NB = ds.nbkg;
+    const double wf = ds.wf, iwf = 1.0 / wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
+    const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, ds.M, ds.S, ds.nl, K, ds.fw);
+    const double* blob = p.dpool + ds.blob;
+    const double c0 = pval(th, ds.cidx[0], 0.0);
+    const double c2 = pval(th, ds.cidx[2], 0.0);
+    const double bb = 1.0 + pval(th, ds.cidx[1], 0.0);
+    if (tid == 0) pre[p.pre_misc + 2 + b] = map_ok(bb, c2, y0, yK) ? 0.0 : 1.0;
+    for (int k = tid; k < K; k += nt) pre[p.pre_F1 + ds.kt0 + k] = flux_factor(th, blob, BL, ds.fw, k);
+    for (int e = tid; e < E; e += nt) {
+      const MappedEdge m = map_edge(blob[BL.edges + e], c0, bb, c2, y0, yK, wf, iwf, K);
+      pre[p.pre_ek + ds.e0 + e] = (double)m.k;
+      pre[p.pre_et + ds.e0 + e] = m.t;
+      pre[p.pre_ey + ds.e0 + e] = m.y;
+      pre[p.pre_eq + ds.e0 + e] = m.ifp;
+    }
+    for (int i = tid; i < Nb; i += nt)
+      pre[p.pre_B + ds.bins0 + i] =
+          background(th, blob, BL, NB, Nb, i, pre + p.pre_bkr + ds.bk0 + i, pre + p.pre_bks + ds.bk0 + i);
+    return;
+  }
+  double e_sum = 0.0, bad = 0.0;
+  for (int r = tid; r < p.NR; r += nt) {
+    int idx;
+    double v, e;
+    prior_row(p, th, r, idx, v, e);
+    pre[p.pre_prv + r] = v;
+    e_sum += e;
+  }
+  for (int i = tid; i < p.P; i += nt)
+    if (!isfinite(th[i])) bad = 1.0;
+  if (tid == 0 && !osc_domain_ok(p.osc, th)) bad = 1.0;
+  e_sum = wave_sum_fixed(e_sum);
+  bad = wave_sum_fixed(bad);
+  const int nw = nt >> 6, w = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[w] = e_sum;
+    red[nw + w] = bad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0, f = 0.0;
+    for (int j = 0; j < nw; ++j) {
+      s += red[j];
+      f += red[nw + j];
+    }
+    pre[p.pre_misc] = s;
+    pre[p.pre_misc + 1] = f > 0.0 ? 1.0 : 0.0;
+  }
+}
+
 template <int FORM>
 __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   constexpr int NM = form_moments<FORM>();
   __shared__ double cfw[4][CF_SIZE];  // coefficient rows per wavefront (blocks of at most 256 threads)
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
+  if ((int)blockIdx.x < a.npre) {
+    parameter_pass(a, blockIdx.x, &cfw[0][0]);
+    return;
+  }
   const int lane = threadIdx.x & 63;
-  const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(
+      (int)(((blockIdx.x - (unsigned)a.npre) * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;  // whole wavefronts leave together
   double* cf = cfw[threadIdx.x >> 6];
   ItemEpi ep{};
@@ -388,8 +459,13 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   constexpr int NPH = form_phases<FORM>();
   __shared__ double cfw[4][CF_SIZE];  // coefficient rows per wavefront (blocks of at most 256 threads)
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
+  if ((int)blockIdx.x < a.npre) {
+    parameter_pass(a, blockIdx.x, &cfw[0][0]);
+    return;
+  }
   const int lane = threadIdx.x & 63;
-  const int item = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6));
+  const int item = __builtin_amdgcn_readfirstlane(
+      (int)(((blockIdx.x - (unsigned)a.npre) * (unsigned)blockDim.x + threadIdx.x) >> 6));
   if (item >= a.nitems) return;
   double* cf = cfw[threadIdx.x >> 6];
   ItemEpi ep{};
@@ -627,9 +703,9 @@ hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t strea
 // kernel's own start and end times.
 hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t stream, hipEvent_t start,
                        hipEvent_t stop) {
-  if (a.nitems <= 0) return hipSuccess;
+  if (a.nitems <= 0 && a.npre <= 0) return hipSuccess;
   const int waves_per_block = block / 64;
-  const dim3 grid((a.nitems + waves_per_block - 1) / waves_per_block);
+  const dim3 grid(a.npre + (a.nitems + waves_per_block - 1) / waves_per_block);
   auto go = [&](auto kernel) {
     if (start || stop) hipExtLaunchKernelGGL(kernel, grid, dim3(block), 0, stream, start, stop, 0, a);
     else hipLaunchKernelGGL(kernel, grid, dim3(block), 0, stream, a);

@@ -75,6 +75,12 @@ struct FoldArgs {
   double* part;         // [num_moments][nitems]
   const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
   FoldFuse fuse;        // used when fuse.seg_cnt != nullptr
+  // parameter pass of the single evaluation, run by the launch's first npre
+  // workgroups (one per dataset, then one for the prior rows) alongside the
+  // event stream, into pre (see DevPlan.pre_*); npre = 0: none
+  DevPlan plan;
+  double* pre;
+  int npre;
 };
 
 // Batched fold: a tile of FT fits per wavefront (FT = 1, 2, 4 or 8, a launch
@@ -105,6 +111,7 @@ struct EvalIO {
   double* bin;          // 6 KT
   int fused;            // bin rows 0..4 and Sseg come from the fold kernel; row 5 (1 + F) is formed here
   int keep_rows;        // fused: leave rows 0..4 in place for a later evaluation that reuses the fold
+  const double* pre;    // nullable: the parameter pass done by the fold launch (DevPlan.pre_*)
 };
 
 // Single evaluation: one workgroup, after the fold kernel has written Sseg and
@@ -125,6 +132,7 @@ struct TailArgs {
                         // with the same fold parameters reuses them without a fold)
   FitArgs fit;
   const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
+  const double* pre;    // the parameter pass written by the fold launch (DevPlan.pre_*)
 };
 
 struct BatchTailArgs {
@@ -159,7 +167,7 @@ __host__ __device__ constexpr int red_doubles(int nt) { return 32 * 4 * (nt / 64
 __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
   const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb, BN = (size_t)p.max_B * p.max_Nb;
   const size_t nd = 3 + 2 * (size_t)p.P + CF_SIZE + (size_t)p.D * DSPLAN_DOUBLES + red_doubles(nt) + 6 * K +
-                    (size_t)p.max_S * K + 2 * Nb + 2 * BN + 4 * E + p.NR + p.max_blob;
+                    (size_t)p.max_S * K + 2 * Nb + 2 * BN + 5 * E + p.NR + p.max_blob;
   const size_t ni = E + K + 2 + p.NR + BN + 2;
   return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }

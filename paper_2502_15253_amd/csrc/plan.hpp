@@ -93,6 +93,8 @@ struct DsPlan {
   int bkg0;         // index of the first BkgPlan
   int blob, blob_n; // dpool offset and length of the static blob (layout: blob_layout)
   int fw;           // flux basis entries per fine bin in the blob's fixed-width rows (>= 1)
+  int e0;           // first mapped edge of this dataset in the parameter-pass buffer (bins0 + dataset)
+  int bk0;          // first background factor of this dataset in the parameter-pass buffer
   int pad_;
 };
 
@@ -166,6 +168,19 @@ struct DevPlan {
   int blk_idx;                  // ipool base
   int blk_mean;                 // dpool base (aligned with blk_idx)
   int blk_inv;                  // ipool: nblk offsets into dpool of row-major V^-1
+  // parameter-pass buffer of the single evaluation (doubles; written by extra
+  // workgroups of the fold launch, read by the bin stages): offsets of
+  int pre_F1;    // KT: 1 + F per global fine bin
+  int pre_ek;    // ET = nbins_total + D: fine bin of each mapped edge (as a double)
+  int pre_et;    // ET: t of each mapped edge
+  int pre_ey;    // ET: y of each mapped edge
+  int pre_eq;    // ET: 1 / f'(y) at each mapped edge
+  int pre_B;     // nbins_total: background expectation per analysis bin
+  int pre_bkr;   // BKT = sum over datasets of backgrounds x bins: dmu/dR
+  int pre_bks;   // BKT: dmu/dbeta
+  int pre_prv;   // NR: gradient contribution of each prior row
+  int pre_misc;  // 2 + D: prior NLL, parameter-domain flag, energy-map domain flag per dataset
+  int pre_total; // doubles of the buffer
 };
 
 }  // namespace nufold

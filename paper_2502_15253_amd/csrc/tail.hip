@@ -53,6 +53,7 @@
 
 #include "kernels.hpp"
 #include "osc.hpp"
+#include "stages.hpp"
 
 namespace nufold {
 
@@ -78,6 +79,7 @@ struct Lds {
   double* eY;     // E     y of each mapped edge
   double* eP;     // E     spline integral from its fine bin's lower edge to the mapped edge (0 outside)
   double* eR;     // E     spline density at the mapped edge over f'(y) (0 outside)
+  double* eQ;     // E     1 / f'(y) at the mapped edge
   double* prv;    // NR    gradient contribution of each prior row
   double* st;     // copy target: the flux-mode and norm-list part of the static blob
   double* fit;    // minimiser scratch
@@ -117,6 +119,7 @@ __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   L.eY = q; q += E;
   L.eP = q; q += E;
   L.eR = q; q += E;
+  L.eQ = q; q += E;
   L.prv = q; q += p.NR;
   q = al(q);
   L.st = q; q += p.max_blob;
@@ -177,37 +180,10 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
   for (int j = 0; j < N; ++j) v[j] = red[32 * R + j];
 }
 
-__device__ __forceinline__ double pval(const double* th, int idx, double dflt) {
-  return idx >= 0 ? th[idx] : dflt;
-}
 
 }  // namespace nufold
 #include "minimize.hpp"
 namespace nufold {
-
-// ---------------------------------------------------------------- priors
-// Prior row r (Eq. 6; third line of Eq. 9): v = its gradient contribution to
-// the row's parameter, e = its NLL contribution. Rows < ngauss are
-// independent Gaussians; the rest are rows of correlated blocks (V^-1 r).
-__device__ __forceinline__ void prior_row(const DevPlan& p, const double* th, int r, int& idx, double& v,
-                                          double& e) {
-  if (r < p.ngauss) {
-    idx = p.ipool[p.gidx + r];
-    const double z = th[idx] - p.dpool[p.gmean + r];
-    v = z * p.dpool[p.ginv + r];
-    e = 0.5 * z * v;
-  } else {
-    const int bl = p.ipool[p.prow_blk + r - p.ngauss];
-    const int b = p.ipool[p.blk_ptr + bl], n = p.ipool[p.blk_ptr + bl + 1] - b;
-    const int row = r - p.ngauss - b;
-    const double* Vi = p.dpool + p.ipool[p.blk_inv + bl] + (int64_t)row * n;
-    v = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < n; ++c) v += Vi[c] * (th[p.ipool[p.blk_idx + b + c]] - p.dpool[p.blk_mean + b + c]);
-    idx = p.ipool[p.blk_idx + b + row];
-    e = 0.5 * (th[idx] - p.dpool[p.blk_mean + b + row]) * v;
-  }
-}
 
 // Asynchronous copies from global memory straight into LDS (global_load_lds:
 // no registers, every load in flight at once). dma_lds<NT, B> moves nbytes (a
@@ -254,58 +230,19 @@ __device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int 
 }
 
 // ---------------------------------------------------------------- inputs
-// What one thread reads for one fine bin, one analysis bin and one mapped
-// edge of a dataset, straight into registers: every load is independent of
-// the others (fixed offsets from the dataset plan), so a thread issues all of
-// them at once when the dataset starts. The fold's rows were written by the
-// fold kernel (single evaluation: plain loads) or by this workgroup's phase A
-// (batched: coherent agent-scope loads).
-struct FineIn {   // parameter pass: the oscillated spectrum and the flux row
-  double hs, fc[FLUX_FW_MAX];
-  int fp[FLUX_FW_MAX];
-};
+// The fold's rows were written by the fold kernel (single evaluation: plain
+// loads) or by this workgroup's phase A (batched: coherent agent-scope loads).
 struct FineRows { // adjoint: the oscillation-slot derivative rows
   double g[4];
 };
-struct BinIn {
-  double n, T[MAX_BKG];
-  int sp[MAX_BKG];
-};
 
 __device__ __forceinline__ double ld(const double* p, int coherent) { return coherent ? load_agent(p) : *p; }
-
-__device__ __forceinline__ void load_fine(const DevPlan& p, const EvalIO& io, const DsPlan& ds,
-                                          const BlobLayout& BL, int k, FineIn& r) {
-  const int fw = ds.fw, co = io.fused ? 0 : 1;
-  const double* b = io.bin + 6 * (int64_t)ds.kt0;
-  const double* blob = p.dpool + ds.blob;
-  const int* fpar = reinterpret_cast<const int*>(blob + BL.fpar);
-  r.hs = ld(b + k, co);
-#pragma unroll
-  for (int j = 0; j < FLUX_FW_MAX; ++j) {
-    r.fc[j] = j < fw ? blob[BL.fcf + k * fw + j] : 0.0;
-    r.fp[j] = j < fw ? fpar[k * fw + j] : -1;
-  }
-}
 
 __device__ __forceinline__ void load_rows(const EvalIO& io, const DsPlan& ds, int k, FineRows& r) {
   const int K = ds.K, co = io.fused ? 0 : 1;
   const double* b = io.bin + 6 * (int64_t)ds.kt0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) r.g[j] = ld(b + (j + 1) * K + k, co);
-}
-
-__device__ __forceinline__ void load_bin(const DevPlan& p, const EvalIO& io, const DsPlan& ds,
-                                         const BlobLayout& BL, int i, int want_nll, BinIn& r) {
-  const int Nb = ds.Nb, NB = ds.nbkg;
-  const double* blob = p.dpool + ds.blob;
-  const int* shp = reinterpret_cast<const int*>(blob + BL.shp);
-  r.n = want_nll ? io.data[ds.data + i] : 0.0;
-#pragma unroll
-  for (int b = 0; b < MAX_BKG; ++b) {
-    r.T[b] = b < NB ? blob[BL.bsc + b] * blob[BL.tmpl + b * Nb + i] : 0.0;
-    r.sp[b] = b < NB ? shp[b * Nb + i] : -1;
-  }
 }
 
 // Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
@@ -315,11 +252,11 @@ __device__ __forceinline__ void load_bin(const DevPlan& p, const EvalIO& io, con
 // prior_e is this thread's part of the prior NLL.
 //
 // Per dataset: (a) the flux-mode and norm-list tables and the per-source
-// spectra go to LDS by asynchronous direct copies; (b) parameter pass, each
-// thread loading its own fine bin, analysis bin and edge into registers (all
-// loads independent): 1 + F, H and m per fine bin, the background
-// expectation and its factors per analysis bin, the mapped edges; (c) per
-// mapped edge the densities, the
+// spectra go to LDS by asynchronous direct copies; (b) parameter pass: 1 + F,
+// H and m per fine bin, the background expectation and its factors per
+// analysis bin, the mapped edges -- read from the fold launch's parameter
+// pass (io.pre, single evaluation) or computed here (batched), with every
+// load independent of the others; (c) per mapped edge the densities, the
 // spline integral up to the edge and its density, and the edge-index table;
 // (d) per analysis bin the signal, expectation, deviance, lambda and the
 // background and energy-scale sums; (e) per fine bin the adjoint; one block
@@ -357,69 +294,65 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     for (int b = 0; b < MAX_BKG; ++b) brt_b[b] = b < NB ? brt[b] : -1;
 
     // ---- (b) parameter pass
-    const double c0 = pval(L.th, ds.cidx[0], 0.0);
-    const double c1 = pval(L.th, ds.cidx[1], 0.0);
-    const double c2 = pval(L.th, ds.cidx[2], 0.0);
-    const double bb = 1.0 + c1;
-    if (tid == 0 && !(bb > 0.0 && bb + 2.0 * c2 * y0 > 0.0 && bb + 2.0 * c2 * yK > 0.0))
-      atomicOr(&L.flag[0], ST_DOMAIN);
-    if (d == 0) {
-      for (int i = tid; i < p.P; i += NT)
-        if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
-      if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
-    }
-    for (int k = tid; k < K; k += NT) {
-      FineIn x;
-      load_fine(p, io, ds, BL, k, x);
-      double F = 0.0;
-#pragma unroll
-      for (int j = 0; j < FLUX_FW_MAX; ++j)
-        if (x.fp[j] >= 0) F += L.th[x.fp[j]] * x.fc[j];
-      const double f1 = 1.0 + F;
-      const double H = x.hs * f1;
-      L.F1[k] = f1;
-      L.Hs[k] = x.hs;
-      L.Hk[k] = H;
-      L.mk[k] = H * iwf;
-    }
-    for (int i = tid; i < Nb; i += NT) {
-      BinIn x;
-      load_bin(p, io, ds, BL, i, want_nll, x);
-      double B = 0.0;
-#pragma unroll
-      for (int b = 0; b < MAX_BKG; ++b)
-        if (b < NB) {
-          const double R = pval(L.th, brt_b[b], 1.0);
-          const double f = 1.0 + pval(L.th, x.sp[b], 0.0);
-          B += R * x.T[b] * f;
-          L.bkr[b * Nb + i] = x.T[b] * f;
-          L.bks[b * Nb + i] = R * x.T[b];
-          L.bki[b * Nb + i] = x.sp[b];
-        }
-      L.Bv[i] = B;
-      if (want_nll) L.lam[i] = x.n;  // the observed count, replaced by lambda in (d)
-    }
-    for (int e = tid; e < E; e += NT) {
-      const double X = blob[BL.edges + e];
-      const double z = X - c0;
-      const double disc = bb * bb + 4.0 * c2 * z;
-      double y;
-      if (disc < 0.0) y = c2 < 0.0 ? INFINITY : -INFINITY;
-      else y = 2.0 * z / (bb + sqrt(disc));
-      int k;
-      double t = 0.0;
-      if (!(y >= y0)) {
-        k = -1;
-      } else if (y >= yK) {
-        k = K;
-      } else {
-        k = (int)floor((y - y0) * iwf);
-        k = k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
-        t = (y - (y0 + k * wf)) * iwf;
+    const double* hsrow = io.bin + 6 * (int64_t)ds.kt0;
+    const int* shp = reinterpret_cast<const int*>(blob + BL.shp);
+    if (io.pre) {
+      const double* pre = io.pre;
+      if (tid == 0 && (pre[p.pre_misc + 2 + d] != 0.0 || (d == 0 && pre[p.pre_misc + 1] != 0.0)))
+        atomicOr(&L.flag[0], ST_DOMAIN);
+      for (int k = tid; k < K; k += NT) {
+        const double f1 = pre[p.pre_F1 + ds.kt0 + k], hs = hsrow[k];
+        const double H = hs * f1;
+        L.F1[k] = f1;
+        L.Hs[k] = hs;
+        L.Hk[k] = H;
+        L.mk[k] = H * iwf;
       }
-      L.ek[e] = k;
-      L.eT[e] = t;
-      L.eY[e] = y;
+      for (int i = tid; i < Nb; i += NT) {
+        L.Bv[i] = pre[p.pre_B + ds.bins0 + i];
+        for (int b = 0; b < NB; ++b) {
+          L.bkr[b * Nb + i] = pre[p.pre_bkr + ds.bk0 + b * Nb + i];
+          L.bks[b * Nb + i] = pre[p.pre_bks + ds.bk0 + b * Nb + i];
+          L.bki[b * Nb + i] = shp[b * Nb + i];
+        }
+        if (want_nll) L.lam[i] = io.data[ds.data + i];  // the observed count, replaced by lambda in (d)
+      }
+      for (int e = tid; e < E; e += NT) {
+        L.ek[e] = (int)pre[p.pre_ek + ds.e0 + e];
+        L.eT[e] = pre[p.pre_et + ds.e0 + e];
+        L.eY[e] = pre[p.pre_ey + ds.e0 + e];
+        L.eQ[e] = pre[p.pre_eq + ds.e0 + e];
+      }
+    } else {
+      const double c0 = pval(L.th, ds.cidx[0], 0.0);
+      const double c2 = pval(L.th, ds.cidx[2], 0.0);
+      const double bb = 1.0 + pval(L.th, ds.cidx[1], 0.0);
+      if (tid == 0 && !map_ok(bb, c2, y0, yK)) atomicOr(&L.flag[0], ST_DOMAIN);
+      if (d == 0) {
+        for (int i = tid; i < p.P; i += NT)
+          if (!isfinite(L.th[i])) atomicOr(&L.flag[0], ST_DOMAIN);
+        if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
+      }
+      for (int k = tid; k < K; k += NT) {
+        const double f1 = flux_factor(L.th, blob, BL, ds.fw, k), hs = load_agent(hsrow + k);
+        const double H = hs * f1;
+        L.F1[k] = f1;
+        L.Hs[k] = hs;
+        L.Hk[k] = H;
+        L.mk[k] = H * iwf;
+      }
+      for (int i = tid; i < Nb; i += NT) {
+        L.Bv[i] = background(L.th, blob, BL, NB, Nb, i, L.bkr + i, L.bks + i);
+        for (int b = 0; b < NB; ++b) L.bki[b * Nb + i] = shp[b * Nb + i];
+        if (want_nll) L.lam[i] = io.data[ds.data + i];  // the observed count, replaced by lambda in (d)
+      }
+      for (int e = tid; e < E; e += NT) {
+        const MappedEdge m = map_edge(blob[BL.edges + e], c0, bb, c2, y0, yK, wf, iwf, K);
+        L.ek[e] = m.k;
+        L.eT[e] = m.t;
+        L.eY[e] = m.y;
+        L.eQ[e] = m.ifp;
+      }
     }
     __syncthreads();
 
@@ -437,12 +370,12 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       const int k = L.ek[e];
       double piece = 0.0, rr = 0.0;
       if (k >= 0 && k < K) {
-        const double t = L.eT[e], y = L.eY[e];
+        const double t = L.eT[e];
         const double dl = dens(k), dh = dens(k + 1), mk = L.mk[k];
         const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
         piece = wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + c * q);
         const double rho = dl * (1.0 - t) + dh * t + c * t * (1.0 - t);
-        rr = rho / (bb + 2.0 * c2 * y);
+        rr = rho * L.eQ[e];
       }
       L.eP[e] = piece;
       L.eR[e] = rr;
@@ -669,26 +602,35 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   return bad ? INFINITY : nll_total;
 }
 
-// Launch prologue shared by the single and batched bin stages, after the
-// parameters and dataset plans have reached LDS (waited for and
-// synchronised): clears the gradient and flag and evaluates the prior rows
-// into LDS. Returns this thread's part of the prior NLL. The caller
-// synchronises before the serial stages read the rows.
+// Launch prologue shared by the single and batched bin stages: clears the
+// gradient and flag and puts the prior rows into LDS -- read from the fold
+// launch's parameter pass (pre: single evaluation; the prior NLL comes summed,
+// thread 0 takes it) or evaluated here from the parameters in LDS (batched).
+// Returns this thread's part of the prior NLL. The caller synchronises before
+// the serial stages read the rows.
 template <int NT>
-__device__ __forceinline__ double prologue(const DevPlan& p, Lds<NT>& L, int want_nll) {
+__device__ __forceinline__ double prologue(const DevPlan& p, Lds<NT>& L, const double* pre, int want_nll) {
   const int tid = threadIdx.x;
   for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
   if (tid == 0) L.flag[0] = 0;
   double e_sum = 0.0;
-  if (want_nll)
+  if (!want_nll) return e_sum;
+  if (pre) {
     for (int r = tid; r < p.NR; r += NT) {
-      int idx;
-      double v, e;
-      prior_row(p, L.th, r, idx, v, e);
-      L.prv[r] = v;
-      L.pri[r] = idx;
-      e_sum += e;
+      L.prv[r] = pre[p.pre_prv + r];
+      L.pri[r] = prior_index(p, r);
     }
+    if (tid == 0) e_sum = pre[p.pre_misc];
+    return e_sum;
+  }
+  for (int r = tid; r < p.NR; r += NT) {
+    int idx;
+    double v, e;
+    prior_row(p, L.th, r, idx, v, e);
+    L.prv[r] = v;
+    L.pri[r] = idx;
+    e_sum += e;
+  }
   return e_sum;
 }
 
@@ -702,16 +644,17 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   Lds<NT> L = carve<NT>(smem, p);
 
   const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
-                  const_cast<double*>(a.bin), 1, a.keep_rows};
+                  const_cast<double*>(a.bin), 1, a.keep_rows, a.pre};
   // the fold kernel has applied the oscillation coefficients; the domain of
   // the oscillation parameters is checked from LDS in the serial stages.
   // Parameters and dataset plans go to LDS by direct copies (dataset 0's plan
   // comes with the kernel arguments).
   copy_to_lds<NT>(L.th, a.theta, p.P);
   copy_to_lds<NT>(reinterpret_cast<double*>(L.dsl), reinterpret_cast<const double*>(p.ds), p.D * DSPLAN_DOUBLES);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  const double pe = prologue<NT>(p, L, a.want_nll);
+  // with the parameter pass done by the fold launch (pre), nothing reads the
+  // parameters or the later plans before these copies are waited for, at the
+  // end of dataset 0's analysis-bin pass
+  const double pe = prologue<NT>(p, L, a.pre, a.want_nll);
   __syncthreads();
   const double f = serial_stages<NT>(p, io, L, pe, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
@@ -769,7 +712,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
                   a.mu_out ? a.mu_out + (int64_t)f * p.nbins_total : nullptr,
                   a.Sseg + (int64_t)f * G,
                   a.bin + (int64_t)f * 6 * KT,
-                  0, 0};
+                  0, 0, nullptr};
   double* tmp = a.segtmp + (int64_t)f * 5 * G;
   // phase A, per segment
   for (int g = tid; g < G; g += NT) {
@@ -816,7 +759,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const double pe = prologue<NT>(p, L, a.want_nll);
+  const double pe = prologue<NT>(p, L, nullptr, a.want_nll);
   __syncthreads();
   const double fval = serial_stages<NT>(p, io, L, pe, a.want_nll, a.want_nll ? a.want_grad : 0);
   if (a.has_fit) {
