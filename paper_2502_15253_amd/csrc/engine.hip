@@ -532,22 +532,15 @@ void parse_model(nf_ctx* c, const char* text) {
     pl.FS = fs;
     // parameter-pass buffer of the single evaluation
     {
-      int bk = 0;
-      for (size_t di = 0; di < c->dsplan.size(); ++di) {
-        c->dsplan[di].e0 = c->dsplan[di].bins0 + (int)di;
-        c->dsplan[di].bk0 = bk;
-        bk += c->dsplan[di].nbkg * c->dsplan[di].Nb;
-      }
-      const int ET = bins0 + pl.D;
       int o = 0;
-      pl.pre_F1 = o; o += std::max(1, kt);
-      pl.pre_ek = o; o += ET;
-      pl.pre_et = o; o += ET;
-      pl.pre_ey = o; o += ET;
-      pl.pre_eq = o; o += ET;
-      pl.pre_B = o; o += std::max(1, bins0);
-      pl.pre_bkr = o; o += std::max(1, bk);
-      pl.pre_bks = o; o += std::max(1, bk);
+      pl.max_pre = 0;
+      for (size_t di = 0; di < c->dsplan.size(); ++di) {
+        DsPlan& q = c->dsplan[di];
+        const PreLayout L = pre_layout(q.K, q.Nb, q.nbkg);
+        q.pre0 = o;
+        o += L.total;
+        pl.max_pre = std::max(pl.max_pre, L.total);
+      }
       pl.pre_prv = o;  // NR is known after the priors below
       pl.pre_total = o;
     }
@@ -704,7 +697,9 @@ void parse_model(nf_ctx* c, const char* text) {
     pl.prow_blk = (int)ip.size();
     for (int b = 0; b < pl.nblk; ++b)
       for (int r = bptr[b]; r < bptr[b + 1]; ++r) ip.push_back(b);
-    pl.pre_misc = pl.pre_prv + std::max(1, pl.NR);
+    pl.pre_pri = pl.pre_prv + pl.NR;
+    pl.pre_misc = pl.pre_pri + (pl.NR + 1) / 2;
+    pl.pre_glob = pl.pre_misc + 2 + pl.D - pl.pre_prv;
     pl.pre_total = pl.pre_misc + 2 + pl.D;
   } catch (const JsonError& e) {
     fail(NF_EPARSE, e.what());

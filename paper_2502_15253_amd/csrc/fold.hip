@@ -338,18 +338,18 @@ __device__ void parameter_pass(const FoldArgs& a, int b, double* red) {
     const double c0 = pval(th, ds.cidx[0], 0.0);
     const double c2 = pval(th, ds.cidx[2], 0.0);
     const double bb = 1.0 + pval(th, ds.cidx[1], 0.0);
+    const PreLayout PL = pre_layout(K, Nb, NB);
+    double* q = pre + ds.pre0;
     if (tid == 0) pre[p.pre_misc + 2 + b] = map_ok(bb, c2, y0, yK) ? 0.0 : 1.0;
-    for (int k = tid; k < K; k += nt) pre[p.pre_F1 + ds.kt0 + k] = flux_factor(th, blob, BL, ds.fw, k);
+    for (int k = tid; k < K; k += nt) q[PL.F1 + k] = flux_factor(th, blob, BL, ds.fw, k);
     for (int e = tid; e < E; e += nt) {
       const MappedEdge m = map_edge(blob[BL.edges + e], c0, bb, c2, y0, yK, wf, iwf, K);
-      pre[p.pre_ek + ds.e0 + e] = (double)m.k;
-      pre[p.pre_et + ds.e0 + e] = m.t;
-      pre[p.pre_ey + ds.e0 + e] = m.y;
-      pre[p.pre_eq + ds.e0 + e] = m.ifp;
+      reinterpret_cast<int*>(q + PL.ek)[e] = m.k;
+      q[PL.et + e] = m.t;
+      q[PL.ey + e] = m.y;
+      q[PL.eq + e] = m.ifp;
     }
-    for (int i = tid; i < Nb; i += nt)
-      pre[p.pre_B + ds.bins0 + i] =
-          background(th, blob, BL, NB, Nb, i, pre + p.pre_bkr + ds.bk0 + i, pre + p.pre_bks + ds.bk0 + i);
+    for (int i = tid; i < Nb; i += nt) q[PL.B + i] = background(th, blob, BL, NB, Nb, i, q + PL.bkr + i, q + PL.bks + i);
     return;
   }
   double e_sum = 0.0, bad = 0.0;
@@ -358,6 +358,7 @@ __device__ void parameter_pass(const FoldArgs& a, int b, double* red) {
     double v, e;
     prior_row(p, th, r, idx, v, e);
     pre[p.pre_prv + r] = v;
+    reinterpret_cast<int*>(pre + p.pre_pri)[r] = idx;
     e_sum += e;
   }
   for (int i = tid; i < p.P; i += nt)

@@ -165,10 +165,12 @@ __host__ __device__ constexpr int red_doubles(int nt) { return 32 * 4 * (nt / 64
 
 // Dynamic LDS bytes used by the bin-stage kernel for a plan (matches carve()).
 __host__ __device__ inline size_t tail_lds_bytes(const DevPlan& p, int nt) {
-  const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb, BN = (size_t)p.max_B * p.max_Nb;
-  const size_t nd = 3 + 2 * (size_t)p.P + CF_SIZE + (size_t)p.D * DSPLAN_DOUBLES + red_doubles(nt) + 6 * K +
-                    (size_t)p.max_S * K + 2 * Nb + 2 * BN + 5 * E + p.NR + p.max_blob;
-  const size_t ni = E + K + 2 + p.NR + BN + 2;
+  const size_t K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
+  // six alignment pads, the regions with a slack double, then the rest
+  const size_t nd = 6 + (size_t)p.max_pre + p.max_blob + p.NR + (p.NR + 1) / 2 + 2 + p.D +
+                    (size_t)p.D * DSPLAN_DOUBLES + (p.P + 1) + ((size_t)p.max_S * K + 1) + (Nb + 1) + K + p.P +
+                    CF_SIZE + red_doubles(nt) + 4 * K + 2 * E;
+  const size_t ni = K + 2 + 2;
   return (nd + fit_lds_doubles(p.P, p.fit_m)) * sizeof(double) + ni * sizeof(int);
 }
 

@@ -93,9 +93,8 @@ struct DsPlan {
   int bkg0;         // index of the first BkgPlan
   int blob, blob_n; // dpool offset and length of the static blob (layout: blob_layout)
   int fw;           // flux basis entries per fine bin in the blob's fixed-width rows (>= 1)
-  int e0;           // first mapped edge of this dataset in the parameter-pass buffer (bins0 + dataset)
-  int bk0;          // first background factor of this dataset in the parameter-pass buffer
-  int pad_;
+  int pre0;         // this dataset's block of the parameter-pass buffer (layout: pre_layout; even)
+  int pad_[2];
 };
 
 static_assert(sizeof(DsPlan) % sizeof(double) == 0, "DsPlan is copied as doubles");
@@ -103,14 +102,15 @@ constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
 
 // Per-dataset static inputs of the bin stages, packed contiguously. Offsets
 // count doubles; the integer arrays hold 32-bit integers, two per double
-// slot. The first hpart doubles (flux modes by column, source norm lists) are
-// what the stages read from LDS, copied there in one batch; the rest (edges,
-// background templates, the flux basis by fine bin in rows of fixed width fw,
-// unused entries with parameter -1) is read by each thread into registers,
-// every load independent of the others.
+// slot. The first hpart doubles (flux modes by column, source norm lists,
+// the parameters of the background rates and shapes) are what the stages
+// read from LDS, copied there in one batch; the rest (edges, background
+// templates, the flux basis by fine bin in rows of fixed width fw, unused
+// entries with parameter -1) is read by the parameter pass, each thread into
+// registers, every load independent of the others.
 struct BlobLayout {
-  int mdc, mdcol, mdk, mdp, nlp, nli, hpart;
-  int edges, tmpl, bsc, fcf, fpar, brt, shp, total;
+  int mdc, mdcol, mdk, mdp, nlp, nli, brt, shp, hpart;
+  int edges, tmpl, bsc, fcf, fpar, total;
 };
 __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K,
                                                   int fw) {
@@ -123,6 +123,8 @@ __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz,
   L.mdp = o; o += ints(M);        // parameter of each mode
   L.nlp = o; o += ints(S + 1);    // norm list of each source: pointers,
   L.nli = o; o += ints(nl);       // parameter indices
+  L.brt = o; o += ints(B);        // rate parameter of each background (-1: none)
+  L.shp = o; o += ints(B * Nb);   // shape parameter of each (background, bin) (-1: none)
   o += o & 1;                     // the global part starts 16-byte aligned
   L.hpart = o;
   L.edges = o; o += E;
@@ -130,8 +132,32 @@ __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz,
   L.bsc = o; o += B;
   L.fcf = o; o += K * fw;         // flux basis by fine bin, fw entries per bin: coefficients,
   L.fpar = o; o += ints(K * fw);  // parameter of each entry (-1: unused)
-  L.brt = o; o += ints(B);
-  L.shp = o; o += ints(B * Nb);
+  L.total = o;
+  return L;
+}
+
+// One dataset's block of the parameter-pass buffer (written by the fold
+// launch for the single evaluation), in the order the bin stages hold it in
+// LDS, so that one copy moves it: 1 + F per fine bin, the background
+// expectation and its rate and shape factors per analysis bin, then per
+// mapped edge t, y, 1 / f'(y) and the fine bin (int32, two per slot).
+// Offsets in doubles; the total is even (16-byte aligned blocks).
+struct PreLayout {
+  int F1, B, bkr, bks, et, ey, eq, ek, total;
+};
+__host__ __device__ inline PreLayout pre_layout(int K, int Nb, int NB) {
+  PreLayout L;
+  const int E = Nb + 1, BN = NB * Nb;
+  int o = 0;
+  L.F1 = o; o += K;
+  L.B = o; o += Nb;
+  L.bkr = o; o += BN;
+  L.bks = o; o += BN;
+  L.et = o; o += E;
+  L.ey = o; o += E;
+  L.eq = o; o += E;
+  L.ek = o; o += (E + 1) / 2;
+  o += o & 1;
   L.total = o;
   return L;
 }
@@ -169,17 +195,13 @@ struct DevPlan {
   int blk_mean;                 // dpool base (aligned with blk_idx)
   int blk_inv;                  // ipool: nblk offsets into dpool of row-major V^-1
   // parameter-pass buffer of the single evaluation (doubles; written by extra
-  // workgroups of the fold launch, read by the bin stages): offsets of
-  int pre_F1;    // KT: 1 + F per global fine bin
-  int pre_ek;    // ET = nbins_total + D: fine bin of each mapped edge (as a double)
-  int pre_et;    // ET: t of each mapped edge
-  int pre_ey;    // ET: y of each mapped edge
-  int pre_eq;    // ET: 1 / f'(y) at each mapped edge
-  int pre_B;     // nbins_total: background expectation per analysis bin
-  int pre_bkr;   // BKT = sum over datasets of backgrounds x bins: dmu/dR
-  int pre_bks;   // BKT: dmu/dbeta
-  int pre_prv;   // NR: gradient contribution of each prior row
+  // workgroups of the fold launch, read by the bin stages): one block per
+  // dataset (DsPlan::pre0, pre_layout), then one contiguous block of
+  int pre_prv;   // NR: gradient contribution of each prior row,
+  int pre_pri;   // (NR + 1) / 2: parameter of each prior row (int32),
   int pre_misc;  // 2 + D: prior NLL, parameter-domain flag, energy-map domain flag per dataset
+  int pre_glob;  // doubles of that block (pre_prv .. pre_misc + 2 + D)
+  int max_pre;   // largest dataset block
   int pre_total; // doubles of the buffer
 };
 

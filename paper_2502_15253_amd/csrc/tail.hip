@@ -59,76 +59,100 @@ namespace nufold {
 
 template <int NT>
 struct Lds {
-  double* th;     // P
+  double* th;     // P     parameters
   double* grad;   // P
   double* coef;   // CF_SIZE
   DsPlan* dsl;    // D dataset plans
   double* red;    // block reduction scratch (red_doubles)
   double* Hk;     // K     H_k = Hs_k (1 + F_k)
   double* mk;     // K     m_k = H_k / w
-  double* F1;     // K     1 + F_k
   double* LF;     // K     lambda_F
   double* LHs;    // K     lambda_Hs (read back only for sources past the first sixteen)
   double* Hs;     // K     the oscillated spectrum with source norms (fold row 0)
-  double* Ss;     // S K   per-source spectra (copy target)
-  double* lam;    // Nb    lambda_mu
+  double* Ss;     // S K   per-source spectra
+  double* lam;    // Nb    observed counts, then lambda_mu
+  double* eP;     // E     spline integral from its fine bin's lower edge to the mapped edge (0 outside)
+  double* eR;     // E     spline density at the mapped edge over f'(y) (0 outside)
+  double* st;     // the LDS part of the dataset's static blob (flux modes, norm lists, background parameters)
+  double* fit;    // minimiser scratch
+  // the dataset's block of the parameter pass (pre_layout), in one region:
+  double* F1;     // K     1 + F_k
   double* Bv;     // Nb    background expectation
   double* bkr;    // B Nb  dmu_i/dR_b
   double* bks;    // B Nb  dmu_i/dbeta_bi
   double* eT;     // E     t of each mapped edge
   double* eY;     // E     y of each mapped edge
-  double* eP;     // E     spline integral from its fine bin's lower edge to the mapped edge (0 outside)
-  double* eR;     // E     spline density at the mapped edge over f'(y) (0 outside)
   double* eQ;     // E     1 / f'(y) at the mapped edge
-  double* prv;    // NR    gradient contribution of each prior row
-  double* st;     // copy target: the flux-mode and norm-list part of the static blob
-  double* fit;    // minimiser scratch
   int* ek;        // E     fine bin of each mapped edge: -1 below y_0, K at or above y_K
-  int* first;     // K + 2 first[q] = first edge whose clamped fine bin is >= q (E: none)
-  int* pri;       // NR    parameter of each prior row
+  // pointers into st:
   int* bki;       // B Nb  shape parameter of (b, i), or -1
+  int* brt;       // B     rate parameter of each background, or -1
+  // the prior rows and flags, in one region (the layout of the parameter
+  // pass's global block):
+  double* prv;    // NR    gradient contribution of each prior row
+  int* pri;       // NR    parameter of each prior row
+  double* misc;   // 2 + D the parameter pass's prior NLL and domain flags (single evaluation)
+  int* first;     // K + 2 first[q] = first edge whose clamped fine bin is >= q (E: none)
   int* flag;      // 2
+  // region bases: copies land at their source's alignment modulo 16 bytes
+  double *thb, *Ssb, *lamb, *dsb;
 };
+
+// Points the per-dataset arrays at the dataset's layout inside their regions.
+template <int NT>
+__device__ __forceinline__ void point_dataset(Lds<NT>& L, const DsPlan& ds, const BlobLayout& BL) {
+  const PreLayout PL = pre_layout(ds.K, ds.Nb, ds.nbkg);
+  L.F1 = L.dsb + PL.F1;
+  L.Bv = L.dsb + PL.B;
+  L.bkr = L.dsb + PL.bkr;
+  L.bks = L.dsb + PL.bks;
+  L.eT = L.dsb + PL.et;
+  L.eY = L.dsb + PL.ey;
+  L.eQ = L.dsb + PL.eq;
+  L.ek = reinterpret_cast<int*>(L.dsb + PL.ek);
+  L.bki = reinterpret_cast<int*>(L.st + BL.shp);
+  L.brt = reinterpret_cast<int*>(L.st + BL.brt);
+}
 
 template <int NT>
 __device__ Lds<NT> carve(double* base, const DevPlan& p) {
   Lds<NT> L;
-  const int K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb, BN = p.max_B * p.max_Nb;
-  // regions filled by direct copies start at 16-byte boundaries (even offsets)
+  const int K = p.max_K, E = p.max_Nb + 1, Nb = p.max_Nb;
+  // regions filled by direct copies start at 16-byte boundaries (even
+  // offsets); those whose sources have no fixed alignment get one double of
+  // slack
   auto al = [](double* x) { return x + (reinterpret_cast<uintptr_t>(x) & 8 ? 1 : 0); };
-  double* q = base;
-  L.th = q; q += p.P;
-  L.grad = q; q += p.P;
-  L.coef = q; q += CF_SIZE;
+  double* q = al(base);
+  L.dsb = q; q += p.max_pre;
+  L.st = q; q += p.max_blob;
+  q = al(q);
+  L.prv = q; q += p.NR;
+  L.pri = reinterpret_cast<int*>(q); q += (p.NR + 1) / 2;
+  L.misc = q; q += 2 + p.D;
   q = al(q);
   L.dsl = reinterpret_cast<DsPlan*>(q); q += p.D * DSPLAN_DOUBLES;
+  L.thb = q; q += p.P + 1;
+  L.th = L.thb;
+  q = al(q);
+  L.Ssb = q; q += p.max_S * K + 1;
+  L.Ss = L.Ssb;
+  q = al(q);
+  L.lamb = q; q += Nb + 1;
+  L.lam = L.lamb;
+  q = al(q);
+  L.Hs = q; q += K;
+  L.grad = q; q += p.P;
+  L.coef = q; q += CF_SIZE;
   L.red = q; q += red_doubles(NT);
   L.Hk = q; q += K;
   L.mk = q; q += K;
-  L.F1 = q; q += K;
   L.LF = q; q += K;
   L.LHs = q; q += K;
-  L.Hs = q; q += K;
-  q = al(q);
-  L.Ss = q; q += p.max_S * K;
-  L.lam = q; q += Nb;
-  L.Bv = q; q += Nb;
-  L.bkr = q; q += BN;
-  L.bks = q; q += BN;
-  L.eT = q; q += E;
-  L.eY = q; q += E;
   L.eP = q; q += E;
   L.eR = q; q += E;
-  L.eQ = q; q += E;
-  L.prv = q; q += p.NR;
-  q = al(q);
-  L.st = q; q += p.max_blob;
   L.fit = q; q += fit_lds_doubles(p.P, p.fit_m);
   int* r = reinterpret_cast<int*>(q);
-  L.ek = r; r += E;
   L.first = r; r += K + 2;
-  L.pri = r; r += p.NR;
-  L.bki = r; r += BN;
   L.flag = r;
   return L;
 }
@@ -187,18 +211,21 @@ namespace nufold {
 
 // Asynchronous copies from global memory straight into LDS (global_load_lds:
 // no registers, every load in flight at once). dma_lds<NT, B> moves nbytes (a
-// multiple of B) in chunks of 64 B bytes, one per wavefront in turn, lane l
+// multiple of B) in chunks of 64 B bytes, one per wavefront in turn starting
+// with wavefront rot (so that many small copies spread over the waves), lane l
 // the B bytes at l B of its chunk; B = 16 needs 16-byte aligned source and
 // destination. The caller waits (s_waitcnt) and synchronises before reading.
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef __attribute__((address_space(1))) const void* global_cvoid_ptr;
 template <int NT, int B>
-__device__ __forceinline__ void dma_lds(char* dst, const char* src, int nbytes) {
+__device__ __forceinline__ void dma_lds(char* dst, const char* src, int nbytes, int rot = 0) {
   static_assert(B == 4 || B == 16, "4- or 16-byte units");
   constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  static_assert((NW & (NW - 1)) == 0, "a power-of-two number of waves");
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // chunk addresses in scalar registers
   const int nunits = nbytes / B;
-  for (int c = wid; c * 64 < nunits; c += NW) {
+  for (int c = (wid - rot) & (NW - 1); c * 64 < nunits; c += NW) {
     const int idx = c * 64 + lane;
     if (idx < nunits) {
       const global_cvoid_ptr g = (global_cvoid_ptr)(src + (size_t)B * idx);
@@ -212,22 +239,23 @@ __device__ __forceinline__ void dma_lds(char* dst, const char* src, int nbytes) 
 // alignment modulo 16 (a leading or trailing double by 4-byte units), else
 // 4-byte units throughout.
 template <int NT>
-__device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int n) {
+__device__ __forceinline__ void copy_to_lds(double* dst, const double* src, int n, int rot = 0) {
   char* d = reinterpret_cast<char*>(dst);
   const char* s = reinterpret_cast<const char*>(src);
   const unsigned da = (unsigned)(uintptr_t)(lds_void_ptr)d;
   const unsigned sa = (unsigned)(uintptr_t)s;
   if (((da ^ sa) & 15u) != 0 || n < 4) {
-    dma_lds<NT, 4>(d, s, 8 * n);
+    dma_lds<NT, 4>(d, s, 8 * n, rot);
     return;
   }
   const int head = (sa & 15u) ? 1 : 0;
   const int body = (n - head) & ~1;
   const int tail = n - head - body;
-  if (head) dma_lds<NT, 4>(d, s, 8);
-  dma_lds<NT, 16>(d + 8 * head, s + 8 * head, 8 * body);
-  if (tail) dma_lds<NT, 4>(d + 8 * (head + body), s + 8 * (head + body), 8);
+  if (head) dma_lds<NT, 4>(d, s, 8, rot + 1);
+  dma_lds<NT, 16>(d + 8 * head, s + 8 * head, 8 * body, rot);
+  if (tail) dma_lds<NT, 4>(d + 8 * (head + body), s + 8 * (head + body), 8, rot + 2);
 }
+
 
 // ---------------------------------------------------------------- inputs
 // The fold's rows were written by the fold kernel (single evaluation: plain
@@ -245,22 +273,68 @@ __device__ __forceinline__ void load_rows(const EvalIO& io, const DsPlan& ds, in
   for (int j = 0; j < 4; ++j) r.g[j] = ld(b + (j + 1) * K + k, co);
 }
 
+// LDS destination for a copy from src into a region with one double of
+// slack: the same alignment modulo 16 bytes as the source.
+__device__ __forceinline__ double* matched(double* region, const double* src) {
+  return region + ((reinterpret_cast<uintptr_t>(src) >> 3) & 1);
+}
+
+// Single evaluation: every input of one dataset that the bin stages read --
+// the LDS part of its static blob, the fold's row 0 and per-source spectra,
+// its block of the fold launch's parameter pass (1 + F per fine bin,
+// backgrounds and their factors, mapped edges) and the observed counts --
+// goes to LDS by five direct copies issued together: one global round trip.
+// The caller waits (s_waitcnt) and synchronises.
+template <int NT>
+__device__ __forceinline__ void gather_inputs(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
+                                              const BlobLayout& BL, int want_nll) {
+  const int K = ds.K;
+  const double* ss = io.Sseg + ds.seg0;
+  const double* dat = io.data + ds.data;
+  L.Ss = matched(L.Ssb, ss);
+  L.lam = matched(L.lamb, dat);
+  copy_to_lds<NT>(L.st, p.dpool + ds.blob, BL.hpart, 0);
+  copy_to_lds<NT>(L.dsb, io.pre + ds.pre0, pre_layout(K, ds.Nb, ds.nbkg).total, 3);
+  copy_to_lds<NT>(L.Ss, ss, ds.S * K, 6);
+  copy_to_lds<NT>(L.Hs, io.bin + 6 * (int64_t)ds.kt0, K, 1);
+  if (want_nll) copy_to_lds<NT>(L.lam, dat, ds.Nb, 4);  // observed counts, replaced by lambda in (d)
+}
+
+// A dataset plan read from LDS in one batch, every 32-bit word made
+// wave-uniform (scalar registers).
+__device__ __forceinline__ DsPlan uniform_plan(const DsPlan* src) {
+  static_assert(sizeof(DsPlan) % 16 == 0, "DsPlan is read in 16-byte units");
+  DsPlan r;
+  const int4* s = reinterpret_cast<const int4*>(src);
+  int* o = reinterpret_cast<int*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(DsPlan) / 16); ++i) {
+    const int4 v = s[i];
+    o[4 * i] = __builtin_amdgcn_readfirstlane(v.x);
+    o[4 * i + 1] = __builtin_amdgcn_readfirstlane(v.y);
+    o[4 * i + 2] = __builtin_amdgcn_readfirstlane(v.z);
+    o[4 * i + 3] = __builtin_amdgcn_readfirstlane(v.w);
+  }
+  return r;
+}
+
 // Serial bin stages, NLL, priors and adjoint of one evaluation; returns the
 // NLL (+inf when out of domain) to every thread; the gradient is in L.grad.
 // On entry the parameters are in LDS (waited for and synchronised), the
 // gradient and flag are clear, the prior rows are in L.prv / L.pri, and
-// prior_e is this thread's part of the prior NLL.
+// prior_e is this thread's part of the prior NLL (batched; a single
+// evaluation takes the prior NLL from L.misc, and dataset 0's inputs are in
+// LDS already).
 //
-// Per dataset: (a) the flux-mode and norm-list tables and the per-source
-// spectra go to LDS by asynchronous direct copies; (b) parameter pass: 1 + F,
-// H and m per fine bin, the background expectation and its factors per
-// analysis bin, the mapped edges -- read from the fold launch's parameter
-// pass (io.pre, single evaluation) or computed here (batched), with every
-// load independent of the others; (c) per mapped edge the densities, the
-// spline integral up to the edge and its density, and the edge-index table;
-// (d) per analysis bin the signal, expectation, deviance, lambda and the
-// background and energy-scale sums; (e) per fine bin the adjoint; one block
-// reduction of every summed gradient; (f) source norms, flux modes, priors.
+// Per dataset: (a, b) inputs -- single evaluation: every one by direct copies
+// (gather_inputs); batched: the flux-mode and norm-list tables by direct
+// copies, then a parameter pass: 1 + F per fine bin, the background
+// expectation and its factors per analysis bin, the mapped edges; (c) H and m
+// per fine bin, per mapped edge the densities, the spline integral up to the
+// edge and its density, and the edge-index table; (d) per analysis bin the
+// signal, expectation, deviance, lambda and the background and energy-scale
+// sums; (e) per fine bin the adjoint; one block reduction of every summed
+// gradient; (f) source norms, flux modes, priors.
 constexpr int ACC_SRC = 16;  // sources reduced together with the other sums
 template <int NT>
 __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, double prior_e, int want_nll,
@@ -274,56 +348,27 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // is hoisted out of the loop (where it would hold registers throughout)
     int d = dloop;
     asm volatile("" : "+s"(d));
-    const DsPlan& ds = d == 0 ? p.ds0 : L.dsl[d];
+    const DsPlan ds = uniform_plan(L.dsl + d);
     const int K = ds.K, Nb = ds.Nb, S = ds.S, E = Nb + 1, M = ds.M, NB = ds.nbkg;
     const double wf = ds.wf, iwf = 1.0 / wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
     const BlobLayout BL = blob_layout(E, NB, Nb, ds.nnz, M, S, ds.nl, K, ds.fw);
     const double* blob = p.dpool + ds.blob;
-    const int* brt = reinterpret_cast<const int*>(blob + BL.brt);
 
-    // ---- (a) inputs
-    copy_to_lds<NT>(L.st, blob, BL.hpart);
-    if (io.fused) {
-      copy_to_lds<NT>(L.Ss, io.Sseg + ds.seg0, S * K);
+    // ---- (a) inputs and (b) parameter pass
+    point_dataset<NT>(L, ds, BL);
+    if (io.pre) {
+      // single evaluation: everything by direct copies (dataset 0's were
+      // issued at kernel start, together with the parameters)
+      if (d > 0) {
+        gather_inputs<NT>(p, io, L, ds, BL, want_nll);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+      }
     } else {
+      copy_to_lds<NT>(L.st, blob, BL.hpart);
       // written by this workgroup's phase A: coherent loads, then LDS stores
       for (int j = tid; j < S * K; j += NT) L.Ss[j] = load_agent(io.Sseg + ds.seg0 + j);
-    }
-    int brt_b[MAX_BKG];
-#pragma unroll
-    for (int b = 0; b < MAX_BKG; ++b) brt_b[b] = b < NB ? brt[b] : -1;
-
-    // ---- (b) parameter pass
-    const double* hsrow = io.bin + 6 * (int64_t)ds.kt0;
-    const int* shp = reinterpret_cast<const int*>(blob + BL.shp);
-    if (io.pre) {
-      const double* pre = io.pre;
-      if (tid == 0 && (pre[p.pre_misc + 2 + d] != 0.0 || (d == 0 && pre[p.pre_misc + 1] != 0.0)))
-        atomicOr(&L.flag[0], ST_DOMAIN);
-      for (int k = tid; k < K; k += NT) {
-        const double f1 = pre[p.pre_F1 + ds.kt0 + k], hs = hsrow[k];
-        const double H = hs * f1;
-        L.F1[k] = f1;
-        L.Hs[k] = hs;
-        L.Hk[k] = H;
-        L.mk[k] = H * iwf;
-      }
-      for (int i = tid; i < Nb; i += NT) {
-        L.Bv[i] = pre[p.pre_B + ds.bins0 + i];
-        for (int b = 0; b < NB; ++b) {
-          L.bkr[b * Nb + i] = pre[p.pre_bkr + ds.bk0 + b * Nb + i];
-          L.bks[b * Nb + i] = pre[p.pre_bks + ds.bk0 + b * Nb + i];
-          L.bki[b * Nb + i] = shp[b * Nb + i];
-        }
-        if (want_nll) L.lam[i] = io.data[ds.data + i];  // the observed count, replaced by lambda in (d)
-      }
-      for (int e = tid; e < E; e += NT) {
-        L.ek[e] = (int)pre[p.pre_ek + ds.e0 + e];
-        L.eT[e] = pre[p.pre_et + ds.e0 + e];
-        L.eY[e] = pre[p.pre_ey + ds.e0 + e];
-        L.eQ[e] = pre[p.pre_eq + ds.e0 + e];
-      }
-    } else {
+      const double* hsrow = io.bin + 6 * (int64_t)ds.kt0;
       const double c0 = pval(L.th, ds.cidx[0], 0.0);
       const double c2 = pval(L.th, ds.cidx[2], 0.0);
       const double bb = 1.0 + pval(L.th, ds.cidx[1], 0.0);
@@ -334,16 +379,11 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         if (tid == 0 && !osc_domain_ok(p.osc, L.th)) atomicOr(&L.flag[0], ST_DOMAIN);
       }
       for (int k = tid; k < K; k += NT) {
-        const double f1 = flux_factor(L.th, blob, BL, ds.fw, k), hs = load_agent(hsrow + k);
-        const double H = hs * f1;
-        L.F1[k] = f1;
-        L.Hs[k] = hs;
-        L.Hk[k] = H;
-        L.mk[k] = H * iwf;
+        L.F1[k] = flux_factor(L.th, blob, BL, ds.fw, k);
+        L.Hs[k] = load_agent(hsrow + k);
       }
       for (int i = tid; i < Nb; i += NT) {
         L.Bv[i] = background(L.th, blob, BL, NB, Nb, i, L.bkr + i, L.bks + i);
-        for (int b = 0; b < NB; ++b) L.bki[b * Nb + i] = shp[b * Nb + i];
         if (want_nll) L.lam[i] = io.data[ds.data + i];  // the observed count, replaced by lambda in (d)
       }
       for (int e = tid; e < E; e += NT) {
@@ -353,25 +393,43 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         L.eY[e] = m.y;
         L.eQ[e] = m.ifp;
       }
+      // the blob's copy (background parameters, read from (d) on) has landed
+      // once every wave has waited for its own and passed the barrier
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
     }
-    __syncthreads();
 
+    // the adjoint's inputs of this thread's fine bin, in flight during (c) and (d)
+    FineRows rows;
+    if (tid < K && want_grad) load_rows(io, ds, tid, rows);
+
+    // m_k = H_k / w with H_k = Hs_k (1 + F_k), in the one order that (c)
+    // and the later passes (through L.mk) share
+    auto mof = [&](int k) { return L.Hs[k] * L.F1[k] * iwf; };
     auto dens = [&](int k) {  // d_k, 0 <= k <= K
-      if (k == 0) return L.mk[0];
-      if (k == K) return L.mk[K - 1];
-      const double a = L.mk[k - 1], b = L.mk[k];
+      if (k == 0) return mof(0);
+      if (k == K) return mof(K - 1);
+      const double a = mof(k - 1), b = mof(k);
       return (a * b > 0.0) ? 2.0 * a * b / (a + b) : 0.0;
     };
     auto clampK = [&](int k) { return k < 0 ? 0 : (k > K ? K : k); };
 
-    // ---- (c) per mapped edge: the spline integral from its fine bin's lower
-    // edge, P_k(t), and the density there over f'(y); edge-index table
+    // ---- (c) H and m per fine bin; per mapped edge the spline integral from
+    // its fine bin's lower edge, P_k(t), and the density there over f'(y);
+    // edge-index table
+    if (io.pre && tid == 0 && (L.misc[2 + d] != 0.0 || (d == 0 && L.misc[1] != 0.0)))
+      atomicOr(&L.flag[0], ST_DOMAIN);
+    for (int k = tid; k < K; k += NT) {
+      const double H = L.Hs[k] * L.F1[k];
+      L.Hk[k] = H;
+      L.mk[k] = H * iwf;
+    }
     for (int e = tid; e < E; e += NT) {
       const int k = L.ek[e];
       double piece = 0.0, rr = 0.0;
       if (k >= 0 && k < K) {
         const double t = L.eT[e];
-        const double dl = dens(k), dh = dens(k + 1), mk = L.mk[k];
+        const double dl = dens(k), dh = dens(k + 1), mk = mof(k);
         const double q = 0.5 * t * t - t * t * t * (1.0 / 3.0), c = 6.0 * (mk - 0.5 * (dl + dh));
         piece = wf * (dl * (t - 0.5 * t * t) + dh * 0.5 * t * t + c * q);
         const double rho = dl * (1.0 - t) + dh * t + c * t * (1.0 - t);
@@ -388,10 +446,6 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         for (int q = kk + 1; q <= K + 1; ++q) L.first[q] = E;
     }
     __syncthreads();
-
-    // the adjoint's inputs of this thread's fine bin, in flight during (d)
-    FineRows rows;
-    if (tid < K && want_grad) load_rows(io, ds, tid, rows);
 
     // acc: 0 NLL, 1..3 energy scale c0..c2, 4..7 oscillation slots,
     // 8..15 background rates, 16..31 the first sixteen source norms
@@ -433,9 +487,9 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       }
       L.lam[i] = lam;
     }
-    if (d == 0) acc[0] += prior_e;
-    // the flux-mode and norm-list copies of (a) have landed once every wave
-    // has waited for its own and passed the next barrier
+    if (d == 0) acc[0] += io.pre ? (tid == 0 && want_nll ? L.misc[0] : 0.0) : prior_e;
+    // (batched) the flux-mode and norm-list copies of (a) have landed once
+    // every wave has waited for its own and passed the next barrier
     __builtin_amdgcn_s_waitcnt(0);
     if (!want_grad) {
       block_sum<NT, 1>(acc, L.red);
@@ -541,7 +595,7 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
         if (p.osc.slot_param[j] >= 0) atomicAdd(&L.grad[p.osc.slot_param[j]], acc[4 + j]);
 #pragma unroll
       for (int b = 0; b < MAX_BKG; ++b)
-        if (b < NB && brt_b[b] >= 0) atomicAdd(&L.grad[brt_b[b]], acc[8 + b]);
+        if (b < NB && L.brt[b] >= 0) atomicAdd(&L.grad[L.brt[b]], acc[8 + b]);
     }
     if (tid < S) {
       const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
@@ -602,27 +656,17 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
   return bad ? INFINITY : nll_total;
 }
 
-// Launch prologue shared by the single and batched bin stages: clears the
-// gradient and flag and puts the prior rows into LDS -- read from the fold
-// launch's parameter pass (pre: single evaluation; the prior NLL comes summed,
-// thread 0 takes it) or evaluated here from the parameters in LDS (batched).
+// Launch prologue of the batched bin stages: clears the gradient and flag
+// and evaluates the prior rows from the parameters in LDS into L.prv / L.pri.
 // Returns this thread's part of the prior NLL. The caller synchronises before
 // the serial stages read the rows.
 template <int NT>
-__device__ __forceinline__ double prologue(const DevPlan& p, Lds<NT>& L, const double* pre, int want_nll) {
+__device__ __forceinline__ double prologue(const DevPlan& p, Lds<NT>& L, int want_nll) {
   const int tid = threadIdx.x;
   for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
   if (tid == 0) L.flag[0] = 0;
   double e_sum = 0.0;
   if (!want_nll) return e_sum;
-  if (pre) {
-    for (int r = tid; r < p.NR; r += NT) {
-      L.prv[r] = pre[p.pre_prv + r];
-      L.pri[r] = prior_index(p, r);
-    }
-    if (tid == 0) e_sum = pre[p.pre_misc];
-    return e_sum;
-  }
   for (int r = tid; r < p.NR; r += NT) {
     int idx;
     double v, e;
@@ -645,18 +689,26 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
 
   const EvalIO io{a.theta, nullptr, a.data, a.out, a.status, a.mu_out, const_cast<double*>(a.Sseg),
                   const_cast<double*>(a.bin), 1, a.keep_rows, a.pre};
-  // the fold kernel has applied the oscillation coefficients; the domain of
-  // the oscillation parameters is checked from LDS in the serial stages.
-  // Parameters and dataset plans go to LDS by direct copies (dataset 0's plan
-  // comes with the kernel arguments).
-  copy_to_lds<NT>(L.th, a.theta, p.P);
-  copy_to_lds<NT>(reinterpret_cast<double*>(L.dsl), reinterpret_cast<const double*>(p.ds), p.D * DSPLAN_DOUBLES);
-  // with the parameter pass done by the fold launch (pre), nothing reads the
-  // parameters or the later plans before these copies are waited for, at the
-  // end of dataset 0's analysis-bin pass
-  const double pe = prologue<NT>(p, L, a.pre, a.want_nll);
+  // The fold launch has applied the oscillation coefficients and, in its
+  // parameter pass, evaluated everything that depends on the parameters (the
+  // domain checks included). The parameters, the dataset plans (dataset 0's
+  // comes with the kernel arguments), the prior rows, the domain flags and
+  // every input of dataset 0 go to LDS by direct copies: one round trip.
+  const int tid = threadIdx.x;
+  L.th = matched(L.thb, a.theta);
+  copy_to_lds<NT>(L.th, a.theta, p.P, 2);
+  copy_to_lds<NT>(reinterpret_cast<double*>(L.dsl), reinterpret_cast<const double*>(p.ds), p.D * DSPLAN_DOUBLES, 5);
+  copy_to_lds<NT>(L.prv, a.pre + p.pre_prv, p.pre_glob, 7);
+  {
+    const DsPlan& ds = p.ds0;
+    const BlobLayout BL = blob_layout(ds.Nb + 1, ds.nbkg, ds.Nb, ds.nnz, ds.M, ds.S, ds.nl, ds.K, ds.fw);
+    gather_inputs<NT>(p, io, L, ds, BL, a.want_nll);
+  }
+  for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
+  if (tid == 0) L.flag[0] = 0;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const double f = serial_stages<NT>(p, io, L, pe, a.want_nll, a.want_grad);
+  const double f = serial_stages<NT>(p, io, L, 0.0, a.want_nll, a.want_grad);
   if (a.has_fit) lbfgs_step<NT>(a.fit, p.P, L.th, f, L.grad, L.fit, L.red);
 }
 
@@ -759,7 +811,7 @@ __global__ __launch_bounds__(NT) void batch_tail_kernel(BatchTailArgs a) {
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const double pe = prologue<NT>(p, L, nullptr, a.want_nll);
+  const double pe = prologue<NT>(p, L, a.want_nll);
   __syncthreads();
   const double fval = serial_stages<NT>(p, io, L, pe, a.want_nll, a.want_nll ? a.want_grad : 0);
   if (a.has_fit) {
