@@ -102,14 +102,15 @@ constexpr int DSPLAN_DOUBLES = (int)(sizeof(DsPlan) / sizeof(double));
 
 // Per-dataset static inputs of the bin stages, packed contiguously. Offsets
 // count doubles; the integer arrays hold 32-bit integers, two per double
-// slot. The first hpart doubles (flux modes by column, source norm lists,
-// the parameters of the background rates and shapes) are what the stages
-// read from LDS, copied there in one batch; the rest (edges, background
-// templates, the flux basis by fine bin in rows of fixed width fw, unused
-// entries with parameter -1) is read by the parameter pass, each thread into
-// registers, every load independent of the others.
+// slot. The first hpart doubles are what the stages read from LDS: the
+// parameters of the background rates and shapes (read by the analysis-bin
+// pass; the first `early` doubles), then the flux modes by column and the
+// source norm lists (read only by the gradient's last pass). The rest (edges,
+// background templates, the flux basis by fine bin in rows of fixed width fw,
+// unused entries with parameter -1) is read by the parameter pass, each
+// thread into registers, every load independent of the others.
 struct BlobLayout {
-  int mdc, mdcol, mdk, mdp, nlp, nli, brt, shp, hpart;
+  int brt, shp, early, mdc, mdcol, mdk, mdp, nlp, nli, hpart;
   int edges, tmpl, bsc, fcf, fpar, total;
 };
 __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz, int M, int S, int nl, int K,
@@ -117,14 +118,16 @@ __host__ __device__ inline BlobLayout blob_layout(int E, int B, int Nb, int nnz,
   auto ints = [](int n) { return (n + 1) / 2; };  // double slots for n int32 values
   BlobLayout L;
   int o = 0;
+  L.brt = o; o += ints(B);        // rate parameter of each background (-1: none)
+  L.shp = o; o += ints(B * Nb);   // shape parameter of each (background, bin) (-1: none)
+  o += o & 1;
+  L.early = o;                    // (16-byte aligned)
   L.mdc = o; o += nnz;           // flux basis by mode (CSC): coefficients,
   L.mdcol = o; o += ints(M + 1);  // column pointers,
   L.mdk = o; o += ints(nnz);      // fine bin of each entry,
   L.mdp = o; o += ints(M);        // parameter of each mode
   L.nlp = o; o += ints(S + 1);    // norm list of each source: pointers,
   L.nli = o; o += ints(nl);       // parameter indices
-  L.brt = o; o += ints(B);        // rate parameter of each background (-1: none)
-  L.shp = o; o += ints(B * Nb);   // shape parameter of each (background, bin) (-1: none)
   o += o & 1;                     // the global part starts 16-byte aligned
   L.hpart = o;
   L.edges = o; o += E;

@@ -279,25 +279,35 @@ __device__ __forceinline__ double* matched(double* region, const double* src) {
   return region + ((reinterpret_cast<uintptr_t>(src) >> 3) & 1);
 }
 
-// Single evaluation: every input of one dataset that the bin stages read --
-// the LDS part of its static blob, the fold's row 0 and per-source spectra,
+// Single evaluation: a dataset's inputs reach LDS by direct copies in two
+// rounds. The early round -- the background parameters of its static blob,
 // its block of the fold launch's parameter pass (1 + F per fine bin,
-// backgrounds and their factors, mapped edges) and the observed counts --
-// goes to LDS by five direct copies issued together: one global round trip.
-// The caller waits (s_waitcnt) and synchronises.
+// backgrounds and their factors, mapped edges), the fold's row 0 and the
+// observed counts -- is issued together and waited for (s_waitcnt, then a
+// barrier) before the edge and analysis-bin passes. The late round -- the
+// flux modes by column, the norm lists and the per-source spectra, read only
+// by the gradient's passes -- is issued after that barrier and lands while
+// those passes run (waited for at the barrier after the analysis bins). A
+// wavefront's issue of direct copies stalls while the compute unit's memory
+// pipeline is busy, so every wavefront takes a share (one wavefront issuing
+// the whole late round held the edge pass up by 2 us).
 template <int NT>
-__device__ __forceinline__ void gather_inputs(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
-                                              const BlobLayout& BL, int want_nll) {
-  const int K = ds.K;
-  const double* ss = io.Sseg + ds.seg0;
+__device__ __forceinline__ void gather_early(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
+                                             const BlobLayout& BL, int want_nll) {
   const double* dat = io.data + ds.data;
-  L.Ss = matched(L.Ssb, ss);
   L.lam = matched(L.lamb, dat);
-  copy_to_lds<NT>(L.st, p.dpool + ds.blob, BL.hpart, 0);
-  copy_to_lds<NT>(L.dsb, io.pre + ds.pre0, pre_layout(K, ds.Nb, ds.nbkg).total, 3);
-  copy_to_lds<NT>(L.Ss, ss, ds.S * K, 6);
-  copy_to_lds<NT>(L.Hs, io.bin + 6 * (int64_t)ds.kt0, K, 1);
-  if (want_nll) copy_to_lds<NT>(L.lam, dat, ds.Nb, 4);  // observed counts, replaced by lambda in (d)
+  copy_to_lds<NT>(L.dsb, io.pre + ds.pre0, pre_layout(ds.K, ds.Nb, ds.nbkg).total, 0);
+  copy_to_lds<NT>(L.st, p.dpool + ds.blob, BL.early, 3);
+  copy_to_lds<NT>(L.Hs, io.bin + 6 * (int64_t)ds.kt0, ds.K, 5);
+  if (want_nll) copy_to_lds<NT>(L.lam, dat, ds.Nb, 7);  // observed counts, replaced by lambda in (d)
+}
+template <int NT>
+__device__ __forceinline__ void gather_late(const DevPlan& p, const EvalIO& io, Lds<NT>& L, const DsPlan& ds,
+                                            const BlobLayout& BL) {
+  const double* ss = io.Sseg + ds.seg0;
+  L.Ss = matched(L.Ssb, ss);
+  copy_to_lds<NT>(L.st + BL.early, p.dpool + ds.blob + BL.early, BL.hpart - BL.early, 0);
+  copy_to_lds<NT>(L.Ss, ss, ds.S * ds.K, 4);
 }
 
 // A dataset plan read from LDS in one batch, every 32-bit word made
@@ -323,12 +333,12 @@ __device__ __forceinline__ DsPlan uniform_plan(const DsPlan* src) {
 // On entry the parameters are in LDS (waited for and synchronised), the
 // gradient and flag are clear, the prior rows are in L.prv / L.pri, and
 // prior_e is this thread's part of the prior NLL (batched; a single
-// evaluation takes the prior NLL from L.misc, and dataset 0's inputs are in
-// LDS already).
+// evaluation takes the prior NLL from L.misc, and dataset 0's early inputs
+// are in LDS already).
 //
 // Per dataset: (a, b) inputs -- single evaluation: every one by direct copies
-// (gather_inputs); batched: the flux-mode and norm-list tables by direct
-// copies, then a parameter pass: 1 + F per fine bin, the background
+// in two rounds (gather_early, gather_late); batched: the static blob's LDS
+// part by direct copies, then a parameter pass: 1 + F per fine bin, the background
 // expectation and its factors per analysis bin, the mapped edges; (c) H and m
 // per fine bin, per mapped edge the densities, the spline integral up to the
 // edge and its density, and the edge-index table; (d) per analysis bin the
@@ -357,13 +367,14 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // ---- (a) inputs and (b) parameter pass
     point_dataset<NT>(L, ds, BL);
     if (io.pre) {
-      // single evaluation: everything by direct copies (dataset 0's were
-      // issued at kernel start, together with the parameters)
+      // single evaluation: everything by direct copies (dataset 0's early
+      // round was issued at kernel start, together with the parameters)
       if (d > 0) {
-        gather_inputs<NT>(p, io, L, ds, BL, want_nll);
+        gather_early<NT>(p, io, L, ds, BL, want_nll);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
       }
+      if (want_grad) gather_late<NT>(p, io, L, ds, BL);
     } else {
       copy_to_lds<NT>(L.st, blob, BL.hpart);
       // written by this workgroup's phase A: coherent loads, then LDS stores
@@ -488,8 +499,8 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       L.lam[i] = lam;
     }
     if (d == 0) acc[0] += io.pre ? (tid == 0 && want_nll ? L.misc[0] : 0.0) : prior_e;
-    // (batched) the flux-mode and norm-list copies of (a) have landed once
-    // every wave has waited for its own and passed the next barrier
+    // (single evaluation) the late copies have landed once every wave has
+    // waited for its own and passed the next barrier
     __builtin_amdgcn_s_waitcnt(0);
     if (!want_grad) {
       block_sum<NT, 1>(acc, L.red);
@@ -588,6 +599,37 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
     // over each source's norm list; flux modes by a gather of lambda_F over
     // each mode's fine bins (CSC); priors. Every gradient entry of this pass
     // may receive several contributions: all adds are atomic.
+    if (tid < S) {
+      // the list's parameter indices, then their values, each read in one
+      // batch (lists of up to NL_FAST entries; longer ones term by term)
+      constexpr int NL_FAST = 4;
+      const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
+      const int* nli = reinterpret_cast<const int*>(L.st + BL.nli);
+      const int b = nlp[tid], e = nlp[tid + 1];
+      if (e - b <= NL_FAST) {
+        int ix[NL_FAST];
+        double tv[NL_FAST];
+#pragma unroll
+        for (int q = 0; q < NL_FAST; ++q) ix[q] = b + q < e ? nli[b + q] : -1;
+#pragma unroll
+        for (int q = 0; q < NL_FAST; ++q) tv[q] = ix[q] >= 0 ? L.th[ix[q]] : 1.0;
+#pragma unroll
+        for (int q = 0; q < NL_FAST; ++q) {
+          double prod = 1.0;
+#pragma unroll
+          for (int r = 0; r < NL_FAST; ++r)
+            if (r != q && r < e - b) prod *= tv[r];
+          if (q < e - b) atomicAdd(&L.grad[ix[q]], gA * prod);
+        }
+      } else {
+        for (int q = b; q < e; ++q) {
+          double prod = 1.0;
+          for (int r = b; r < e; ++r)
+            if (r != q) prod *= L.th[nli[r]];
+          atomicAdd(&L.grad[nli[q]], gA * prod);
+        }
+      }
+    }
     if (tid == NT - 1) {  // a thread with no source to apply (S <= MAX_SOURCES < NT)
       for (int j = 0; j < 3; ++j)
         if (ds.cidx[j] >= 0) atomicAdd(&L.grad[ds.cidx[j]], acc[1 + j]);
@@ -596,17 +638,6 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
 #pragma unroll
       for (int b = 0; b < MAX_BKG; ++b)
         if (b < NB && L.brt[b] >= 0) atomicAdd(&L.grad[L.brt[b]], acc[8 + b]);
-    }
-    if (tid < S) {
-      const int* nlp = reinterpret_cast<const int*>(L.st + BL.nlp);
-      const int* nli = reinterpret_cast<const int*>(L.st + BL.nli);
-      const int b = nlp[tid], e = nlp[tid + 1];
-      for (int q = b; q < e; ++q) {
-        double prod = 1.0;
-        for (int r = b; r < e; ++r)
-          if (r != q) prod *= L.th[nli[r]];
-        atomicAdd(&L.grad[nli[q]], gA * prod);
-      }
     }
     {
       const int* mdcol = reinterpret_cast<const int*>(L.st + BL.mdcol);
@@ -702,7 +733,7 @@ __global__ __launch_bounds__(NT) void tail_kernel(TailArgs a) {
   {
     const DsPlan& ds = p.ds0;
     const BlobLayout BL = blob_layout(ds.Nb + 1, ds.nbkg, ds.Nb, ds.nnz, ds.M, ds.S, ds.nl, ds.K, ds.fw);
-    gather_inputs<NT>(p, io, L, ds, BL, a.want_nll);
+    gather_early<NT>(p, io, L, ds, BL, a.want_nll);
   }
   for (int i = tid; i < p.P; i += NT) L.grad[i] = 0.0;
   if (tid == 0) L.flag[0] = 0;
