@@ -34,5 +34,29 @@ def build(verbose=False):
     return LIB
 
 
+# AddressSanitizer and UndefinedBehaviorSanitizer on the host pass only (the
+# device code is built as usual, at -O1 to keep the build short): the JSON
+# reader, the schema checks and the plan build run under the sanitizers when
+# a host program calls nf_create (without a GPU it returns NF_EDEVICE after
+# the plan build).
+SANITIZE_FLAGS = [
+    f"--offload-arch={ARCH}", "-O1", "-std=c++17", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Xarch_host", "-g",
+    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+]
+
+
+def build_host_sanitized(out_dir):
+    os.makedirs(out_dir, exist_ok=True)
+    lib = os.path.join(out_dir, "libnufold_hostsan.so")
+    cmd = [HIPCC, *SANITIZE_FLAGS, "-o", lib, *[os.path.join(CSRC, s) for s in SOURCES]]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the host-sanitized library")
+    return lib
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -1,7 +1,10 @@
 // Minimal JSON reader for model descriptions (objects, arrays, numbers,
-// strings, true/false/null). Throws JsonError with a position on bad input.
+// strings, true/false/null). Throws JsonError with a position on bad input:
+// malformed text, nesting deeper than MAX_DEPTH, and numbers that are not
+// finite or not in JSON's decimal form.
 #pragma once
 
+#include <cmath>
 #include <cstdlib>
 #include <map>
 #include <memory>
@@ -58,6 +61,7 @@ struct Json {
 
 class JsonParser {
  public:
+  static constexpr int MAX_DEPTH = 256;
   explicit JsonParser(const char* s) : p_(s), start_(s) {}
 
   Json parse() {
@@ -70,6 +74,7 @@ class JsonParser {
  private:
   const char* p_;
   const char* start_;
+  int depth_ = 0;
 
   [[noreturn]] void fail(const std::string& what) {
     throw JsonError("JSON: " + what + " at offset " + std::to_string(p_ - start_));
@@ -89,11 +94,12 @@ class JsonParser {
     ws();
     Json v;
     char c = *p_;
+    if ((c == '{' || c == '[') && ++depth_ > MAX_DEPTH) fail("nesting deeper than " + std::to_string(MAX_DEPTH));
     if (c == '{') {
       v.kind = Json::Object;
       ++p_;
       ws();
-      if (*p_ == '}') { ++p_; return v; }
+      if (*p_ == '}') { ++p_; --depth_; return v; }
       for (;;) {
         ws();
         if (*p_ != '"') fail("expected a key string");
@@ -107,11 +113,12 @@ class JsonParser {
         if (*p_ == '}') { ++p_; break; }
         fail("expected ',' or '}'");
       }
+      --depth_;
     } else if (c == '[') {
       v.kind = Json::Array;
       ++p_;
       ws();
-      if (*p_ == ']') { ++p_; return v; }
+      if (*p_ == ']') { ++p_; --depth_; return v; }
       for (;;) {
         v.arr.push_back(value());
         ws();
@@ -119,6 +126,7 @@ class JsonParser {
         if (*p_ == ']') { ++p_; break; }
         fail("expected ',' or ']'");
       }
+      --depth_;
     } else if (c == '"') {
       v.kind = Json::String;
       v.str = strlit();
@@ -131,11 +139,17 @@ class JsonParser {
     } else if (lit("NaN") || lit("Infinity") || lit("-Infinity")) {
       fail("non-finite numbers are not allowed");
     } else if (c == '-' || (c >= '0' && c <= '9')) {
+      // JSON's decimal form only (strtod alone would also take inf, nan and
+      // hexadecimal forms), and a finite value
+      const char* q = p_;
+      while ((*q >= '0' && *q <= '9') || *q == '-' || *q == '+' || *q == '.' || *q == 'e' || *q == 'E') ++q;
+      const std::string tok(p_, q);
       char* end = nullptr;
       v.kind = Json::Number;
-      v.num = std::strtod(p_, &end);
-      if (end == p_) fail("bad number");
-      p_ = end;
+      v.num = std::strtod(tok.c_str(), &end);
+      if (end != tok.c_str() + tok.size() || tok.empty()) fail("bad number");
+      if (!std::isfinite(v.num)) fail("number out of range");
+      p_ = q;
     } else {
       fail("unexpected character");
     }
