@@ -137,6 +137,67 @@ def cpu_baseline_all_cores(n_events, seconds=15.0):
 COPY_BYTES = 512 << 20
 
 
+def mlp_profile(torch, batches=(1024, 4096), steps=100, warm=5):
+    """Training steps of the surrogate network of the medium-baseline model
+    (20 inputs, four hidden layers of 512, 400 outputs; random data) at each
+    batch size, for a kernel trace: prints each step's products (pass, M, N,
+    K, output tile, grid) and the step rate, so the trace's dispatches can be
+    read per product shape."""
+    import math
+    from paper_2502_15253_amd import nufold as nf
+    n_in, width, depth, n_out = 20, 512, 4, 400
+    stream = torch.cuda.Stream()
+    net = nf.Mlp(n_in, width, depth, n_out, max(batches), stream=stream.cuda_stream)
+    rng = np.random.default_rng(0)
+    parts = []
+    for a, b in net.layer_shapes():
+        parts.append(rng.standard_normal(a * b) * math.sqrt(2.0 / a))
+        parts.append(np.zeros(b))
+    net.set_params(np.concatenate(parts).astype(np.float32))
+    dims = [n_in] + [width] * depth + [n_out]
+    kin = (n_in + 7) // 8 * 8
+
+    def grid(M, N, K, splits=1):
+        kslice = max(32, ((K + splits - 1) // splits + 31) // 32 * 32)
+        z = max(1, (K + kslice - 1) // kslice)
+        t = 128 if ((N + 127) // 128) * ((M + 127) // 128) * z >= 512 else 64
+        return t, ((N + t - 1) // t, (M + t - 1) // t, z)
+
+    out = {"network": f"{n_in}-{'-'.join([str(width)] * depth)}-{n_out}", "params": net.nparam, "batches": []}
+    for B in batches:
+        prods = []
+        for l in range(depth + 1):
+            M, N, K = B, dims[l + 1], kin if l == 0 else dims[l]
+            prods.append(("forward", l, M, N, K, *grid(M, N, K)))
+        for l in range(depth, -1, -1):
+            M, N, K = dims[l], dims[l + 1], B
+            tiles = ((M + 127) // 128) * ((N + 127) // 128)
+            sp = min(32, max(1, min(512 // tiles, B // 256)))
+            prods.append(("weight grad", l, M, N, K, *grid(M, N, K, sp)))
+            if l > 0:
+                M2, N2, K2 = B, dims[l], dims[l + 1]
+                prods.append(("input grad", l, M2, N2, K2, *grid(M2, N2, K2)))
+        x = torch.randn(B, n_in, device="cuda", dtype=torch.float32)
+        t = torch.randn(B, n_out, device="cuda", dtype=torch.float32)
+        torch.cuda.synchronize()
+        for _ in range(warm):
+            net.train_step(x, t, 1e-5, want_loss=False)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            net.train_step(x, t, 1e-5, want_loss=False)
+        stream.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        flop = sum(2.0 * M * N * K for (_, _, M, N, K, _, _) in prods)
+        out["batches"].append({"batch": B, "steps": steps, "us_per_step": dt * 1e6,
+                               "gemm_gflop_per_step": flop / 1e9, "tflops": flop / dt / 1e12,
+                               "products": [dict(pass_=p_, layer=l, M=M, N=N, K=K, tile=tt, grid=list(g))
+                                            for (p_, l, M, N, K, tt, g) in prods]})
+        log(f"batch {B}: {dt * 1e6:.1f} us per step, {flop / dt / 1e12:.1f} TFLOP/s over its products")
+    net.close()
+    print(json.dumps(out))
+
+
 def copy_probe(torch, reps=8):
     """Plain device-to-device copies of COPY_BYTES each: the reference that
     scales the memory counters of a profiled run to bytes."""
@@ -583,6 +644,8 @@ def main():
     ap.add_argument("--plain-fits", type=int, default=64, help="fits of the plain per-fit GPU path")
     ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
                     help="training spectra for the warm-start section (0 skips it)")
+    ap.add_argument("--mlp-profile", action="store_true",
+                    help="surrogate-network training steps only (for a kernel trace per product shape)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device copy of known size (counter calibration) and exit")
     ap.add_argument("--no-autotune", action="store_true",
@@ -605,6 +668,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.mlp_profile:
+        mlp_profile(torch)
         return
     if args.event_sweep:
         event_sweep(args, nf, synth, torch, [int(float(x)) for x in args.event_sweep.split(",")])
