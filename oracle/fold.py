@@ -11,7 +11,7 @@ on an edge belongs to the upper bin; events outside [y_0, y_K) are dropped.
 """
 import numpy as np
 
-from .oscillation import prob_eq1, prob_3nu, prob_4nu
+from .oscillation import prob_eq1, prob_3nu, prob_4nu, prob_3nu_matter
 
 
 def fine_edges(ds):
@@ -44,9 +44,12 @@ def baseline_over_energy(ds, events):
     return ds.baselines[src] / np.asarray(events["e_true"], dtype=np.float64)
 
 
-def survival(model, u, osc):
+def survival(model, u, osc, L=None):
+    """P at u = L/E (L in m, needed by the matter form only)."""
     if model.formula == "eq1":
         return prob_eq1(u, *osc)
+    if model.formula == "3nu_matter":
+        return prob_3nu_matter(u, L, *osc, model.rho_ye)
     if model.formula == "4nu":
         s13, m31, s14, m41 = osc
         s12, m21 = model.osc_constants
@@ -59,8 +62,9 @@ def fold_dataset(model, ds, events, osc):
     k, keep = bin_events(ds, events["e_reco"])
     u = baseline_over_energy(ds, events)[keep]
     w = np.asarray(events["weight"], dtype=np.float64)[keep]
-    seg = np.asarray(events["source"], dtype=np.int64)[keep] * ds.K + k[keep]
-    p = survival(model, u, osc)
+    src = np.asarray(events["source"], dtype=np.int64)[keep]
+    seg = src * ds.K + k[keep]
+    p = survival(model, u, osc, ds.baselines[src])
     a = w * p
     n = ds.S * ds.K
     if np.iscomplexobj(a):

@@ -3,9 +3,11 @@
 The model description is a plain dict (JSON-compatible):
   params      list of {name, start, prior: [mean, sigma] | None, fixed}
   cov_priors  list of {params: [names], mean: [...], cov: [[...]]}   (Eq. 6, Eq. 9 third line)
-  osc         {formula: "eq1" | "3nu" | "4nu", <slot>: {param: name} | {value: v}}
+  osc         {formula: "eq1" | "3nu" | "4nu" | "3nu_matter", <slot>: {param: name} | {value: v}}
               eq1 slots: sin2_2t13, dm2_ee, sin2_t12, dm2_21   (Eq. 1)
               3nu slots: sin2_t12, sin2_t13, dm2_21, dm2_31    (exact vacuum form of Eq. 10)
+              3nu_matter: the 3nu slots plus rho_ye (number, g/cm^3 x electrons per
+                  nucleon): exact three flavours in matter of constant density
               4nu slots: sin2_t13, dm2_31, sin2_2t14, dm2_41   (vacuum 3+1, sterile searches)
                   plus fixed values sin2_t12, dm2_21: {value: v}
   datasets    list of {name, fine: {y0, width, n}, edges, sources: [{baseline_m, norm}],
@@ -72,9 +74,10 @@ class Model:
                                 np.asarray(c["cov"], dtype=np.float64)))
         osc = desc["osc"]
         self.formula = osc["formula"]
-        if self.formula not in ("eq1", "3nu", "4nu"):
+        if self.formula not in ("eq1", "3nu", "4nu", "3nu_matter"):
             raise ValueError(self.formula)
-        slots = {"eq1": EQ1_SLOTS, "3nu": NU3_SLOTS, "4nu": NU4_SLOTS}[self.formula]
+        slots = {"eq1": EQ1_SLOTS, "3nu": NU3_SLOTS, "4nu": NU4_SLOTS, "3nu_matter": NU3_SLOTS}[self.formula]
+        self.rho_ye = float(osc["rho_ye"]) if self.formula == "3nu_matter" else 0.0
         self.osc_constants = ([float(osc[c]["value"]) for c in NU4_CONSTANTS]
                               if self.formula == "4nu" else [])
         self.osc_slots = []

@@ -121,3 +121,69 @@ def prob_4nu(u, s2_t12, s2_t13, dm2_21, dm2_31, s2_2t14, dm2_41):
             d = PHASE_K * (m2[j] - m2[i]) * u
             p = p - 4.0 * ue[i] * ue[j] * np.sin(d) ** 2
     return p
+
+
+# Constant-density matter (next step of the medium-baseline analysis: the
+# paper's JUNO-like fit takes matter effects from GLoBES, "Description of the
+# input model"). The electron-antineutrino Hamiltonian, in units of 1/(2E) and
+# eV^2, is M = U* diag(0, dm2_21, dm2_31) U^T - A e e^T with A = 2 sqrt(2) G_F
+# N_e E. With N_e = rho Y_e N_A per cm^3 (rho in g/cm^3, one gram per mole of
+# nucleons), G_F = 1.1663787e-5 GeV^-2, hbar c = 1.973269804593025e-14 GeV cm
+# and N_A = 6.02214076e23 / mol:  sqrt(2) G_F N_e = V * rho Y_e with V in eV,
+# and A = 2 V rho Y_e E = MATTER_A * rho Y_e * E[MeV] in eV^2.
+GF_GEV2 = 1.1663787e-5
+HBARC_GEV_CM = 1.973269804593025e-14
+AVOGADRO = 6.02214076e23
+MATTER_V_EV = np.sqrt(2.0) * GF_GEV2 * HBARC_GEV_CM ** 3 * AVOGADRO * 1e9  # eV per (g/cm^3)
+MATTER_A = 2.0 * MATTER_V_EV * 1e6  # eV^2 per (g/cm^3 MeV)
+
+
+def cubic_real_roots(a, b, c):
+    """The three real roots of x^3 + a x^2 + b x + c (trigonometric form of
+    Cardano's solution; requires three real roots). Works on complex inputs
+    (complex-step derivatives) through numpy's analytic sqrt/arccos/cos."""
+    p = b - a * a / 3.0
+    q = 2.0 * a ** 3 / 27.0 - a * b / 3.0 + c
+    r = 2.0 * np.sqrt(-p / 3.0)
+    phi = np.arccos((3.0 * q / (2.0 * p)) * np.sqrt(-3.0 / p)) / 3.0
+    return [r * np.cos(phi - 2.0 * np.pi * k / 3.0) - a / 3.0 for k in range(3)]
+
+
+def prob_3nu_matter(u, L, s2_t12, s2_t13, dm2_21, dm2_31, rho_ye):
+    """Exact three-flavour electron-antineutrino survival probability in matter
+    of constant electron density rho_ye (g/cm^3 times electrons per nucleon).
+
+    The eigenvalues l_i of M (eV^2) are the roots of its characteristic
+    polynomial. M differs from the vacuum matrix M0 only in its ee entry, so
+      det(l - M) = l (l - dm2_21)(l - dm2_31) + A Q(l),
+    Q(l) = det(l - N) for the (mu, tau) block N of M0, which matter does not
+    touch: Q(l) = l^2 + q1 l + q0, q1 = -(tr M0 - (M0)_ee), q0 = det N
+    = |Ue1|^2 dm2_21 dm2_31 (vacuum eigenvector-eigenvalue identity at l = 0),
+    (M0)_ee = |Ue2|^2 dm2_21 + |Ue3|^2 dm2_31. The mixing in matter follows from
+    the same identity: |Ue_i^m|^2 = Q(l_i) / prod_{j != i} (l_i - l_j). Then
+      P = 1 - 4 sum_{i<j} |Ue_i^m|^2 |Ue_j^m|^2 sin^2((l_i - l_j) L / 4E).
+    theta23 and the CP phase drop out of P_ee (the rotations they belong to
+    leave the electron row alone). u = L/E in m/MeV, L in m; units of the
+    mass splittings as in prob_3nu.
+    """
+    c2_12 = 1.0 - s2_t12
+    c2_13 = 1.0 - s2_t13
+    m21 = dm2_21 * DM2_21_UNIT
+    m31 = dm2_31 * DM2_31_UNIT
+    A = MATTER_A * rho_ye * (L / u)
+    ee = s2_t12 * c2_13 * m21 + s2_t13 * m31
+    q1 = -(m21 + m31 - ee)
+    q0 = c2_12 * c2_13 * m21 * m31
+    lam = cubic_real_roots(-(m21 + m31) + A, m21 * m31 + A * q1, A * q0)
+    x = []
+    for i in range(3):
+        den = 1.0
+        for j in range(3):
+            if j != i:
+                den = den * (lam[i] - lam[j])
+        x.append((lam[i] * lam[i] + q1 * lam[i] + q0) / den)
+    p = 1.0
+    for i in range(3):
+        for j in range(i + 1, 3):
+            p = p - 4.0 * x[i] * x[j] * np.sin(PHASE_K * (lam[i] - lam[j]) * u) ** 2
+    return p
