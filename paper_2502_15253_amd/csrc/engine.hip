@@ -179,6 +179,7 @@ struct nf_ctx {
   DevBuf<WorkItem> d_items;
   DevBuf<int> d_seg_item;
   DevBuf<double> d_Wseg;
+  DevBuf<double> d_Lseg;           // baseline of each segment's source (the matter form)
   DevBuf<double> d_part;
   DevBuf<double> d_theta;
   DevBuf<double> d_out;
@@ -250,7 +251,7 @@ struct nf_ctx {
   ~nf_ctx() {
     d_dpool.release(); d_ipool.release(); d_ds.release(); d_bkg.release();
     d_u64.release(); d_u32.release(); d_w.release(); d_items.release(); d_seg_item.release();
-    d_Wseg.release(); d_part.release(); d_theta.release(); d_out.release(); d_status.release();
+    d_Wseg.release(); d_Lseg.release(); d_part.release(); d_theta.release(); d_out.release(); d_status.release();
     d_data.release(); d_mu.release(); d_Sseg.release(); d_bin.release();
     d_seg_cnt.release(); d_kt_cnt.release(); d_seg_kt.release(); d_kt_need.release(); d_segm.release();
     d_epi.release();
@@ -346,8 +347,18 @@ void parse_model(nf_ctx* c, const char* text) {
       c->osc.cst[0] = o.at("sin2_t12").at("value").number();
       c->osc.cst[1] = o.at("dm2_21").at("value").number();
     }
-    else fail(NF_EPARSE, "osc.formula must be eq1, 3nu or 4nu");
-    c->osc.fp32_phase = c->mode == NF_M32 ? 1 : 0;
+    else if (f == "3nu_matter") {
+      // exact three flavours in matter of constant density rho Y_e (g/cm^3)
+      c->osc.formula = FORM_MATTER;
+      slots = nu3;
+      const double rho_ye = o.at("rho_ye").number();
+      if (!(rho_ye >= 0.0) || !std::isfinite(rho_ye)) fail(NF_EPARSE, "osc.rho_ye must be a finite number >= 0");
+      c->osc.cst[0] = MATTER_A_PER_MEV * rho_ye;
+    }
+    else fail(NF_EPARSE, "osc.formula must be eq1, 3nu, 4nu or 3nu_matter");
+    // FP32 phases and their frequency correction: vacuum forms only (the
+    // matter form evaluates every event in FP64 in both modes)
+    c->osc.fp32_phase = (c->mode == NF_M32 && c->osc.formula != FORM_MATTER) ? 1 : 0;
     for (int j = 0; j < NSLOT; ++j) {
       const Json& s = o.at(slots[j]);
       if (s.has("param")) {
@@ -875,6 +886,13 @@ void rebuild_events(nf_ctx* c) {
     c->d_epi.upload(epi, c->stream);
   }
   c->d_Wseg.upload(Wseg, c->stream);
+  {
+    std::vector<double> Lseg(std::max(1, c->plan.G), 0.0);
+    for (auto& d : c->ds)
+      for (int s = 0; s < d.S; ++s)
+        for (int k = 0; k < d.K; ++k) Lseg[d.seg0 + s * d.K + k] = d.baselines[s];
+    c->d_Lseg.upload(Lseg, c->stream);
+  }
   c->d_part.alloc((size_t)MAX_MOM * std::max(1, c->nitems));
   {
     // segments with work items per fine bin; fine bins and segments without
@@ -1017,6 +1035,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.zpad = c->zpad;
   fa.theta = theta_dev;
   fa.osc = c->osc;
+  fa.Lseg = c->d_Lseg.p;
   fa.part = sc.part;
   fa.plan = c->plan;
   fa.pre = sc.pre;
@@ -1363,6 +1382,7 @@ BatchFoldArgs batch_fold_args(nf_ctx* c, int B, bool fit) {
   a.B = B;
   a.theta = c->bt_theta.p;
   a.osc = c->osc;
+  a.Lseg = c->d_Lseg.p;
   a.part = c->bt_part.p;
   a.hdr = fit ? c->bf_hdr.p : nullptr;
   a.osc_last = fit ? c->bt_osc_last.p : nullptr;

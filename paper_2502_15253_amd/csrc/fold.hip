@@ -37,6 +37,7 @@
 
 #include "fastmath.hpp"
 #include "kernels.hpp"
+#include "matter.hpp"
 #include "osc.hpp"
 #include "stages.hpp"
 
@@ -561,6 +562,69 @@ __global__ __launch_bounds__(256) void fold_m32_kernel(FoldArgs a) {
   fold_finish<NM>(a, cf, m, item, it.seg, ep, a.fuse.seg_cnt ? item_norm(ep, thv) : 1.0);
 }
 
+// Matter form (both event formats, FP64 arithmetic): no moments; per event P
+// and its four slot derivatives (matter_event), summed per item as five
+// values, with the item records, parameter-pass workgroups and fine-bin
+// epilogue of the vacuum forms (identity coefficient rows). Zero-weight
+// padding events are evaluated at u = 1 and contribute nothing.
+template <typename T>
+__device__ __forceinline__ void matter_accum(T ut, float wf, double aL, const double* v, double* m) {
+  const double w = (double)wf;
+  const double u = wf != 0.0f ? (double)ut : 1.0;
+  double P, dP[NSLOT];
+  matter_event(u, aL, v[0], v[1], v[2], v[3], P, dP);
+  m[0] = fma(w, P, m[0]);
+#pragma unroll
+  for (int j = 0; j < NSLOT; ++j) m[1 + j] = fma(w, dP[j], m[1 + j]);
+}
+// slot values of the matter form: sin^2 th12, sin^2 th13, dm2_21 and dm2_31 in eV^2
+__device__ __forceinline__ void matter_slots(const OscPlan& o, const double* th, double* v) {
+  v[0] = slot_val(o, th, 0);
+  v[1] = slot_val(o, th, 1);
+  v[2] = slot_val(o, th, 2) * UNIT_1EM5;
+  v[3] = slot_val(o, th, 3) * UNIT_1EM3;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fold_matter_kernel(FoldArgs a) {
+  constexpr int NM = 5;
+  __shared__ double cfw[4][CF_SIZE];  // coefficient rows per wavefront (blocks of at most 256 threads)
+  if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
+  if ((int)blockIdx.x < a.npre) {
+    parameter_pass(a, blockIdx.x, &cfw[0][0]);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int item = __builtin_amdgcn_readfirstlane(
+      (int)(((blockIdx.x - (unsigned)a.npre) * (unsigned)blockDim.x + threadIdx.x) >> 6));
+  if (item >= a.nitems) return;  // whole wavefronts leave together
+  double* cf = cfw[threadIdx.x >> 6];
+  ItemEpi ep{};
+  double thv[NLMAX];
+  const WorkItem it = a.items[item];
+  double v[NSLOT];
+  matter_slots(a.osc, a.theta, v);
+  const double aL = a.osc.cst[0] * a.Lseg[it.seg];
+  item_prefetch(a, item, ep, thv);
+  wave_coefficients(a, cf);
+  const T* __restrict__ u = static_cast<const T*>(a.u) + it.begin;
+  const float* __restrict__ w = a.w + it.begin;
+  double m[NM];
+#pragma unroll
+  for (int c = 0; c < NM; ++c) m[c] = 0.0;
+  for (int e = lane * 4; e < it.count; e += 256) {
+    const float4 w4 = *reinterpret_cast<const float4*>(w + e);
+    T u4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u4[q] = u[e + q];
+    matter_accum<T>(u4[0], w4.x, aL, v, m);
+    matter_accum<T>(u4[1], w4.y, aL, v, m);
+    matter_accum<T>(u4[2], w4.z, aL, v, m);
+    matter_accum<T>(u4[3], w4.w, aL, v, m);
+  }
+  fold_finish<NM>(a, cf, m, item, it.seg, ep, a.fuse.seg_cnt ? item_norm(ep, thv) : 1.0);
+}
+
 // ---------------------------------------------------------------- batched
 // One wavefront per (work item, tile of FOLD_FT fits): the events are read
 // once and folded for every active fit of the tile. A fit is skipped when its
@@ -673,6 +737,54 @@ __global__ __launch_bounds__(256) void fold_batch_m32_kernel(BatchFoldArgs a) {
   }
 }
 
+// Matter form, batched: per event and active fit of the tile, P and its slot
+// derivatives (five values per fit).
+template <typename T, int FT>
+__global__ __launch_bounds__(256) void fold_batch_matter_kernel(BatchFoldArgs a) {
+  constexpr int NM = 5;
+  const int lane = threadIdx.x & 63;
+  const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  if (item >= a.nitems) return;
+  const int f0 = blockIdx.y * FT;
+  double v[FT][NSLOT];
+  bool act[FT];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < FT; ++j) {
+    double af[3];
+    act[j] = batch_fit_active<FORM_MATTER>(a, f0 + j, af);
+    if (act[j]) matter_slots(a.osc, a.theta + (int64_t)(f0 + j) * a.P, v[j]);
+    any = any || act[j];
+  }
+  if (!any) return;
+  const WorkItem it = a.items[item];
+  const double aL = a.osc.cst[0] * a.Lseg[it.seg];
+  const T* __restrict__ u = static_cast<const T*>(a.u) + it.begin;
+  const float* __restrict__ w = a.w + it.begin;
+  double m[FT][NM];
+#pragma unroll
+  for (int j = 0; j < FT; ++j)
+#pragma unroll
+    for (int c = 0; c < NM; ++c) m[j][c] = 0.0;
+  for (int e = lane * 4; e < it.count; e += 256) {
+    const float4 w4 = *reinterpret_cast<const float4*>(w + e);
+    T u4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u4[q] = u[e + q];
+#pragma unroll
+    for (int j = 0; j < FT; ++j) {
+      if (!act[j]) continue;
+      matter_accum<T>(u4[0], w4.x, aL, v[j], m[j]);
+      matter_accum<T>(u4[1], w4.y, aL, v[j], m[j]);
+      matter_accum<T>(u4[2], w4.z, aL, v[j], m[j]);
+      matter_accum<T>(u4[3], w4.w, aL, v[j], m[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < FT; ++j)
+    if (act[j]) wave_sum_store<NM>(m[j], a.part + (int64_t)(f0 + j) * NM * a.nitems, a.nitems, item, lane);
+}
+
 // ft: fits per wavefront tile (1, 2, 4 or 8); each tile reads the events once.
 hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t stream, int ft) {
   if (a.nitems <= 0 || a.B <= 0) return hipSuccess;
@@ -680,7 +792,14 @@ hipError_t launch_fold_batch(int mode, const BatchFoldArgs& a, hipStream_t strea
   const dim3 block(256);
   auto go = [&](auto tile) {
     constexpr int T = decltype(tile)::value;
-    if (mode == 0) {
+    if (a.osc.formula == FORM_MATTER) {
+      // at most two fits per wavefront: the per-event work is large and
+      // each fit's registers are many
+      constexpr int TM = T < 2 ? T : 2;
+      const dim3 gm((a.nitems + 3) / 4, (a.B + TM - 1) / TM);
+      if (mode == 0) hipLaunchKernelGGL((fold_batch_matter_kernel<double, TM>), gm, block, 0, stream, a);
+      else hipLaunchKernelGGL((fold_batch_matter_kernel<float, TM>), gm, block, 0, stream, a);
+    } else if (mode == 0) {
       if (a.osc.formula == FORM_EQ1) hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_EQ1, T>), grid, block, 0, stream, a);
       else if (a.osc.formula == FORM_3NU) hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_3NU, T>), grid, block, 0, stream, a);
       else hipLaunchKernelGGL((fold_batch_m64_kernel<FORM_4NU, T>), grid, block, 0, stream, a);
@@ -711,7 +830,10 @@ hipError_t launch_fold(int mode, const FoldArgs& a, int block, hipStream_t strea
     if (start || stop) hipExtLaunchKernelGGL(kernel, grid, dim3(block), 0, stream, start, stop, 0, a);
     else hipLaunchKernelGGL(kernel, grid, dim3(block), 0, stream, a);
   };
-  if (mode == 0) {
+  if (a.osc.formula == FORM_MATTER) {
+    if (mode == 0) go(fold_matter_kernel<double>);
+    else go(fold_matter_kernel<float>);
+  } else if (mode == 0) {
     if (a.osc.formula == FORM_EQ1) go(fold_m64_kernel<FORM_EQ1>);
     else if (a.osc.formula == FORM_3NU) go(fold_m64_kernel<FORM_3NU>);
     else go(fold_m64_kernel<FORM_4NU>);

@@ -81,6 +81,7 @@ struct FoldArgs {
   DevPlan plan;
   double* pre;
   int npre;
+  const double* Lseg;   // G: baseline of each segment's source (m; the matter form)
 };
 
 // Batched fold: a tile of FT fits per wavefront (FT = 1, 2, 4 or 8, a launch
@@ -94,6 +95,7 @@ struct BatchFoldArgs {
   int P, B;
   const double* theta;     // [B][P] trial points
   OscPlan osc;
+  const double* Lseg;      // G: baseline of each segment's source (m; the matter form)
   double* part;            // [B][NM][nitems]
   const FitHeader* hdr;    // [B] nullable: fits that are not RUNNING are skipped
   const double* osc_last;  // [B][4] nullable: fits whose slot values equal these are skipped

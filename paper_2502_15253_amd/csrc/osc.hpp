@@ -145,6 +145,14 @@ __device__ inline bool osc_domain_ok(const OscPlan& o, const double* th) {
     ok = ok && isfinite(v);
     if (j == 0 && o.formula == FORM_EQ1) ok = ok && v < 1.0;
     if (j == 2 && o.formula == FORM_4NU) ok = ok && v < 1.0;
+    if (o.formula == FORM_MATTER) {
+      // mixing in [0, 1] (theta13 below pi/2), dm2_21 > 0 and dm2_31 != 0:
+      // three distinct eigenvalues in matter
+      if (j == 0) ok = ok && v >= 0.0 && v <= 1.0;
+      if (j == 1) ok = ok && v >= 0.0 && v < 1.0;
+      if (j == 2) ok = ok && v > 0.0;
+      if (j == 3) ok = ok && v != 0.0;
+    }
   }
   return ok;
 }
@@ -173,7 +181,8 @@ __device__ __forceinline__ void osc_freqs_form(const OscPlan& o, const double* t
 __device__ __forceinline__ void osc_freqs(const OscPlan& o, const double* th, double* a) {
   if (o.formula == FORM_EQ1) osc_freqs_form<FORM_EQ1>(o, th, a);
   else if (o.formula == FORM_3NU) osc_freqs_form<FORM_3NU>(o, th, a);
-  else osc_freqs_form<FORM_4NU>(o, th, a);
+  else if (o.formula == FORM_4NU) osc_freqs_form<FORM_4NU>(o, th, a);
+  // the matter form has no fixed frequencies
 }
 
 // FP32 frequency in revolutions per (m/MeV) used by the M32 fold: the phase
@@ -211,7 +220,7 @@ __device__ __forceinline__ void fp32_correction_form(const OscPlan& o, const dou
 __device__ inline void fp32_frequency_correction(const OscPlan& o, const double* th, double* cf) {
   if (o.formula == FORM_EQ1) fp32_correction_form<FORM_EQ1>(o, th, cf);
   else if (o.formula == FORM_3NU) fp32_correction_form<FORM_3NU>(o, th, cf);
-  else fp32_correction_form<FORM_4NU>(o, th, cf);
+  else if (o.formula == FORM_4NU) fp32_correction_form<FORM_4NU>(o, th, cf);
 }
 
 __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, double* cf) {
@@ -269,6 +278,10 @@ __device__ inline bool osc_coefficients(const OscPlan& o, const double* th, doub
     r3[4] = -0.5 * K21 * a21; r3[6] = 0.5 * K32 * a21;
     // d/d dm2_31
     r4[5] = -0.5 * K31 * a31; r4[6] = -0.5 * K32 * a31;
+  } else if (o.formula == FORM_MATTER) {
+    // the fold sums S and its slot derivatives per event (moments 1..5)
+    for (int r = 0; r < 5; ++r) cf[CF_STRIDE * r + 1 + r] = 1.0;
+    return ok && osc_domain_ok(o, th);
   } else {
     // 3+1: |U_e1..4|^2 = c12 c13 c14, s12 c13 c14, s13 c14, s14 (squared sines
     // and cosines), P = 1 - sum_{i<j} K_ij sin^2(x_ji / 2), K_ij = 4 |U_ei|^2 |U_ej|^2.

@@ -11,6 +11,7 @@ namespace nufold {
 constexpr int FORM_EQ1 = 0;  // Eq. 1: slots sin2_2t13, dm2_ee, sin2_t12, dm2_21
 constexpr int FORM_3NU = 1;  // exact vacuum 3-flavour: sin2_t12, sin2_t13, dm2_21, dm2_31
 constexpr int FORM_4NU = 2;  // vacuum 3+1: sin2_t13, dm2_31, sin2_2t14, dm2_41 (sin2_t12, dm2_21 constants)
+constexpr int FORM_MATTER = 3;  // exact 3-flavour in matter of constant density: the 3nu slots (rho Y_e constant)
 constexpr int NSLOT = 4;
 constexpr int MAX_MOM = 12;  // per-segment moments produced by the fold
 constexpr int MAX_SOURCES = 64;
@@ -26,8 +27,22 @@ constexpr double TWO_PHASE_K = 2.0 * 1.266932679039099;
 constexpr double UNIT_1EM3 = 1e-3;
 constexpr double UNIT_1EM5 = 1e-5;
 
+// Matter potential of electron antineutrinos: A = 2 sqrt(2) G_F N_e E in
+// eV^2 is MATTER_A_PER_MEV rho Y_e E[MeV] for a density rho in g/cm^3 with
+// Y_e electrons per nucleon (N_e = rho Y_e N_A per cm^3, one gram per mole of
+// nucleons), from G_F = 1.1663787e-5 GeV^-2, hbar c = 1.973269804593025e-14
+// GeV cm (exact SI-2019 value) and N_A = 6.02214076e23 / mol:
+//   sqrt(2) G_F (hbar c)^3 N_A = 7.6325e-14 eV per g/cm^3, times 2 E = 2e6 eV per MeV.
+constexpr double MATTER_GF = 1.1663787e-5;
+constexpr double MATTER_HBARC_CM = 1.973269804593025e-14;
+constexpr double MATTER_NA = 6.02214076e23;
+constexpr double MATTER_A_PER_MEV = 2.0e6 * 1.4142135623730950488 * MATTER_GF * MATTER_HBARC_CM * MATTER_HBARC_CM *
+                                    MATTER_HBARC_CM * MATTER_NA * 1e9;
+
+// moments the fold produces per segment (the matter form: S and its four slot
+// derivatives directly)
 __host__ __device__ inline int num_moments(int formula) {
-  return formula == FORM_EQ1 ? 4 : formula == FORM_3NU ? 6 : 12;
+  return formula == FORM_EQ1 ? 4 : formula == FORM_3NU ? 6 : formula == FORM_MATTER ? 5 : 12;
 }
 
 struct OscPlan {
@@ -37,7 +52,8 @@ struct OscPlan {
                            // coefficient rows then carry the first-order frequency correction
   int pad_;
   double slot_value[NSLOT];
-  double cst[2];           // FORM_4NU: the fixed sin2_t12 and dm2_21 (1e-5 eV^2)
+  double cst[2];           // FORM_4NU: the fixed sin2_t12 and dm2_21 (1e-5 eV^2);
+                           // FORM_MATTER: cst[0] = MATTER_A_PER_MEV rho Y_e
 };
 
 // A contiguous run of sorted events that all belong to one segment

@@ -316,6 +316,15 @@ def config3_model():
         params=params, cov_priors=[], datasets=[ds])
 
 
+def config3_matter_model(rho_ye=1.3):
+    """The medium-baseline model with the exact three-flavour probability in
+    matter of constant density (crust: rho about 2.6 g/cm^3, Y_e about 0.5)."""
+    m = config3_model()
+    m["osc"]["formula"] = "3nu_matter"
+    m["osc"]["rho_ye"] = float(rho_ye)
+    return m
+
+
 def config3_events(n=10_000_000):
     return [make_events(n, 1.8, 12.0, 10, 1.0e5, event_seed(3, 0), "c3")]
 
@@ -502,6 +511,8 @@ def model_and_events(config, n_events=None):
         return config2_model(), config2_events(*(() if n_events is None else (n_events,)))
     if config == 3:
         return config3_model(), config3_events(*(() if n_events is None else (n_events,)))
+    if config == "c3_matter":
+        return config3_matter_model(), config3_events(*(() if n_events is None else (n_events,)))
     if config == "sterile":
         return sterile_model(), sterile_events(*(() if n_events is None else (n_events,)))
     if config == "split":
@@ -578,6 +589,11 @@ def tiny_model(seed, formula="eq1", n_datasets=2, n_sources=2, fine_n=12, nb=8,
         osc = dict(formula="3nu", sin2_t12=dict(param="osc.sin2_t12"),
                    sin2_t13=dict(param="osc.sin2_t13"), dm2_21=dict(param="osc.dm2_21"),
                    dm2_31=dict(param="osc.dm2_31"))
+        if formula == "3nu_matter":
+            # a density far above the Earth's, so that matter changes P at
+            # these short baselines (A comparable to dm2_31 at a few MeV)
+            osc["formula"] = "3nu_matter"
+            osc["rho_ye"] = float(rng.uniform(800.0, 2500.0))
     params += [param(f"src{s}.norm", 1.0 + 0.01 * rng.uniform(-1, 1), (1.0, 0.02))
                for s in range(n_sources)]
     cov_priors = []

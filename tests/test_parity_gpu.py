@@ -103,7 +103,7 @@ def displaced(desc, seed, scale=0.3):
 
 
 @pytest.mark.parametrize("mode", ["m64", "m32"])
-@pytest.mark.parametrize("formula", ["eq1", "3nu", "4nu"])
+@pytest.mark.parametrize("formula", ["eq1", "3nu", "4nu", "3nu_matter"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("deterministic", [0, 1])
 def test_tiny_models(mode, formula, seed, deterministic):
