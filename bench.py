@@ -477,6 +477,44 @@ def sterile_raster_section(nf, synth, torch, stream, n_pe=100):
     return res
 
 
+def matter_section(nf, synth, torch, stream, events, thetas, steps=200):
+    """The medium-baseline workload with the exact three-flavour probability in
+    matter of constant density (rho Y_e = 1.3 g/cm^3) on the same 1e7 events, M64:
+    evaluations per second (graph replays of consecutive evaluations, as the
+    headline) and the fold and bin-stage durations (HIP events on each
+    dispatch). The matter fold evaluates the eigen-system per event in FP64,
+    so it is bound by FP64 arithmetic, not by HBM."""
+    desc = synth.config3_matter_model()
+    eng = nf.Engine(desc, "m64", stream=stream.cuda_stream)
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+    n_in = sum(len(ev["weight"]) for ev in events) - sum(eng.dropped(d) for d in range(eng.D))
+    start = synth.start_vector(desc)
+    for d, mu in enumerate(eng.expected(start)[0]):
+        eng.set_data(d, mu)
+    th_dev = torch.tensor(thetas, dtype=torch.float64, device="cuda")
+    out_dev = torch.zeros((len(thetas), 1 + eng.P), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    n_graph = max(d for d in range(1, 65) if steps % d == 0)
+    eng.eval_device_many(n_graph, th_dev.data_ptr(), out_dev.data_ptr())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // n_graph):
+        eng.eval_device_many(n_graph, th_dev.data_ptr(), out_dev.data_ptr())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cnt, fold_ms, tail_ms, _ = event_timed(
+        torch, eng, lambda k: eng.eval_device(th_dev[k % 64].data_ptr(), out_dev[k % 64].data_ptr()), steps)
+    assert cnt == steps and bool(torch.isfinite(out_dev).all())
+    eng.close()
+    fold_us = fold_ms / cnt * 1e3
+    res = dict(model="medium baseline, exact 3 flavours in matter, rho Y_e = 1.3 g/cm^3", mode="m64",
+               events_in_range=n_in, evals_per_s=steps / (t1 - t0), ms_per_step=(t1 - t0) * 1e3 / steps,
+               fold_us=fold_us, tail_us=tail_ms / cnt * 1e3, events_per_s_fold=n_in / (fold_us * 1e-6))
+    log(f"matter: {json.dumps(res)}")
+    return res
+
+
 def warm_start_section(nf, synth, torch, stream, n_samples, E=256, n_plain=16):
     """Medium-baseline pseudo-experiments at random points of the training box:
     exact batched fits from the box centre (cold) and from the surrogate's
@@ -644,6 +682,7 @@ def main():
     ap.add_argument("--plain-fits", type=int, default=64, help="fits of the plain per-fit GPU path")
     ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
                     help="training spectra for the warm-start section (0 skips it)")
+    ap.add_argument("--no-matter", action="store_true", help="skip the constant-density matter section")
     ap.add_argument("--mlp-profile", action="store_true",
                     help="surrogate-network training steps only (for a kernel trace per product shape)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -864,6 +903,7 @@ def main():
     fits = None
     if not args.no_fits:
         fits = fits_section(nf, synth, torch, stream, args.plain_fits, args.surrogate_samples)
+    matter = None if args.no_matter else matter_section(nf, synth, torch, stream, events, thetas)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (whole evaluations, about ten seconds)")
@@ -906,6 +946,8 @@ def main():
     }
     if other is not None:
         line["other_mode"] = {"mode": "m64" if args.mode == "m32" else "m32", **other}
+    if matter is not None:
+        line["matter"] = matter
     print(json.dumps(line), flush=True)
 
 
