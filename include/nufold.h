@@ -439,6 +439,13 @@ int nf_mlp_grad(nf_mlp* net, int B, const float* x, const float* dy, float* grad
  * loss NULL the step is only enqueued on the network's stream. */
 int nf_mlp_train_step(nf_mlp* net, int B, const float* x, const float* t, float lr, float* loss, int on_device);
 
+/* Training steps as replays of one captured HIP graph per batch size (on,
+ * the default) or as separate launches (on = 0). Both run the same kernels on
+ * the same buffers and give bit-identical results; the graph saves the
+ * launch overhead of the step's ~40 kernels. Changing B re-captures.
+ * Returns NF_OK or NF_EINVAL (null net). */
+int nf_mlp_use_graphs(nf_mlp* net, int on);
+
 /* Warm start: for each of B rows, minimise over the inputs x the surrogate
  * Poisson deviance  sum_j [mu_j - n_j + n_j ln(n_j / mu_j)],
  * mu_j = exp(y_j out_std_j + out_mean_j), plus the Gaussian input prior

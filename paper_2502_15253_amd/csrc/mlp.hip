@@ -70,13 +70,15 @@ struct GemmArgs {
   const float* Zin;    // DGELU: pre-activation of the layer below, [M][ldc]
 };
 
-constexpr int TK = 32, LDK = TK + 8;  // LDS row pitch (bf16) padded against bank conflicts
+constexpr int TK = 32;  // contraction of one MFMA (and the granularity of K slices)
 
-// One operand tile (ROWS x TK, k contiguous in memory) into registers; rows
-// >= R and k >= K read as zero.
-template <int ROWS>
+// One operand tile (ROWS x KT, k contiguous in memory) into registers; rows
+// >= R and k >= K read as zero. LDS rows are padded by 8 bf16 against bank
+// conflicts.
+template <int ROWS, int KT>
 struct TileRegs {
-  static constexpr int NV = ROWS * TK / 8 / 256;  // 16-byte vectors per thread
+  static constexpr int LDK = KT + 8;
+  static constexpr int NV = ROWS * KT / 8 / 256;  // 16-byte vectors per thread
   bf16x8 v[NV];
 
   __device__ void load(const uint16_t* __restrict__ src, int ld, int r0, int R, int k0, int K, int tid) {
@@ -84,7 +86,7 @@ struct TileRegs {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int e = tid + 256 * j;
-      const int r = e / (TK / 8), k = (e % (TK / 8)) * 8;
+      const int r = e / (KT / 8), k = (e % (KT / 8)) * 8;
       const int gr = r0 + r, gk = k0 + k;
       if (vec_ok && gr < R && gk + 8 <= K) {
         v[j] = *reinterpret_cast<const bf16x8*>(src + (int64_t)gr * ld + gk);
@@ -101,14 +103,18 @@ struct TileRegs {
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int e = tid + 256 * j;
-      *reinterpret_cast<bf16x8*>(&lds[e / (TK / 8)][(e % (TK / 8)) * 8]) = v[j];
+      *reinterpret_cast<bf16x8*>(&lds[e / (KT / 8)][(e % (KT / 8)) * 8]) = v[j];
     }
   }
 };
 
-template <int BM, int BN, int EPI>
+// C tile BM x BN per workgroup of four waves (2 x 2 wave tiles), K in steps
+// of KT: the next step's operands are loaded into registers while this
+// step's KT/32 MFMA chunks run from LDS (double-buffered).
+template <int BM, int BN, int EPI, int KT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int FM = BM / 32, FN = BN / 32;
+  constexpr int LDK = KT + 8;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -121,9 +127,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  TileRegs<BM> ra;
-  TileRegs<BN> rb;
-  const int nk = ke > kb ? (ke - kb + TK - 1) / TK : 0;
+  TileRegs<BM, KT> ra;
+  TileRegs<BN, KT> rb;
+  const int nk = ke > kb ? (ke - kb + KT - 1) / KT : 0;
   if (nk > 0) {
     ra.load(g.A, g.lda, m0, g.M, kb, ke, tid);
     rb.load(g.B, g.ldb, n0, g.N, kb, ke, tid);
@@ -135,18 +141,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      ra.load(g.A, g.lda, m0, g.M, kb + (kt + 1) * TK, ke, tid);
-      rb.load(g.B, g.ldb, n0, g.N, kb + (kt + 1) * TK, ke, tid);
+      ra.load(g.A, g.lda, m0, g.M, kb + (kt + 1) * KT, ke, tid);
+      rb.load(g.B, g.ldb, n0, g.N, kb + (kt + 1) * KT, ke, tid);
     }
-    bf16x8 af[FM], bfr[FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + i * 16 + r][kq]);
+    for (int kc = 0; kc < KT; kc += TK) {
+      bf16x8 af[FM], bfr[FN];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + j * 16 + r][kq]);
+      for (int i = 0; i < FM; ++i) af[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + i * 16 + r][kc + kq]);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int j = 0; j < FN; ++j) bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + j * 16 + r][kc + kq]);
 #pragma unroll
-      for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
     if (kt + 1 < nk) {
       ra.store(As[cur ^ 1], tid);
       rb.store(Bs[cur ^ 1], tid);
@@ -212,10 +222,12 @@ hipError_t gemm(GemmArgs g, hipStream_t s, int splits = 1, int* slices = nullptr
   const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128) * z;
   if (t128 >= 512) {
     const dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, z);
-    hipLaunchKernelGGL((gemm_kernel<128, 128, EPI>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<128, 128, EPI, 32>), grid, dim3(256), 0, s, g);
   } else {
+    // 64 x 64 tiles take K in steps of 64 (half the global round trips of
+    // steps of 32; 36 KB of LDS)
     const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, z);
-    hipLaunchKernelGGL((gemm_kernel<64, 64, EPI>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<64, 64, EPI, 64>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }
@@ -315,10 +327,21 @@ __global__ void mse_kernel(const float* y, const float* t, int B, int N, float s
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
-                            float eps, float c1, float c2) {
+// Adam on the master weights; the step's learning rate and bias corrections
+// come from device memory (sc = {lr, 1 - b1^t, 1 - b2^t}), so that a captured
+// training step replays with each step's values.
+__global__ void set_scalars_kernel(float* sc, float lr, float c1, float c2) {
+  if (threadIdx.x == 0) {
+    sc[0] = lr;
+    sc[1] = c1;
+    sc[2] = c2;
+  }
+}
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, const float* sc, float b1,
+                            float b2, float eps) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const float lr = sc[0], c1 = sc[1], c2 = sc[2];
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.f - b1) * gi;
   const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -417,15 +440,22 @@ struct nf_mlp {
   float* partial = nullptr;           // loss partials
   float* csum = nullptr;              // column-sum partials
   float* kpart = nullptr;             // weight-gradient slices, MAX_SPLITS x maxdw
+  float* scal = nullptr;              // learning rate and Adam bias corrections of the current step
   int adam_t = 0;
+  // one training step of batch graph_B captured as a HIP graph (inputs and
+  // step scalars are written before each replay)
+  bool use_graph = true;
+  int graph_B = 0;
+  hipGraphExec_t step_graph = nullptr;
   ~nf_mlp() {
     for (void* p : {(void*)w, (void*)g, (void*)am, (void*)av, (void*)wb, (void*)wbt, (void*)xf, (void*)xb,
                     (void*)xt, (void*)Y, (void*)T, (void*)dYf, (void*)dZf, (void*)dYb, (void*)dZb, (void*)dYt,
-                    (void*)dZt, (void*)dX, (void*)partial, (void*)csum, (void*)kpart})
+                    (void*)dZt, (void*)dX, (void*)partial, (void*)csum, (void*)kpart, (void*)scal})
       if (p) (void)hipFree(p);
     for (auto* p : Z) (void)hipFree(p);
     for (auto* p : H) (void)hipFree(p);
     for (auto* p : HT) (void)hipFree(p);
+    if (step_graph) (void)hipGraphExecDestroy(step_graph);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -466,9 +496,12 @@ void prep_input(nf_mlp* n, int B) {
                      n->kin, n->xb, n->xt);
 }
 
-void upload_x(nf_mlp* n, int B, const float* x, int on_device) {
+void copy_x(nf_mlp* n, int B, const float* x, int on_device) {
   mck(hipMemcpyAsync(n->xf, x, sizeof(float) * B * n->n_in, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                      n->stream), "x copy");
+}
+void upload_x(nf_mlp* n, int B, const float* x, int on_device) {
+  copy_x(n, B, x, on_device);
   prep_input(n, B);
 }
 
@@ -617,6 +650,7 @@ int nf_mlp_create(nf_mlp** out, int n_in, int width, int depth, int n_out, int m
     n->partial = dalloc<float>((B * n_out + 255) / 256 + 1);
     n->csum = dalloc<float>(((B + CS_ROWS - 1) / CS_ROWS) * wmax);
     n->kpart = dalloc<float>((size_t)MAX_SPLITS * n->maxdw);
+    n->scal = dalloc<float>(4);
     mck(hipMemsetAsync(n->w, 0, sizeof(float) * off, n->stream), "memset");
     mck(hipMemsetAsync(n->am, 0, sizeof(float) * off, n->stream), "memset");
     mck(hipMemsetAsync(n->av, 0, sizeof(float) * off, n->stream), "memset");
@@ -697,21 +731,54 @@ int nf_mlp_grad(nf_mlp* n, int B, const float* x, const float* dy, float* grad, 
 int nf_mlp_train_step(nf_mlp* n, int B, const float* x, const float* t, float lr, float* loss, int on_device) {
   return mguard(n, [&] {
     if (B < 1 || B > n->max_batch || !x || !t || !(lr > 0.f)) throw MlpError(NF_EINVAL, "bad arguments");
-    upload_x(n, B, x, on_device);
     const int64_t cnt = (int64_t)B * n->n_out;
+    const int nb = (int)((cnt + 255) / 256);
+    // inputs and the step's scalars, then the step itself: input conversion,
+    // forward, loss and its gradient, backward, Adam, bf16 refresh -- as
+    // launches, or as one replay of the step captured for this batch size
+    copy_x(n, B, x, on_device);
     mck(hipMemcpyAsync(n->T, t, sizeof(float) * cnt, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                        n->stream), "t copy");
-    forward(n, B, true);
-    const int nb = (int)((cnt + 255) / 256);
-    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, n->stream, n->Y, n->T, B, n->n_out, 1.0f / (float)cnt,
-                       n->dYf, n->dYb, n->dYt, n->partial);
-    backward(n, B, false, true);
     n->adam_t += 1;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
-    hipLaunchKernelGGL(adam_kernel, blocks(n->nparam), dim3(256), 0, n->stream, n->w, n->g, n->am, n->av, n->nparam,
-                       lr, b1, b2, 1e-8f, c1, c2);
-    refresh_bf16(n);
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, n->stream, n->scal, lr, c1, c2);
+    auto body = [&] {
+      prep_input(n, B);
+      forward(n, B, true);
+      hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, n->stream, n->Y, n->T, B, n->n_out,
+                         1.0f / (float)cnt, n->dYf, n->dYb, n->dYt, n->partial);
+      backward(n, B, false, true);
+      hipLaunchKernelGGL(adam_kernel, blocks(n->nparam), dim3(256), 0, n->stream, n->w, n->g, n->am, n->av,
+                         n->nparam, (const float*)n->scal, b1, b2, 1e-8f);
+      refresh_bf16(n);
+    };
+    if (!n->use_graph) {
+      body();
+    } else {
+      if (n->step_graph && n->graph_B != B) {
+        (void)hipGraphExecDestroy(n->step_graph);
+        n->step_graph = nullptr;
+      }
+      if (!n->step_graph) {
+        mck(hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+          body();
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(n->stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        hipGraph_t g = nullptr;
+        mck(hipStreamEndCapture(n->stream, &g), "hipStreamEndCapture");
+        const hipError_t e = hipGraphInstantiate(&n->step_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        mck(e, "hipGraphInstantiate");
+        n->graph_B = B;
+      }
+      mck(hipGraphLaunch(n->step_graph, n->stream), "hipGraphLaunch");
+    }
     if (loss) {
       std::vector<float> part(nb);
       mck(hipMemcpyAsync(part.data(), n->partial, sizeof(float) * nb, hipMemcpyDeviceToHost, n->stream), "D2H");
@@ -721,6 +788,19 @@ int nf_mlp_train_step(nf_mlp* n, int B, const float* x, const float* t, float lr
       *loss = (float)(s / (double)cnt);
     } else if (!on_device) {
       mck(hipStreamSynchronize(n->stream), "sync");
+    }
+    return NF_OK;
+  });
+}
+
+int nf_mlp_use_graphs(nf_mlp* n, int on) {
+  return mguard(n, [&] {
+    n->use_graph = on != 0;
+    if (!n->use_graph && n->step_graph) {
+      mck(hipStreamSynchronize(n->stream), "sync");
+      (void)hipGraphExecDestroy(n->step_graph);
+      n->step_graph = nullptr;
+      n->graph_B = 0;
     }
     return NF_OK;
   });

@@ -95,6 +95,7 @@ SIGNATURES["nf_mlp_grad"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void
                                        C.c_int])
 SIGNATURES["nf_mlp_train_step"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_float,
                                              C.POINTER(C.c_float), C.c_int])
+SIGNATURES["nf_mlp_use_graphs"] = (C.c_int, [C.c_void_p, C.c_int])
 SIGNATURES["nf_mlp_fit_inputs"] = (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                              C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.c_void_p])
 
@@ -453,6 +454,10 @@ class Mlp:
         self._check(load().nf_mlp_grad(self.h, x.shape[0], x.ctypes.data, dy.ctypes.data, g.ctypes.data,
                                        dx.ctypes.data if want_dx else None, 0))
         return g, dx
+
+    def use_graphs(self, on=True):
+        """Training steps as replays of a captured graph (default) or as launches."""
+        self._check(load().nf_mlp_use_graphs(self.h, 1 if on else 0))
 
     def train_step(self, x, t, lr, want_loss=True):
         """Host arrays, or device tensors (torch, float32, contiguous). Without

@@ -161,3 +161,36 @@ def test_mlp_argument_errors():
     assert ei.value.code == nf.NF_EINVAL
     with pytest.raises(nf.NufoldError):
         net.train_step(np.zeros((2, 4), np.float32), np.zeros((2, 3), np.float32), -1.0)
+
+
+def test_train_step_graph_replays_match_launches():
+    """The captured training step (replayed with each step's inputs, learning
+    rate and bias corrections, other work and synchronisations in between)
+    gives the same weights, bit for bit, as the same steps launched one kernel
+    at a time; a change of batch size re-captures."""
+    import torch
+    say("mlp train step graph")
+    rng = np.random.default_rng(9)
+    n_in, width, depth, n_out = 20, 128, 3, 40
+    shapes = O.layer_dims(n_in, width, depth, n_out)
+    w = init(shapes, rng).astype(np.float32)
+    nets = []
+    for graphs in (False, True):
+        net = nf.Mlp(n_in, width, depth, n_out, max_batch=512)
+        net.set_params(w)
+        net.use_graphs(graphs)
+        nets.append(net)
+    for step in range(8):
+        B = 256 if step < 5 else 384
+        x = torch.from_numpy(rng.uniform(-1, 1, (B, n_in)).astype(np.float32)).cuda()
+        t = torch.from_numpy(rng.standard_normal((B, n_out)).astype(np.float32)).cuda()
+        lr = 1e-3 * (1.0 + 0.1 * step)
+        losses = [net.train_step(x, t, lr, want_loss=True) for net in nets]
+        # unrelated eager work between the replays
+        _ = [net.forward(rng.uniform(-1, 1, (7, n_in)).astype(np.float32)) for net in nets]
+        torch.cuda.synchronize()
+        p0, p1 = nets[0].get_params(), nets[1].get_params()
+        assert losses[0] == losses[1], (step, losses)
+        assert np.array_equal(p0, p1), (step, float(np.max(np.abs(p0 - p1))))
+    for net in nets:
+        net.close()
