@@ -41,7 +41,8 @@ def log(*a):
 
 def fold_source_hash():
     h = hashlib.sha256()
-    for f in ("fold.hip", "fastmath.hpp", "sincos_coeffs.hpp", "osc.hpp", "kernels.hpp", "plan.hpp"):
+    for f in ("fold.hip", "fastmath.hpp", "sincos_coeffs.hpp", "osc.hpp", "kernels.hpp", "plan.hpp", "matter.hpp",
+              "stages.hpp"):
         with open(os.path.join(ROOT, "paper_2502_15253_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

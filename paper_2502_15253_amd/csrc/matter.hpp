@@ -50,21 +50,22 @@ __device__ __forceinline__ void matter_event(double u, double aL, double s12, do
   const double p = fma(-a, a3, b);
   const double q = fma(a3 * a3, 2.0 * a3, fma(-a3, b, c));
   const double rr = 2.0 * sqrt(-p * THIRD);
-  double x = (1.5 * q / p) * sqrt(-3.0 / p);
+  double x = 3.0 * q / (p * rr);  // (3q / 2p) sqrt(-3/p), as sqrt(-3/p) = 2 / rr
   x = fmin(1.0, fmax(-1.0, x));
   double sp, cp;
   sincos_fold(acos(x) * THIRD, sp, cp);
   double l[3] = {fma(rr, cp, -a3), fma(rr, fma(-0.5, cp, HALF_SQRT3 * sp), -a3),
                  fma(rr, fma(-0.5, cp, -HALF_SQRT3 * sp), -a3)};
   double rp[3], X[3];
+  // Newton step; 1/P' is taken before the step (the root moves by far less
+  // than the roots' separation, so 1/P' changes in its last bits only)
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     double y = l[k];
     const double f = fma(fma(y + a, y, b), y, c);
-    const double d = fma(fma(3.0, y, 2.0 * a), y, b);
-    y -= f / d;
-    l[k] = y;
     rp[k] = 1.0 / fma(fma(3.0, y, 2.0 * a), y, b);
+    y = fma(-f, rp[k], y);
+    l[k] = y;
     X[k] = fma(y + q1, y, q0) * rp[k];
   }
   // pairs 01, 02, 12: sin^2 of the phase and sin of twice the phase

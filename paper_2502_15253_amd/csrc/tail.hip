@@ -644,12 +644,15 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
       const int* mdk = reinterpret_cast<const int*>(L.st + BL.mdk);
       const double* mdc = L.st + BL.mdc;
       const int* mdp = reinterpret_cast<const int*>(L.st + BL.mdp);
-      for (int m = tid; m < M; m += NT) {
+      // four lanes (a quad) per mode, each taking blocks of four entries in
+      // turn: the index and coefficient reads of a block, then its lambda_F
+      // reads, are independent (two LDS round trips per sixteen entries);
+      // the quad's sums are combined in a fixed order
+      const int lq = tid & 3;
+      for (int m = tid >> 2; m < M; m += NT / 4) {
         double gm = 0.0;
         const int e0 = mdcol[m], e1 = mdcol[m + 1];
-        // four entries per step: their index and coefficient reads, then
-        // their lambda_F reads, are independent (two LDS round trips per step)
-        for (int e = e0; e < e1; e += 4) {
+        for (int e = e0 + 4 * lq; e < e1; e += 16) {
           int kq[4];
           double cq[4];
 #pragma unroll
@@ -661,7 +664,9 @@ __device__ double serial_stages(const DevPlan& p, const EvalIO& io, Lds<NT>& L, 
 #pragma unroll
           for (int q = 0; q < 4; ++q) gm += L.LF[kq[q]] * cq[q];
         }
-        atomicAdd(&L.grad[mdp[m]], gm);
+        gm += dpp_swap<0xB1>(gm);  // quad_perm [1,0,3,2]
+        gm += dpp_swap<0x4E>(gm);  // quad_perm [2,3,0,1]
+        if (lq == 0) atomicAdd(&L.grad[mdp[m]], gm);
       }
     }
     if (d == 0)
