@@ -472,7 +472,7 @@ def sterile_raster_section(nf, synth, torch, stream, n_pe=100):
     eng.close()
     res = dict(points=len(s_values) * len(m_values), pseudo_experiments_per_point=n_pe, fits=r["fits"],
                seconds=r["seconds"], fit_seconds=r["fit_seconds"], fits_per_s=r["fits"] / r["fit_seconds"],
-               converged=r["converged"], excluded_points=int(r["excluded"].sum()),
+               fit_results=r["results"], converged=r["converged"], excluded_points=int(r["excluded"].sum()),
                dm2_41_range_ev2=[float(m_values[0]) * 1e-3, float(m_values[-1]) * 1e-3])
     log(f"sterile raster: {json.dumps(res)}")
     return res

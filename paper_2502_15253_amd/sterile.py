@@ -54,6 +54,20 @@ class RasterScan:
         self.nfits += len(starts)
         return r
 
+    def _free_fit(self, starts, data_idx):
+        """Fits with sin^2(2 theta14) free, each run twice: the second from
+        the first's result with a fresh minimiser history, so that a fit that
+        stopped on a flat direction of the first history continues (its lower
+        NLL is kept)."""
+        a = self._fit(starts, False, data_idx)
+        b = self._fit(a["theta"], False, data_idx)
+        take = b["nll"] < a["nll"]
+        out = dict(a)
+        out["nll"] = np.where(take, b["nll"], a["nll"])
+        out["theta"] = np.where(take[:, None], b["theta"], a["theta"])
+        out["status"] = np.where(take, b["status"], a["status"])
+        return out
+
     def _points(self, s_values, m_values, base=None):
         S, M = len(s_values), len(m_values)
         th = np.tile(self.start if base is None else base, (S * M, 1))
@@ -77,7 +91,7 @@ class RasterScan:
         best_s = np.argmin(nll0, axis=1)  # R x M
         th_c = cond["theta"].reshape(R, S, M, -1)
         fst = th_c[np.arange(R)[:, None], best_s, np.arange(M)[None, :]].reshape(R * M, -1)
-        free = self._fit(fst, False, np.repeat(np.arange(R), M))
+        free = self._free_fit(fst, np.repeat(np.arange(R), M))
         nll1 = np.minimum(free["nll"].reshape(R, M), nll0.min(axis=1))
         t = 2.0 * (nll0 - nll1[:, None, :])
         return np.maximum(t, 0.0), th_c, cond["status"].reshape(R, S, M), free["status"].reshape(R, M)
@@ -95,7 +109,7 @@ class RasterScan:
         st = np.repeat(theta_points, n_pe, axis=0)
         didx = np.arange(K * n_pe)
         cond = self._fit(st, True, didx)
-        free = self._fit(cond["theta"], False, didx)
+        free = self._free_fit(cond["theta"], didx)
         t = 2.0 * (cond["nll"] - np.minimum(free["nll"], cond["nll"]))
         return np.maximum(t, 0.0).reshape(K, n_pe), cond["status"], free["status"]
 
@@ -109,6 +123,9 @@ class RasterScan:
         t_pe, s_c, s_f = self.ensemble(th_c.reshape(S * M, -1), n_pe, seed)
         crit = np.quantile(t_pe, cl, axis=1).reshape(S, M)
         wall = time.perf_counter() - t0
+        # fits: device fits run (the free fits' second passes included);
+        # results: the fits behind the statistics, converged: those with status 0
         return dict(t_obs=t_obs[0], t_crit=crit, excluded=t_obs[0] > crit, t_pe=t_pe.reshape(S, M, n_pe),
                     fits=self.nfits, fit_seconds=self.fit_seconds, seconds=wall,
+                    results=int(st0.size + st1.size + s_c.size + s_f.size),
                     converged=int(np.sum(st0 == 0) + np.sum(st1 == 0) + np.sum(s_c == 0) + np.sum(s_f == 0)))

@@ -28,6 +28,9 @@ def setup(n_events, mode="m64"):
     mus, _ = LK.expected(m, events, truth)
     data = synth.poisson_data(mus, synth.data_seed(7))
     eng = nf.Engine(desc, mode)
+    # bit-reproducible sums (the fits' paths, and so which of two nearby
+    # minima a fit stops in, then repeat from run to run)
+    eng.set_option("deterministic", 1)
     for d, ev in enumerate(events):
         eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
     return desc, events, m, data, eng
@@ -67,7 +70,7 @@ def test_raster_ensembles_and_exclusion():
     res = rs.run(np.concatenate(data), s_values, m_values, n_pe=48, cl=0.9, seed=3)
     print(f"[raster] t_obs {res['t_obs'].tolist()} t_crit {res['t_crit'].tolist()} "
           f"fits {res['fits']} in {res['fit_seconds']:.2f} s", flush=True)
-    assert res["converged"] >= 0.98 * res["fits"]
+    assert res["converged"] >= 0.98 * res["results"]
     assert np.all(res["t_pe"] >= 0.0) and np.all(np.isfinite(res["t_pe"]))
     # data drawn without sterile mixing: at the true point (s = 0) the observed
     # statistic is an ordinary member of its ensemble (below the ensemble's
