@@ -684,6 +684,8 @@ def main():
     ap.add_argument("--surrogate-samples", type=int, default=1_000_000,
                     help="training spectra for the warm-start section (0 skips it)")
     ap.add_argument("--no-matter", action="store_true", help="skip the constant-density matter section")
+    ap.add_argument("--matter-only", action="store_true",
+                    help="only the constant-density matter section (for kernel traces and counters)")
     ap.add_argument("--mlp-profile", action="store_true",
                     help="surrogate-network training steps only (for a kernel trace per product shape)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -722,6 +724,10 @@ def main():
     desc, events = synth.model_and_events(3, n_events)
     thetas = synth.osc_theta_list(desc, 64, seed=5)
     start = synth.start_vector(desc)
+    if args.matter_only:
+        print(json.dumps(dict(matter=matter_section(nf, synth, torch, stream, events, thetas, steps=args.steps))),
+              flush=True)
+        return
 
     def run(mode):
         eng = nf.Engine(desc, mode, stream=stream.cuda_stream)
