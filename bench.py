@@ -171,13 +171,15 @@ def mlp_profile(torch, batches=(1024, 4096), steps=100, warm=5):
             M, N, K = B, dims[l + 1], kin if l == 0 else dims[l]
             prods.append(("forward", l, M, N, K, *grid(M, N, K)))
         for l in range(depth, -1, -1):
+            # the training step takes each layer's input gradient before its
+            # weight gradient (the weights are updated right after the latter)
+            if l > 0:
+                M2, N2, K2 = B, dims[l], dims[l + 1]
+                prods.append(("input grad", l, M2, N2, K2, *grid(M2, N2, K2)))
             M, N, K = dims[l], dims[l + 1], B
             tiles = ((M + 127) // 128) * ((N + 127) // 128)
             sp = min(32, max(1, min(512 // tiles, B // 256)))
             prods.append(("weight grad", l, M, N, K, *grid(M, N, K, sp)))
-            if l > 0:
-                M2, N2, K2 = B, dims[l], dims[l + 1]
-                prods.append(("input grad", l, M2, N2, K2, *grid(M2, N2, K2)))
         x = torch.randn(B, n_in, device="cuda", dtype=torch.float32)
         t = torch.randn(B, n_out, device="cuda", dtype=torch.float32)
         torch.cuda.synchronize()

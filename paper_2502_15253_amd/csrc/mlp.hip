@@ -303,6 +303,41 @@ __global__ void colsum_final_kernel(const float* __restrict__ part, int nrb, int
   out[n] = s;
 }
 
+// Update of one layer inside the training step, right after its gradient
+// products: the weight gradient's K slices summed in slice order and the
+// bias gradient's column-sum partials in row-block order (the same sums as
+// slice_sum_kernel and colsum_final_kernel), Adam on the fp32 master weights
+// (step scalars sc as set by set_scalars_kernel), and the layer's bf16
+// copies, as stored and transposed for the forward product (to_bf16_kernel,
+// transpose_bf16_kernel).
+// Pointers are the layer's: w, g, m, v, wb at its weights (biases follow).
+__global__ void layer_update_kernel(float* w, float* g, float* m, float* v, uint16_t* wb, uint16_t* wt,
+                                    const float* __restrict__ kpart, int Z, const float* __restrict__ csum,
+                                    int nrb, int din, int dout, int dinp, const float* sc, float b1, float b2,
+                                    float eps) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nw = (int64_t)din * dout;
+  if (i >= nw + dout) return;
+  float gi = 0.f;
+  if (i < nw) {
+    for (int z = 0; z < Z; ++z) gi += kpart[(int64_t)z * nw + i];
+  } else {
+    const int c = (int)(i - nw);
+    for (int r = 0; r < nrb; ++r) gi += csum[(int64_t)r * dout + c];
+  }
+  g[i] = gi;
+  const float lr = sc[0], c1 = sc[1], c2 = sc[2];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  const uint16_t bw = f2bf(wi);
+  wb[i] = bw;
+  if (i < nw) wt[(int64_t)(i % dout) * dinp + i / dout] = bw;
+}
+
 // MSE over B x N: dy = 2 (y - t) / (B N) as fp32, bf16 and transposed bf16; per-block loss partials
 __global__ void mse_kernel(const float* y, const float* t, int B, int N, float scale, float* dyf, uint16_t* dyb,
                            uint16_t* dyt, float* partial) {
@@ -327,9 +362,12 @@ __global__ void mse_kernel(const float* y, const float* t, int B, int N, float s
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// Adam on the master weights; the step's learning rate and bias corrections
-// come from device memory (sc = {lr, 1 - b1^t, 1 - b2^t}), so that a captured
-// training step replays with each step's values.
+// Adam's moment decay rates and epsilon for the weight update.
+constexpr float ADAM_B1 = 0.9f, ADAM_B2 = 0.999f, ADAM_EPS = 1e-8f;
+
+// The Adam step's learning rate and bias corrections come from device memory
+// (sc = {lr, 1 - b1^t, 1 - b2^t}), so that a captured training step replays
+// with each step's values.
 __global__ void set_scalars_kernel(float* sc, float lr, float c1, float c2) {
   if (threadIdx.x == 0) {
     sc[0] = lr;
@@ -337,19 +375,6 @@ __global__ void set_scalars_kernel(float* sc, float lr, float c1, float c2) {
     sc[2] = c2;
   }
 }
-__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, const float* sc, float b1,
-                            float b2, float eps) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float lr = sc[0], c1 = sc[1], c2 = sc[2];
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-}
-
 // Surrogate Poisson deviance per row with Gaussian input priors, and dL/dy:
 // mu = exp(y std + mean), L = sum [mu - n + n ln(n/mu)] + 1/2 sum w_j (x_j - xbar_j)^2
 __global__ void surrogate_nll_kernel(const float* y, const float* nobs, const float* mean, const float* stdv,
@@ -539,12 +564,35 @@ void forward(nf_mlp* n, int B, bool keep_t) {
 
 // backward from the output gradient (fp32 n->dYf, bf16 n->dYb and, when
 // want_dw, transposed bf16 n->dYt, B x n_out): parameter gradients into n->g
-// when want_dw; input gradient into n->dX when want_dx
-void backward(nf_mlp* n, int B, bool want_dx, bool want_dw) {
+// when want_dw; input gradient into n->dX when want_dx. update: the training
+// step's form -- each layer's input gradient first (with the layer's weights
+// before the step), then its parameter gradients and, in one kernel, its
+// Adam step and bf16 copies (step scalars in n->scal).
+void backward(nf_mlp* n, int B, bool want_dx, bool want_dw, bool update = false) {
   float* cf = n->dYf;
   uint16_t* cb = n->dYb;
   uint16_t* ct = n->dYt;
   for (int l = n->L - 1; l >= 0; --l) {
+    float* nf = (cf == n->dZf) ? n->dYf : n->dZf;
+    uint16_t* nb = (cb == n->dZb) ? n->dYb : n->dZb;
+    uint16_t* nt = (ct == n->dZt) ? n->dYt : n->dZt;
+    auto input_grad = [&] {
+      // d(inp) = dcur W_l^T (B x din): W_l as stored is [din][dout], k = dout contiguous
+      GemmArgs gd{};
+      gd.M = B; gd.N = n->din[l]; gd.K = n->dout[l];
+      gd.A = cb; gd.lda = n->dout[l];
+      gd.B = n->wb + n->woff[l]; gd.ldb = n->dout[l];
+      gd.ldc = n->din[l];
+      if (l > 0) {
+        gd.Cf = nf; gd.Cb = nb; gd.Ct = want_dw ? nt : nullptr; gd.ldt = B; gd.Zin = n->Z[l - 1];
+        mck(gemm<EPI_DGELU>(gd, n->stream), "gemm dH");
+      } else {
+        gd.Cf = n->dX;
+        mck(gemm<EPI_F32>(gd, n->stream), "gemm dX");
+      }
+    };
+    const bool want_in = l > 0 || want_dx;
+    if (update && want_in) input_grad();
     if (want_dw) {
       // dW_l = inp^T dcur (din x dout), contraction over the batch in slices
       GemmArgs gw{};
@@ -557,33 +605,29 @@ void backward(nf_mlp* n, int B, bool want_dx, bool want_dw) {
       int zs = 1;
       mck(gemm<EPI_PARTIAL>(gw, n->stream, splits, &zs), "gemm dW");
       const int64_t mn = (int64_t)gw.M * gw.N;
-      hipLaunchKernelGGL(slice_sum_kernel, blocks(mn), dim3(256), 0, n->stream, n->kpart, zs, mn, n->g + n->woff[l]);
       // db_l = column sums of dcur
       const int nrb = (B + CS_ROWS - 1) / CS_ROWS;
       hipLaunchKernelGGL(colsum_partial_kernel, dim3((n->dout[l] + 63) / 64, nrb), dim3(256), 0, n->stream, cf, B,
                          n->dout[l], n->csum);
-      hipLaunchKernelGGL(colsum_final_kernel, blocks(n->dout[l]), dim3(256), 0, n->stream, n->csum, nrb, n->dout[l],
-                         n->g + n->boff[l]);
+      if (update) {
+        const int64_t o = n->woff[l];
+        hipLaunchKernelGGL(layer_update_kernel, blocks(mn + n->dout[l]), dim3(256), 0, n->stream, n->w + o, n->g + o,
+                           n->am + o, n->av + o, n->wb + o, n->wbt + n->toff[l], (const float*)n->kpart, zs,
+                           (const float*)n->csum, nrb, n->din[l], n->dout[l], n->dinp[l], (const float*)n->scal,
+                           ADAM_B1, ADAM_B2, ADAM_EPS);
+      } else {
+        hipLaunchKernelGGL(slice_sum_kernel, blocks(mn), dim3(256), 0, n->stream, n->kpart, zs, mn,
+                           n->g + n->woff[l]);
+        hipLaunchKernelGGL(colsum_final_kernel, blocks(n->dout[l]), dim3(256), 0, n->stream, n->csum, nrb,
+                           n->dout[l], n->g + n->boff[l]);
+      }
     }
-    if (l == 0 && !want_dx) break;
-    // d(inp) = dcur W_l^T (B x din): W_l as stored is [din][dout], k = dout contiguous
-    GemmArgs gd{};
-    gd.M = B; gd.N = n->din[l]; gd.K = n->dout[l];
-    gd.A = cb; gd.lda = n->dout[l];
-    gd.B = n->wb + n->woff[l]; gd.ldb = n->dout[l];
-    gd.ldc = n->din[l];
+    if (!want_in) break;
+    if (!update) input_grad();
     if (l > 0) {
-      float* nf = (cf == n->dZf) ? n->dYf : n->dZf;
-      uint16_t* nb = (cb == n->dZb) ? n->dYb : n->dZb;
-      uint16_t* nt = (ct == n->dZt) ? n->dYt : n->dZt;
-      gd.Cf = nf; gd.Cb = nb; gd.Ct = want_dw ? nt : nullptr; gd.ldt = B; gd.Zin = n->Z[l - 1];
-      mck(gemm<EPI_DGELU>(gd, n->stream), "gemm dH");
       cf = nf;
       cb = nb;
       ct = nt;
-    } else {
-      gd.Cf = n->dX;
-      mck(gemm<EPI_F32>(gd, n->stream), "gemm dX");
     }
   }
 }
@@ -740,18 +784,14 @@ int nf_mlp_train_step(nf_mlp* n, int B, const float* x, const float* t, float lr
     mck(hipMemcpyAsync(n->T, t, sizeof(float) * cnt, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                        n->stream), "t copy");
     n->adam_t += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.f - std::pow(b1, (float)n->adam_t), c2 = 1.f - std::pow(b2, (float)n->adam_t);
+    const float c1 = 1.f - std::pow(ADAM_B1, (float)n->adam_t), c2 = 1.f - std::pow(ADAM_B2, (float)n->adam_t);
     hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, n->stream, n->scal, lr, c1, c2);
     auto body = [&] {
       prep_input(n, B);
       forward(n, B, true);
       hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, n->stream, n->Y, n->T, B, n->n_out,
                          1.0f / (float)cnt, n->dYf, n->dYb, n->dYt, n->partial);
-      backward(n, B, false, true);
-      hipLaunchKernelGGL(adam_kernel, blocks(n->nparam), dim3(256), 0, n->stream, n->w, n->g, n->am, n->av,
-                         n->nparam, (const float*)n->scal, b1, b2, 1e-8f);
-      refresh_bf16(n);
+      backward(n, B, false, true, true);  // Adam and the bf16 copies per layer
     };
     if (!n->use_graph) {
       body();
