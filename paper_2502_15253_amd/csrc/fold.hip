@@ -108,15 +108,41 @@ __device__ __forceinline__ void accum_moments(T w, T wu, const T* s, const T* c,
   }
 }
 
+// FP64 path: ak = a TAB_PER_RAD, the angular frequencies in sin/cos table
+// units per (m/MeV); tab: the table in LDS (see load_sincos_table).
 template <int FORM>
-__device__ __forceinline__ void accum64(double u, float wf, const double* a, double* m) {
+__device__ __forceinline__ void accum64(double u, float wf, const double* ak, const double* tab, double* m) {
   constexpr int NPH = form_phases<FORM>();
   const double w = (double)wf;
   const double wu = w * u;
   double s[NPH], c[NPH];
 #pragma unroll
-  for (int q = 0; q < NPH; ++q) sincos_fold(a[q] * u, s[q], c[q]);
+  for (int q = 0; q < NPH; ++q) sincos_tab(ak[q] * u, tab, s[q], c[q]);
   accum_moments<FORM, double>(w, wu, s, c, m);
+}
+
+// The FP64 folds' sin/cos table (TAB_N (sin, cos) pairs, 4 KiB) goes to LDS
+// in two halves: the global loads first (each thread takes entries tid,
+// tid + blockDim, ...; blocks of at least 64 threads), the LDS stores later,
+// so that a kernel can issue its first event loads in between and the
+// table's latency overlaps theirs. A block barrier must follow the stores.
+struct TabRegs {
+  double2 v[TAB_N / 64];
+};
+__device__ __forceinline__ void load_sincos_table(TabRegs& r) {
+  const double2* T = reinterpret_cast<const double2*>(SINCOS_TAB);
+#pragma unroll
+  for (int k = 0; k < TAB_N / 64; ++k) {
+    const int e = threadIdx.x + k * blockDim.x;
+    if (e < TAB_N) r.v[k] = T[e];
+  }
+}
+__device__ __forceinline__ void store_sincos_table(const TabRegs& r, double* tab) {
+#pragma unroll
+  for (int k = 0; k < TAB_N / 64; ++k) {
+    const int e = threadIdx.x + k * blockDim.x;
+    if (e < TAB_N) reinterpret_cast<double2*>(tab)[e] = r.v[k];
+  }
 }
 
 // FP32 path: phases in revolutions, t = fract(f u) with the FP32 frequency
@@ -388,24 +414,34 @@ template <int FORM>
 __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   constexpr int NM = form_moments<FORM>();
   __shared__ double cfw[4][CF_SIZE];  // coefficient rows per wavefront (blocks of at most 256 threads)
+  __shared__ __attribute__((aligned(16))) double tab[2 * TAB_N];
   if (a.skip && *a.skip != FIT_RUNNING) return;  // uniform over the launch
   if ((int)blockIdx.x < a.npre) {
     parameter_pass(a, blockIdx.x, &cfw[0][0]);
     return;
   }
+  if (a.nitems == 0) return;
+  TabRegs tr;
+  load_sincos_table(tr);
+  __builtin_amdgcn_sched_barrier(0);
   const int lane = threadIdx.x & 63;
   const int item = __builtin_amdgcn_readfirstlane(
       (int)(((blockIdx.x - (unsigned)a.npre) * (unsigned)blockDim.x + threadIdx.x) >> 6));
-  if (item >= a.nitems) return;  // whole wavefronts leave together
+  // wavefronts past the last item take part in the table's barrier, with
+  // no events (every position loads from zpad), then leave
+  const bool live = item < a.nitems;
+  const int ic = live ? item : 0;
   double* cf = cfw[threadIdx.x >> 6];
   ItemEpi ep{};
   double thv[NLMAX];
   double af[3];
   osc_freqs_form<FORM>(a.osc, a.theta, af);
-  const WorkItem it = a.items[item];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) af[q] *= TAB_PER_RAD;
+  const WorkItem it = a.items[ic];
   const double* __restrict__ u = static_cast<const double*>(a.u);
   const float* __restrict__ w = a.w;
-  const int cnt = it.count;
+  const int cnt = live ? it.count : 0;
   const int niter = (cnt + 255) >> 8;
   double m[NM];
 #pragma unroll
@@ -420,13 +456,16 @@ __global__ __launch_bounds__(256) void fold_m64_kernel(FoldArgs a) {
   double2 pb = load_stream2(u + o);
   double2 qb = load_stream2(u + o + 2);
   float4 wb = load_stream4(w + o);
-  item_prefetch(a, item, ep, thv);
+  item_prefetch(a, ic, ep, thv);
   wave_coefficients(a, cf);
+  store_sincos_table(tr, tab);
+  __syncthreads();
+  if (!live) return;  // whole wavefronts leave together
   auto fold4 = [&](const double2& pp, const double2& qq, const float4& ww) {
-    accum64<FORM>(pp.x, ww.x, af, m);
-    accum64<FORM>(pp.y, ww.y, af, m);
-    accum64<FORM>(qq.x, ww.z, af, m);
-    accum64<FORM>(qq.y, ww.w, af, m);
+    accum64<FORM>(pp.x, ww.x, af, tab, m);
+    accum64<FORM>(pp.y, ww.y, af, tab, m);
+    accum64<FORM>(qq.x, ww.z, af, tab, m);
+    accum64<FORM>(qq.y, ww.w, af, tab, m);
   };
   // three register sets rotate: each step's loads are issued two steps ahead
   // of its folding (the scheduling barriers keep them ahead of the
@@ -647,6 +686,13 @@ __device__ __forceinline__ bool batch_fit_active(const BatchFoldArgs& a, int f, 
 template <int FORM, int FT>
 __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
   constexpr int NM = form_moments<FORM>();
+  __shared__ __attribute__((aligned(16))) double tab[2 * TAB_N];
+  {
+    TabRegs tr;
+    load_sincos_table(tr);
+    store_sincos_table(tr, tab);
+  }
+  __syncthreads();  // before any wavefront leaves
   const int lane = threadIdx.x & 63;
   const int item = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   if (item >= a.nitems) return;
@@ -659,6 +705,8 @@ __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
     af[j][0] = af[j][1] = af[j][2] = 0.0;
     act[j] = batch_fit_active<FORM>(a, f0 + j, af[j]);
     any = any || act[j];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) af[j][q] *= TAB_PER_RAD;
   }
   if (!any) return;
   const WorkItem it = a.items[item];
@@ -676,10 +724,10 @@ __global__ __launch_bounds__(256) void fold_batch_m64_kernel(BatchFoldArgs a) {
 #pragma unroll
     for (int j = 0; j < FT; ++j) {
       if (!act[j]) continue;
-      accum64<FORM>(u01.x, w4.x, af[j], m[j]);
-      accum64<FORM>(u01.y, w4.y, af[j], m[j]);
-      accum64<FORM>(u23.x, w4.z, af[j], m[j]);
-      accum64<FORM>(u23.y, w4.w, af[j], m[j]);
+      accum64<FORM>(u01.x, w4.x, af[j], tab, m[j]);
+      accum64<FORM>(u01.y, w4.y, af[j], tab, m[j]);
+      accum64<FORM>(u23.x, w4.z, af[j], tab, m[j]);
+      accum64<FORM>(u23.y, w4.w, af[j], tab, m[j]);
     }
   }
 #pragma unroll
