@@ -1180,7 +1180,8 @@ void ensure_fit_graph(nf_ctx* c) {
 }
 
 // Diagonal preconditioner: prior variance, else covariance-block diagonal,
-// else (5% of the start value, at least 1e-3)^2.
+// else (5% of the start value, at least 1e-3)^2, a scale guess, stored
+// negated so that the minimiser can tell it from a variance.
 std::vector<double> preconditioner(nf_ctx* c, const double* start) {
   std::vector<double> d2(c->P, -1.0);
   const DevPlan& pl = c->plan;
@@ -1196,7 +1197,7 @@ std::vector<double> preconditioner(nf_ctx* c, const double* start) {
   for (int i = 0; i < c->P; ++i)
     if (d2[i] < 0) {
       const double s = 0.05 * std::max(std::fabs(start[i]), 0.02);
-      d2[i] = s * s;
+      d2[i] = -(s * s);
     }
   return d2;
 }
@@ -1319,7 +1320,7 @@ int fit_impl(nf_ctx* c, const double* start, const uint8_t* fixed, const nf_fit_
     double fdum;
     for (int a = 0; a < n; ++a) {
       const int j = fi[a];
-      const double hstep = 1e-3 * std::sqrt(d2[j]);
+      const double hstep = 1e-3 * std::sqrt(std::fabs(d2[j]));
       th[j] = x[j] + hstep;
       eval_host(c, th.data(), &fdum, gp.data(), nullptr);
       th[j] = x[j] - hstep;

@@ -11,7 +11,7 @@ namespace nufold {
 // Minimiser state of one fit (device memory).
 constexpr int FIT_RUNNING = 0, FIT_CONVERGED = 1, FIT_MAXITER = 2, FIT_LSFAIL = 3, FIT_DOMAIN = 4;
 struct FitHeader {
-  int status, phase, iter, nevals, ls_steps, hist_n, hist_head, resets, max_iter, pad_;
+  int status, phase, iter, nevals, ls_steps, hist_n, hist_head, resets, max_iter, checks;
   double f, edm, alpha, dphi0;
   double a_prev, f_prev, d_prev;
   double a_lo, f_lo, d_lo, a_hi, f_hi, d_hi;

@@ -16,6 +16,13 @@
 //            decrease point and accepts it
 // Convergence: EDM < tol and the last accepted step lowered f by less than
 // tol (the limited-memory metric can underestimate the distance early on).
+// Along directions the history has not explored, H is gamma D, and gamma
+// (set by the stiffest recent directions) can make the EDM there far too
+// small for a parameter whose D is only a scale guess (no prior, so its
+// variance is unknown; such entries of D are stored negated). So a point
+// that passes is checked once more with max(gamma, 1) in place of gamma on
+// those parameters; if that EDM is not below tol, the fit goes on along the
+// direction of the re-check (at most MAX_CHECKS times per fit).
 // Direction: two-loop recursion over the last m pairs (s, y) with
 // H0 = gamma D, D a diagonal preconditioner (prior variances or a scale per
 // parameter), gamma = s^T y / y^T D y of the newest pair. Fixed parameters
@@ -30,6 +37,7 @@ namespace nufold {
 constexpr int PH_INIT = 0, PH_BRACKET = 1, PH_ZOOM = 2, PH_FORCE = 3;
 constexpr double LS_C1 = 1e-4, LS_C2 = 0.9, LS_AMAX = 64.0;
 constexpr int LS_MAX_STEPS = 40;
+constexpr int MAX_CHECKS = 4;
 
 template <int NT>
 __device__ __forceinline__ double bdot(const double* a, const double* b, int n, double* red) {
@@ -65,11 +73,13 @@ __device__ inline double cubic_step(double a, double fa, double da, double b, do
 }
 
 // Direction p = -H g (two-loop recursion); everything in LDS. Returns g^T p.
+// gfloor: lower bound on the scale gamma of H0 = gamma D on the parameters
+// whose D is a scale guess (negative in F.d2).
 template <int NT>
 __device__ double lbfgs_direction(const FitArgs& F, int P, int hn, int head, const double* g, double* q,
                                   double* r, double* pdir, const double* Sl, const double* Yl,
                                   const double* rho, const double* gam, double* alph, const double* D,
-                                  const double* fr, double* red) {
+                                  const double* fr, double* red, double gfloor = 0.0) {
   const int m = F.m;
   for (int i = threadIdx.x; i < P; i += NT) q[i] = g[i] * fr[i];
   for (int j = 0; j < hn; ++j) {
@@ -79,7 +89,12 @@ __device__ double lbfgs_direction(const FitArgs& F, int P, int hn, int head, con
     for (int i = threadIdx.x; i < P; i += NT) q[i] -= a * Yl[(int64_t)idx * P + i];
   }
   const double gm = hn > 0 ? gam[(head - 1 + m) % m] : 1.0;
-  for (int i = threadIdx.x; i < P; i += NT) r[i] = gm * D[i] * q[i];
+  if (gfloor > gm) {
+    const double gg = gfloor;
+    for (int i = threadIdx.x; i < P; i += NT) r[i] = (F.d2[i] < 0.0 ? gg : gm) * D[i] * q[i];
+  } else {
+    for (int i = threadIdx.x; i < P; i += NT) r[i] = gm * D[i] * q[i];
+  }
   __syncthreads();
   for (int j = hn - 1; j >= 0; --j) {
     const int idx = (head - 1 - j + m) % m;
@@ -122,7 +137,7 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
   FitHeader h = *H;  // private snapshot; written back by thread 0 at the end
   int hn = h.hist_n, head = h.hist_head;
   for (int i = tid; i < P; i += NT) {
-    D[i] = F.d2[i];
+    D[i] = fabs(F.d2[i]);
     fr[i] = F.freem[i];
     gx[i] = F.g[i];
     pd[i] = F.p[i];
@@ -273,10 +288,21 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
       head = 0;
       d0 = lbfgs_direction<NT>(F, P, 0, 0, gx, q, r, pd, Sl, Yl, rho, gam, alph, D, fr, red);
     }
-    const double edm = -0.5 * d0;
+    double edm = -0.5 * d0;
     int st = FIT_RUNNING;
     const bool small_step = h.iter > 0 && h.df < fmax(h.edm_tol, 1e-15 * fabs(h.f));
-    if (!(d0 < 0.0) || (edm < h.edm_tol && small_step)) st = FIT_CONVERGED;
+    bool conv = !(d0 < 0.0) || (edm < h.edm_tol && small_step);
+    if (conv && d0 < 0.0 && hn > 0 && h.checks < MAX_CHECKS && gam[(head - 1 + m) % m] < 1.0) {
+      // re-check with gamma at least 1 (uniform: every thread holds hn, head, gam)
+      const double d1 = lbfgs_direction<NT>(F, P, hn, head, gx, q, r, pd, Sl, Yl, rho, gam, alph, D, fr, red, 1.0);
+      if (d1 < 0.0 && -0.5 * d1 >= h.edm_tol) {
+        conv = false;  // go on along the re-check's direction
+        h.checks += 1;
+        d0 = d1;
+        edm = -0.5 * d1;
+      }
+    }
+    if (conv) st = FIT_CONVERGED;
     else if (h.iter >= h.max_iter) st = FIT_MAXITER;
     else if (h.resets > 3) st = FIT_LSFAIL;
     for (int i = tid; i < P; i += NT) {
