@@ -22,12 +22,16 @@
 // variance is unknown; such entries of D are stored negated). So a point
 // that passes is checked once more with max(gamma, 1) in place of gamma on
 // those parameters; if that EDM is not below tol, the fit goes on along the
-// direction of the re-check (at most MAX_CHECKS times per fit).
+// direction of the re-check (at most MAX_CHECKS times per fit). After such a
+// re-check, a line search that fails or ends only by its forced step marks a
+// domain boundary or a flat ridge rather than a missed minimum: the fit
+// stops there as converged (its point passed the rule before).
 // Direction: two-loop recursion over the last m pairs (s, y) with
 // H0 = gamma D, D a diagonal preconditioner (prior variances or a scale per
 // parameter), gamma = s^T y / y^T D y of the newest pair. Fixed parameters
 // have zero gradient and direction. A failed line search drops the history
-// and retries along -D g; three failures end the fit.
+// and retries along -D g; a forced step that lowers f by less than tol also
+// counts as a failure; more than three failures end the fit.
 #pragma once
 
 #include "kernels.hpp"
@@ -136,6 +140,7 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
 
   FitHeader h = *H;  // private snapshot; written back by thread 0 at the end
   int hn = h.hist_n, head = h.hist_head;
+  const bool forced_trial = h.phase == PH_FORCE;
   for (int i = tid; i < P; i += NT) {
     D[i] = fabs(F.d2[i]);
     fr[i] = F.freem[i];
@@ -178,8 +183,12 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
     double alo = h.a_lo, flo = h.f_lo, dlo = h.d_lo, ahi = h.a_hi, fhi = h.f_hi, dhi = h.d_hi;
     int ph = h.phase;
     if (ph == PH_FORCE) {
-      if (isfinite(f_t) && f_t < f0) accept = true;
-      else {
+      if (isfinite(f_t) && f_t < f0) {
+        accept = true;
+        // a forced step that gains next to nothing (e.g. along a domain
+        // boundary the direction keeps pointing across) counts as a failure
+        if (f0 - f_t < fmax(h.edm_tol, 1e-15 * fabs(f0))) h.resets += 1;
+      } else {
         restart = true;
         h.resets += 1;
       }
@@ -291,8 +300,9 @@ __device__ void lbfgs_step(const FitArgs& F, int P, const double* th_t, double f
     double edm = -0.5 * d0;
     int st = FIT_RUNNING;
     const bool small_step = h.iter > 0 && h.df < fmax(h.edm_tol, 1e-15 * fabs(h.f));
-    bool conv = !(d0 < 0.0) || (edm < h.edm_tol && small_step);
-    if (conv && d0 < 0.0 && hn > 0 && h.checks < MAX_CHECKS && gam[(head - 1 + m) % m] < 1.0) {
+    const bool stuck = h.checks > 0 && (restart || (accept && forced_trial));
+    bool conv = stuck || !(d0 < 0.0) || (edm < h.edm_tol && small_step);
+    if (!stuck && conv && d0 < 0.0 && hn > 0 && h.checks < MAX_CHECKS && gam[(head - 1 + m) % m] < 1.0) {
       // re-check with gamma at least 1 (uniform: every thread holds hn, head, gam)
       const double d1 = lbfgs_direction<NT>(F, P, hn, head, gx, q, r, pd, Sl, Yl, rho, gam, alph, D, fr, red, 1.0);
       if (d1 < 0.0 && -0.5 * d1 >= h.edm_tol) {
