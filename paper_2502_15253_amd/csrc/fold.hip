@@ -122,27 +122,24 @@ __device__ __forceinline__ void accum64(double u, float wf, const double* ak, co
 }
 
 // The FP64 folds' sin/cos table (TAB_N (sin, cos) pairs, 4 KiB) goes to LDS
-// in two halves: the global loads first (each thread takes entries tid,
-// tid + blockDim, ...; blocks of at least 64 threads), the LDS stores later,
-// so that a kernel can issue its first event loads in between and the
-// table's latency overlaps theirs. A block barrier must follow the stores.
+// in two halves: thread i's global load of entry i first, the LDS stores
+// later, so that a kernel can issue its first event loads in between and the
+// table's latency overlaps theirs. One entry per thread keeps the registers
+// held across those loads to one pair; entries past the block size (blocks
+// of fewer than TAB_N threads) are loaded and stored by the second half. A
+// block barrier must follow the stores.
 struct TabRegs {
-  double2 v[TAB_N / 64];
+  double2 v;
 };
 __device__ __forceinline__ void load_sincos_table(TabRegs& r) {
   const double2* T = reinterpret_cast<const double2*>(SINCOS_TAB);
-#pragma unroll
-  for (int k = 0; k < TAB_N / 64; ++k) {
-    const int e = threadIdx.x + k * blockDim.x;
-    if (e < TAB_N) r.v[k] = T[e];
-  }
+  if (threadIdx.x < TAB_N) r.v = T[threadIdx.x];
 }
 __device__ __forceinline__ void store_sincos_table(const TabRegs& r, double* tab) {
-#pragma unroll
-  for (int k = 0; k < TAB_N / 64; ++k) {
-    const int e = threadIdx.x + k * blockDim.x;
-    if (e < TAB_N) reinterpret_cast<double2*>(tab)[e] = r.v[k];
-  }
+  const double2* T = reinterpret_cast<const double2*>(SINCOS_TAB);
+  double2* D = reinterpret_cast<double2*>(tab);
+  if (threadIdx.x < TAB_N) D[threadIdx.x] = r.v;
+  for (int e = threadIdx.x + blockDim.x; e < TAB_N; e += blockDim.x) D[e] = T[e];
 }
 
 // FP32 path: phases in revolutions, t = fract(f u) with the FP32 frequency
