@@ -1039,7 +1039,7 @@ void enqueue_eval(nf_ctx* c, const double* theta_dev, double* out_dev, int32_t* 
   fa.part = sc.part;
   fa.plan = c->plan;
   fa.pre = sc.pre;
-  fa.npre = c->plan.D + 1;
+  fa.npre = 3 * c->plan.D + 1;
   FoldFuse& fu = fa.fuse;
   fu.epi = c->d_epi.p;
   fu.seg_item = c->d_seg_item.p;

@@ -341,11 +341,13 @@ __device__ __forceinline__ void fold_finish(const FoldArgs& a, const double* cf,
   }
 }
 
-// Parameter pass of the single evaluation, in the first npre workgroups of
-// the fold launch (they run alongside the event stream): workgroup b < D
-// forms dataset b's flux factors, mapped edges and background terms;
-// workgroup D evaluates the prior rows, sums their NLL in a fixed order and
-// checks the parameters' domain. The parameters are read from global memory
+// Parameter pass of the single evaluation, in the first npre = 3 D + 1
+// workgroups of the fold launch (they run alongside the event stream):
+// workgroups 3d, 3d + 1 and 3d + 2 form dataset d's flux factors, its mapped
+// edges (and the energy map's domain flag) and its background terms; the
+// last one evaluates the prior rows, sums their NLL in a fixed order and
+// checks the parameters' domain. (One workgroup per dataset took about
+// 13 us, longer than the whole event stream below a few million events.) The parameters are read from global memory
 // (a few hundred values, cached). red: this workgroup's LDS rows (at least
 // 2 x (blockDim / 64) doubles).
 __device__ void parameter_pass(const FoldArgs& a, int b, double* red) {
@@ -353,7 +355,9 @@ __device__ void parameter_pass(const FoldArgs& a, int b, double* red) {
   const double* th = a.theta;
   double* pre = a.pre;
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (b < p.D) {
+  if (b < 3 * p.D) {
+    const int part = b % 3;
+    b /= 3;
     const DsPlan& ds = b == 0 ? p.ds0 : p.ds[b];
     const int K = ds.K, Nb = ds.Nb, E = Nb + 1, NB = ds.nbkg;
     const double wf = ds.wf, iwf = 1.0 / wf, y0 = ds.y0, yK = ds.y0 + ds.wf * K;
@@ -364,16 +368,21 @@ __device__ void parameter_pass(const FoldArgs& a, int b, double* red) {
     const double bb = 1.0 + pval(th, ds.cidx[1], 0.0);
     const PreLayout PL = pre_layout(K, Nb, NB);
     double* q = pre + ds.pre0;
-    if (tid == 0) pre[p.pre_misc + 2 + b] = map_ok(bb, c2, y0, yK) ? 0.0 : 1.0;
-    for (int k = tid; k < K; k += nt) q[PL.F1 + k] = flux_factor(th, blob, BL, ds.fw, k);
-    for (int e = tid; e < E; e += nt) {
-      const MappedEdge m = map_edge(blob[BL.edges + e], c0, bb, c2, y0, yK, wf, iwf, K);
-      reinterpret_cast<int*>(q + PL.ek)[e] = m.k;
-      q[PL.et + e] = m.t;
-      q[PL.ey + e] = m.y;
-      q[PL.eq + e] = m.ifp;
+    if (part == 0) {
+      for (int k = tid; k < K; k += nt) q[PL.F1 + k] = flux_factor(th, blob, BL, ds.fw, k);
+    } else if (part == 1) {
+      if (tid == 0) pre[p.pre_misc + 2 + b] = map_ok(bb, c2, y0, yK) ? 0.0 : 1.0;
+      for (int e = tid; e < E; e += nt) {
+        const MappedEdge m = map_edge(blob[BL.edges + e], c0, bb, c2, y0, yK, wf, iwf, K);
+        reinterpret_cast<int*>(q + PL.ek)[e] = m.k;
+        q[PL.et + e] = m.t;
+        q[PL.ey + e] = m.y;
+        q[PL.eq + e] = m.ifp;
+      }
+    } else {
+      for (int i = tid; i < Nb; i += nt)
+        q[PL.B + i] = background(th, blob, BL, NB, Nb, i, q + PL.bkr + i, q + PL.bks + i);
     }
-    for (int i = tid; i < Nb; i += nt) q[PL.B + i] = background(th, blob, BL, NB, Nb, i, q + PL.bkr + i, q + PL.bks + i);
     return;
   }
   double e_sum = 0.0, bad = 0.0;

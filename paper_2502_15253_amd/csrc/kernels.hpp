@@ -76,8 +76,8 @@ struct FoldArgs {
   const int* skip;      // nullable: skip the launch unless *skip == FIT_RUNNING
   FoldFuse fuse;        // used when fuse.seg_cnt != nullptr
   // parameter pass of the single evaluation, run by the launch's first npre
-  // workgroups (one per dataset, then one for the prior rows) alongside the
-  // event stream, into pre (see DevPlan.pre_*); npre = 0: none
+  // workgroups (three per dataset, then one for the prior rows) alongside
+  // the event stream, into pre (see DevPlan.pre_*); npre = 0: none
   DevPlan plan;
   double* pre;
   int npre;
