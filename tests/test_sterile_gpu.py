@@ -84,3 +84,33 @@ def test_raster_ensembles_and_exclusion():
     # points between 1 and 6); far from it they need not
     assert 0.3 < float(res["t_pe"][1].mean()) < 2.0
     assert np.all((res["t_crit"][:2] > 1.0) & (res["t_crit"][:2] < 6.0))
+
+
+def test_raster_fits_at_the_mixing_boundary_end_promptly():
+    """Free fits whose sin^2(2 theta14) runs to the edge of its domain (at a
+    small dm2_41 many pseudo-experiments prefer maximal mixing) must end by
+    the convergence rule or as line-search failures within a bounded number
+    of evaluations, not by stepping along the boundary until the iteration
+    limit: one such fit holds its whole batch of fits."""
+    say("sterile raster boundary fits")
+    desc, events = synth.model_and_events("sterile", None)
+    eng = nf.Engine(desc, "m64")
+    for d, ev in enumerate(events):
+        eng.set_events(d, ev["e_true"], ev["e_reco"], ev["source"], ev["weight"])
+    mus, _ = eng.expected(synth.start_vector(desc))
+    row = np.concatenate(synth.poisson_data(mus, synth.data_seed(7)))
+    rs = RasterScan(eng, desc)
+    seen = []
+    orig = rs._fit
+
+    def spy(starts, fix_s, didx):
+        r = orig(starts, fix_s, didx)
+        seen.append((bool(fix_s), int(r["iters"].max()), int(r["evals"].max()), r["status"].copy()))
+        return r
+    rs._fit = spy
+    rs.run(row, np.linspace(0.0, 0.2, 8), np.geomspace(0.5, 500.0, 10), n_pe=100, cl=0.9, seed=2)
+    for fix_s, it_max, ev_max, status in seen:
+        print(f"[raster] fixed s {fix_s}: max iterations {it_max}, max evaluations {ev_max}", flush=True)
+        assert it_max < rs.max_iter and ev_max < 5000, (fix_s, it_max, ev_max)
+        assert np.all((status == nf.NF_OK) | (status == 3)), np.unique(status)
+    eng.close()
