@@ -193,6 +193,53 @@ def test_work_item_chunking_does_not_change_results(mode):
             assert np.max(np.abs(g - ref[1])) <= 1e-12 * max(1, np.max(np.abs(g)))
 
 
+@pytest.mark.parametrize("mode", ["m64", "m32"])
+def test_launch_options_do_not_change_results(mode):
+    # every fold workgroup size (64, 128, 256 threads: blocks smaller than the
+    # FP64 folds' sin/cos table fill the rest of it in a second pass) and
+    # every bin-stage workgroup size the autotuner may choose, on every form.
+    # Work items do not depend on these options, so the fold's sums are the
+    # same; only the bin stages' block sums change order: every option agrees
+    # with the default one to 1e-12, and the default one with the oracle (M64:
+    # the 1e-9 bar throughout; M32: the per-component gradient bar; its
+    # whole-vector bar is checked on the other workloads)
+    say("launch options", mode)
+    tol, gtol = TOL[mode], GRAD_TOL[mode]
+    for formula in ("eq1", "3nu", "4nu", "3nu_matter"):
+        desc = synth.tiny_model(31, formula=formula, n_datasets=2, n_sources=2)
+        events = synth.tiny_events(desc, 20000, 8)
+        data = oracle_data(desc, events, 9)
+        th = displaced(desc, 10)
+        m = Model(desc)
+        mus_o, _ = LK.expected(m, events, th)
+        f_o, g_o, F = LK.nll_grad(m, events, data, th, fisher=True)
+        ref = None
+        for fb in (256, 64, 128):
+            for tt in (512, 256, 1024):
+                what = f"{formula} fold_block {fb} tail_threads {tt}"
+                eng = make_engine(desc, events, data, mode)
+                eng.set_option("fold_block", fb)
+                eng.set_option("tail_threads", tt)
+                mus_g, code = eng.expected(th)
+                assert code == nf.NF_OK, what
+                f_g, g_g, code = eng.eval_nll_grad(th)
+                assert code == nf.NF_OK, what
+                eng.close()
+                if ref is None:
+                    ref = (mus_g, f_g, g_g)
+                    for mo, mg in zip(mus_o, mus_g):
+                        assert np.max(np.abs(mg - mo) / np.maximum(np.abs(mo), 1e-300)) <= tol, what
+                    assert abs(f_g - f_o) <= tol * max(1.0, abs(f_o)), (what, f_g, f_o)
+                    if mode == "m64":
+                        assert np.max(np.abs(g_g - g_o)) <= tol * max(1.0, np.max(np.abs(g_o))), what
+                    gradcheck.check(g_g, g_o, F, gtol, what, m.names)
+                    continue
+                for mr, mg in zip(ref[0], mus_g):
+                    assert np.max(np.abs(mg - mr) / np.maximum(np.abs(mr), 1e-300)) <= 1e-12, what
+                assert abs(f_g - ref[1]) <= 1e-12 * max(1.0, abs(ref[1])), what
+                assert np.max(np.abs(g_g - ref[2])) <= 1e-12 * max(1.0, np.max(np.abs(ref[2]))), what
+
+
 def test_repeated_evaluations_are_bitwise_identical():
     say("determinism")
     desc, events = synth.model_and_events(1)
